@@ -1,0 +1,338 @@
+"""Plain FP64 CPU oracle for the sheared model-H time step.
+
+TEST INFRASTRUCTURE ONLY.  This module is the independent reference that the
+GPU library is checked against.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import it; the product path never does.
+It shares no code, tables or helpers with the HIP implementation.
+
+What it computes (Fielding, "The need for inertia in nonequilibrium steady
+states of sheared binary fluids"):
+
+* the 2D model-H equations posed in the cosheared frame (section "Numerical
+  method", Eqs. equation1-equation4, with the sawtooth strain s(t) of Eq.
+  coshearedNabluFinal);
+* advanced by the three-stage split step of Appendix B: explicit-Euler
+  advection with the shear-interpolated y stencil (Eqs. advective, p1y),
+  the Cahn-Hilliard diffusive update in Fourier space with explicit Euler for
+  the nabla^2 terms and Crank-Nicolson for nabla^4, mu and the vorticity
+  source g by finite differences, Crank-Nicolson for omega, and the
+  per-wavenumber solve for psi (or the biharmonic solve at rho = 0, Appendix B
+  "Algorithm at zero Reynolds number").
+
+Readings taken where the paper is silent (each is listed in the design notes):
+
+* general free energy mu = B phi^3 - A phi - kappa nabla_c^2 phi and
+  d_t phi = M nabla_c^2 mu (the paper's units are A = B = 1, kappa = M = l^2);
+* the paper's per-mode 4x4 real blocks act on one complex Fourier coefficient
+  per mode as the scalar lambda = D + Delta = -|q_lab|^2; the odd cross term
+  q_x q_y is set to zero on the Nyquist row and column so every multiplier is
+  Hermitian;
+* every operator of step n uses s_n; f = (phi^n)^3; the omega Crank-Nicolson
+  update starts from the advected omega^{n+1/2};
+* the q = 0 mode: phi untouched, omega and psi set to zero;
+* at a strain wrap s -> s - c (c = Lx/Ly) the fields are remapped row by row,
+  new[j][i] = old[j][(i - r j) mod Nx] with r = Nx/Ny, so the lab-frame field
+  is continuous;
+* the sheared y stencil uses offsets +-r cells in x with weight |s|/c, which is
+  the paper's "i -+ 2, weight s/2" at its own geometry (Lx = 2 Ly, Nx = 2 Ny).
+
+Arrays are indexed a[j, i]: j along y (gradient direction), i along x (flow
+direction), x fastest.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Params:
+    """Problem statement of section "Choice of units" plus the grid.
+
+    f(phi) = -A/2 phi^2 + B/4 phi^4 + kappa/2 |grad phi|^2; mobility M;
+    viscosity eta; density rho (rho == 0 selects the Stokes branch); shear
+    rate gdot; box lx x ly on an nx x ny grid; time step dt.
+    """
+
+    nx: int
+    ny: int
+    lx: float
+    ly: float
+    gdot: float = 0.0
+    A: float = 1.0
+    B: float = 1.0
+    kappa: float = 1.0
+    M: float = 1.0
+    eta: float = 1.0
+    rho: float = 1.0
+    dt: float = 0.005
+
+    @property
+    def dx(self) -> float:
+        return self.lx / self.nx
+
+    @property
+    def dy(self) -> float:
+        return self.ly / self.ny
+
+    @property
+    def c(self) -> float:
+        """Box aspect ratio Lx/Ly: the height of the sawtooth's jumps."""
+        return self.lx / self.ly
+
+    @property
+    def r(self) -> int:
+        """Grid ratio Nx/Ny: the x offset (in cells) of the sheared stencil."""
+        return self.nx // self.ny
+
+
+@dataclasses.dataclass
+class State:
+    phi: np.ndarray
+    omega: np.ndarray  # zeros (and unused) when rho == 0
+    psi: np.ndarray
+    step: int = 0
+    wraps: int = 0
+
+
+# ---------------------------------------------------------------------------
+# Shear clock (section "Numerical method", sawtooth s(t))
+# ---------------------------------------------------------------------------
+
+def strain_total(p: Params, n: int) -> float:
+    """Accumulated strain gdot * t at step n, formed as gdot * (n * dt)."""
+    return p.gdot * (float(n) * p.dt)
+
+
+def wrap_count(p: Params, n: int) -> int:
+    """Number of jumps of height c taken by step n (s kept in [-c/2, c/2))."""
+    X = strain_total(p, n)
+    return int(math.floor((X + 0.5 * p.c) / p.c))
+
+
+def strain_offset(p: Params, n: int) -> float:
+    """The sawtooth s(t_n) of the cosheared gradient operator."""
+    return strain_total(p, n) - p.c * wrap_count(p, n)
+
+
+def remap(p: Params, a: np.ndarray, dk: int) -> np.ndarray:
+    """Re-express a cosheared-frame field after s -> s - dk*c.
+
+    Keeps the lab-frame field unchanged: new[j, i] = old[j, (i - dk*r*j) mod Nx].
+    """
+    out = np.empty_like(a)
+    for j in range(p.ny):
+        shift = (dk * p.r * j) % p.nx
+        out[j] = np.roll(a[j], shift)  # out[j, i] = a[j, i - shift]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Finite-difference stencils (Appendix B, Eq. p1y and the mu stencils)
+# ---------------------------------------------------------------------------
+
+def at(a: np.ndarray, dj: int, di: int) -> np.ndarray:
+    """Periodic neighbour: at(a, dj, di)[j, i] = a[j + dj, i + di]."""
+    return np.roll(a, (-dj, -di), axis=(0, 1))
+
+
+def d_x(p: Params, a: np.ndarray) -> np.ndarray:
+    """Central first difference in x."""
+    return (at(a, 0, 1) - at(a, 0, -1)) / (2.0 * p.dx)
+
+
+def d_y_sheared(p: Params, a: np.ndarray, s: float) -> np.ndarray:
+    """Shear-interpolated central y difference of Eq. p1y.
+
+    Blends the plain central difference with one taken along the grid
+    diagonal (j+1, i - sign(s) r) / (j-1, i + sign(s) r), weight |s|/c.
+    It approximates the lab-frame derivative d_y - s d_x to second order.
+    """
+    w = abs(s) / p.c
+    sg = 1 if s >= 0 else -1
+    plain = at(a, 1, 0) - at(a, -1, 0)
+    diag = at(a, 1, -sg * p.r) - at(a, -1, sg * p.r)
+    return ((1.0 - w) * plain + w * diag) / (2.0 * p.dy)
+
+
+def d_xx(p: Params, a: np.ndarray) -> np.ndarray:
+    return (at(a, 0, 1) - 2.0 * a + at(a, 0, -1)) / (p.dx * p.dx)
+
+
+def d_yy(p: Params, a: np.ndarray) -> np.ndarray:
+    return (at(a, 1, 0) - 2.0 * a + at(a, -1, 0)) / (p.dy * p.dy)
+
+
+def d_xy(p: Params, a: np.ndarray) -> np.ndarray:
+    """Four-point mixed derivative."""
+    return (at(a, 1, 1) - at(a, -1, 1) - at(a, 1, -1) + at(a, -1, -1)) / (
+        4.0 * p.dx * p.dy)
+
+
+def advection(p: Params, psi: np.ndarray, a: np.ndarray, s: float) -> np.ndarray:
+    """The bracket d_y psi d_x a - d_x psi d_y a of Eq. advective."""
+    return d_y_sheared(p, psi, s) * d_x(p, a) - d_x(p, psi) * d_y_sheared(p, a, s)
+
+
+def chemical_potential(p: Params, phi: np.ndarray, s: float) -> np.ndarray:
+    """mu = B phi^3 - A phi - kappa[(1+s^2) d_xx + d_yy - 2 s d_xy] phi."""
+    lap_c = (1.0 + s * s) * d_xx(p, phi) + d_yy(p, phi) - 2.0 * s * d_xy(p, phi)
+    return p.B * phi ** 3 - p.A * phi - p.kappa * lap_c
+
+
+def korteweg_bracket(p: Params, phi: np.ndarray, mu: np.ndarray, s: float) -> np.ndarray:
+    """K = d_x phi d_y mu - d_y phi d_x mu (Eq. G without the -1/rho)."""
+    return d_x(p, phi) * d_y_sheared(p, mu, s) - d_y_sheared(p, phi, s) * d_x(p, mu)
+
+
+# ---------------------------------------------------------------------------
+# Fourier space (Appendix B: D, Delta, a = 1 + s^2, b = 2s)
+# ---------------------------------------------------------------------------
+
+def wavenumbers(p: Params):
+    """Signed wavenumbers qx[m], qy[n] and the Nyquist masks."""
+    m = np.arange(p.nx)
+    n = np.arange(p.ny)
+    ms = np.where(m >= p.nx // 2, m - p.nx, m)
+    ns = np.where(n >= p.ny // 2, n - p.ny, n)
+    qx = 2.0 * math.pi * ms / p.lx
+    qy = 2.0 * math.pi * ns / p.ly
+    return qx, qy, (m == p.nx // 2), (n == p.ny // 2)
+
+
+def symbol_laplacian(p: Params, s: float) -> np.ndarray:
+    """lambda(q; s), the eigenvalue D + Delta of the cosheared Laplacian block.
+
+    D = -(a qx^2 + qy^2), Delta = b qx qy with a = 1 + s^2, b = 2s; the cross
+    term is dropped on the Nyquist row/column.  Shape (ny, nx).
+    """
+    qx, qy, nyq_x, nyq_y = wavenumbers(p)
+    QX = qx[None, :]
+    QY = qy[:, None]
+    P = QX * QY
+    P = np.where(nyq_x[None, :] | nyq_y[:, None], 0.0, P)
+    D = -((1.0 + s * s) * QX * QX + QY * QY)
+    Delta = 2.0 * s * P
+    return D + Delta
+
+
+def fft2(a: np.ndarray) -> np.ndarray:
+    """Unnormalised forward DFT F[a](m, n) = sum a_ij exp(-2 pi i (mi/Nx + nj/Ny))."""
+    return np.fft.fft2(a)
+
+
+def ifft2_real(A: np.ndarray) -> np.ndarray:
+    """Inverse DFT with 1/N, real part (the imaginary part is rounding only)."""
+    return np.real(np.fft.ifft2(A))
+
+
+# ---------------------------------------------------------------------------
+# The split step (Appendix B, stages 1-3, and the zero-Reynolds variant)
+# ---------------------------------------------------------------------------
+
+def stage_advect(p: Params, st: State, s: float):
+    """Stage 1a: explicit-Euler advection of phi (and omega when rho > 0), and f."""
+    phi_h = st.phi - p.dt * advection(p, st.psi, st.phi, s)
+    if p.rho > 0.0:
+        omega_h = st.omega - p.dt * advection(p, st.psi, st.omega, s)
+    else:
+        omega_h = st.omega
+    f = st.phi ** 3
+    return phi_h, omega_h, f
+
+
+def stage_cahn_hilliard(p: Params, phi_h: np.ndarray, f: np.ndarray, s: float) -> np.ndarray:
+    """Stage 1b: per-mode update, explicit in nabla^2 and f, Crank-Nicolson in nabla^4.
+
+    phi' = phi_h + (1 + dt kM lam^2/2)^-1 (-dt A M lam phi_h - dt kM lam^2 phi_h
+                                           + dt B M lam F)
+    """
+    lam = symbol_laplacian(p, s)
+    Ph = fft2(phi_h)
+    F = fft2(f)
+    d2 = p.dt * p.M * lam          # tilde D_2 acting on phi (times A) and f (times B)
+    d4 = p.dt * p.kappa * p.M * lam * lam   # tilde D_4
+    incr = (-p.A * d2 * Ph - d4 * Ph + p.B * d2 * F) / (1.0 + 0.5 * d4)
+    return ifft2_real(Ph + incr)
+
+
+def vorticity_source(p: Params, phi_new: np.ndarray, s: float) -> np.ndarray:
+    """Stage 2a: the bracket K at phi^{n+1}; g = -K/rho, or -K/eta when rho == 0."""
+    mu = chemical_potential(p, phi_new, s)
+    K = korteweg_bracket(p, phi_new, mu, s)
+    return -K / (p.rho if p.rho > 0.0 else p.eta)
+
+
+def stage_flow(p: Params, omega_h: np.ndarray, g: np.ndarray, s: float):
+    """Stages 2b and 3: Crank-Nicolson for omega, then psi per wavenumber.
+
+    rho > 0:  Om' = Om_h + (1 - dt nu lam/2)^-1 (dt nu lam Om_h + dt G),
+              Psi' = -Om' / lam.
+    rho == 0: Psi' = G / lam^2 (biharmonic solve).  q = 0: Om' = Psi' = 0.
+    """
+    lam = symbol_laplacian(p, s)
+    G = fft2(g)
+    zero = np.zeros_like(lam, dtype=bool)
+    zero[0, 0] = True
+    safe = np.where(zero, 1.0, lam)
+    if p.rho > 0.0:
+        nu = p.eta / p.rho
+        Om = fft2(omega_h)
+        c_t = p.dt * nu * lam      # tilde C = dt nu lambda
+        Om_new = Om + (c_t * Om + p.dt * G) / (1.0 - 0.5 * c_t)
+        Om_new[0, 0] = 0.0
+        Psi = -Om_new / safe
+        Psi[0, 0] = 0.0
+        return ifft2_real(Om_new), ifft2_real(Psi)
+    Psi = G / (safe * safe)
+    Psi[0, 0] = 0.0
+    return np.zeros_like(omega_h), ifft2_real(Psi)
+
+
+def initial_state(p: Params, phi0: np.ndarray, omega0: np.ndarray | None = None) -> State:
+    """State at n = 0 (s = 0) with psi consistent with the flow constraint.
+
+    rho > 0: Poisson solve from omega0; rho == 0: Stokes solve from phi0.
+    """
+    phi = np.array(phi0, dtype=np.float64, copy=True)
+    if omega0 is None or p.rho == 0.0:
+        omega = np.zeros_like(phi)
+    else:
+        omega = np.array(omega0, dtype=np.float64, copy=True)
+    s0 = strain_offset(p, 0)
+    lam = symbol_laplacian(p, s0)
+    safe = lam.copy()
+    safe[0, 0] = 1.0
+    if p.rho > 0.0:
+        Psi = -fft2(omega) / safe
+    else:
+        Psi = fft2(vorticity_source(p, phi, s0)) / (safe * safe)
+    Psi[0, 0] = 0.0
+    return State(phi=phi, omega=omega, psi=ifft2_real(Psi), step=0,
+                 wraps=wrap_count(p, 0))
+
+
+def step(p: Params, st: State) -> State:
+    """One full time step n -> n+1, then the sawtooth shift and remap if due."""
+    n = st.step
+    s = strain_offset(p, n)
+    phi_h, omega_h, f = stage_advect(p, st, s)
+    phi_new = stage_cahn_hilliard(p, phi_h, f, s)
+    g = vorticity_source(p, phi_new, s)
+    omega_new, psi_new = stage_flow(p, omega_h, g, s)
+    k_old = wrap_count(p, n)
+    k_new = wrap_count(p, n + 1)
+    if k_new != k_old:
+        dk = k_new - k_old
+        phi_new = remap(p, phi_new, dk)
+        omega_new = remap(p, omega_new, dk)
+        psi_new = remap(p, psi_new, dk)
+    return State(phi=phi_new, omega=omega_new, psi=psi_new, step=n + 1, wraps=k_new)
+
+
+def run(p: Params, st: State, nsteps: int) -> State:
+    for _ in range(nsteps):
+        st = step(p, st)
+    return st

@@ -1,0 +1,32 @@
+"""Named workloads (parameter sets only; no arithmetic of the method).
+
+Common setting: A = B = kappa = M = 1, grid spacing 1 (box = grid), eta = 1,
+dt = 0.005, phi0 = U(-0.05, 0.05) per site, omega0 = 0.
+"""
+from __future__ import annotations
+
+
+def model_h(nx, ny, gdot=0.01, rho=1.0, eta=1.0, dt=0.005, lx=None, ly=None,
+            A=1.0, B=1.0, kappa=1.0, M=1.0):
+    return dict(nx=nx, ny=ny, lx=float(nx if lx is None else lx),
+                ly=float(ny if ly is None else ly), gdot=gdot, A=A, B=B,
+                kappa=kappa, M=M, eta=eta, rho=rho, dt=dt)
+
+
+# 64x64 inertial, gdot = 0.01, 200 steps: the case the oracle finishes in seconds.
+SMALL_64 = dict(params=model_h(64, 64, gdot=0.01, rho=1.0), steps=200, amp=0.05)
+
+# 1024x1024 single run, inertial and Stokes, gdot in {0.001, 0.01}: the
+# throughput workload (10^4 steps in the full protocol).
+def single_1024(rho=1.0, gdot=0.01):
+    return dict(params=model_h(1024, 1024, gdot=gdot, rho=rho), steps=10000, amp=0.05)
+
+
+# 4096x4096 inertial, gdot = 0.001: the large single-GPU case.
+LARGE_4096 = dict(params=model_h(4096, 4096, gdot=0.001, rho=1.0), steps=50000, amp=0.05)
+
+
+def paper_units(l, eta, rho, gdot, lx, nx, ny, dt):
+    """Table I parameters mapped to A = B = 1, kappa = M = l^2, Ly = 1."""
+    return dict(nx=nx, ny=ny, lx=float(lx), ly=1.0, gdot=gdot, A=1.0, B=1.0,
+                kappa=l * l, M=l * l, eta=eta, rho=rho, dt=dt)

@@ -1,0 +1,468 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's formulas: each compares it with a brute
+force computation, a closed form written from the continuum equations, an
+invariant or a special case solved by an independent textbook routine.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import model_h as mh
+from paper_0710_5912_amd import inputs
+
+
+def P(**kw):
+    base = dict(nx=32, ny=32, lx=32.0, ly=32.0, gdot=0.0, A=1.0, B=1.0,
+                kappa=1.0, M=1.0, eta=1.0, rho=1.0, dt=0.005)
+    base.update(kw)
+    return mh.Params(**base)
+
+
+# ---------------------------------------------------------------- P7: DFT
+
+@pytest.mark.parametrize("ny,nx", [(8, 8), (8, 16), (16, 8)])
+def test_fft_matches_brute_force_dft(ny, nx):
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((ny, nx))
+    brute = np.zeros((ny, nx), dtype=complex)
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    for n in range(ny):
+        for m in range(nx):
+            brute[n, m] = np.sum(a * np.exp(-2j * math.pi * (m * ii / nx + n * jj / ny)))
+    got = mh.fft2(a)
+    assert np.max(np.abs(got - brute)) <= 1e-13 * np.max(np.abs(brute))
+    back = mh.ifft2_real(brute)
+    assert np.max(np.abs(back - a)) <= 1e-13
+
+
+# ---------------------------------------------------------- P8: stencils
+
+def plane_wave(p, m, n):
+    j, i = np.meshgrid(np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    # reduce the phase exactly in integers before scaling, to keep it accurate
+    return np.exp(1j * 2 * math.pi * (((m * i) % p.nx) / p.nx + ((n * j) % p.ny) / p.ny))
+
+
+@pytest.mark.parametrize("geom", [dict(nx=16, ny=16, lx=16.0, ly=16.0),
+                                  dict(nx=32, ny=16, lx=2.0, ly=1.0)])
+@pytest.mark.parametrize("s", [0.0, 0.3, -0.45, 0.5, -0.5, 1.0])
+def test_stencil_symbols(geom, s):
+    p = P(**geom)
+    if abs(s) > p.c / 2:
+        return
+    for (m, n) in [(1, 0), (0, 1), (3, 2), (-2, 5), (5, -3), (p.nx // 2, 1)]:
+        e = plane_wave(p, m, n)
+        tx = 2 * math.pi * m / p.nx          # theta_x = kx dx
+        ty = 2 * math.pi * n / p.ny
+        w = abs(s) / p.c
+        sg = 1 if s >= 0 else -1
+        sym = {
+            "dx": 1j * math.sin(tx) / p.dx,
+            "dys": 1j * ((1 - w) * math.sin(ty) + w * math.sin(ty - sg * p.r * tx)) / p.dy,
+            "dxx": -4 * math.sin(tx / 2) ** 2 / p.dx ** 2,
+            "dyy": -4 * math.sin(ty / 2) ** 2 / p.dy ** 2,
+            "dxy": -math.sin(tx) * math.sin(ty) / (p.dx * p.dy),
+        }
+        got = {
+            "dx": mh.d_x(p, e), "dys": mh.d_y_sheared(p, e, s),
+            "dxx": mh.d_xx(p, e), "dyy": mh.d_yy(p, e), "dxy": mh.d_xy(p, e),
+        }
+        norm1 = {"dx": 1 / p.dx, "dys": 2 / p.dy, "dxx": 4 / p.dx ** 2,
+                 "dyy": 4 / p.dy ** 2, "dxy": 1 / (p.dx * p.dy)}   # stencil 1-norms
+        for k in sym:
+            assert np.max(np.abs(got[k] - sym[k] * e)) <= 1e-14 * norm1[k], k
+
+
+def test_sheared_y_stencil_is_second_order_lab_derivative():
+    """d_y_sheared -> d_y - s d_x with error O(dy^2) on a smooth field."""
+    errs = []
+    s = 0.37
+    for n in (16, 32, 64):
+        p = P(nx=2 * n, ny=n, lx=2.0, ly=1.0)
+        j, i = np.meshgrid(np.arange(p.ny), np.arange(p.nx), indexing="ij")
+        x, y = i * p.dx, j * p.dy
+        kx, ky = 2 * math.pi / p.lx, 2 * math.pi / p.ly
+        a = np.sin(kx * x + 2 * ky * y) + 0.5 * np.cos(3 * kx * x - ky * y)
+        exact_dy = 2 * ky * np.cos(kx * x + 2 * ky * y) + 0.5 * ky * np.sin(3 * kx * x - ky * y)
+        exact_dx = kx * np.cos(kx * x + 2 * ky * y) - 1.5 * kx * np.sin(3 * kx * x - ky * y)
+        errs.append(np.max(np.abs(mh.d_y_sheared(p, a, s) - (exact_dy - s * exact_dx))))
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(2)]
+    assert all(abs(o - 2.0) < 0.2 for o in orders), orders
+
+
+# ------------------------------------------------- P6: per-mode inverses
+
+def spectral_derivs(p, a):
+    """Independent 1D spectral derivatives; odd derivatives vanish at Nyquist."""
+    kx = 2 * math.pi * np.fft.fftfreq(p.nx, d=p.dx)
+    ky = 2 * math.pi * np.fft.fftfreq(p.ny, d=p.dy)
+    kx_odd = kx.copy(); kx_odd[p.nx // 2] = 0.0
+    ky_odd = ky.copy(); ky_odd[p.ny // 2] = 0.0
+    A = np.fft.fft(np.fft.fft(a, axis=1), axis=0)
+    dxx = np.real(np.fft.ifft2(A * (-(kx ** 2))[None, :]))
+    dyy = np.real(np.fft.ifft2(A * (-(ky ** 2))[:, None]))
+    dxy = np.real(np.fft.ifft2(A * (-(ky_odd[:, None] * kx_odd[None, :]))))
+    return dxx, dyy, dxy
+
+
+def lap_c(p, a, s):
+    dxx, dyy, dxy = spectral_derivs(p, a)
+    return (1 + s * s) * dxx + dyy - 2 * s * dxy
+
+
+@pytest.mark.parametrize("s", [0.0, 0.5, -0.5, 0.3])
+def test_poisson_solve_inverts_cosheared_laplacian(s):
+    p = P(nx=32, ny=16, lx=32.0, ly=16.0, dt=0.0)   # dt = 0: CN is the identity
+    w = inputs.noise_omega0(p.ny, p.nx, 5)
+    w -= w.mean()
+    om, psi = mh.stage_flow(p, w, np.zeros_like(w), s)
+    assert np.max(np.abs(om - w)) <= 1e-14
+    assert np.max(np.abs(lap_c(p, psi, s) + w)) <= 1e-13 * np.max(np.abs(w)) * 10
+
+
+@pytest.mark.parametrize("s", [0.0, 0.5, -0.5, 0.3])
+def test_stokes_solve_inverts_biharmonic(s):
+    p = P(nx=32, ny=16, lx=32.0, ly=16.0, rho=0.0, eta=2.0)
+    g = inputs.noise_omega0(p.ny, p.nx, 6)
+    g -= g.mean()
+    _, psi = mh.stage_flow(p, np.zeros_like(g), g, s)
+    # psi carries the low modes amplified by 1/lambda^2 (~700 here); its
+    # rounding comes back multiplied by lambda_max^2, hence the looser bound.
+    assert np.max(np.abs(lap_c(p, lap_c(p, psi, s), s) - g)) <= 1e-11 * np.max(np.abs(g))
+
+
+# --------------------------------------------------- P1: mean conservation
+
+def test_mean_phi_conserved_through_wraps():
+    p = P(nx=32, ny=32, lx=32.0, ly=32.0, gdot=0.5, dt=0.005)   # wraps at strain 0.5, 1.5, 2.5
+    st = mh.initial_state(p, inputs.noise_phi0(32, 32, 0, amp=0.5, mean=0.1),
+                          inputs.noise_omega0(32, 32, 0, amp=0.2))
+    m0 = st.phi.mean()
+    st = mh.run(p, st, 1000)
+    assert st.wraps == 3
+    assert abs(st.phi.mean() - m0) <= 1e-13
+    assert abs(st.omega.mean()) <= 1e-14 and abs(st.psi.mean()) <= 1e-14
+
+
+# ----------------------------------------- P2: single Cahn-Hilliard mode
+
+@pytest.mark.parametrize("gdot", [0.0, 0.05])
+def test_single_mode_growth_factor(gdot):
+    p = P(nx=32, ny=32, lx=40.0, ly=40.0, gdot=gdot, dt=0.01, kappa=1.3, M=0.7, A=0.9)
+    m, n = 3, 2
+    j, i = np.meshgrid(np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    eps = 1e-6
+    kx, ky = 2 * math.pi * m / p.lx, 2 * math.pi * n / p.ly
+    phi0 = eps * np.cos(kx * i * p.dx + ky * j * p.dy)
+    st = mh.initial_state(p, phi0, np.zeros_like(phi0))
+    amp = eps
+    for k in range(40):
+        X = gdot * (k * p.dt)
+        q2 = kx ** 2 + (ky - X * kx) ** 2          # lab |q|^2, no wrap in this window
+        lam = -q2
+        G = (1 - p.dt * p.A * p.M * lam - 0.5 * p.dt * p.kappa * p.M * lam ** 2) / (
+            1 + 0.5 * p.dt * p.kappa * p.M * lam ** 2)
+        amp *= G
+        st = mh.step(p, st)
+    got = 2 * np.abs(mh.fft2(st.phi)[n, m]) / (p.nx * p.ny)
+    assert abs(got - abs(amp)) <= 1e-10 * abs(amp)
+    # continuum: d_t ln A = M q^2 (A - kappa q^2); the scheme is O(dt) accurate.
+    T = 40 * p.dt
+    ts = np.linspace(0, T, 4001)
+    q2t = kx ** 2 + (ky - gdot * ts * kx) ** 2
+    rate = p.M * q2t * (p.A - p.kappa * q2t)
+    cont = eps * math.exp(np.trapezoid(rate, ts))
+    assert abs(got / cont - 1) < 5 * p.dt
+
+
+# ------------------------------------------- P3: flat interface stationarity
+
+def flat_equilibrium(p, mean):
+    """Newton on B phi^3 - A phi - kappa d_yy phi = mu0, sum phi fixed (pseudo-spectral d_yy)."""
+    ny = p.ny
+    y = np.arange(ny) * p.dy
+    xi = math.sqrt(p.kappa / p.A)
+    a0 = math.sqrt(p.A / p.B)
+    L = p.ly
+    phi = a0 * np.tanh((y - L / 4) / (math.sqrt(2) * xi)) * np.tanh((3 * L / 4 - y) / (math.sqrt(2) * xi))
+    phi += mean - phi.mean()
+    k = 2 * math.pi * np.fft.fftfreq(ny, d=p.dy)
+    F = np.fft.fft(np.eye(ny), axis=0)
+    Dyy = np.real(np.linalg.inv(F) @ np.diag(-k ** 2) @ F)   # spectral second derivative matrix
+    mu0 = 0.0
+    for _ in range(60):
+        res = np.concatenate([p.B * phi ** 3 - p.A * phi - p.kappa * Dyy @ phi - mu0,
+                              [phi.sum() - mean * ny]])
+        J = np.zeros((ny + 1, ny + 1))
+        J[:ny, :ny] = np.diag(3 * p.B * phi ** 2 - p.A) - p.kappa * Dyy
+        J[:ny, ny] = -1.0
+        J[ny, :ny] = 1.0
+        # translation along y is a null direction of J: take the minimum-norm step
+        d = np.linalg.lstsq(J, -res, rcond=1e-13)[0]
+        phi += d[:ny]
+        mu0 += d[ny]
+        if np.max(np.abs(d)) < 1e-15:
+            break
+    return phi
+
+
+@pytest.mark.parametrize("gdot", [0.0, 0.7])
+def test_flat_interface_stationary(gdot):
+    # xi = 4 dy; dt M lambda_max < 1 keeps the explicit nabla^2 part stable
+    p = P(nx=32, ny=64, lx=8.0, ly=16.0, gdot=gdot, dt=0.002)
+    prof = flat_equilibrium(p, 0.05)
+    phi0 = np.repeat(prof[:, None], p.nx, axis=1)
+    st = mh.initial_state(p, phi0, np.zeros_like(phi0))
+    st = mh.run(p, st, 1000)
+    assert np.max(np.abs(st.phi - phi0)) <= 1e-12
+    assert np.max(np.abs(st.omega)) == 0.0 and np.max(np.abs(st.psi)) == 0.0
+
+
+def test_flat_interface_independent_of_shear_and_relaxes():
+    p0 = P(nx=8, ny=32, lx=4.0, ly=16.0, dt=0.01)
+    p1 = P(nx=8, ny=32, lx=4.0, ly=16.0, dt=0.01, gdot=0.3)
+    y = np.arange(p0.ny) * p0.dy
+    prof = np.tanh((y - 4) / math.sqrt(2)) * np.tanh((12 - y) / math.sqrt(2))
+    phi0 = np.repeat(prof[:, None], p0.nx, axis=1)
+    a = mh.run(p0, mh.initial_state(p0, phi0), 300)
+    b = mh.run(p1, mh.initial_state(p1, phi0), 300)
+    assert np.max(np.abs(a.phi - b.phi)) <= 1e-14
+    assert np.max(np.abs(b.omega)) == 0.0 and np.max(np.abs(b.psi)) == 0.0
+    eq = flat_equilibrium(p0, phi0.mean())
+    d0 = np.max(np.abs(phi0[:, 0] - eq))
+    dists = []
+    for _ in range(4):
+        a = mh.run(p0, a, 1000)
+        dists.append(np.max(np.abs(a.phi[:, 0] - eq)))
+    assert all(dists[k + 1] < dists[k] for k in range(3))
+    assert dists[-1] < 1e-2 * d0
+
+
+# ----------------------------------------------------- P4: uniform Couette
+
+def test_uniform_state_exact_through_wraps():
+    p = P(nx=32, ny=16, lx=2.0, ly=1.0, gdot=1.0, dt=0.01, kappa=1e-3, M=1e-3)
+    st = mh.initial_state(p, np.full((16, 32), 0.3), np.zeros((16, 32)))
+    st = mh.run(p, st, 250)          # strain 2.5 at c = 2: one wrap
+    assert st.wraps == 1
+    assert np.max(np.abs(st.phi - 0.3)) <= 1e-14
+    assert np.max(np.abs(st.omega)) <= 1e-14 and np.max(np.abs(st.psi)) <= 1e-14
+
+
+# ---------------------------------------------------- P5: sheared Kelvin mode
+
+@pytest.mark.parametrize("gdot", [0.0, 0.2])
+def test_kelvin_mode_decay(gdot):
+    p = P(nx=32, ny=32, lx=32.0, ly=32.0, gdot=gdot, dt=0.02, eta=1.5, rho=2.0)
+    m, n = 1, 2
+    kx, ky = 2 * math.pi * m / p.lx, 2 * math.pi * n / p.ly
+    j, i = np.meshgrid(np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    eps = 1e-3
+    w0 = eps * np.cos(kx * i * p.dx + ky * j * p.dy)
+    st = mh.initial_state(p, np.zeros_like(w0), w0)
+    nu = p.eta / p.rho
+    amp = eps
+    nsteps = 200          # strain 0.8 at gdot=0.2: one wrap (c = 1), labels shift by m
+    for k in range(nsteps):
+        X = gdot * (k * p.dt)
+        lam = -(kx ** 2 + (ky - X * kx) ** 2)
+        amp *= (1 + 0.5 * p.dt * nu * lam) / (1 - 0.5 * p.dt * nu * lam)
+        st = mh.step(p, st)
+    W = mh.fft2(st.omega)
+    nlab = (n - st.wraps * m) % p.ny
+    got = 2 * abs(W[nlab, m]) / (p.nx * p.ny)
+    assert abs(got - amp) <= 1e-12 * amp + 1e-15
+    t = nsteps * p.dt
+    if gdot == 0:
+        expo = (kx ** 2 + ky ** 2) * t
+    else:
+        expo = kx ** 2 * t + (ky ** 3 - (ky - gdot * t * kx) ** 3) / (3 * gdot * kx)
+    cont = eps * math.exp(-nu * expo)
+    assert abs(got / cont - 1) < 2 * p.dt
+
+
+# ---------------------------------------------------------------- P9: wrap
+
+def test_remap_is_fourier_relabel():
+    p = P(nx=32, ny=16, lx=2.0, ly=1.0)
+    a = inputs.noise_phi0(16, 32, 9)
+    b = mh.remap(p, a, 1)
+    A, Bf = mh.fft2(a), mh.fft2(b)
+    for n in range(p.ny):
+        for m in range(p.nx):
+            assert abs(Bf[n, m] - A[(n + m) % p.ny, m]) <= 1e-12
+
+
+@pytest.mark.parametrize("geom", [dict(nx=32, ny=16, lx=2.0, ly=1.0),
+                                  dict(nx=16, ny=16, lx=16.0, ly=16.0)])
+def test_stencil_continuous_across_wrap(geom):
+    p = P(**geom)
+    a = inputs.noise_phi0(p.ny, p.nx, 11)
+    b = mh.remap(p, a, 1)
+    lhs = mh.remap(p, mh.d_y_sheared(p, a, p.c / 2), 1)
+    rhs = mh.d_y_sheared(p, b, -p.c / 2)
+    assert np.array_equal(lhs, rhs)
+
+
+def test_step_across_wrap_matches_unwrapped_step():
+    """A smooth field stepped across a wrap agrees with the un-wrapped step."""
+    p = P(nx=64, ny=32, lx=2.0, ly=1.0, gdot=1.0, dt=1e-4, kappa=4e-4, M=4e-4)
+    j, i = np.meshgrid(np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    x, y = i * p.dx, j * p.dy
+    phi = 0.4 * np.cos(2 * math.pi * x / p.lx + 2 * math.pi * y) + 0.1
+    om = 0.3 * np.sin(2 * math.pi * y) + 0.2 * np.cos(4 * math.pi * x / p.lx)
+    n0 = int(round(1.0 / p.dt)) - 1      # step n0 -> n0+1 crosses s = c/2 (c = 2)
+    st = mh.initial_state(p, phi, om)
+    st = mh.State(st.phi, st.omega, st.psi, step=n0, wraps=mh.wrap_count(p, n0))
+    wrapped = mh.step(p, st)
+    assert wrapped.wraps == st.wraps + 1
+    s = mh.strain_offset(p, n0)
+    ph, oh, f = mh.stage_advect(p, st, s)
+    pn = mh.stage_cahn_hilliard(p, ph, f, s)
+    on, psn = mh.stage_flow(p, oh, mh.vorticity_source(p, pn, s), s)
+    for got, ref in ((wrapped.phi, pn), (wrapped.omega, on), (wrapped.psi, psn)):
+        assert np.max(np.abs(got - mh.remap(p, ref, 1))) <= 1e-14
+    # next step: remapped data at s - c versus un-remapped at s (w > 1/2)
+    nxt = mh.step(p, wrapped)
+    s1 = mh.strain_offset(p, n0) + p.gdot * p.dt
+    alt = mh.State(pn, on, psn, step=n0 + 1)
+    ph, oh, f = mh.stage_advect(p, alt, s1)
+    pn2 = mh.stage_cahn_hilliard(p, ph, f, s1)
+    assert np.max(np.abs(nxt.phi - mh.remap(p, pn2, 1))) <= 1e-8
+
+
+# --------------------------------------------------------- P10: convergence
+
+def smooth_init(p):
+    j, i = np.meshgrid(np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    x, y = 2 * math.pi * i / p.nx, 2 * math.pi * j / p.ny
+    phi = 0.5 * np.cos(x) * np.sin(y) + 0.3 * np.sin(x + y) + 0.05
+    om = 0.5 * np.sin(x) + 0.4 * np.cos(x - y)
+    return phi, om
+
+
+@pytest.mark.slow
+def test_space_convergence_order_two():
+    T = 0.4
+    sols = []
+    for nn in (16, 32, 64):
+        p = P(nx=nn, ny=nn, lx=8.0, ly=8.0, gdot=0.3, kappa=0.5, M=0.5, dt=0.4 * (8.0 / nn) ** 2 / 4)
+        phi, om = smooth_init(p)
+        st = mh.run(p, mh.initial_state(p, phi, om), int(round(T / p.dt)))
+        sols.append(st)
+    e1 = np.max(np.abs(sols[0].phi - sols[1].phi[::2, ::2]))
+    e2 = np.max(np.abs(sols[1].phi - sols[2].phi[::2, ::2]))
+    order = math.log2(e1 / e2)
+    assert abs(order - 2.0) < 0.2, order
+
+
+@pytest.mark.slow
+def test_time_convergence_order_one():
+    T = 0.32
+    sols = []
+    for dt in (0.02, 0.01, 0.005):
+        p = P(nx=32, ny=32, lx=8.0, ly=8.0, gdot=0.3, kappa=0.05, M=0.5, dt=dt)
+        phi, om = smooth_init(p)
+        sols.append(mh.run(p, mh.initial_state(p, phi, om), int(round(T / dt))))
+    e1 = np.max(np.abs(sols[0].phi - sols[1].phi)) + np.max(np.abs(sols[0].omega - sols[1].omega))
+    e2 = np.max(np.abs(sols[1].phi - sols[2].phi)) + np.max(np.abs(sols[1].omega - sols[2].omega))
+    order = math.log2(e1 / e2)
+    assert abs(order - 1.0) < 0.2, order
+
+
+# ------------------------- P8': FD operators converge to the continuum terms
+
+def _smooth_fields(p):
+    j, i = np.meshgrid(np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    x, y = 2 * math.pi * i / p.nx, 2 * math.pi * j / p.ny
+    phi = 0.6 * np.cos(x + 2 * y) + 0.3 * np.sin(2 * x - y) + 0.1
+    psi = 0.4 * np.sin(x - y) + 0.2 * np.cos(3 * x + y)
+    return phi, psi
+
+
+def _spec_grad(p, a, s):
+    """Independent spectral lab-frame gradient (d_x a, (d_y - s d_x) a)."""
+    kx = 2 * math.pi * np.fft.fftfreq(p.nx, d=p.dx)
+    ky = 2 * math.pi * np.fft.fftfreq(p.ny, d=p.dy)
+    ax = np.real(np.fft.ifft(1j * kx[None, :] * np.fft.fft(a, axis=1), axis=1))
+    ay = np.real(np.fft.ifft(1j * ky[:, None] * np.fft.fft(a, axis=0), axis=0))
+    return ax, ay - s * ax
+
+
+@pytest.mark.parametrize("s", [0.0, 0.41, -0.27])
+def test_fd_terms_second_order_to_continuum(s):
+    errs = {"mu": [], "K": [], "adv": []}
+    for nn in (32, 64, 128):
+        p = P(nx=2 * nn, ny=nn, lx=8.0, ly=4.0, kappa=0.3, A=0.8, B=1.1)
+        phi, psi = _smooth_fields(p)
+        mu_c = p.B * phi ** 3 - p.A * phi - p.kappa * lap_c(p, phi, s)
+        errs["mu"].append(np.max(np.abs(mh.chemical_potential(p, phi, s) - mu_c)))
+        px, py = _spec_grad(p, phi, s)
+        mx, my = _spec_grad(p, mu_c, s)
+        K_c = px * my - py * mx
+        errs["K"].append(np.max(np.abs(mh.korteweg_bracket(p, phi, mu_c, s) - K_c)))
+        sx, sy = _spec_grad(p, psi, s)
+        adv_c = sy * px - sx * py
+        errs["adv"].append(np.max(np.abs(mh.advection(p, psi, phi, s) - adv_c)))
+    for k, e in errs.items():
+        orders = [math.log2(e[q] / e[q + 1]) for q in range(2)]
+        assert all(abs(o - 2.0) < 0.25 for o in orders), (k, orders)
+
+
+# --------------------------- model-H energy is a Lyapunov functional at gdot=0
+
+def _energy(p, st):
+    """Free energy plus kinetic energy, from spectral gradients (independent)."""
+    px, py = _spec_grad(p, st.phi, 0.0)
+    f = -0.5 * p.A * st.phi ** 2 + 0.25 * p.B * st.phi ** 4 + 0.5 * p.kappa * (px ** 2 + py ** 2)
+    e = np.sum(f)
+    if p.rho > 0:
+        sx, sy = _spec_grad(p, st.psi, 0.0)
+        e += 0.5 * p.rho * np.sum(sx ** 2 + sy ** 2)
+    return e * p.dx * p.dy
+
+
+@pytest.mark.parametrize("rho", [1.0, 0.0])
+def test_energy_decreases_without_shear(rho):
+    """Surface tension drives flow that lowers the total energy; a flipped
+    coupling sign in g (or in the advection bracket) makes it grow."""
+    p = P(nx=32, ny=32, lx=32.0, ly=32.0, rho=rho, eta=0.3, dt=0.01)
+    st = mh.initial_state(p, inputs.noise_phi0(32, 32, 4, amp=0.8))
+    st = mh.run(p, st, 300)           # past the spinodal transient
+    es = [_energy(p, st)]
+    for _ in range(10):
+        st = mh.run(p, st, 20)
+        es.append(_energy(p, st))
+    assert all(es[k + 1] < es[k] for k in range(10)), es
+    assert np.max(np.abs(st.psi)) > 1e-3      # the flow is not trivially absent
+
+
+def _free_energy(p, phi):
+    px, py = _spec_grad(p, phi, 0.0)
+    return np.sum(-0.5 * p.A * phi ** 2 + 0.25 * p.B * phi ** 4
+                  + 0.5 * p.kappa * (px ** 2 + py ** 2)) * p.dx * p.dy
+
+
+@pytest.mark.parametrize("rho", [0.0, 1.0])
+def test_flow_lowers_free_energy(rho):
+    """The flow driven by phi grad mu must carry phi so as to lower F.
+
+    Stokes: d F/dt|adv = -(1/eta) <phi grad mu, S(phi grad mu)> <= 0 for the
+    (positive) Stokes operator S.  Inertial, started from rest: after one step
+    the velocity is the impulse of -phi grad mu / rho, with the same sign.
+    """
+    p = P(nx=32, ny=32, lx=32.0, ly=32.0, rho=rho, eta=0.1, dt=0.01)
+    st = mh.initial_state(p, inputs.noise_phi0(32, 32, 8, amp=0.8))
+    st = mh.run(p, st, 200)
+    if rho > 0:    # restart from rest, take one step to build the flow
+        st = mh.initial_state(p, st.phi)
+        st = mh.step(p, st)
+    for s in (0.0,):
+        phi_h, _, _ = mh.stage_advect(p, st, s)
+        dF = _free_energy(p, phi_h) - _free_energy(p, st.phi)
+        assert np.max(np.abs(st.psi)) > 1e-4
+        assert dF < 0.0, dF
