@@ -1,0 +1,208 @@
+"""Throughput of the sheared model-H time step on one MI355X.
+
+Workload (the single-run configuration): 1024 x 1024 grid, spacing 1,
+A = B = kappa = M = eta = 1, rho = 1, gdot = 0.01, dt = 0.005, phi0 uniform in
+[-0.05, 0.05] (seed 0), omega0 = 0; observables (L(t), S(k), stress) every 100
+steps inside the timed region.  A step is one pass of every stage of the split
+step.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, vendor figure
+
+
+def stage_bytes(params, precision):
+    """Algorithmic HBM bytes per launch of each stage (compulsory reads + writes)."""
+    w = 8 if precision == "fp64" else 4
+    nx, ny = params["nx"], params["ny"]
+    real = nx * ny * w
+    spec = ny * (nx // 2 + 1) * 2 * w
+    inertial = params["rho"] > 0
+    if inertial:
+        return {
+            "row_inv_flow": 2 * spec + 2 * real,
+            "advect": 3 * real + 3 * spec,
+            "column_ch": 3 * spec,
+            "row_inv_phi": spec + real,
+            "mu_source": real + spec,
+            "column_flow": 4 * spec,
+        }
+    return {
+        "row_inv_flow": spec + real,
+        "advect": 2 * real + 2 * spec,
+        "column_ch": 3 * spec,
+        "row_inv_phi": spec + real,
+        "mu_source": real + spec,
+        "column_flow": 2 * spec,
+    }
+
+
+def run_variant(le, torch, params, precision, steps, warmup, obs_every, seed=0):
+    from paper_0710_5912_amd import inputs
+
+    nx, ny = params["nx"], params["ny"]
+    phi0 = inputs.noise_phi0(ny, nx, seed, amp=0.05)
+    stream = torch.cuda.Stream()          # default priority; the library enqueues on it
+    ctx = le.Context(params, phi0, precision=precision, stream=stream.cuda_stream)
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    series = []
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    done = 0
+    while done < steps:
+        n = min(obs_every, steps - done)
+        ctx.step(n)
+        done += n
+        if done % obs_every == 0:
+            o, _ = ctx.observables(sk=True)
+            series.append((o["t"], o["Ls"], o["sigma_xy"], o["mean_phi"]))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    times = ctx.stage_times()
+    ctx.profile(False)
+    ctx.close()
+    return dict(wall=wall, gpu_ms=gpu_ms, times=times, series=series)
+
+
+def roofline_of(params, precision, times):
+    b = stage_bytes(params, precision)
+    rows = {}
+    for k, (ms, n) in times.items():
+        if n == 0:
+            continue
+        avg_s = ms / n * 1e-3
+        rows[k] = dict(avg_us=avg_s * 1e6, bytes=b[k], gbs=b[k] / avg_s / 1e9)
+    dom = max(rows, key=lambda k: rows[k]["avg_us"])
+    return dom, rows
+
+
+def cpu_baseline(params, budget_s=15.0):
+    """The FP64 oracle, untuned, on a bounded number of steps of the same workload."""
+    import numpy as np
+
+    from oracle import model_h as mh
+    from paper_0710_5912_amd import inputs
+
+    p = mh.Params(**params)
+    phi0 = inputs.noise_phi0(p.ny, p.nx, 0, amp=0.05)
+    st = mh.initial_state(p, phi0)
+    st = mh.step(p, st)           # first step outside the clock (allocations)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        st = mh.step(p, st)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s and n >= 3:
+            break
+    dt = time.perf_counter() - t0
+    assert np.isfinite(st.phi).all()
+    return dict(value=p.nx * p.ny * n / dt, unit="site-updates/s", cores=1, kind="oracle",
+                sample=f"{n} steps of the {p.nx}x{p.ny} inertial workload after 1 untimed "
+                       f"step ({dt:.1f} s); NumPy FFT and ufuncs, single thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--obs-every", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the time step of one grid is not sharded across GPUs here)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    from paper_0710_5912_amd import configs, le
+
+    params = configs.single_1024(rho=1.0, gdot=0.01)["params"]
+    print(f"bench: 1024x1024 fp64 inertial, {args.warmup} warmup + {args.steps} timed steps",
+          file=sys.stderr, flush=True)
+    r = run_variant(le, torch, params, "fp64", args.steps, args.warmup, args.obs_every)
+    sites = params["nx"] * params["ny"]
+    sec = r["gpu_ms"] * 1e-3
+    value = sites * args.steps / sec
+    dom, rows = roofline_of(params, "fp64", r["times"])
+    out = {
+        "metric": "site-updates/s/GPU (plain FP64 vs FP32, batched, learned corrector) at stated L(t) error",
+        "value": value,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["gpu_ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "sheared model H, 1024x1024, inertial rho=1, eta=1, gdot=0.01, "
+                               "dt=0.005, A=B=kappa=M=1, dx=1, phi0 U(-0.05,0.05) seed 0, "
+                               "plain FP64 step, observables every 100 steps",
+                   "grid": [1024, 1024], "precision": "fp64", "rho": 1.0, "gdot": 0.01,
+                   "obs_every": args.obs_every},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": rows[dom]["gbs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": rows[dom]["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": rows[dom]["bytes"],
+                     "avg_launch_us": rows[dom]["avg_us"]},
+        "stages": {k: {"avg_us": round(v["avg_us"], 2), "GBs": round(v["gbs"], 1)}
+                   for k, v in rows.items()},
+        "wall_s": r["wall"],
+        "parity": "FP64 path within 1e-10 of the FP64 oracle after 100 steps (tests)",
+    }
+    if not args.no_variants:
+        var = {}
+        for name, prec, rho, n in (("fp32_inertial", "fp32", 1.0, 2000),
+                                   ("fp64_stokes", "fp64", 0.0, 2000),
+                                   ("fp32_stokes", "fp32", 0.0, 2000)):
+            p = configs.single_1024(rho=rho, gdot=0.01)["params"]
+            print(f"bench: variant {name}", file=sys.stderr, flush=True)
+            rv = run_variant(le, torch, p, prec, n, 100, args.obs_every)
+            d, rw = roofline_of(p, prec, rv["times"])
+            var[name] = dict(value=sites * n / (rv["gpu_ms"] * 1e-3),
+                             ms_per_step=rv["gpu_ms"] / n,
+                             dominant=d, dominant_frac=rw[d]["gbs"] / HBM_PEAK_GBS)
+        # the large single-GPU grid
+        p = configs.LARGE_4096["params"]
+        print("bench: variant fp64_4096", file=sys.stderr, flush=True)
+        rv = run_variant(le, torch, p, "fp64", 200, 20, 100)
+        d, rw = roofline_of(p, "fp64", rv["times"])
+        var["fp64_4096_inertial"] = dict(value=4096 * 4096 * 200 / (rv["gpu_ms"] * 1e-3),
+                                         ms_per_step=rv["gpu_ms"] / 200, dominant=d,
+                                         dominant_frac=rw[d]["gbs"] / HBM_PEAK_GBS)
+        out["variants"] = var
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(params)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,158 @@
+/*
+ * le.h -- C ABI of the MI355X sheared model-H time step.
+ *
+ * The library advances 2D model H (Cahn-Hilliard for the composition phi
+ * coupled to the Navier-Stokes streamfunction/vorticity equations) under an
+ * applied shear flow, in the cosheared frame of Fielding's paper ("Numerical
+ * method"; Appendix A), by the split step of Appendix B:
+ *
+ *   1a  phi, omega advected by psi^n (explicit Euler, Eq. advective, with the
+ *       shear-interpolated y stencil of Eq. p1y); f = phi^3;
+ *   1b  Cahn-Hilliard diffusive update per Fourier mode (explicit in
+ *       nabla_c^2 and f, Crank-Nicolson in nabla_c^4);
+ *   2a  mu and the vorticity source g = -[d_x phi d_y mu - d_y phi d_x mu]/rho
+ *       by finite differences (Eqs. vortNum, G);
+ *   2b  omega by Crank-Nicolson per mode (Eq. forOmega);
+ *   3   psi = -omega / lambda per mode, or at rho = 0 the biharmonic solve
+ *       psi = g / lambda^2 ("Algorithm at zero Reynolds number").
+ *
+ * The sawtooth strain s(t) of Eq. coshearedNabluFinal is kept in
+ * [-Lx/2Ly, Lx/2Ly); at each jump the fields are remapped so the lab-frame
+ * field is continuous.
+ *
+ * Conventions for every function below:
+ *   - Host arrays are nx*ny doubles, row-major [j][i], x (flow direction)
+ *     fastest, in the cosheared frame.  They are read or written during the
+ *     call only; the library never keeps a caller pointer.  In LE_FP32 mode
+ *     they are converted on upload and download.
+ *   - The context owns all device memory it allocates.  Caller-provided
+ *     outputs are written only when the call returns LE_OK.
+ *   - All functions return LE_OK (0) or a negative LE_E* code; no C++
+ *     exception crosses this boundary.  le_strerror() names a code.
+ *   - A context is used by one host thread at a time; separate contexts are
+ *     independent.  Work is enqueued on the context's HIP stream and every
+ *     function returns after that stream has drained.
+ */
+#ifndef LE_H
+#define LE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LE_OK = 0,
+  LE_EINVAL = -1,     /* invalid parameters or arguments; nothing allocated */
+  LE_ENOMEM = -2,     /* device or host allocation failed */
+  LE_EDEVICE = -3,    /* a HIP call failed (no device, launch error, ...) */
+  LE_ENONFINITE = -4, /* the state became non-finite; stepping stopped */
+  LE_ESTATE = -5      /* call not valid in the context's current state */
+};
+
+enum { LE_FP64 = 0, LE_FP32 = 1 };
+
+typedef struct le_ctx le_ctx;
+
+/*
+ * Problem statement of the paper's "Governing equations", "Flow geometry" and
+ * "Choice of units" sections, with the free energy written generally:
+ *   mu = B phi^3 - A phi - kappa nabla^2 phi,  d_t phi + v.grad phi = M nabla^2 mu,
+ *   rho (d_t omega + v.grad omega) = eta nabla^2 omega - [curl(phi grad mu)].z.
+ * The paper's units are A = B = 1, kappa = M = l^2, ly = 1.
+ */
+typedef struct le_params {
+  int32_t nx, ny;      /* powers of two, 8 <= nx, ny <= 4096; if gdot != 0
+                          then nx must be a multiple of ny (strain-wrap remap) */
+  double lx, ly;       /* box; dx = lx/nx, dy = ly/ny */
+  double gdot;         /* applied shear rate, any sign; 0 = unsheared */
+  double A, B, kappa;  /* free-energy constants, all > 0 */
+  double M;            /* mobility > 0 */
+  double eta, rho;     /* viscosity > 0; density >= 0 (0 = Stokes branch) */
+  double dt;           /* time step > 0 */
+  int32_t precision;   /* LE_FP64, or LE_FP32: FP32 storage, stencils and
+                          FFTs with the per-mode solves and all reductions in
+                          FP64 */
+  void* stream;        /* hipStream_t to enqueue on (e.g. torch's current
+                          stream); NULL = the library creates its own */
+} le_params;
+
+/*
+ * Observables of the paper's "Lengthscales and timescales" section at the
+ * context's current step.  Wave vectors are lab-frame, q_lab = (qx, qy - s qx).
+ */
+typedef struct le_obs {
+  int64_t step, wraps;   /* steps taken; strain jumps taken */
+  double t, strain, s;   /* t = step*dt; strain = gdot*t; s = sawtooth offset */
+  double mean_phi;       /* (1/N) sum phi -- conserved by the method */
+  double phi2;           /* (1/N) sum phi^2 */
+  double Ls;             /* Eq. L_structure: sum_{q!=0} S/|q| / sum_{q!=0} S */
+  double Dxx, Dxy, Dyy;  /* Eq. L_matrix: l sum q_a q_b S / sum S, l = sqrt(kappa/A) */
+  double L_par, L_perp;  /* 1/lambda_min(D) (inf if <= 0), 1/lambda_max(D) */
+  double sigma_xy;       /* interfacial excess shear stress -kappa <d_x phi d_y phi> */
+  double sigma_xy_re;    /* Reynolds stress -rho <v_x v_y> of the flow (0 if rho = 0) */
+  int32_t nbins;         /* number of S(k) shells reported (ny/2) */
+  double dk;             /* shell width 2 pi / ly; shell b covers |q| in [(b-1/2)dk, (b+1/2)dk) */
+  int32_t finite;        /* 1 if every phi value is finite */
+} le_obs;
+
+/*
+ * Create a context: validate p, allocate the device state, upload phi0 and
+ * omega0 (omega0 may be NULL: zero vorticity; ignored when rho == 0) and set
+ * psi0 from the flow constraint at s = 0 (a Poisson solve from omega0, or the
+ * Stokes solve from phi0 at rho = 0).  On success *out owns the context.
+ * Errors: LE_EINVAL (bad p or NULL phi0/out), LE_ENOMEM, LE_EDEVICE.
+ */
+int le_create(const le_params* p, const double* phi0, const double* omega0,
+              le_ctx** out);
+
+/* Advance nsteps >= 0 full time steps (the sawtooth clock advances with
+ * them).  Returns LE_ENONFINITE if phi became non-finite, checked at the end
+ * of the call. */
+int le_step(le_ctx* c, int64_t nsteps);
+
+/*
+ * Compute the observables of the current state into *o.  If Sk is non-NULL,
+ * the shell-averaged structure factor S(k_b) = mean over the modes of shell
+ * b of |F[phi](q)|^2 / N is written for b = 1 .. min(sk_cap, ny/2) into
+ * Sk[0 ..]; shells with no modes read 0.
+ */
+int le_observables(le_ctx* c, le_obs* o, double* Sk, int32_t sk_cap);
+
+/* Release the context and everything it owns.  NULL is accepted. */
+void le_destroy(le_ctx* c);
+
+/* Copy the current state to the host (any pointer may be NULL to skip that
+ * field; psi and omega are real-space fields).  step/wraps may be NULL. */
+int le_get_state(le_ctx* c, double* phi, double* omega, double* psi,
+                 int64_t* step, int64_t* wraps);
+
+/* Replace the state (phi and psi required; omega required when rho > 0) and
+ * the clock (step >= 0; wraps must equal the wrap count implied by step). */
+int le_set_state(le_ctx* c, const double* phi, const double* omega,
+                 const double* psi, int64_t step, int64_t wraps);
+
+/* Static description of an error code. */
+const char* le_strerror(int code);
+
+/*
+ * Per-stage GPU timing.  With profiling enabled, le_step brackets every stage
+ * launch with HIP events on the context's stream and accumulates the elapsed
+ * time per stage.  Stage indices:
+ *   0 inverse row transform of omega and psi    3 inverse row transform of phi
+ *   1 advection + forward row transforms (1a)    4 mu and g + forward row transform (2a)
+ *   2 column pass, Cahn-Hilliard update (1b)     5 column pass, omega and psi (2b, 3)
+ * le_profile(c, 1) enables and clears the counters, le_profile(c, 0) disables.
+ * le_stage_times writes min(cap, LE_NSTAGES) accumulated milliseconds and
+ * launch counts (either pointer may be NULL).
+ */
+enum { LE_NSTAGES = 6 };
+int le_profile(le_ctx* c, int enable);
+int le_stage_times(le_ctx* c, double* ms, int64_t* launches, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LE_H */

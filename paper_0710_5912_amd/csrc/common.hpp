@@ -1,0 +1,43 @@
+// common.hpp -- shared device/host definitions of the model-H library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace le {
+
+// Geometry and physical constants of one run (see le_params in le.h).
+struct Geo {
+  int nx, ny;     // grid
+  int r;          // nx / ny: x offset in cells of the sheared y stencil
+  int pad0;
+  double lx, ly, dx, dy, c;   // c = lx / ly, the sawtooth jump
+  double A, B, kappa, M, eta, rho, dt;
+};
+
+// Per-step values computed by the host shear clock.
+struct StepArgs {
+  double s;       // sawtooth strain offset s_n used by every operator of step n
+  double pad;
+};
+
+// Column-kernel variants (per-mode update applied between the transforms).
+enum ColMode { COL_CH = 0, COL_FLOW = 1, COL_STOKES = 2, COL_POISSON = 3 };
+
+// Observable partial sums (FP64), in this order.
+enum {
+  OBS_SUM_S = 0,       // sum over all modes of S
+  OBS_SUM_S_NZ,        // sum over q != 0 of S
+  OBS_SUM_S_OVER_Q,    // sum over q != 0 of S / |q_lab|
+  OBS_XX,              // sum qx^2 S
+  OBS_XY,              // sum qx q_lab_y S
+  OBS_YY,              // sum q_lab_y^2 S
+  OBS_RE,              // sum qx q_lab_y |Psi|^2
+  OBS_NSPEC,
+  OBS_SUM_PHI = OBS_NSPEC,   // real-space sum phi
+  OBS_SUM_PHI2,              // real-space sum phi^2
+  OBS_NONFINITE,             // count of non-finite phi values
+  OBS_NTOTAL
+};
+
+}  // namespace le

@@ -1,0 +1,207 @@
+"""ctypes binding of the C ABI in include/le.h (argument marshalling only).
+
+Every step of the method runs in the HIP library; this module converts NumPy
+arrays and dicts to the C structs and back.  It loads ``libmodelh.so`` from
+this package directory and raises if the library has not been built: there is
+no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmodelh.so")
+
+LE_OK, LE_EINVAL, LE_ENOMEM, LE_EDEVICE, LE_ENONFINITE, LE_ESTATE = 0, -1, -2, -3, -4, -5
+LE_FP64, LE_FP32 = 0, 1
+
+SYMBOLS = ("le_create", "le_step", "le_observables", "le_destroy", "le_get_state",
+           "le_set_state", "le_strerror", "le_profile", "le_stage_times")
+LE_NSTAGES = 6
+STAGES = ("row_inv_flow", "advect", "column_ch", "row_inv_phi", "mu_source", "column_flow")
+
+
+class LeParams(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("lx", C.c_double),
+                ("ly", C.c_double), ("gdot", C.c_double), ("A", C.c_double),
+                ("B", C.c_double), ("kappa", C.c_double), ("M", C.c_double),
+                ("eta", C.c_double), ("rho", C.c_double), ("dt", C.c_double),
+                ("precision", C.c_int32), ("stream", C.c_void_p)]
+
+
+class LeObs(C.Structure):
+    _fields_ = [("step", C.c_int64), ("wraps", C.c_int64), ("t", C.c_double),
+                ("strain", C.c_double), ("s", C.c_double), ("mean_phi", C.c_double),
+                ("phi2", C.c_double), ("Ls", C.c_double), ("Dxx", C.c_double),
+                ("Dxy", C.c_double), ("Dyy", C.c_double), ("L_par", C.c_double),
+                ("L_perp", C.c_double), ("sigma_xy", C.c_double),
+                ("sigma_xy_re", C.c_double), ("nbins", C.c_int32), ("dk", C.c_double),
+                ("finite", C.c_int32)]
+
+
+class LeError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+_LIB = None
+_DP = C.POINTER(C.c_double)
+
+
+def lib():
+    """Load the HIP library once; raise if it is missing."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_0710_5912_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        L.le_create.argtypes = [C.POINTER(LeParams), _DP, _DP, C.POINTER(C.c_void_p)]
+        L.le_create.restype = C.c_int
+        L.le_step.argtypes = [C.c_void_p, C.c_int64]
+        L.le_step.restype = C.c_int
+        L.le_observables.argtypes = [C.c_void_p, C.POINTER(LeObs), _DP, C.c_int32]
+        L.le_observables.restype = C.c_int
+        L.le_destroy.argtypes = [C.c_void_p]
+        L.le_destroy.restype = None
+        L.le_get_state.argtypes = [C.c_void_p, _DP, _DP, _DP, C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_int64)]
+        L.le_get_state.restype = C.c_int
+        L.le_set_state.argtypes = [C.c_void_p, _DP, _DP, _DP, C.c_int64, C.c_int64]
+        L.le_set_state.restype = C.c_int
+        L.le_profile.argtypes = [C.c_void_p, C.c_int]
+        L.le_profile.restype = C.c_int
+        L.le_stage_times.argtypes = [C.c_void_p, _DP, C.POINTER(C.c_int64), C.c_int32]
+        L.le_stage_times.restype = C.c_int
+        L.le_strerror.argtypes = [C.c_int]
+        L.le_strerror.restype = C.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def strerror(code: int) -> str:
+    return lib().le_strerror(code).decode()
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(_DP)
+
+
+def _f64(a, shape):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def make_params(params: dict, precision: str = "fp64", stream=None) -> LeParams:
+    p = LeParams()
+    for k in ("nx", "ny"):
+        setattr(p, k, int(params[k]))
+    for k in ("lx", "ly", "gdot", "A", "B", "kappa", "M", "eta", "rho", "dt"):
+        setattr(p, k, float(params[k]))
+    p.precision = {"fp64": LE_FP64, "fp32": LE_FP32}[precision]
+    p.stream = stream
+    return p
+
+
+class Context:
+    """One run of the sheared model-H step on the GPU."""
+
+    def __init__(self, params: dict, phi0, omega0=None, precision: str = "fp64",
+                 stream=None):
+        self.params = dict(params)
+        self.precision = precision
+        self.shape = (int(params["ny"]), int(params["nx"]))
+        self._p = make_params(params, precision, stream)
+        phi0 = _f64(phi0, self.shape)
+        omega0 = _f64(omega0, self.shape)
+        h = C.c_void_p()
+        rc = lib().le_create(C.byref(self._p), _dp(phi0), _dp(omega0), C.byref(h))
+        if rc != LE_OK:
+            raise LeError(rc, "le_create")
+        self._h = h
+
+    def _check(self):
+        if self._h is None:
+            raise ValueError("context is closed")
+
+    def step(self, nsteps: int) -> None:
+        self._check()
+        rc = lib().le_step(self._h, int(nsteps))
+        if rc != LE_OK:
+            raise LeError(rc, "le_step")
+
+    def observables(self, sk: bool = True):
+        """Return (dict of le_obs fields, S(k) array or None)."""
+        self._check()
+        o = LeObs()
+        nb = self.shape[0] // 2
+        Sk = np.zeros(nb) if sk else None
+        rc = lib().le_observables(self._h, C.byref(o), _dp(Sk), nb if sk else 0)
+        if rc != LE_OK:
+            raise LeError(rc, "le_observables")
+        d = {name: getattr(o, name) for name, _ in LeObs._fields_}
+        return d, Sk
+
+    def get_state(self):
+        self._check()
+        phi = np.empty(self.shape)
+        om = np.empty(self.shape)
+        psi = np.empty(self.shape)
+        step = C.c_int64()
+        wraps = C.c_int64()
+        rc = lib().le_get_state(self._h, _dp(phi), _dp(om), _dp(psi), C.byref(step),
+                                C.byref(wraps))
+        if rc != LE_OK:
+            raise LeError(rc, "le_get_state")
+        return dict(phi=phi, omega=om, psi=psi, step=step.value, wraps=wraps.value)
+
+    def set_state(self, phi, omega, psi, step: int, wraps: int) -> None:
+        self._check()
+        phi = _f64(phi, self.shape)
+        omega = _f64(omega, self.shape)
+        psi = _f64(psi, self.shape)
+        rc = lib().le_set_state(self._h, _dp(phi), _dp(omega), _dp(psi), int(step), int(wraps))
+        if rc != LE_OK:
+            raise LeError(rc, "le_set_state")
+
+    def profile(self, enable: bool) -> None:
+        """Enable (and clear) or disable per-stage event timing."""
+        self._check()
+        rc = lib().le_profile(self._h, 1 if enable else 0)
+        if rc != LE_OK:
+            raise LeError(rc, "le_profile")
+
+    def stage_times(self):
+        """Dict stage -> (accumulated ms, launches)."""
+        self._check()
+        ms = np.zeros(LE_NSTAGES)
+        n = (C.c_int64 * LE_NSTAGES)()
+        rc = lib().le_stage_times(self._h, _dp(ms), n, LE_NSTAGES)
+        if rc != LE_OK:
+            raise LeError(rc, "le_stage_times")
+        return {STAGES[k]: (float(ms[k]), int(n[k])) for k in range(LE_NSTAGES)}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().le_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -1,0 +1,162 @@
+"""GPU path (through the C ABI) against the FP64 oracle, element by element.
+
+Bar: FP64 fields within 1e-10 relative (max norm over the field) of the
+oracle after 100 steps on the same seeded inputs; observables within 1e-12
+relative.  FP32 runs are held to the bound derived in the design notes.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import model_h as mh
+from oracle import observables as ob
+from paper_0710_5912_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+le = pytest.importorskip("paper_0710_5912_amd.le")
+
+
+def params(nx, ny, **kw):
+    base = dict(nx=nx, ny=ny, lx=float(nx), ly=float(ny), gdot=0.01, A=1.0, B=1.0,
+                kappa=1.0, M=1.0, eta=1.0, rho=1.0, dt=0.005)
+    base.update(kw)
+    return base
+
+
+def rel(a, b):
+    den = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0))
+
+
+def run_pair(p, steps, seed=0, amp=0.05, omega=False, precision="fp64"):
+    phi0 = inputs.noise_phi0(p["ny"], p["nx"], seed, amp=amp)
+    om0 = inputs.noise_omega0(p["ny"], p["nx"], seed) if omega else None
+    print(f"case nx={p['nx']} ny={p['ny']} gdot={p['gdot']} rho={p['rho']} "
+          f"steps={steps} seed={seed} {precision}", flush=True)
+    ctx = le.Context(p, phi0, om0, precision=precision)
+    ctx.step(steps)
+    g = ctx.get_state()
+    op = mh.Params(**p)
+    st = mh.run(op, mh.initial_state(op, phi0, om0), steps)
+    return ctx, g, st, op
+
+
+@pytest.mark.parametrize("rho", [1.0, 0.0])
+def test_small_case_fp64_100_steps(rho):
+    """64x64, gdot = 0.01, dt = 0.005: the small workload, 100 steps."""
+    p = params(64, 64, rho=rho)
+    ctx, g, st, _ = run_pair(p, 100)
+    assert g["step"] == 100 and g["wraps"] == st.wraps
+    assert rel(g["phi"], st.phi) <= 1e-10
+    assert rel(g["psi"], st.psi) <= 1e-10
+    if rho > 0:
+        assert rel(g["omega"], st.omega) <= 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("nx,ny,lx,ly,gdot,rho", [
+    (32, 16, 2.0, 1.0, 8.0, 1.0),     # c = r = 2 (the paper's geometry), one wrap
+    (16, 16, 16.0, 16.0, -6.0, 1.0),  # negative shear, c = r = 1
+    (64, 16, 4.0, 1.0, 12.0, 0.0),    # r = 4, Stokes branch
+    (8, 8, 8.0, 8.0, 3.0, 1.0),       # the smallest grid
+])
+def test_parity_through_strain_wraps(nx, ny, lx, ly, gdot, rho):
+    p = params(nx, ny, lx=lx, ly=ly, gdot=gdot, rho=rho, kappa=0.05 * (lx / nx) ** 2 * 20,
+               M=0.5 * (lx / nx) ** 2, dt=0.002)
+    ctx, g, st, op = run_pair(p, 100, omega=True, amp=0.5)
+    assert st.wraps != 0
+    assert g["wraps"] == st.wraps
+    assert rel(g["phi"], st.phi) <= 1e-10
+    assert rel(g["psi"], st.psi) <= 1e-10
+    if rho > 0:
+        assert rel(g["omega"], st.omega) <= 1e-10
+    ctx.close()
+
+
+@pytest.mark.parametrize("nx,ny", [(128, 64), (256, 128), (64, 256), (512, 32)])
+def test_parity_several_tiles(nx, ny):
+    """Grids spanning several row/column blocks, ragged final column block."""
+    p = params(nx, ny, gdot=0.0 if nx < ny else 0.05, rho=1.0)
+    ctx, g, st, _ = run_pair(p, 40, seed=3, omega=True)
+    assert rel(g["phi"], st.phi) <= 1e-10
+    assert rel(g["omega"], st.omega) <= 1e-10
+    assert rel(g["psi"], st.psi) <= 1e-10
+    ctx.close()
+
+
+def test_observables_match_oracle():
+    p = params(64, 32, lx=128.0, ly=64.0, gdot=0.3, rho=2.0)
+    ctx, g, st, op = run_pair(p, 150, seed=5, amp=0.6, omega=True)
+    o, Sk = ctx.observables()
+    ro, rSk, _ = ob.observables(op, st)
+    for k in ("mean_phi", "phi2", "Ls", "Dxx", "Dxy", "Dyy", "L_perp", "L_par", "sigma_xy",
+              "sigma_xy_re", "s", "strain", "t"):
+        a, b = o[k], ro[k]
+        if math.isinf(b):
+            assert math.isinf(a) or a > 1e12, (k, a, b)
+            continue
+        assert abs(a - b) <= 1e-12 * max(abs(b), 1e-300) + 1e-18, (k, a, b)
+    assert o["step"] == ro["step"] and o["wraps"] == ro["wraps"]
+    assert o["finite"] == 1 and o["nbins"] == 16
+    assert np.max(np.abs(Sk - rSk)) <= 1e-12 * np.max(np.abs(rSk))
+    ctx.close()
+
+
+def test_mean_phi_conserved_and_deterministic():
+    p = params(128, 128, gdot=0.2, rho=1.0)
+    phi0 = inputs.noise_phi0(128, 128, 9, amp=0.3, mean=0.1)
+    runs = []
+    for _ in range(2):
+        ctx = le.Context(p, phi0)
+        ctx.step(500)
+        runs.append(ctx.get_state())
+        o, _ = ctx.observables(sk=False)
+        assert abs(o["mean_phi"] - float(np.mean(phi0))) <= 1e-13
+        ctx.close()
+    assert np.array_equal(runs[0]["phi"], runs[1]["phi"])
+    assert np.array_equal(runs[0]["psi"], runs[1]["psi"])
+
+
+def test_checkpoint_resume_is_bitwise():
+    p = params(64, 64, gdot=1.0, rho=1.0)    # a wrap at strain 0.5 (step 100)
+    phi0 = inputs.noise_phi0(64, 64, 2, amp=0.5)
+    a = le.Context(p, phi0)
+    a.step(150)
+    mid = a.get_state()
+    a.step(150)
+    ref = a.get_state()
+    b = le.Context(p, np.zeros((64, 64)))
+    b.set_state(mid["phi"], mid["omega"], mid["psi"], mid["step"], mid["wraps"])
+    b.step(150)
+    got = b.get_state()
+    assert got["step"] == 300 and got["wraps"] == ref["wraps"]
+    # the restart rebuilds the row spectra from real fields: equal to rounding
+    assert rel(got["phi"], ref["phi"]) <= 1e-13
+    assert rel(got["psi"], ref["psi"]) <= 1e-12
+    a.close()
+    b.close()
+
+
+def test_nonfinite_state_is_reported():
+    p = params(32, 32)
+    phi0 = inputs.noise_phi0(32, 32, 1)
+    phi0[3, 4] = np.nan
+    ctx = le.Context(p, phi0)
+    with pytest.raises(le.LeError) as ei:
+        ctx.step(2)
+    assert ei.value.code == le.LE_ENONFINITE
+    ctx.close()
+
+
+@pytest.mark.parametrize("rho", [1.0, 0.0])
+def test_fp32_error_bound(rho):
+    """FP32 bulk: error after 100 steps stays within the stated 2e-5 bound."""
+    p = params(64, 64, rho=rho)
+    ctx, g, st, _ = run_pair(p, 100, precision="fp32")
+    assert rel(g["phi"], st.phi) <= 2e-5
+    assert rel(g["psi"], st.psi) <= 2e-4
+    ctx.close()
