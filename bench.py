@@ -49,7 +49,8 @@ def stage_bytes(params, precision):
     }
 
 
-def run_variant(le, torch, params, precision, steps, warmup, obs_every, seed=0):
+def run_variant(le, torch, params, precision, steps, warmup, obs_every, seed=0,
+                profile=True):
     from paper_0710_5912_amd import inputs
 
     nx, ny = params["nx"], params["ny"]
@@ -58,7 +59,7 @@ def run_variant(le, torch, params, precision, steps, warmup, obs_every, seed=0):
     ctx = le.Context(params, phi0, precision=precision, stream=stream.cuda_stream)
     ctx.step(warmup)
     torch.cuda.synchronize()
-    ctx.profile(True)
+    ctx.profile(profile)
     series = []
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -91,6 +92,8 @@ def roofline_of(params, precision, times):
             continue
         avg_s = ms / n * 1e-3
         rows[k] = dict(avg_us=avg_s * 1e6, bytes=b[k], gbs=b[k] / avg_s / 1e9)
+    if not rows:
+        return None, {}
     dom = max(rows, key=lambda k: rows[k]["avg_us"])
     return dom, rows
 
@@ -149,6 +152,9 @@ def main():
     sec = r["gpu_ms"] * 1e-3
     value = sites * args.steps / sec
     dom, rows = roofline_of(params, "fp64", r["times"])
+    print("bench: same workload without stage events", file=sys.stderr, flush=True)
+    r_np = run_variant(le, torch, params, "fp64", min(args.steps, 2000), 50, args.obs_every,
+                       profile=False)
     out = {
         "metric": "site-updates/s/GPU (plain FP64 vs FP32, batched, learned corrector) at stated L(t) error",
         "value": value,
@@ -175,6 +181,7 @@ def main():
         "stages": {k: {"avg_us": round(v["avg_us"], 2), "GBs": round(v["gbs"], 1)}
                    for k, v in rows.items()},
         "wall_s": r["wall"],
+        "ms_per_step_without_stage_events": r_np["gpu_ms"] / min(args.steps, 2000),
         "parity": "FP64 path within 1e-10 of the FP64 oracle after 100 steps (tests)",
     }
     if not args.no_variants:

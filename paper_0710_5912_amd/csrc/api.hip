@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -79,6 +80,9 @@ struct le_ctx {
   double* h_out = nullptr;     // pinned
   int nsblk = 0, nbins = 0;
   void* h_stage = nullptr;     // pinned host staging for up/downloads
+  // captured step sequences, keyed by their length in steps
+  bool use_graphs = true;
+  std::map<int64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
   // stage timing (le_profile)
   bool profiling = false;
   std::vector<hipEvent_t> events;   // kProfChunk * (LE_NSTAGES + 1)
@@ -97,6 +101,11 @@ void release(le_ctx* c) {
   if (c->h_args) (void)hipHostFree(c->h_args);
   if (c->h_out) (void)hipHostFree(c->h_out);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
+  for (auto& kv : c->graphs) {
+    (void)hipGraphExecDestroy(kv.second.second);
+    (void)hipGraphDestroy(kv.second.first);
+  }
+  c->graphs.clear();
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   c->events.clear();
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -242,6 +251,46 @@ void harvest_times(le_ctx* c, int64_t count) {
   }
 }
 
+// Enqueue `count` steps reading their StepArgs from d_args[0 .. count).  Runs
+// of at least kGraphMin steps are captured once into a HIP graph per length
+// and replayed; the per-step strain offsets stay in device memory, so one
+// graph serves every chunk of that length.
+constexpr int64_t kGraphMin = 8;
+constexpr size_t kGraphCacheMax = 4;
+int enqueue_steps(le_ctx* c, int64_t count) {
+  if (!c->use_graphs || count < kGraphMin) {
+    for (int64_t k = 0; k < count; ++k)
+      enqueue_step(c, c->d_args + k,
+                   c->profiling ? &c->events[(size_t)k * (LE_NSTAGES + 1)] : nullptr);
+    return LE_OK;
+  }
+  // timing graphs carry their event-record nodes: key them apart
+  const int64_t key = c->profiling ? -count : count;
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    if (c->graphs.size() >= kGraphCacheMax) {
+      auto old = c->graphs.begin();
+      (void)hipGraphExecDestroy(old->second.second);
+      (void)hipGraphDestroy(old->second.first);
+      c->graphs.erase(old);
+    }
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    LE_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    for (int64_t k = 0; k < count; ++k)
+      enqueue_step(c, c->d_args + k,
+                   c->profiling ? &c->events[(size_t)k * (LE_NSTAGES + 1)] : nullptr);
+    LE_TRY(hipStreamEndCapture(c->stream, &g));
+    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return LE_EDEVICE;
+    }
+    it = c->graphs.emplace(key, std::make_pair(g, ge)).first;
+  }
+  LE_TRY(hipGraphLaunch(it->second.second, c->stream));
+  return LE_OK;
+}
+
 // Remap the state after the strain offset jumped by -dk * c.
 void enqueue_remap(le_ctx* c, int64_t dk) {
   const int dkr = (int)((dk * (int64_t)c->geo.r) % c->p.nx);
@@ -319,6 +368,10 @@ int le_create(const le_params* p, const double* phi0, const double* omega0, le_c
   g.rho = p->rho;
   g.dt = p->dt;
   c->inertial = p->rho > 0.0;
+  {
+    const char* e = std::getenv("LE_GRAPHS");
+    c->use_graphs = !(e && e[0] == '0');
+  }
   c->tsize = p->precision == LE_FP64 ? sizeof(double) : sizeof(float);
   c->n_real = (size_t)p->nx * p->ny;
   c->n_spec = (size_t)p->ny * (p->nx / 2 + 1);
@@ -414,9 +467,8 @@ int le_step(le_ctx* c, int64_t nsteps) {
     }
     LE_TRY(hipMemcpyAsync(c->d_args, c->h_args, (size_t)count * sizeof(StepArgs),
                           hipMemcpyHostToDevice, c->stream));
-    for (int64_t k = 0; k < count; ++k)
-      enqueue_step(c, c->d_args + k,
-                   c->profiling ? &c->events[(size_t)k * (LE_NSTAGES + 1)] : nullptr);
+    int rc = enqueue_steps(c, count);
+    if (rc) return rc;
     c->step = n0 + count;
     if (k_end != c->wraps) {
       enqueue_remap(c, k_end - c->wraps);

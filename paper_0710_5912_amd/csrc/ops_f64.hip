@@ -3,31 +3,44 @@
 
 namespace le {
 
-// Final fixed-order reduction over blocks.  out: OBS_NTOTAL sums, then nbins
-// shell sums, then nbins shell weights.
-__global__ void k_obs_final(const double* __restrict__ spart, int nsblk,
-                            const double* __restrict__ rpart, int nrblk,
-                            const double* __restrict__ bins, const double* __restrict__ counts,
-                            int nbins, double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Final fixed-order reduction over blocks; block i produces output i.
+// out: OBS_NTOTAL sums, then nbins shell sums, then nbins shell weights.
+__global__ __launch_bounds__(256) void k_obs_final(const double* __restrict__ spart, int nsblk,
+                                                   const double* __restrict__ rpart, int nrblk,
+                                                   const double* __restrict__ bins,
+                                                   const double* __restrict__ counts, int nbins,
+                                                   double* __restrict__ out) {
+  __shared__ double red[2][256];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  double a = 0.0, w = 0.0;
   if (i < OBS_NSPEC) {
-    double a = 0.0;
-    for (int b = 0; b < nsblk; ++b) a += spart[(size_t)b * OBS_NSPEC + i];
-    out[i] = a;
+    for (int b = tid; b < nsblk; b += 256) a += spart[(size_t)b * OBS_NSPEC + i];
   } else if (i < OBS_NTOTAL) {
-    const int k = i - OBS_NSPEC;
-    double a = 0.0;
-    for (int b = 0; b < nrblk; ++b) a += rpart[(size_t)b * 3 + k];
-    out[i] = a;
-  } else if (i < OBS_NTOTAL + nbins) {
+    for (int b = tid; b < nrblk; b += 256) a += rpart[(size_t)b * 3 + (i - OBS_NSPEC)];
+  } else {
     const int k = i - OBS_NTOTAL;
-    double a = 0.0, w = 0.0;
-    for (int b = 0; b < nsblk; ++b) {
+    for (int b = tid; b < nsblk; b += 256) {
       a += bins[(size_t)b * nbins + k];
       w += counts[(size_t)b * nbins + k];
     }
-    out[OBS_NTOTAL + k] = a;
-    out[OBS_NTOTAL + nbins + k] = w;
+  }
+  red[0][tid] = a;
+  red[1][tid] = w;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if (tid < h) {
+      red[0][tid] += red[0][tid + h];
+      red[1][tid] += red[1][tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (i < OBS_NTOTAL) {
+      out[i] = red[0][0];
+    } else {
+      out[i] = red[0][0];
+      out[i + nbins] = red[1][0];
+    }
   }
 }
 
@@ -36,9 +49,8 @@ bool get_ops_f64(int nx, int ny, Ops* ops) { return fill_ops<double>(nx, ny, ops
 void launch_obs_final(const double* spart, int nsblk, const double* rpart, int nrblk,
                       const double* bins, const double* counts, int nbins, double* out,
                       hipStream_t st) {
-  const int n = OBS_NTOTAL + nbins;
-  hipLaunchKernelGGL(k_obs_final, dim3((n + 255) / 256), dim3(256), 0, st, spart, nsblk, rpart,
-                     nrblk, bins, counts, nbins, out);
+  hipLaunchKernelGGL(k_obs_final, dim3(OBS_NTOTAL + nbins), dim3(256), 0, st, spart, nsblk,
+                     rpart, nrblk, bins, counts, nbins, out);
 }
 
 }  // namespace le

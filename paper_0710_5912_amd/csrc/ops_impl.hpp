@@ -18,7 +18,9 @@ struct RowLaunch {
   }
   static void c2r(const void* X0, void* x0, const void* X1, void* x1, const Geo& g,
                   const void* tw, hipStream_t st) {
-    hipLaunchKernelGGL((k_row_c2r<T, L>), grid(g), dim3(C::THREADS), 0, st,
+    dim3 gr = grid(g);
+    gr.y = X1 ? 2 : 1;
+    hipLaunchKernelGGL((k_row_c2r<T, L>), gr, dim3(C::THREADS), 0, st,
                        static_cast<const c2<T>*>(X0), static_cast<T*>(x0),
                        static_cast<const c2<T>*>(X1), static_cast<T*>(x1), g.ny,
                        static_cast<const c2<T>*>(tw));
@@ -26,23 +28,19 @@ struct RowLaunch {
   static void advect(const void* phi, const void* om, const void* psi, void* phih, void* fh,
                      void* omh, const StepArgs* sa, const Geo& g, const void* tw,
                      bool inertial, hipStream_t st) {
-    if (inertial)
-      hipLaunchKernelGGL((k_advect<T, L, true>), grid(g), dim3(C::THREADS), 0, st,
-                         static_cast<const T*>(phi), static_cast<const T*>(om),
-                         static_cast<const T*>(psi), static_cast<c2<T>*>(phih),
-                         static_cast<c2<T>*>(fh), static_cast<c2<T>*>(omh), sa, g,
-                         static_cast<const c2<T>*>(tw));
-    else
-      hipLaunchKernelGGL((k_advect<T, L, false>), grid(g), dim3(C::THREADS), 0, st,
-                         static_cast<const T*>(phi), static_cast<const T*>(om),
-                         static_cast<const T*>(psi), static_cast<c2<T>*>(phih),
-                         static_cast<c2<T>*>(fh), static_cast<c2<T>*>(omh), sa, g,
-                         static_cast<const c2<T>*>(tw));
+    dim3 gr = grid(g);
+    gr.y = inertial ? 3 : 2;
+    hipLaunchKernelGGL((k_advect<T, L>), gr, dim3(C::THREADS), 0, st,
+                       static_cast<const T*>(phi), static_cast<const T*>(om),
+                       static_cast<const T*>(psi), static_cast<c2<T>*>(phih),
+                       static_cast<c2<T>*>(fh), static_cast<c2<T>*>(omh), sa, g,
+                       static_cast<const c2<T>*>(tw));
   }
   static void mu_source(const void* phi, void* gh, const StepArgs* sa, const Geo& g,
                         double inv, const void* tw, hipStream_t st) {
-    hipLaunchKernelGGL((k_mu_source<T, L>), grid(g), dim3(C::THREADS), 0, st,
-                       static_cast<const T*>(phi), static_cast<c2<T>*>(gh), sa, g, inv,
+    using M = MuCfg<L>;
+    hipLaunchKernelGGL((k_mu_source<T, L>), dim3((g.ny + M::G - 1) / M::G), dim3(M::THREADS),
+                       0, st, static_cast<const T*>(phi), static_cast<c2<T>*>(gh), sa, g, inv,
                        static_cast<const c2<T>*>(tw));
   }
 };

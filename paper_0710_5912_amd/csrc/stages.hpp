@@ -17,23 +17,43 @@
 
 namespace le {
 
+// Launch shapes.  E: values per thread of a transform (P = L/E threads per
+// transform); G: rows per block; CW: adjacent columns per block.
+constexpr int row_elems(int L) { return L >= 1024 ? 16 : (L >= 8 ? 8 : L); }
+constexpr int col_elems(int L) { return L >= 2048 ? 16 : (L >= 16 ? 8 : L); }
+constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
 template <int L>
 struct RowCfg {
-  static constexpr int E = elems_for(L);
+  static constexpr int E = row_elems(L);
   static constexpr int P = L / E;
-  static constexpr int G0 = 256 / P;
-  static constexpr int G = G0 < 1 ? 1 : (G0 > 16 ? 16 : G0);
+  static constexpr int G = clampi(128 / P, 1, 16);
+  static constexpr int THREADS = G * P;
+};
+
+template <int L>
+struct MuCfg {
+  static constexpr int E = row_elems(L);
+  static constexpr int P = L / E;
+  static constexpr int G = clampi(256 / P, 1, 16);
   static constexpr int THREADS = G * P;
 };
 
 template <int L>
 struct ColCfg {
-  static constexpr int E = elems_for(L);
+  static constexpr int E = col_elems(L);
   static constexpr int P = L / E;
-  static constexpr int CW0 = 256 / P;
-  static constexpr int CW = CW0 < 1 ? 1 : (CW0 > 64 ? 64 : CW0);
+  static constexpr int CW = clampi(256 / P, 1, 64);
   static constexpr int THREADS = CW * P;
 };
+
+// Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Give each XCD a contiguous range of logical blocks so that neighbouring
+// rows (stencil halos) and columns sharing cache lines meet in one L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, rem = nb & 7, x = b & 7;
+  return x * q + (x < rem ? x : rem) + (b >> 3);
+}
 
 // ---------------------------------------------------------------- helpers
 
@@ -95,7 +115,7 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) void k_row_r2c(
   using C = RowCfg<L>;
   __shared__ c2<T> lds[C::G * L];
   const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
-  const int j = blockIdx.x * C::G + g;
+  const int j = xcd_block(blockIdx.x, gridDim.x) * C::G + g;
   const bool ok = j < ny;
   const c2<T>* xr = reinterpret_cast<const c2<T>*>(x + (size_t)(ok ? j : 0) * 2 * L);
   c2<T> v[C::E];
@@ -105,7 +125,7 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) void k_row_r2c(
   if (ok) store_row_spec<T, L, C::E>(X + (size_t)j * (L + 1), v, t);
 }
 
-// Inverse row transform of one or two fields (X1 == nullptr: one field).
+// Inverse row transform; blockIdx.y selects the field (X0 -> x0, X1 -> x1).
 template <typename T, int L>
 __global__ __launch_bounds__(RowCfg<L>::THREADS) void k_row_c2r(
     const c2<T>* __restrict__ X0, T* __restrict__ x0, const c2<T>* __restrict__ X1,
@@ -113,22 +133,18 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) void k_row_c2r(
   using C = RowCfg<L>;
   __shared__ c2<T> lds[C::G * L];
   const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
-  const int j = blockIdx.x * C::G + g;
+  const int j = xcd_block(blockIdx.x, gridDim.x) * C::G + g;
   const bool ok = j < ny;
   const int jj = ok ? j : 0;
+  const c2<T>* X = blockIdx.y == 0 ? X0 : X1;
+  T* x = blockIdx.y == 0 ? x0 : x1;
   c2<T> v[C::E];
-  for (int f = 0; f < 2; ++f) {
-    const c2<T>* X = f == 0 ? X0 : X1;
-    T* x = f == 0 ? x0 : x1;
-    if (X == nullptr) break;
-    if (f) __syncthreads();
-    load_row_spec<T, L, C::E>(X + (size_t)jj * (L + 1), v, t);
-    row_c2r<T, L, C::E>(v, lds + g * L, tw, t);
-    if (ok) {
-      c2<T>* xr = reinterpret_cast<c2<T>*>(x + (size_t)j * 2 * L);
+  load_row_spec<T, L, C::E>(X + (size_t)jj * (L + 1), v, t);
+  row_c2r<T, L, C::E>(v, lds + g * L, tw, t);
+  if (ok) {
+    c2<T>* xr = reinterpret_cast<c2<T>*>(x + (size_t)j * 2 * L);
 #pragma unroll
-      for (int q = 0; q < C::E; ++q) xr[t + q * C::P] = v[q];
-    }
+    for (int q = 0; q < C::E; ++q) xr[t + q * C::P] = v[q];
   }
 }
 
@@ -186,10 +202,12 @@ __device__ __forceinline__ void dys_pair(const T* f, int jp, int jm, int i, int 
   }
 }
 
-// Stage 1a (Eq. advective): phi_h = phi - dt [Dys psi Dx phi - Dx psi Dys phi],
-// the same for omega when INERTIAL, and f = phi^3; then the forward row
-// transforms of phi_h, f (and omega_h).
-template <typename T, int L, bool INERTIAL>
+// Stage 1a (Eq. advective), one output field per blockIdx.y:
+//   0: phi_h = phi - dt [Dys psi Dx phi - Dx psi Dys phi]
+//   1: f = phi^3
+//   2: omega_h = omega - dt [Dys psi Dx omega - Dx psi Dys omega]  (inertial)
+// followed by the forward row transform of that field.
+template <typename T, int L>
 __global__ __launch_bounds__(RowCfg<L>::THREADS) void k_advect(
     const T* __restrict__ phi, const T* __restrict__ om, const T* __restrict__ psi,
     c2<T>* __restrict__ phih, c2<T>* __restrict__ fh, c2<T>* __restrict__ omh,
@@ -198,64 +216,56 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) void k_advect(
   constexpr int NX = 2 * L;
   __shared__ c2<T> lds[C::G * L];
   const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
-  const int j0 = blockIdx.x * C::G + g;
+  const int j0 = xcd_block(blockIdx.x, gridDim.x) * C::G + g;
   const bool ok = j0 < geo.ny;
   const int j = ok ? j0 : 0;
   const int jp = (j + 1 == geo.ny) ? 0 : j + 1;
   const int jm = (j == 0) ? geo.ny - 1 : j - 1;
+  const int field = blockIdx.y;
   const Stencil<T> st = make_stencil<T>(geo, sa->s);
   const T dt = T(geo.dt);
-  c2<T> v0[C::E], v1[C::E];
+  c2<T> v[C::E];
+  if (field == 1) {
 #pragma unroll
-  for (int q = 0; q < C::E; ++q) {
-    const int i = 2 * (t + q * C::P);
-    T sx0, sx1, sy0, sy1, ax0, ax1, ay0, ay1;
-    dx_pair(psi, j, i, NX, st.inv2dx, sx0, sx1);
-    dys_pair(psi, jp, jm, i, NX, st, sy0, sy1);
-    dx_pair(phi, j, i, NX, st.inv2dx, ax0, ax1);
-    dys_pair(phi, jp, jm, i, NX, st, ay0, ay1);
-    const T p0 = at(phi, j, i, NX), p1 = at(phi, j, i + 1, NX);
-    v0[q] = {p0 - dt * (sy0 * ax0 - sx0 * ay0), p1 - dt * (sy1 * ax1 - sx1 * ay1)};
-    v1[q] = {p0 * p0 * p0, p1 * p1 * p1};
-  }
-  row_r2c<T, L, C::E>(v0, lds + g * L, tw, t);
-  if (ok) store_row_spec<T, L, C::E>(phih + (size_t)j * (L + 1), v0, t);
-  __syncthreads();
-  row_r2c<T, L, C::E>(v1, lds + g * L, tw, t);
-  if (ok) store_row_spec<T, L, C::E>(fh + (size_t)j * (L + 1), v1, t);
-  if constexpr (INERTIAL) {
+    for (int q = 0; q < C::E; ++q) {
+      const int i = 2 * (t + q * C::P);
+      const T p0 = phi[(size_t)j * NX + i], p1 = phi[(size_t)j * NX + i + 1];
+      v[q] = {p0 * p0 * p0, p1 * p1 * p1};
+    }
+  } else {
+    const T* a = field == 0 ? phi : om;
 #pragma unroll
     for (int q = 0; q < C::E; ++q) {
       const int i = 2 * (t + q * C::P);
       T sx0, sx1, sy0, sy1, ax0, ax1, ay0, ay1;
       dx_pair(psi, j, i, NX, st.inv2dx, sx0, sx1);
       dys_pair(psi, jp, jm, i, NX, st, sy0, sy1);
-      dx_pair(om, j, i, NX, st.inv2dx, ax0, ax1);
-      dys_pair(om, jp, jm, i, NX, st, ay0, ay1);
-      const T w0 = at(om, j, i, NX), w1 = at(om, j, i + 1, NX);
-      v0[q] = {w0 - dt * (sy0 * ax0 - sx0 * ay0), w1 - dt * (sy1 * ax1 - sx1 * ay1)};
+      dx_pair(a, j, i, NX, st.inv2dx, ax0, ax1);
+      dys_pair(a, jp, jm, i, NX, st, ay0, ay1);
+      const T a0 = a[(size_t)j * NX + i], a1 = a[(size_t)j * NX + i + 1];
+      v[q] = {a0 - dt * (sy0 * ax0 - sx0 * ay0), a1 - dt * (sy1 * ax1 - sx1 * ay1)};
     }
-    __syncthreads();
-    row_r2c<T, L, C::E>(v0, lds + g * L, tw, t);
-    if (ok) store_row_spec<T, L, C::E>(omh + (size_t)j * (L + 1), v0, t);
   }
+  row_r2c<T, L, C::E>(v, lds + g * L, tw, t);
+  c2<T>* out = field == 0 ? phih : (field == 1 ? fh : omh);
+  if (ok) store_row_spec<T, L, C::E>(out + (size_t)j * (L + 1), v, t);
 }
 
 // Stage 2a: mu = B phi^3 - A phi - kappa [(1+s^2) Dxx + Dyy - 2 s Dxy] phi on
 // rows j0-1 .. j0+G (into LDS), then g = -[Dx phi Dys mu - Dys phi Dx mu] * inv
 // (inv = 1/rho, or 1/eta on the Stokes branch) and its forward row transform.
 template <typename T, int L>
-__global__ __launch_bounds__(RowCfg<L>::THREADS) void k_mu_source(
+__global__ __launch_bounds__(MuCfg<L>::THREADS) void k_mu_source(
     const T* __restrict__ phi, c2<T>* __restrict__ gh, const StepArgs* __restrict__ sa,
     Geo geo, double inv_coef, const c2<T>* __restrict__ tw) {
-  using C = RowCfg<L>;
+  using C = MuCfg<L>;
   constexpr int NX = 2 * L;
   constexpr int MU_ROWS = C::G + 2;
   constexpr int LDS_T = MU_ROWS * NX;  // >= C::G * L complex
   __shared__ __attribute__((aligned(16))) T smu[LDS_T];
   c2<T>* lds = reinterpret_cast<c2<T>*>(smu);
   const int ny = geo.ny;
-  const int jbase = blockIdx.x * C::G;
+  const int jbase = xcd_block(blockIdx.x, gridDim.x) * C::G;
   const double s = sa->s;
   const T cxx = T((1.0 + s * s) / (geo.dx * geo.dx));
   const T cyy = T(1.0 / (geo.dy * geo.dy));
@@ -364,7 +374,7 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_column(
   __shared__ c2<T> lds[C::CW * L];
   const int S = geo.nx / 2 + 1;
   const int c = threadIdx.x % C::CW, t = threadIdx.x / C::CW;
-  const int m0 = blockIdx.x * C::CW + c;
+  const int m0 = xcd_block(blockIdx.x, gridDim.x) * C::CW + c;
   const bool ok = m0 < S;
   const int m = ok ? m0 : 0;
   c2<T> v0[C::E], v1[C::E];
@@ -474,7 +484,7 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_obs_spectral(
 
   const int S = geo.nx / 2 + 1;
   const int c = threadIdx.x % C::CW, t = threadIdx.x / C::CW;
-  const int m0 = blockIdx.x * C::CW + c;
+  const int m0 = xcd_block(blockIdx.x, gridDim.x) * C::CW + c;
   const bool ok = m0 < S;
   const int m = ok ? m0 : 0;
   c2<T> v0[C::E], v1[C::E];
@@ -534,23 +544,51 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_obs_spectral(
     if (threadIdx.x == 0) part[(size_t)blockIdx.x * OBS_NSPEC + k] = red[0];
     __syncthreads();
   }
-  // shells: thread owns shells b = 1 + tid + k * THREADS, scans the block in order
-  double sb[NBT], cb[NBT];
-#pragma unroll
-  for (int k = 0; k < NBT; ++k) { sb[k] = 0.0; cb[k] = 0.0; }
-  for (int e = 0; e < NE; ++e) {
-    const int d = bidx[e] - 1 - (int)threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < NBT; ++k) {
-      if (d == k * C::THREADS) { sb[k] += bval[e]; cb[k] += bwgt[e]; }
-    }
-  }
-#pragma unroll
+  // Shells: thread owns shells b = 1 + tid + k * THREADS.  For each column
+  // the modes of shell b lie in at most two runs of n (|q_lab| is a parabola
+  // in qy); each run is bracketed from the shell radii, widened by two rows,
+  // and the stored per-mode decisions pick the members, in increasing n.
+  __syncthreads();
+  const int ny = geo.ny;
+  const double rad = geo.ly / 6.283185307179586476925286766559;  // n' per unit qy
   for (int k = 0; k < NBT; ++k) {
-    const int b = (int)threadIdx.x + k * C::THREADS;
-    if (b < NB) {
-      bins[(size_t)blockIdx.x * NB + b] = sb[k];
-      counts[(size_t)blockIdx.x * NB + b] = cb[k];
+    const int b = 1 + (int)threadIdx.x + k * C::THREADS;
+    double sb = 0.0, cb = 0.0;
+    if (b <= NB) {
+      const double qlo = (b - 0.5) * dk, qhi = (b + 0.5) * dk;
+      for (int cc = 0; cc < C::CW; ++cc) {
+        const int mc = xcd_block(blockIdx.x, gridDim.x) * C::CW + cc;
+        if (mc >= S) break;
+        // the Nyquist row (and the whole Nyquist column) drop the cross
+        // term: they are checked outright
+        auto take = [&](int n) {
+          const int e = n * C::CW + cc;
+          if (bidx[e] == b) { sb += bval[e]; cb += bwgt[e]; }
+        };
+        if (mc == geo.nx / 2) {
+          for (int n = 0; n < ny; ++n) take(n);
+          continue;
+        }
+        take(ny / 2);
+        const Modes md = modes(geo, mc, 0);
+        const double qx2 = md.qx * md.qx;
+        if (qhi * qhi <= qx2 * (1.0 - 1e-12)) continue;
+        const double a = sqrt(fmax(0.0, qlo * qlo - qx2));
+        const double c2v = sqrt(fmax(0.0, qhi * qhi - qx2));
+        const double sh = s * md.qx;
+        int lo1 = (int)floor((-c2v + sh) * rad) - 2, hi1 = (int)ceil((-a + sh) * rad) + 2;
+        int lo2 = (int)floor((a + sh) * rad) - 2, hi2 = (int)ceil((c2v + sh) * rad) + 2;
+        if (lo2 <= hi1 + 1) { hi1 = hi2; lo2 = 1; hi2 = 0; }   // the runs touch: merge
+        const int nlo = -ny / 2 + 1, nhi = ny / 2 - 1;          // Nyquist row done above
+        for (int run = 0; run < 2; ++run) {
+          int lo = run == 0 ? lo1 : lo2, hi = run == 0 ? hi1 : hi2;
+          lo = lo < nlo ? nlo : lo;
+          hi = hi > nhi ? nhi : hi;
+          for (int np = lo; np <= hi; ++np) take(np < 0 ? np + ny : np);
+        }
+      }
+      bins[(size_t)blockIdx.x * NB + (b - 1)] = sb;
+      counts[(size_t)blockIdx.x * NB + (b - 1)] = cb;
     }
   }
 }

@@ -160,3 +160,26 @@ def test_fp32_error_bound(rho):
     assert rel(g["phi"], st.phi) <= 2e-5
     assert rel(g["psi"], st.psi) <= 2e-4
     ctx.close()
+
+
+def test_graph_replays_match_eager_launches(monkeypatch):
+    """Captured step graphs replayed many times, with eager work between the
+    replays, give bit-identical states to plain launches."""
+    p = params(128, 64, lx=256.0, ly=128.0, gdot=0.5, rho=1.0)   # wraps every 200 steps
+    phi0 = inputs.noise_phi0(64, 128, 4, amp=0.5)
+    monkeypatch.setenv("LE_GRAPHS", "0")
+    eager = le.Context(p, phi0)
+    monkeypatch.setenv("LE_GRAPHS", "1")
+    graph = le.Context(p, phi0)
+    for _ in range(6):
+        eager.step(50)
+        graph.step(50)
+        a, b = eager.get_state(), graph.get_state()
+        assert a["step"] == b["step"] and a["wraps"] == b["wraps"]
+        for k in ("phi", "omega", "psi"):
+            assert np.array_equal(a[k], b[k]), k
+        oa, _ = eager.observables()
+        ob_, _ = graph.observables()
+        assert oa["Ls"] == ob_["Ls"]
+    eager.close()
+    graph.close()
