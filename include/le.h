@@ -136,6 +136,10 @@ int le_set_state(le_ctx* c, const double* phi, const double* omega,
 /* Static description of an error code. */
 const char* le_strerror(int code);
 
+/* Text naming the last HIP call that failed on the calling thread and the
+ * HIP error it returned ("" if none); valid until the next failure. */
+const char* le_last_error(void);
+
 /*
  * Per-stage GPU timing.  With profiling enabled, le_step brackets every stage
  * launch with HIP events on the context's stream and accumulates the elapsed

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -21,9 +22,19 @@ constexpr int kArgsCap = 4096;   // steps per host chunk (one StepArgs each)
 constexpr int kRealBlocks = 256;  // blocks of the real-space reduction
 constexpr int kProfChunk = 256;   // steps per chunk while stage timing is on
 
-#define LE_TRY(expr)                                \
-  do {                                              \
-    if ((expr) != hipSuccess) return LE_EDEVICE;    \
+// Text of the last failing HIP call on this thread (le_last_error).
+thread_local char g_last_error[256] = "";
+
+int fail_hip(hipError_t e, const char* what, int line) {
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s (line %d): %s", what, line,
+                hipGetErrorString(e));
+  return LE_EDEVICE;
+}
+
+#define LE_TRY(expr)                                             \
+  do {                                                           \
+    const hipError_t le_e_ = (expr);                             \
+    if (le_e_ != hipSuccess) return fail_hip(le_e_, #expr, __LINE__); \
   } while (0)
 
 // ---- shear clock (section "Numerical method": the sawtooth s(t)) --------
@@ -258,16 +269,12 @@ void harvest_times(le_ctx* c, int64_t count) {
 constexpr int64_t kGraphMin = 8;
 constexpr size_t kGraphCacheMax = 4;
 int enqueue_steps(le_ctx* c, int64_t count) {
-  if (!c->use_graphs || count < kGraphMin) {
-    for (int64_t k = 0; k < count; ++k)
-      enqueue_step(c, c->d_args + k,
-                   c->profiling ? &c->events[(size_t)k * (LE_NSTAGES + 1)] : nullptr);
-    return LE_OK;
-  }
-  // timing graphs carry their event-record nodes: key them apart
-  const int64_t key = c->profiling ? -count : count;
-  auto it = c->graphs.find(key);
-  if (it == c->graphs.end()) {
+  // Stage timing brackets direct launches with events (event-record nodes
+  // are not taken under capture here), so timed chunks are never captured.
+  const int64_t key = count;
+  const bool graph_ok = c->use_graphs && count >= kGraphMin && !c->profiling;
+  auto it = graph_ok ? c->graphs.find(key) : c->graphs.end();
+  if (graph_ok && it == c->graphs.end()) {
     if (c->graphs.size() >= kGraphCacheMax) {
       auto old = c->graphs.begin();
       (void)hipGraphExecDestroy(old->second.second);
@@ -276,18 +283,36 @@ int enqueue_steps(le_ctx* c, int64_t count) {
     }
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
-    LE_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-    for (int64_t k = 0; k < count; ++k)
-      enqueue_step(c, c->d_args + k,
-                   c->profiling ? &c->events[(size_t)k * (LE_NSTAGES + 1)] : nullptr);
-    LE_TRY(hipStreamEndCapture(c->stream, &g));
-    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
-      (void)hipGraphDestroy(g);
-      return LE_EDEVICE;
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      for (int64_t k = 0; k < count; ++k) enqueue_step(c, c->d_args + k, nullptr);
+      e = hipStreamEndCapture(c->stream, &g);
     }
-    it = c->graphs.emplace(key, std::make_pair(g, ge)).first;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      // leave capture mode, drop the partial graph and launch directly
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(c->stream, &cs) == hipSuccess &&
+          cs != hipStreamCaptureStatusNone) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(c->stream, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+      }
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      fail_hip(e, "graph capture (falling back to direct launches)", __LINE__);
+      c->use_graphs = false;
+    } else {
+      it = c->graphs.emplace(key, std::make_pair(g, ge)).first;
+    }
   }
-  LE_TRY(hipGraphLaunch(it->second.second, c->stream));
+  if (it != c->graphs.end()) {
+    LE_TRY(hipGraphLaunch(it->second.second, c->stream));
+    return LE_OK;
+  }
+  for (int64_t k = 0; k < count; ++k)
+    enqueue_step(c, c->d_args + k,
+                 c->profiling ? &c->events[(size_t)k * (LE_NSTAGES + 1)] : nullptr);
   return LE_OK;
 }
 
@@ -325,6 +350,8 @@ int alloc(void** p, size_t bytes) {
 }  // namespace
 
 extern "C" {
+
+const char* le_last_error(void) { return g_last_error; }
 
 const char* le_strerror(int code) {
   switch (code) {
@@ -367,6 +394,8 @@ int le_create(const le_params* p, const double* phi0, const double* omega0, le_c
   g.eta = p->eta;
   g.rho = p->rho;
   g.dt = p->dt;
+  g.kx0 = 6.283185307179586476925286766559 / p->lx;
+  g.ky0 = 6.283185307179586476925286766559 / p->ly;
   c->inertial = p->rho > 0.0;
   {
     const char* e = std::getenv("LE_GRAPHS");

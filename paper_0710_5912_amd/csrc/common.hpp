@@ -13,6 +13,7 @@ struct Geo {
   int pad0;
   double lx, ly, dx, dy, c;   // c = lx / ly, the sawtooth jump
   double A, B, kappa, M, eta, rho, dt;
+  double kx0, ky0;   // 2 pi / lx, 2 pi / ly (wavenumber quanta)
 };
 
 // Per-step values computed by the host shear clock.

@@ -19,8 +19,15 @@ namespace le {
 
 // Launch shapes.  E: values per thread of a transform (P = L/E threads per
 // transform); G: rows per block; CW: adjacent columns per block.
-constexpr int row_elems(int L) { return L >= 1024 ? 16 : (L >= 8 ? 8 : L); }
-constexpr int col_elems(int L) { return L >= 2048 ? 16 : (L >= 16 ? 8 : L); }
+constexpr int row_elems(int L) { return L >= 8 ? 8 : L; }
+constexpr int col_elems(int L) { return L >= 8 ? 8 : L; }
+
+// Occupancy hint for the stage kernels (waves per SIMD the register
+// allocation must allow).
+#define LE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(2)))
+// Keep the scheduler from interleaving consecutive unrolled iterations (which
+// would hoist every iteration's loads and blow the register budget).
+#define LE_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 template <int L>
@@ -88,7 +95,20 @@ __device__ __forceinline__ void load_row_spec(const c2<T>* __restrict__ X, c2<T>
 struct Modes {
   double qx, qy, P;
 };
+// Step kernels: wavenumbers as multiples of the quanta 2 pi / l.
 __device__ __forceinline__ Modes modes(const Geo& g, int m, int n) {
+  const int ms = (m >= g.nx / 2) ? m - g.nx : m;
+  const int ns = (n >= g.ny / 2) ? n - g.ny : n;
+  Modes r;
+  r.qx = g.kx0 * (double)ms;
+  r.qy = g.ky0 * (double)ns;
+  r.P = (m == g.nx / 2 || n == g.ny / 2) ? 0.0 : r.qx * r.qy;
+  return r;
+}
+
+// Observables: wavenumbers formed as (2 pi m) / l, the exact rounding the
+// shell decision is specified with.
+__device__ __forceinline__ Modes modes_exact(const Geo& g, int m, int n) {
   const int ms = (m >= g.nx / 2) ? m - g.nx : m;
   const int ns = (n >= g.ny / 2) ? n - g.ny : n;
   const double twopi = 6.283185307179586476925286766559;
@@ -97,6 +117,16 @@ __device__ __forceinline__ Modes modes(const Geo& g, int m, int n) {
   r.qy = twopi * (double)ns / g.ly;
   r.P = (m == g.nx / 2 || n == g.ny / 2) ? 0.0 : r.qx * r.qy;
   return r;
+}
+
+// 1/x to full double precision: hardware estimate plus two Newton steps
+// (x != 0; the callers mask the q = 0 mode).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
 }
 
 // lambda(q; s) = D + Delta, D = -((1 + s^2) qx^2 + qy^2), Delta = 2 s qx qy:
@@ -110,7 +140,7 @@ __device__ __forceinline__ double lambda_of(const Modes& q, double s) {
 
 // Forward row transform of one real field (used at set-up and for observables).
 template <typename T, int L>
-__global__ __launch_bounds__(RowCfg<L>::THREADS) void k_row_r2c(
+__global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_row_r2c(
     const T* __restrict__ x, c2<T>* __restrict__ X, int ny, const c2<T>* __restrict__ tw) {
   using C = RowCfg<L>;
   __shared__ c2<T> lds[C::G * L];
@@ -127,7 +157,7 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) void k_row_r2c(
 
 // Inverse row transform; blockIdx.y selects the field (X0 -> x0, X1 -> x1).
 template <typename T, int L>
-__global__ __launch_bounds__(RowCfg<L>::THREADS) void k_row_c2r(
+__global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_row_c2r(
     const c2<T>* __restrict__ X0, T* __restrict__ x0, const c2<T>* __restrict__ X1,
     T* __restrict__ x1, int ny, const c2<T>* __restrict__ tw) {
   using C = RowCfg<L>;
@@ -208,7 +238,7 @@ __device__ __forceinline__ void dys_pair(const T* f, int jp, int jm, int i, int 
 //   2: omega_h = omega - dt [Dys psi Dx omega - Dx psi Dys omega]  (inertial)
 // followed by the forward row transform of that field.
 template <typename T, int L>
-__global__ __launch_bounds__(RowCfg<L>::THREADS) void k_advect(
+__global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_advect(
     const T* __restrict__ phi, const T* __restrict__ om, const T* __restrict__ psi,
     c2<T>* __restrict__ phih, c2<T>* __restrict__ fh, c2<T>* __restrict__ omh,
     const StepArgs* __restrict__ sa, Geo geo, const c2<T>* __restrict__ tw) {
@@ -244,6 +274,7 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) void k_advect(
       dys_pair(a, jp, jm, i, NX, st, ay0, ay1);
       const T a0 = a[(size_t)j * NX + i], a1 = a[(size_t)j * NX + i + 1];
       v[q] = {a0 - dt * (sy0 * ax0 - sx0 * ay0), a1 - dt * (sy1 * ax1 - sx1 * ay1)};
+      LE_SCHED_FENCE();
     }
   }
   row_r2c<T, L, C::E>(v, lds + g * L, tw, t);
@@ -255,7 +286,7 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) void k_advect(
 // rows j0-1 .. j0+G (into LDS), then g = -[Dx phi Dys mu - Dys phi Dx mu] * inv
 // (inv = 1/rho, or 1/eta on the Stokes branch) and its forward row transform.
 template <typename T, int L>
-__global__ __launch_bounds__(MuCfg<L>::THREADS) void k_mu_source(
+__global__ __launch_bounds__(MuCfg<L>::THREADS) LE_OCCUPANCY void k_mu_source(
     const T* __restrict__ phi, c2<T>* __restrict__ gh, const StepArgs* __restrict__ sa,
     Geo geo, double inv_coef, const c2<T>* __restrict__ tw) {
   using C = MuCfg<L>;
@@ -321,6 +352,7 @@ __global__ __launch_bounds__(MuCfg<L>::THREADS) void k_mu_source(
       }
     }
     v[q] = {neg_inv * (px0 * my0 - py0 * mx0), neg_inv * (px1 * my1 - py1 * mx1)};
+    LE_SCHED_FENCE();
   }
   __syncthreads();  // mu is dead; its LDS becomes the transform's
   row_r2c<T, L, C::E>(v, lds + g * L, tw, t);
@@ -364,7 +396,7 @@ __global__ void k_remap_real(const T* __restrict__ in, T* __restrict__ out, int 
 //  COL_STOKES  g -> psi'                  zero-Reynolds solve
 //  COL_POISSON omega -> psi               set-up: psi from omega
 template <typename T, int L, int MODE>
-__global__ __launch_bounds__(ColCfg<L>::THREADS) void k_column(
+__global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY void k_column(
     const c2<T>* __restrict__ in0, const c2<T>* __restrict__ in1, c2<T>* __restrict__ out0,
     c2<T>* __restrict__ out1, const StepArgs* __restrict__ sa, Geo geo,
     const c2<T>* __restrict__ tw) {
@@ -389,6 +421,7 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_column(
   }
   const double s = sa->s;
   const double inv_ny = 1.0 / (double)geo.ny;
+  const double dtnu = geo.rho > 0.0 ? geo.dt * (geo.eta / geo.rho) : 0.0;
 #pragma unroll
   for (int q = 0; q < C::E; ++q) {
     const int n = t + q * C::P;
@@ -400,7 +433,7 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_column(
       // phi' = phi_h + (1 + D4/2)^-1 (-A D2 phi_h - D4 phi_h + B D2 f)
       const double d2 = geo.dt * geo.M * lam;
       const double d4 = geo.dt * geo.kappa * geo.M * lam * lam;
-      const double den = 1.0 / (1.0 + 0.5 * d4);
+      const double den = rcp64(1.0 + 0.5 * d4);
       const double h1 = (1.0 + (-geo.A * d2 - d4) * den) * inv_ny;
       const double h2 = (geo.B * d2 * den) * inv_ny;
       const double a1x = (double)v1[q].x, a1y = (double)v1[q].y;
@@ -408,12 +441,11 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_column(
     } else if constexpr (MODE == COL_FLOW) {
       // omega' = omega_h + (1 - C/2)^-1 (C omega_h + dt g), C = dt nu lambda;
       // psi' = -omega' / lambda; the q = 0 mode of both is zero.
-      const double nu = geo.eta / geo.rho;
-      const double ct = geo.dt * nu * lam;
-      const double den = 1.0 / (1.0 - 0.5 * ct);
+      const double ct = dtnu * lam;
+      const double den = rcp64(1.0 - 0.5 * ct);
       double b1 = (1.0 + ct * den) * inv_ny;
       double b2 = (geo.dt * den) * inv_ny;
-      double il = zero ? 0.0 : -1.0 / lam;
+      double il = zero ? 0.0 : -rcp64(lam);
       if (zero) { b1 = 0.0; b2 = 0.0; }
       const double a1x = (double)v1[q].x, a1y = (double)v1[q].y;
       const double ox = b1 * a0x + b2 * a1x, oy = b1 * a0y + b2 * a1y;
@@ -421,13 +453,14 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_column(
       v1[q] = {T(il * ox), T(il * oy)};
     } else if constexpr (MODE == COL_STOKES) {
       // psi' = g / lambda^2
-      const double p = zero ? 0.0 : inv_ny / (lam * lam);
+      const double p = zero ? 0.0 : inv_ny * rcp64(lam * lam);
       v0[q] = {T(p * a0x), T(p * a0y)};
     } else {
       // psi = -omega / lambda
-      const double p = zero ? 0.0 : -inv_ny / lam;
+      const double p = zero ? 0.0 : -inv_ny * rcp64(lam);
       v0[q] = {T(p * a0x), T(p * a0y)};
     }
+    LE_SCHED_FENCE();
   }
   __syncthreads();
   fft_group<T, L, C::E, +1>(v0, lds + c, C::CW, tw, t);
@@ -453,7 +486,7 @@ __device__ __forceinline__ void obs_mode(const Geo& g, int m, int n, double s, d
                                          double& xx, double& xy, double& yy, double& qmod,
                                          int& bin) {
 #pragma clang fp contract(off)
-  const Modes md = modes(g, m, n);
+  const Modes md = modes_exact(g, m, n);
   xx = md.qx * md.qx;
   xy = md.P - s * xx;
   yy = md.qy * md.qy - 2.0 * s * md.P + s * s * xx;
@@ -465,7 +498,7 @@ __device__ __forceinline__ void obs_mode(const Geo& g, int m, int n, double s, d
 // Spectral observables: column transforms of phi (and psi), per-block fixed
 // order partial sums of OBS_* and of the S(k) shells.
 template <typename T, int L>
-__global__ __launch_bounds__(ColCfg<L>::THREADS) void k_obs_spectral(
+__global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY void k_obs_spectral(
     const c2<T>* __restrict__ phih, const c2<T>* __restrict__ psih, double* __restrict__ part,
     double* __restrict__ bins, double* __restrict__ counts, const StepArgs* __restrict__ sa,
     Geo geo, const c2<T>* __restrict__ tw) {
@@ -532,6 +565,7 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) void k_obs_spectral(
     bidx[e] = inb ? bin : 0;
     bval[e] = inb ? wS : 0.0;
     bwgt[e] = inb ? wgt : 0.0;
+    LE_SCHED_FENCE();
   }
   // fixed-order block reduction of each sum
   for (int k = 0; k < OBS_NSPEC; ++k) {

@@ -18,7 +18,7 @@ LE_OK, LE_EINVAL, LE_ENOMEM, LE_EDEVICE, LE_ENONFINITE, LE_ESTATE = 0, -1, -2, -
 LE_FP64, LE_FP32 = 0, 1
 
 SYMBOLS = ("le_create", "le_step", "le_observables", "le_destroy", "le_get_state",
-           "le_set_state", "le_strerror", "le_profile", "le_stage_times")
+           "le_set_state", "le_strerror", "le_profile", "le_stage_times", "le_last_error")
 LE_NSTAGES = 6
 STAGES = ("row_inv_flow", "advect", "column_ch", "row_inv_phi", "mu_source", "column_flow")
 
@@ -43,7 +43,10 @@ class LeObs(C.Structure):
 
 class LeError(RuntimeError):
     def __init__(self, code: int, what: str):
-        super().__init__(f"{what}: {strerror(code)} ({code})")
+        msg = f"{what}: {strerror(code)} ({code})"
+        if code == LE_EDEVICE:
+            msg += f" [{lib().le_last_error().decode()}]"
+        super().__init__(msg)
         self.code = code
 
 
@@ -76,6 +79,8 @@ def lib():
         L.le_profile.restype = C.c_int
         L.le_stage_times.argtypes = [C.c_void_p, _DP, C.POINTER(C.c_int64), C.c_int32]
         L.le_stage_times.restype = C.c_int
+        L.le_last_error.argtypes = []
+        L.le_last_error.restype = C.c_char_p
         L.le_strerror.argtypes = [C.c_int]
         L.le_strerror.restype = C.c_char_p
         _LIB = L
