@@ -155,6 +155,33 @@ enum { LE_NSTAGES = 6 };
 int le_profile(le_ctx* c, int enable);
 int le_stage_times(le_ctx* c, double* ms, int64_t* launches, int32_t cap);
 
+/*
+ * Batched runs.  Many independent runs (each with its own grid, shear rate,
+ * density, precision and initial state) advance together: every stage of a
+ * step is one launch per group of runs sharing (nx, ny, precision, rho > 0),
+ * and chunks of steps are replayed from captured HIP graphs.  Each run's
+ * result is the one le_create/le_step would give for it alone.
+ *
+ * le_batch_create: n >= 1 runs; ps[i], phi0s[i] as for le_create; omega0s may
+ *   be NULL (all zero) or hold NULL entries.  Every ps[i].stream must be equal
+ *   (the batch runs on one stream).  Errors as le_create.
+ * le_batch_step: advance every run by nsteps (one common step counter).
+ * le_batch_observables / le_batch_get_state: as le_observables /
+ *   le_get_state for run index 0 <= run < n (LE_EINVAL otherwise).
+ * le_batch_profile / le_batch_stage_times: as le_profile / le_stage_times,
+ *   each stage timed across all runs.
+ */
+typedef struct le_batch le_batch;
+int le_batch_create(int32_t n, const le_params* ps, const double* const* phi0s,
+                    const double* const* omega0s, le_batch** out);
+int le_batch_step(le_batch* b, int64_t nsteps);
+int le_batch_observables(le_batch* b, int32_t run, le_obs* o, double* Sk, int32_t sk_cap);
+int le_batch_get_state(le_batch* b, int32_t run, double* phi, double* omega, double* psi,
+                       int64_t* step, int64_t* wraps);
+int le_batch_profile(le_batch* b, int enable);
+int le_batch_stage_times(le_batch* b, double* ms, int64_t* launches, int32_t cap);
+void le_batch_destroy(le_batch* b);  /* NULL-safe */
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,7 +1,16 @@
-// api.hip -- the C ABI of include/le.h: context, device buffers, shear clock,
-// step schedule and observables.
+// api.hip -- the C ABI of include/le.h.
+//
+// One engine serves both entry families: a single run (le_ctx) is an engine
+// with one run, a batch (le_batch) an engine with many.  Runs are grouped in
+// classes of equal (nx, ny, precision, inertial); each stage of a step is one
+// launch per class covering all of its runs (grid z = run), so a step of a
+// 96-run batch is a handful of launches, and chunks of steps are captured
+// once into a HIP graph and replayed.  The shear clock of every run is kept
+// on the host; the per-step strain offsets reach the kernels through a
+// device table [step][run] refreshed once per chunk.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -18,11 +27,12 @@ using namespace le;
 
 namespace {
 
-constexpr int kArgsCap = 4096;   // steps per host chunk (one StepArgs each)
-constexpr int kRealBlocks = 256;  // blocks of the real-space reduction
-constexpr int kProfChunk = 256;   // steps per chunk while stage timing is on
+constexpr int64_t kChunkCap = 1024;  // steps per host chunk
+constexpr int64_t kProfChunk = 256;  // steps per chunk while stage timing is on
+constexpr int kRealBlocks = 256;     // blocks of the real-space reduction
+constexpr int64_t kGraphMin = 8;     // shortest chunk worth capturing
+constexpr size_t kGraphCacheMax = 4;
 
-// Text of the last failing HIP call on this thread (le_last_error).
 thread_local char g_last_error[256] = "";
 
 int fail_hip(hipError_t e, const char* what, int line) {
@@ -31,10 +41,16 @@ int fail_hip(hipError_t e, const char* what, int line) {
   return LE_EDEVICE;
 }
 
-#define LE_TRY(expr)                                             \
-  do {                                                           \
-    const hipError_t le_e_ = (expr);                             \
+#define LE_TRY(expr)                                                  \
+  do {                                                                \
+    const hipError_t le_e_ = (expr);                                  \
     if (le_e_ != hipSuccess) return fail_hip(le_e_, #expr, __LINE__); \
+  } while (0)
+
+#define LE_RC(expr)            \
+  do {                         \
+    const int le_rc_ = (expr); \
+    if (le_rc_) return le_rc_; \
   } while (0)
 
 // ---- shear clock (section "Numerical method": the sawtooth s(t)) --------
@@ -54,73 +70,6 @@ double strain_offset(const le_params& p, int64_t n) {
 
 bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
-
-}  // namespace
-
-struct le_ctx {
-  le_params p;
-  Geo geo;
-  Ops ops;
-  size_t tsize;         // bytes per real value (4 or 8)
-  size_t n_real;        // nx * ny
-  size_t n_spec;        // ny * (nx/2 + 1) complex values
-  bool inertial;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int64_t step = 0, wraps = 0;
-  // device buffers (storage type T)
-  void* phi = nullptr;   // real, state
-  void* om_s = nullptr;  // row spectrum of omega, state (inertial)
-  void* ps_s = nullptr;  // row spectrum of psi, state
-  void* om_r = nullptr;  // real scratch
-  void* ps_r = nullptr;  // real scratch
-  void* phih = nullptr;  // row spectra, scratch
-  void* fh = nullptr;
-  void* omh = nullptr;
-  void* gh = nullptr;
-  void* phin = nullptr;
-  void* twx = nullptr;   // exp(-2 pi i k / nx), k < nx
-  void* twy = nullptr;   // exp(-2 pi i k / (2 ny)), k < 2 ny
-  StepArgs* d_args = nullptr;
-  StepArgs* h_args = nullptr;  // pinned
-  double* d_spart = nullptr;
-  double* d_rpart = nullptr;
-  double* d_bins = nullptr;
-  double* d_counts = nullptr;
-  double* d_out = nullptr;
-  double* h_out = nullptr;     // pinned
-  int nsblk = 0, nbins = 0;
-  void* h_stage = nullptr;     // pinned host staging for up/downloads
-  // captured step sequences, keyed by their length in steps
-  bool use_graphs = true;
-  std::map<int64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
-  // stage timing (le_profile)
-  bool profiling = false;
-  std::vector<hipEvent_t> events;   // kProfChunk * (LE_NSTAGES + 1)
-  double stage_ms[LE_NSTAGES] = {0};
-  int64_t stage_n[LE_NSTAGES] = {0};
-};
-
-namespace {
-
-void release(le_ctx* c) {
-  void* dev[] = {c->phi, c->om_s, c->ps_s, c->om_r, c->ps_r, c->phih, c->fh, c->omh,
-                 c->gh, c->phin, c->twx, c->twy, c->d_args, c->d_spart, c->d_rpart,
-                 c->d_bins, c->d_counts, c->d_out};
-  for (void* d : dev)
-    if (d) (void)hipFree(d);
-  if (c->h_args) (void)hipHostFree(c->h_args);
-  if (c->h_out) (void)hipHostFree(c->h_out);
-  if (c->h_stage) (void)hipHostFree(c->h_stage);
-  for (auto& kv : c->graphs) {
-    (void)hipGraphExecDestroy(kv.second.second);
-    (void)hipGraphDestroy(kv.second.first);
-  }
-  c->graphs.clear();
-  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
-  c->events.clear();
-  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
-}
 
 int validate(const le_params* p) {
   if (!p) return LE_EINVAL;
@@ -149,202 +98,608 @@ std::vector<T> twiddles(int n) {
   return tw;
 }
 
-int upload_twiddles(le_ctx* c) {
-  const int nx = c->p.nx, ny = c->p.ny;
-  if (c->p.precision == LE_FP64) {
-    auto a = twiddles<double>(nx);
-    auto b = twiddles<double>(2 * ny);
-    LE_TRY(hipMemcpy(c->twx, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice));
-    LE_TRY(hipMemcpy(c->twy, b.data(), b.size() * sizeof(double), hipMemcpyHostToDevice));
-  } else {
-    auto a = twiddles<float>(nx);
-    auto b = twiddles<float>(2 * ny);
-    LE_TRY(hipMemcpy(c->twx, a.data(), a.size() * sizeof(float), hipMemcpyHostToDevice));
-    LE_TRY(hipMemcpy(c->twy, b.data(), b.size() * sizeof(float), hipMemcpyHostToDevice));
-  }
-  return LE_OK;
-}
+struct RunHost {
+  le_params p;
+  Geo g;
+  bool inertial;
+  size_t tsize, n_real, n_spec;
+  void* buf[NBUF];
+  void* twx = nullptr;
+  void* twy = nullptr;
+  int64_t wraps = 0;   // wrap count the stored fields are expressed in
+  int cls = 0;         // class index
+  int internal = 0;    // position in the class-grouped order
+};
 
-// host doubles -> device storage type, through the pinned staging buffer
-int upload_real(le_ctx* c, const double* src, void* dst) {
-  if (c->tsize == sizeof(double)) {
-    std::memcpy(c->h_stage, src, c->n_real * sizeof(double));
-  } else {
-    float* s = static_cast<float*>(c->h_stage);
-    for (size_t i = 0; i < c->n_real; ++i) s[i] = (float)src[i];
-  }
-  LE_TRY(hipMemcpyAsync(dst, c->h_stage, c->n_real * c->tsize, hipMemcpyHostToDevice, c->stream));
-  LE_TRY(hipStreamSynchronize(c->stream));
-  return LE_OK;
-}
+struct Class {
+  int nx, ny, prec;
+  bool inertial;
+  Ops ops;
+  std::vector<int> members;  // run ids
+  int first = 0;             // internal index of members[0]
+};
 
-int download_real(le_ctx* c, const void* src, double* dst) {
-  LE_TRY(hipMemcpyAsync(c->h_stage, src, c->n_real * c->tsize, hipMemcpyDeviceToHost, c->stream));
-  LE_TRY(hipStreamSynchronize(c->stream));
-  if (c->tsize == sizeof(double)) {
-    std::memcpy(dst, c->h_stage, c->n_real * sizeof(double));
-  } else {
-    const float* s = static_cast<const float*>(c->h_stage);
-    for (size_t i = 0; i < c->n_real; ++i) dst[i] = (double)s[i];
-  }
-  return LE_OK;
-}
+}  // namespace
 
-// One StepArgs (s at step n) into d_args[0], for set-up and observables.
-int set_args0(le_ctx* c, int64_t n) {
-  c->h_args[0].s = strain_offset(c->p, n);
-  c->h_args[0].pad = 0.0;
-  LE_TRY(hipMemcpyAsync(c->d_args, c->h_args, sizeof(StepArgs), hipMemcpyHostToDevice, c->stream));
-  return LE_OK;
-}
+struct le_ctx {
+  std::vector<RunHost> runs;
+  std::vector<Class> classes;
+  int nruns = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int64_t step = 0;
+  Run* d_desc = nullptr;         // descriptors, internal order
+  StepArgs* d_args = nullptr;    // [kChunkCap][nruns]
+  StepArgs* h_args = nullptr;    // pinned
+  // observables scratch (sized for the largest run)
+  double* d_spart = nullptr;
+  double* d_rpart = nullptr;
+  double* d_bins = nullptr;
+  double* d_counts = nullptr;
+  double* d_out = nullptr;
+  double* h_out = nullptr;
+  int nsblk_max = 0, nbins_max = 0;
+  void* h_stage = nullptr;       // pinned staging, largest run
+  size_t stage_bytes = 0;
+  bool use_graphs = true;
+  std::map<int64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  bool profiling = false;
+  std::vector<hipEvent_t> events;  // kProfChunk * (LE_NSTAGES + 1)
+  double stage_ms[LE_NSTAGES] = {0};
+  int64_t stage_n[LE_NSTAGES] = {0};
+};
 
-// psi from the flow constraint at the current step (Poisson from omega, or
-// the Stokes solve from phi); omega's row spectrum must be current.
-int solve_psi(le_ctx* c) {
-  int rc = set_args0(c, c->step);
-  if (rc) return rc;
-  if (c->inertial) {
-    c->ops.column(COL_POISSON, c->om_s, nullptr, c->ps_s, nullptr, c->d_args, c->geo, c->twy,
-                  c->stream);
-  } else {
-    c->ops.mu_source(c->phi, c->gh, c->d_args, c->geo, 1.0 / c->p.eta, c->twx, c->stream);
-    c->ops.column(COL_STOKES, c->gh, nullptr, c->ps_s, nullptr, c->d_args, c->geo, c->twy,
-                  c->stream);
-  }
-  LE_TRY(hipGetLastError());
-  return LE_OK;
-}
+// A batch handle owns an engine of many runs.
+struct le_batch {
+  le_ctx* e;
+};
 
-// The stages of one step n -> n+1 at s = sa->s.  ev: LE_NSTAGES + 1 events
-// recorded around the stages when timing, else nullptr.
-void enqueue_step(le_ctx* c, const StepArgs* sa, hipEvent_t* ev) {
-  const Ops& o = c->ops;
-  auto mark = [&](int k) {
-    if (ev) (void)hipEventRecord(ev[k], c->stream);
-  };
-  mark(0);
-  if (c->inertial) {
-    o.row_c2r(c->om_s, c->om_r, c->ps_s, c->ps_r, c->geo, c->twx, c->stream);
-  } else {
-    o.row_c2r(c->ps_s, c->ps_r, nullptr, nullptr, c->geo, c->twx, c->stream);
-  }
-  mark(1);
-  o.advect(c->phi, c->om_r, c->ps_r, c->phih, c->fh, c->omh, sa, c->geo, c->twx, c->inertial,
-           c->stream);
-  mark(2);
-  o.column(COL_CH, c->phih, c->fh, c->phin, nullptr, sa, c->geo, c->twy, c->stream);
-  mark(3);
-  o.row_c2r(c->phin, c->phi, nullptr, nullptr, c->geo, c->twx, c->stream);
-  mark(4);
-  if (c->inertial) {
-    o.mu_source(c->phi, c->gh, sa, c->geo, 1.0 / c->p.rho, c->twx, c->stream);
-    mark(5);
-    o.column(COL_FLOW, c->omh, c->gh, c->om_s, c->ps_s, sa, c->geo, c->twy, c->stream);
-  } else {
-    o.mu_source(c->phi, c->gh, sa, c->geo, 1.0 / c->p.eta, c->twx, c->stream);
-    mark(5);
-    o.column(COL_STOKES, c->gh, nullptr, c->ps_s, nullptr, sa, c->geo, c->twy, c->stream);
-  }
-  mark(6);
-}
+namespace {
 
-// Accumulate the stage times of `count` profiled steps (stream drained).
-void harvest_times(le_ctx* c, int64_t count) {
-  for (int64_t k = 0; k < count; ++k) {
-    hipEvent_t* ev = &c->events[(size_t)k * (LE_NSTAGES + 1)];
-    for (int s = 0; s < LE_NSTAGES; ++s) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[s], ev[s + 1]) == hipSuccess) {
-        c->stage_ms[s] += ms;
-        c->stage_n[s] += 1;
-      }
-    }
-  }
-}
+using Engine = le_ctx;
 
-// Enqueue `count` steps reading their StepArgs from d_args[0 .. count).  Runs
-// of at least kGraphMin steps are captured once into a HIP graph per length
-// and replayed; the per-step strain offsets stay in device memory, so one
-// graph serves every chunk of that length.
-constexpr int64_t kGraphMin = 8;
-constexpr size_t kGraphCacheMax = 4;
-int enqueue_steps(le_ctx* c, int64_t count) {
-  // Stage timing brackets direct launches with events (event-record nodes
-  // are not taken under capture here), so timed chunks are never captured.
-  const int64_t key = count;
-  const bool graph_ok = c->use_graphs && count >= kGraphMin && !c->profiling;
-  auto it = graph_ok ? c->graphs.find(key) : c->graphs.end();
-  if (graph_ok && it == c->graphs.end()) {
-    if (c->graphs.size() >= kGraphCacheMax) {
-      auto old = c->graphs.begin();
-      (void)hipGraphExecDestroy(old->second.second);
-      (void)hipGraphDestroy(old->second.first);
-      c->graphs.erase(old);
-    }
-    hipGraph_t g = nullptr;
-    hipGraphExec_t ge = nullptr;
-    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
-    if (e == hipSuccess) {
-      for (int64_t k = 0; k < count; ++k) enqueue_step(c, c->d_args + k, nullptr);
-      e = hipStreamEndCapture(c->stream, &g);
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      // leave capture mode, drop the partial graph and launch directly
-      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-      if (hipStreamIsCapturing(c->stream, &cs) == hipSuccess &&
-          cs != hipStreamCaptureStatusNone) {
-        hipGraph_t junk = nullptr;
-        (void)hipStreamEndCapture(c->stream, &junk);
-        if (junk) (void)hipGraphDestroy(junk);
-      }
-      if (g) (void)hipGraphDestroy(g);
-      (void)hipGetLastError();
-      fail_hip(e, "graph capture (falling back to direct launches)", __LINE__);
-      c->use_graphs = false;
-    } else {
-      it = c->graphs.emplace(key, std::make_pair(g, ge)).first;
-    }
-  }
-  if (it != c->graphs.end()) {
-    LE_TRY(hipGraphLaunch(it->second.second, c->stream));
-    return LE_OK;
-  }
-  for (int64_t k = 0; k < count; ++k)
-    enqueue_step(c, c->d_args + k,
-                 c->profiling ? &c->events[(size_t)k * (LE_NSTAGES + 1)] : nullptr);
-  return LE_OK;
-}
+const Run* desc(const Engine* e, const RunHost& r) { return e->d_desc + r.internal; }
 
-// Remap the state after the strain offset jumped by -dk * c.
-void enqueue_remap(le_ctx* c, int64_t dk) {
-  const int dkr = (int)((dk * (int64_t)c->geo.r) % c->p.nx);
-  c->ops.remap_real(c->phi, c->om_r, c->geo, dkr, c->stream);
-  std::swap(c->phi, c->om_r);
-  c->ops.remap_spec(c->ps_s, c->geo, dkr, c->twx, c->stream);
-  if (c->inertial) c->ops.remap_spec(c->om_s, c->geo, dkr, c->twx, c->stream);
-}
-
-// Sums of the observables into h_out (OBS_NTOTAL values + 2 nbins).
-int reduce_observables(le_ctx* c) {
-  int rc = set_args0(c, c->step);
-  if (rc) return rc;
-  c->ops.row_r2c(c->phi, c->phih, c->geo, c->twx, c->stream);
-  c->ops.obs_spectral(c->phih, c->inertial ? c->ps_s : nullptr, c->d_spart, c->d_bins,
-                      c->d_counts, c->d_args, c->geo, c->twy, c->stream);
-  c->ops.obs_real(c->phi, c->n_real, c->d_rpart, kRealBlocks, c->stream);
-  launch_obs_final(c->d_spart, c->nsblk, c->d_rpart, kRealBlocks, c->d_bins, c->d_counts,
-                   c->nbins, c->d_out, c->stream);
-  LE_TRY(hipGetLastError());
-  const size_t nout = OBS_NTOTAL + 2 * (size_t)c->nbins;
-  LE_TRY(hipMemcpyAsync(c->h_out, c->d_out, nout * sizeof(double), hipMemcpyDeviceToHost,
-                        c->stream));
-  LE_TRY(hipStreamSynchronize(c->stream));
-  return LE_OK;
+void release(Engine* e) {
+  for (auto& kv : e->graphs) {
+    (void)hipGraphExecDestroy(kv.second.second);
+    (void)hipGraphDestroy(kv.second.first);
+  }
+  e->graphs.clear();
+  for (hipEvent_t ev : e->events)
+    if (ev) (void)hipEventDestroy(ev);
+  e->events.clear();
+  for (auto& r : e->runs) {
+    for (void*& b : r.buf)
+      if (b) (void)hipFree(b);
+    if (r.twx) (void)hipFree(r.twx);
+    if (r.twy) (void)hipFree(r.twy);
+  }
+  void* dev[] = {e->d_desc, e->d_args, e->d_spart, e->d_rpart, e->d_bins, e->d_counts, e->d_out};
+  for (void* d : dev)
+    if (d) (void)hipFree(d);
+  if (e->h_args) (void)hipHostFree(e->h_args);
+  if (e->h_out) (void)hipHostFree(e->h_out);
+  if (e->h_stage) (void)hipHostFree(e->h_stage);
+  if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
 }
 
 int alloc(void** p, size_t bytes) {
   return hipMalloc(p, bytes) == hipSuccess ? LE_OK : LE_ENOMEM;
+}
+
+int upload_real(Engine* e, const RunHost& r, const double* src, int b) {
+  if (r.tsize == sizeof(double)) {
+    std::memcpy(e->h_stage, src, r.n_real * sizeof(double));
+  } else {
+    float* s = static_cast<float*>(e->h_stage);
+    for (size_t i = 0; i < r.n_real; ++i) s[i] = (float)src[i];
+  }
+  LE_TRY(hipMemcpyAsync(r.buf[b], e->h_stage, r.n_real * r.tsize, hipMemcpyHostToDevice,
+                        e->stream));
+  LE_TRY(hipStreamSynchronize(e->stream));
+  return LE_OK;
+}
+
+int download_real(Engine* e, const RunHost& r, int b, double* dst) {
+  LE_TRY(hipMemcpyAsync(e->h_stage, r.buf[b], r.n_real * r.tsize, hipMemcpyDeviceToHost,
+                        e->stream));
+  LE_TRY(hipStreamSynchronize(e->stream));
+  if (r.tsize == sizeof(double)) {
+    std::memcpy(dst, e->h_stage, r.n_real * sizeof(double));
+  } else {
+    const float* s = static_cast<const float*>(e->h_stage);
+    for (size_t i = 0; i < r.n_real; ++i) dst[i] = (double)s[i];
+  }
+  return LE_OK;
+}
+
+// StepArgs of run r at step n into the table slot d_args[r.internal].
+int set_args_one(Engine* e, const RunHost& r, int64_t n) {
+  StepArgs* h = e->h_args + r.internal;
+  h->s = strain_offset(r.p, n);
+  h->pad = 0.0;
+  LE_TRY(hipMemcpyAsync(e->d_args + r.internal, h, sizeof(StepArgs), hipMemcpyHostToDevice,
+                        e->stream));
+  return LE_OK;
+}
+
+// psi of run r from the flow constraint at the current step (Poisson from
+// omega, or the Stokes solve from phi); omega's row spectrum must be current.
+int solve_psi(Engine* e, const RunHost& r) {
+  LE_RC(set_args_one(e, r, e->step));
+  const Class& k = e->classes[r.cls];
+  const StepArgs* sa = e->d_args + r.internal;
+  if (r.inertial) {
+    k.ops.column(COL_POISSON, desc(e, r), 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S,
+                 e->stream);
+  } else {
+    k.ops.mu_source(desc(e, r), 1, r.p.ny, sa, e->stream);
+    k.ops.column(COL_STOKES, desc(e, r), 1, r.p.nx, sa, B_GH, B_GH, B_PS_S, B_PS_S, e->stream);
+  }
+  LE_TRY(hipGetLastError());
+  return LE_OK;
+}
+
+// The stages of one step for every run; sa: the step's row of the table.
+// ev: LE_NSTAGES + 1 events recorded around the stages when timing.
+void enqueue_step(Engine* e, const StepArgs* sa, hipEvent_t* ev) {
+  auto mark = [&](int k) {
+    if (ev) (void)hipEventRecord(ev[k], e->stream);
+  };
+  hipStream_t st = e->stream;
+  mark(0);
+  for (const Class& k : e->classes) {
+    const Run* d = e->d_desc + k.first;
+    const int n = (int)k.members.size();
+    if (k.inertial)
+      k.ops.row_c2r(d, n, k.ny, B_OM_S, B_OM_R, B_PS_S, B_PS_R, 2, st);
+    else
+      k.ops.row_c2r(d, n, k.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1, st);
+  }
+  mark(1);
+  for (const Class& k : e->classes)
+    k.ops.advect(e->d_desc + k.first, (int)k.members.size(), k.ny, sa + k.first, k.inertial,
+                 st);
+  mark(2);
+  for (const Class& k : e->classes)
+    k.ops.column(COL_CH, e->d_desc + k.first, (int)k.members.size(), k.nx, sa + k.first,
+                 B_PHIH, B_FH, B_PHIN, B_PHIN, st);
+  mark(3);
+  for (const Class& k : e->classes)
+    k.ops.row_c2r(e->d_desc + k.first, (int)k.members.size(), k.ny, B_PHIN, B_PHI, B_PHIN,
+                  B_PHI, 1, st);
+  mark(4);
+  for (const Class& k : e->classes)
+    k.ops.mu_source(e->d_desc + k.first, (int)k.members.size(), k.ny, sa + k.first, st);
+  mark(5);
+  for (const Class& k : e->classes) {
+    if (k.inertial)
+      k.ops.column(COL_FLOW, e->d_desc + k.first, (int)k.members.size(), k.nx, sa + k.first,
+                   B_OMH, B_GH, B_OM_S, B_PS_S, st);
+    else
+      k.ops.column(COL_STOKES, e->d_desc + k.first, (int)k.members.size(), k.nx,
+                   sa + k.first, B_GH, B_GH, B_PS_S, B_PS_S, st);
+  }
+  mark(6);
+}
+
+// Enqueue `count` steps whose StepArgs rows are d_args[0 .. count).  Chunks
+// of at least kGraphMin steps are captured once per length into a HIP graph
+// and replayed (the strain offsets stay in device memory, so one graph
+// serves every chunk of that length).  Stage timing brackets direct launches
+// with events, so timed chunks are never captured.
+int enqueue_steps(Engine* e, int64_t count) {
+  const size_t row = (size_t)e->nruns;
+  const bool graph_ok = e->use_graphs && count >= kGraphMin && !e->profiling;
+  auto it = graph_ok ? e->graphs.find(count) : e->graphs.end();
+  if (graph_ok && it == e->graphs.end()) {
+    if (e->graphs.size() >= kGraphCacheMax) {
+      auto old = e->graphs.begin();
+      (void)hipGraphExecDestroy(old->second.second);
+      (void)hipGraphDestroy(old->second.first);
+      e->graphs.erase(old);
+    }
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    hipError_t err = hipStreamBeginCapture(e->stream, hipStreamCaptureModeRelaxed);
+    if (err == hipSuccess) {
+      for (int64_t k = 0; k < count; ++k) enqueue_step(e, e->d_args + k * row, nullptr);
+      err = hipStreamEndCapture(e->stream, &g);
+    }
+    if (err == hipSuccess) err = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (err != hipSuccess) {
+      // leave capture mode, drop the partial graph and launch directly
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(e->stream, &cs) == hipSuccess &&
+          cs != hipStreamCaptureStatusNone) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(e->stream, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+      }
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      fail_hip(err, "graph capture (falling back to direct launches)", __LINE__);
+      e->use_graphs = false;
+    } else {
+      it = e->graphs.emplace(count, std::make_pair(g, ge)).first;
+    }
+  }
+  if (it != e->graphs.end()) {
+    LE_TRY(hipGraphLaunch(it->second.second, e->stream));
+    return LE_OK;
+  }
+  for (int64_t k = 0; k < count; ++k)
+    enqueue_step(e, e->d_args + k * row,
+                 e->profiling ? &e->events[(size_t)k * (LE_NSTAGES + 1)] : nullptr);
+  return LE_OK;
+}
+
+// Re-express run r's state after its strain offset jumped by -dk c.
+void enqueue_remap(Engine* e, const RunHost& r, int64_t dk) {
+  const int dkr = (int)((dk * (int64_t)r.g.r) % r.p.nx);
+  const Ops& o = e->classes[r.cls].ops;
+  o.remap_real(desc(e, r), B_PHI, B_TMP, dkr, e->stream);
+  o.copy_real(desc(e, r), B_TMP, B_PHI, e->stream);
+  o.remap_spec(desc(e, r), B_PS_S, dkr, e->stream);
+  if (r.inertial) o.remap_spec(desc(e, r), B_OM_S, dkr, e->stream);
+}
+
+void harvest_times(Engine* e, int64_t count) {
+  for (int64_t k = 0; k < count; ++k) {
+    hipEvent_t* ev = &e->events[(size_t)k * (LE_NSTAGES + 1)];
+    for (int s = 0; s < LE_NSTAGES; ++s) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[s], ev[s + 1]) == hipSuccess) {
+        e->stage_ms[s] += ms;
+        e->stage_n[s] += 1;
+      }
+    }
+  }
+}
+
+// Sums of run r's observables into h_out (OBS_NTOTAL values + 2 nbins).
+int reduce_observables(Engine* e, const RunHost& r, bool spectral) {
+  const Ops& o = e->classes[r.cls].ops;
+  const int nbins = r.p.ny / 2;
+  int nsblk = 0;
+  if (spectral) {
+    LE_RC(set_args_one(e, r, e->step));
+    o.row_r2c(desc(e, r), 1, r.p.ny, B_PHI, B_PHIH, e->stream);
+    o.obs_spectral(desc(e, r), r.p.nx, e->d_args + r.internal, B_PHIH,
+                   r.inertial ? B_PS_S : -1, e->d_spart, e->d_bins, e->d_counts, e->stream);
+    nsblk = o.obs_blocks(r.p.nx);
+  }
+  o.obs_real(desc(e, r), B_PHI, e->d_rpart, kRealBlocks, e->stream);
+  launch_obs_final(e->d_spart, nsblk, e->d_rpart, kRealBlocks, e->d_bins, e->d_counts,
+                   spectral ? nbins : 0, e->d_out, e->stream);
+  LE_TRY(hipGetLastError());
+  const size_t nout = OBS_NTOTAL + (spectral ? 2 * (size_t)nbins : 0);
+  LE_TRY(hipMemcpyAsync(e->h_out, e->d_out, nout * sizeof(double), hipMemcpyDeviceToHost,
+                        e->stream));
+  LE_TRY(hipStreamSynchronize(e->stream));
+  return LE_OK;
+}
+
+int observables_of(Engine* e, const RunHost& r, le_obs* o, double* Sk, int32_t sk_cap) {
+  LE_RC(reduce_observables(e, r, true));
+  const double* h = e->h_out;
+  const double N = (double)r.n_real;
+  const int nbins = r.p.ny / 2;
+  le_obs v;
+  std::memset(&v, 0, sizeof(v));
+  v.step = e->step;
+  v.wraps = r.wraps;
+  v.t = (double)e->step * r.p.dt;
+  v.strain = strain_total(r.p, e->step);
+  v.s = strain_offset(r.p, e->step);
+  v.mean_phi = h[OBS_SUM_PHI] / N;
+  v.phi2 = h[OBS_SUM_PHI2] / N;
+  v.Ls = h[OBS_SUM_S_NZ] > 0.0 ? h[OBS_SUM_S_OVER_Q] / h[OBS_SUM_S_NZ] : 0.0;
+  const double l = std::sqrt(r.p.kappa / r.p.A);
+  const double tot = h[OBS_SUM_S];
+  v.Dxx = tot > 0.0 ? l * h[OBS_XX] / tot : 0.0;
+  v.Dxy = tot > 0.0 ? l * h[OBS_XY] / tot : 0.0;
+  v.Dyy = tot > 0.0 ? l * h[OBS_YY] / tot : 0.0;
+  const double mid = 0.5 * (v.Dxx + v.Dyy);
+  const double rad = std::sqrt(0.25 * (v.Dxx - v.Dyy) * (v.Dxx - v.Dyy) + v.Dxy * v.Dxy);
+  const double hi = mid + rad, lo = mid - rad;
+  v.L_perp = hi > 0.0 ? 1.0 / hi : INFINITY;
+  v.L_par = lo > 0.0 ? 1.0 / lo : INFINITY;
+  v.sigma_xy = -r.p.kappa * h[OBS_XY] / N;
+  v.sigma_xy_re = r.inertial ? r.p.rho * h[OBS_RE] / (N * N) : 0.0;
+  v.nbins = nbins;
+  v.dk = 6.283185307179586476925286766559 / r.p.ly;
+  v.finite = h[OBS_NONFINITE] == 0.0 ? 1 : 0;
+  if (Sk) {
+    const int nb = sk_cap < nbins ? sk_cap : nbins;
+    for (int b = 0; b < nb; ++b) {
+      const double w = h[OBS_NTOTAL + nbins + b];
+      Sk[b] = w > 0.0 ? h[OBS_NTOTAL + b] / w : 0.0;
+    }
+  }
+  *o = v;
+  return LE_OK;
+}
+
+// Build an engine for n runs; on failure everything is released.
+int create_engine(int32_t n, const le_params* ps, const double* const* phi0s,
+                  const double* const* omega0s, Engine** out) {
+  if (!out || n < 1 || !ps || !phi0s) return LE_EINVAL;
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    LE_RC(validate(&ps[i]));
+    if (!phi0s[i]) return LE_EINVAL;
+    if (ps[i].stream != ps[0].stream) return LE_EINVAL;
+  }
+  Engine* e = new (std::nothrow) Engine();
+  if (!e) return LE_ENOMEM;
+  e->nruns = n;
+  e->runs.resize(n);
+  {
+    const char* env = std::getenv("LE_GRAPHS");
+    e->use_graphs = !(env && env[0] == '0');
+  }
+  for (int i = 0; i < n; ++i) {
+    RunHost& r = e->runs[i];
+    const le_params& p = ps[i];
+    r.p = p;
+    r.p.stream = nullptr;
+    for (void*& b : r.buf) b = nullptr;
+    Geo& g = r.g;
+    g.nx = p.nx;
+    g.ny = p.ny;
+    g.r = p.nx >= p.ny ? p.nx / p.ny : 0;
+    g.pad0 = 0;
+    g.lx = p.lx;
+    g.ly = p.ly;
+    g.dx = p.lx / p.nx;
+    g.dy = p.ly / p.ny;
+    g.c = p.lx / p.ly;
+    g.A = p.A;
+    g.B = p.B;
+    g.kappa = p.kappa;
+    g.M = p.M;
+    g.eta = p.eta;
+    g.rho = p.rho;
+    g.dt = p.dt;
+    g.kx0 = 6.283185307179586476925286766559 / p.lx;
+    g.ky0 = 6.283185307179586476925286766559 / p.ly;
+    r.inertial = p.rho > 0.0;
+    r.tsize = p.precision == LE_FP64 ? sizeof(double) : sizeof(float);
+    r.n_real = (size_t)p.nx * p.ny;
+    r.n_spec = (size_t)p.ny * (p.nx / 2 + 1);
+    r.wraps = wrap_count(r.p, 0);
+    int cls = -1;
+    for (size_t k = 0; k < e->classes.size(); ++k) {
+      const Class& c = e->classes[k];
+      if (c.nx == p.nx && c.ny == p.ny && c.prec == p.precision && c.inertial == r.inertial)
+        cls = (int)k;
+    }
+    if (cls < 0) {
+      Class c;
+      c.nx = p.nx;
+      c.ny = p.ny;
+      c.prec = p.precision;
+      c.inertial = r.inertial;
+      if (!get_ops(p.precision, p.nx, p.ny, &c.ops)) {
+        delete e;
+        return LE_EINVAL;
+      }
+      e->classes.push_back(c);
+      cls = (int)e->classes.size() - 1;
+    }
+    r.cls = cls;
+    e->classes[cls].members.push_back(i);
+  }
+  int pos = 0;
+  for (Class& c : e->classes) {
+    c.first = pos;
+    for (size_t k = 0; k < c.members.size(); ++k) e->runs[c.members[k]].internal = pos + (int)k;
+    pos += (int)c.members.size();
+  }
+
+  int dev_count = 0;
+  if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) {
+    delete e;
+    return LE_EDEVICE;
+  }
+  int rc = LE_OK;
+  if (ps[0].stream) {
+    e->stream = static_cast<hipStream_t>(ps[0].stream);
+  } else if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) == hipSuccess) {
+    e->own_stream = true;
+  } else {
+    rc = LE_EDEVICE;
+  }
+  size_t max_real = 0;
+  for (RunHost& r : e->runs) {
+    const size_t rb = r.n_real * r.tsize, sb = r.n_spec * 2 * r.tsize;
+    max_real = std::max(max_real, r.n_real);
+    const int specs[] = {B_PS_S, B_PHIH, B_FH, B_GH, B_PHIN};
+    const int reals[] = {B_PHI, B_OM_R, B_PS_R, B_TMP};
+    for (int b : specs) rc = rc ? rc : alloc(&r.buf[b], sb);
+    for (int b : reals) rc = rc ? rc : alloc(&r.buf[b], rb);
+    if (r.inertial) {
+      rc = rc ? rc : alloc(&r.buf[B_OM_S], sb);
+      rc = rc ? rc : alloc(&r.buf[B_OMH], sb);
+    }
+    rc = rc ? rc : alloc(&r.twx, (size_t)r.p.nx * 2 * r.tsize);
+    rc = rc ? rc : alloc(&r.twy, (size_t)r.p.ny * 4 * r.tsize);
+    if (!rc) {
+      if (r.tsize == sizeof(double)) {
+        auto a = twiddles<double>(r.p.nx);
+        auto b = twiddles<double>(2 * r.p.ny);
+        if (hipMemcpy(r.twx, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice) ||
+            hipMemcpy(r.twy, b.data(), b.size() * sizeof(double), hipMemcpyHostToDevice))
+          rc = LE_EDEVICE;
+      } else {
+        auto a = twiddles<float>(r.p.nx);
+        auto b = twiddles<float>(2 * r.p.ny);
+        if (hipMemcpy(r.twx, a.data(), a.size() * sizeof(float), hipMemcpyHostToDevice) ||
+            hipMemcpy(r.twy, b.data(), b.size() * sizeof(float), hipMemcpyHostToDevice))
+          rc = LE_EDEVICE;
+      }
+    }
+    const Ops& o = e->classes[r.cls].ops;
+    e->nsblk_max = std::max(e->nsblk_max, o.obs_blocks(r.p.nx));
+    e->nbins_max = std::max(e->nbins_max, r.p.ny / 2);
+  }
+  // descriptors in the class-grouped order
+  if (!rc) {
+    std::vector<Run> h(n);
+    for (const RunHost& r : e->runs) {
+      Run& d = h[r.internal];
+      d.g = r.g;
+      for (int b = 0; b < NBUF; ++b) d.buf[b] = r.buf[b];
+      d.twx = r.twx;
+      d.twy = r.twy;
+    }
+    rc = alloc((void**)&e->d_desc, sizeof(Run) * n);
+    if (!rc && hipMemcpy(e->d_desc, h.data(), sizeof(Run) * n, hipMemcpyHostToDevice))
+      rc = LE_EDEVICE;
+  }
+  const size_t nout = OBS_NTOTAL + 2 * (size_t)e->nbins_max;
+  rc = rc ? rc : alloc((void**)&e->d_args, sizeof(StepArgs) * kChunkCap * n);
+  rc = rc ? rc : alloc((void**)&e->d_spart, (size_t)e->nsblk_max * OBS_NSPEC * sizeof(double));
+  rc = rc ? rc : alloc((void**)&e->d_rpart, (size_t)kRealBlocks * 3 * sizeof(double));
+  rc = rc ? rc : alloc((void**)&e->d_bins, (size_t)e->nsblk_max * e->nbins_max * sizeof(double));
+  rc = rc ? rc : alloc((void**)&e->d_counts,
+                       (size_t)e->nsblk_max * e->nbins_max * sizeof(double));
+  rc = rc ? rc : alloc((void**)&e->d_out, nout * sizeof(double));
+  if (!rc && hipHostMalloc((void**)&e->h_args, sizeof(StepArgs) * kChunkCap * n) != hipSuccess)
+    rc = LE_ENOMEM;
+  if (!rc && hipHostMalloc((void**)&e->h_out, nout * sizeof(double)) != hipSuccess)
+    rc = LE_ENOMEM;
+  e->stage_bytes = max_real * sizeof(double);
+  if (!rc && hipHostMalloc(&e->h_stage, e->stage_bytes) != hipSuccess) rc = LE_ENOMEM;
+  // initial state: phi0, omega0 and psi0 from the flow constraint at s = 0
+  for (int i = 0; i < n && !rc; ++i) {
+    RunHost& r = e->runs[i];
+    rc = upload_real(e, r, phi0s[i], B_PHI);
+    if (!rc && r.inertial) {
+      const double* w0 = omega0s ? omega0s[i] : nullptr;
+      if (w0) {
+        rc = upload_real(e, r, w0, B_OM_R);
+      } else if (hipMemsetAsync(r.buf[B_OM_R], 0, r.n_real * r.tsize, e->stream) !=
+                 hipSuccess) {
+        rc = LE_EDEVICE;
+      }
+      if (!rc) e->classes[r.cls].ops.row_r2c(desc(e, r), 1, r.p.ny, B_OM_R, B_OM_S, e->stream);
+    }
+    if (!rc) rc = solve_psi(e, r);
+  }
+  if (!rc && hipStreamSynchronize(e->stream) != hipSuccess) rc = LE_EDEVICE;
+  if (rc) {
+    release(e);
+    delete e;
+    return rc;
+  }
+  *out = e;
+  return LE_OK;
+}
+
+int step_engine(Engine* e, int64_t nsteps) {
+  if (!e || nsteps < 0) return LE_EINVAL;
+  const size_t row = (size_t)e->nruns;
+  int64_t remaining = nsteps;
+  while (remaining > 0) {
+    const int64_t n0 = e->step;
+    const int64_t cap = e->profiling ? kProfChunk : kChunkCap;
+    int64_t count = remaining < cap ? remaining : cap;
+    // fill the table; end the chunk after the first step on which any run wraps
+    for (int64_t k = 0; k < count; ++k) {
+      bool wrap = false;
+      for (const RunHost& r : e->runs) {
+        StepArgs& a = e->h_args[(size_t)k * row + r.internal];
+        a.s = strain_offset(r.p, n0 + k);
+        a.pad = 0.0;
+        wrap = wrap || wrap_count(r.p, n0 + k + 1) != wrap_count(r.p, n0 + k);
+      }
+      if (wrap) {
+        count = k + 1;
+        break;
+      }
+    }
+    LE_TRY(hipMemcpyAsync(e->d_args, e->h_args, (size_t)count * row * sizeof(StepArgs),
+                          hipMemcpyHostToDevice, e->stream));
+    LE_RC(enqueue_steps(e, count));
+    e->step = n0 + count;
+    for (RunHost& r : e->runs) {
+      const int64_t k_new = wrap_count(r.p, e->step);
+      if (k_new != r.wraps) {
+        enqueue_remap(e, r, k_new - r.wraps);
+        r.wraps = k_new;
+      }
+    }
+    LE_TRY(hipGetLastError());
+    LE_TRY(hipStreamSynchronize(e->stream));  // h_args is reused by the next chunk
+    if (e->profiling) harvest_times(e, count);
+    remaining -= count;
+  }
+  if (nsteps > 0) {
+    for (const RunHost& r : e->runs) {
+      LE_RC(reduce_observables(e, r, false));
+      if (e->h_out[OBS_NONFINITE] != 0.0) return LE_ENONFINITE;
+    }
+  }
+  return LE_OK;
+}
+
+int get_state_of(Engine* e, int run, double* phi, double* omega, double* psi, int64_t* step,
+                 int64_t* wraps) {
+  if (!e || run < 0 || run >= e->nruns) return LE_EINVAL;
+  const RunHost& r = e->runs[run];
+  const Ops& o = e->classes[r.cls].ops;
+  if (phi) LE_RC(download_real(e, r, B_PHI, phi));
+  if (omega) {
+    if (r.inertial) {
+      o.row_c2r(desc(e, r), 1, r.p.ny, B_OM_S, B_OM_R, B_OM_S, B_OM_R, 1, e->stream);
+      LE_TRY(hipGetLastError());
+      LE_RC(download_real(e, r, B_OM_R, omega));
+    } else {
+      std::memset(omega, 0, r.n_real * sizeof(double));
+    }
+  }
+  if (psi) {
+    o.row_c2r(desc(e, r), 1, r.p.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1, e->stream);
+    LE_TRY(hipGetLastError());
+    LE_RC(download_real(e, r, B_PS_R, psi));
+  }
+  if (step) *step = e->step;
+  if (wraps) *wraps = r.wraps;
+  return LE_OK;
+}
+
+int profile_engine(Engine* e, int enable) {
+  if (!e) return LE_EINVAL;
+  if (enable && e->events.empty()) {
+    e->events.assign((size_t)kProfChunk * (LE_NSTAGES + 1), nullptr);
+    for (auto& ev : e->events) LE_TRY(hipEventCreate(&ev));
+  }
+  e->profiling = enable != 0;
+  for (int s = 0; s < LE_NSTAGES; ++s) {
+    e->stage_ms[s] = 0.0;
+    e->stage_n[s] = 0;
+  }
+  return LE_OK;
+}
+
+int stage_times_of(Engine* e, double* ms, int64_t* launches, int32_t cap) {
+  if (!e || cap < 0) return LE_EINVAL;
+  const int n = cap < LE_NSTAGES ? cap : LE_NSTAGES;
+  for (int s = 0; s < n; ++s) {
+    if (ms) ms[s] = e->stage_ms[s];
+    if (launches) launches[s] = e->stage_n[s];
+  }
+  return LE_OK;
+}
+
+void destroy_engine(Engine* e) {
+  if (!e) return;
+  if (e->stream) (void)hipStreamSynchronize(e->stream);
+  release(e);
+  delete e;
 }
 
 }  // namespace
@@ -366,281 +721,94 @@ const char* le_strerror(int code) {
 }
 
 int le_create(const le_params* p, const double* phi0, const double* omega0, le_ctx** out) {
-  if (!out || !phi0) return LE_EINVAL;
-  *out = nullptr;
-  int rc = validate(p);
-  if (rc) return rc;
-  le_ctx* c = new (std::nothrow) le_ctx();
-  if (!c) return LE_ENOMEM;
-  c->p = *p;
-  if (!get_ops(p->precision, p->nx, p->ny, &c->ops)) {
-    delete c;
-    return LE_EINVAL;
-  }
-  Geo& g = c->geo;
-  g.nx = p->nx;
-  g.ny = p->ny;
-  g.r = p->nx >= p->ny ? p->nx / p->ny : 0;
-  g.pad0 = 0;
-  g.lx = p->lx;
-  g.ly = p->ly;
-  g.dx = p->lx / p->nx;
-  g.dy = p->ly / p->ny;
-  g.c = p->lx / p->ly;
-  g.A = p->A;
-  g.B = p->B;
-  g.kappa = p->kappa;
-  g.M = p->M;
-  g.eta = p->eta;
-  g.rho = p->rho;
-  g.dt = p->dt;
-  g.kx0 = 6.283185307179586476925286766559 / p->lx;
-  g.ky0 = 6.283185307179586476925286766559 / p->ly;
-  c->inertial = p->rho > 0.0;
-  {
-    const char* e = std::getenv("LE_GRAPHS");
-    c->use_graphs = !(e && e[0] == '0');
-  }
-  c->tsize = p->precision == LE_FP64 ? sizeof(double) : sizeof(float);
-  c->n_real = (size_t)p->nx * p->ny;
-  c->n_spec = (size_t)p->ny * (p->nx / 2 + 1);
-  c->nsblk = c->ops.obs_blocks(g);
-  c->nbins = p->ny / 2;
-  c->step = 0;
-  c->wraps = wrap_count(c->p, 0);
-
-  int dev_count = 0;
-  if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) {
-    delete c;
-    return LE_EDEVICE;
-  }
-  if (p->stream) {
-    c->stream = static_cast<hipStream_t>(p->stream);
-  } else {
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete c;
-      return LE_EDEVICE;
-    }
-    c->own_stream = true;
-  }
-  const size_t rb = c->n_real * c->tsize, sb = c->n_spec * 2 * c->tsize;
-  rc = LE_OK;
-  rc = rc ? rc : alloc(&c->phi, rb);
-  rc = rc ? rc : alloc(&c->ps_s, sb);
-  rc = rc ? rc : alloc(&c->om_r, rb);
-  rc = rc ? rc : alloc(&c->ps_r, rb);
-  rc = rc ? rc : alloc(&c->phih, sb);
-  rc = rc ? rc : alloc(&c->fh, sb);
-  rc = rc ? rc : alloc(&c->gh, sb);
-  rc = rc ? rc : alloc(&c->phin, sb);
-  if (c->inertial) {
-    rc = rc ? rc : alloc(&c->om_s, sb);
-    rc = rc ? rc : alloc(&c->omh, sb);
-  }
-  rc = rc ? rc : alloc(&c->twx, (size_t)p->nx * 2 * c->tsize);
-  rc = rc ? rc : alloc(&c->twy, (size_t)p->ny * 4 * c->tsize);
-  rc = rc ? rc : alloc((void**)&c->d_args, kArgsCap * sizeof(StepArgs));
-  rc = rc ? rc : alloc((void**)&c->d_spart, (size_t)c->nsblk * OBS_NSPEC * sizeof(double));
-  rc = rc ? rc : alloc((void**)&c->d_rpart, (size_t)kRealBlocks * 3 * sizeof(double));
-  rc = rc ? rc : alloc((void**)&c->d_bins, (size_t)c->nsblk * c->nbins * sizeof(double));
-  rc = rc ? rc : alloc((void**)&c->d_counts, (size_t)c->nsblk * c->nbins * sizeof(double));
-  rc = rc ? rc : alloc((void**)&c->d_out, (OBS_NTOTAL + 2 * (size_t)c->nbins) * sizeof(double));
-  if (!rc && hipHostMalloc((void**)&c->h_args, kArgsCap * sizeof(StepArgs)) != hipSuccess)
-    rc = LE_ENOMEM;
-  if (!rc && hipHostMalloc((void**)&c->h_out, (OBS_NTOTAL + 2 * (size_t)c->nbins) *
-                                                  sizeof(double)) != hipSuccess)
-    rc = LE_ENOMEM;
-  if (!rc && hipHostMalloc(&c->h_stage, c->n_real * sizeof(double)) != hipSuccess)
-    rc = LE_ENOMEM;
-  if (!rc) rc = upload_twiddles(c);
-  if (!rc) rc = upload_real(c, phi0, c->phi);
-  if (!rc && c->inertial) {
-    if (omega0) {
-      rc = upload_real(c, omega0, c->om_r);
-    } else if (hipMemsetAsync(c->om_r, 0, rb, c->stream) != hipSuccess) {
-      rc = LE_EDEVICE;
-    }
-    if (!rc) {
-      c->ops.row_r2c(c->om_r, c->om_s, c->geo, c->twx, c->stream);
-      if (hipGetLastError() != hipSuccess) rc = LE_EDEVICE;
-    }
-  }
-  if (!rc) rc = solve_psi(c);
-  if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = LE_EDEVICE;
-  if (rc) {
-    release(c);
-    delete c;
-    return rc;
-  }
-  *out = c;
-  return LE_OK;
+  if (!out || !phi0 || !p) return LE_EINVAL;
+  const double* const phis[1] = {phi0};
+  const double* const oms[1] = {omega0};
+  return create_engine(1, p, phis, oms, out);
 }
 
-int le_step(le_ctx* c, int64_t nsteps) {
-  if (!c || nsteps < 0) return LE_EINVAL;
-  int64_t remaining = nsteps;
-  while (remaining > 0) {
-    const int64_t n0 = c->step;
-    const int64_t cap = c->profiling ? kProfChunk : kArgsCap;
-    int64_t count = remaining < cap ? remaining : cap;
-    int64_t k_end = wrap_count(c->p, n0);
-    for (int64_t k = 0; k < count; ++k) {
-      c->h_args[k].s = strain_offset(c->p, n0 + k);
-      c->h_args[k].pad = 0.0;
-      const int64_t kn = wrap_count(c->p, n0 + k + 1);
-      if (kn != k_end) {   // this step ends on a strain jump: remap after it
-        count = k + 1;
-        k_end = kn;
-        break;
-      }
-    }
-    LE_TRY(hipMemcpyAsync(c->d_args, c->h_args, (size_t)count * sizeof(StepArgs),
-                          hipMemcpyHostToDevice, c->stream));
-    int rc = enqueue_steps(c, count);
-    if (rc) return rc;
-    c->step = n0 + count;
-    if (k_end != c->wraps) {
-      enqueue_remap(c, k_end - c->wraps);
-      c->wraps = k_end;
-    }
-    LE_TRY(hipGetLastError());
-    LE_TRY(hipStreamSynchronize(c->stream));  // h_args is reused by the next chunk
-    if (c->profiling) harvest_times(c, count);
-    remaining -= count;
-  }
-  if (nsteps > 0) {
-    c->ops.obs_real(c->phi, c->n_real, c->d_rpart, kRealBlocks, c->stream);
-    launch_obs_final(c->d_spart, 0, c->d_rpart, kRealBlocks, c->d_bins, c->d_counts, 0,
-                     c->d_out, c->stream);
-    LE_TRY(hipGetLastError());
-    LE_TRY(hipMemcpyAsync(c->h_out, c->d_out, OBS_NTOTAL * sizeof(double),
-                          hipMemcpyDeviceToHost, c->stream));
-    LE_TRY(hipStreamSynchronize(c->stream));
-    if (c->h_out[OBS_NONFINITE] != 0.0) return LE_ENONFINITE;
-  }
-  return LE_OK;
-}
+int le_step(le_ctx* c, int64_t nsteps) { return step_engine(c, nsteps); }
 
 int le_observables(le_ctx* c, le_obs* o, double* Sk, int32_t sk_cap) {
   if (!c || !o) return LE_EINVAL;
-  int rc = reduce_observables(c);
-  if (rc) return rc;
-  const double* h = c->h_out;
-  const double N = (double)c->n_real;
-  le_obs r;
-  std::memset(&r, 0, sizeof(r));
-  r.step = c->step;
-  r.wraps = c->wraps;
-  r.t = (double)c->step * c->p.dt;
-  r.strain = strain_total(c->p, c->step);
-  r.s = strain_offset(c->p, c->step);
-  r.mean_phi = h[OBS_SUM_PHI] / N;
-  r.phi2 = h[OBS_SUM_PHI2] / N;
-  r.Ls = h[OBS_SUM_S_NZ] > 0.0 ? h[OBS_SUM_S_OVER_Q] / h[OBS_SUM_S_NZ] : 0.0;
-  const double l = std::sqrt(c->p.kappa / c->p.A);
-  const double tot = h[OBS_SUM_S];
-  r.Dxx = tot > 0.0 ? l * h[OBS_XX] / tot : 0.0;
-  r.Dxy = tot > 0.0 ? l * h[OBS_XY] / tot : 0.0;
-  r.Dyy = tot > 0.0 ? l * h[OBS_YY] / tot : 0.0;
-  const double mid = 0.5 * (r.Dxx + r.Dyy);
-  const double rad = std::sqrt(0.25 * (r.Dxx - r.Dyy) * (r.Dxx - r.Dyy) + r.Dxy * r.Dxy);
-  const double hi = mid + rad, lo = mid - rad;
-  r.L_perp = hi > 0.0 ? 1.0 / hi : INFINITY;
-  r.L_par = lo > 0.0 ? 1.0 / lo : INFINITY;
-  r.sigma_xy = -c->p.kappa * h[OBS_XY] / N;
-  r.sigma_xy_re = c->inertial ? c->p.rho * h[OBS_RE] / (N * N) : 0.0;
-  r.nbins = c->nbins;
-  r.dk = 6.283185307179586476925286766559 / c->p.ly;
-  r.finite = h[OBS_NONFINITE] == 0.0 ? 1 : 0;
-  if (Sk) {
-    const int nb = sk_cap < c->nbins ? sk_cap : c->nbins;
-    for (int b = 0; b < nb; ++b) {
-      const double w = h[OBS_NTOTAL + c->nbins + b];
-      Sk[b] = w > 0.0 ? h[OBS_NTOTAL + b] / w : 0.0;
-    }
-  }
-  *o = r;
-  return LE_OK;
+  return observables_of(c, c->runs[0], o, Sk, sk_cap);
 }
 
-void le_destroy(le_ctx* c) {
-  if (!c) return;
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
-  release(c);
-  delete c;
-}
+void le_destroy(le_ctx* c) { destroy_engine(c); }
 
 int le_get_state(le_ctx* c, double* phi, double* omega, double* psi, int64_t* step,
                  int64_t* wraps) {
-  if (!c) return LE_EINVAL;
-  int rc;
-  if (phi && (rc = download_real(c, c->phi, phi))) return rc;
-  if (omega) {
-    if (c->inertial) {
-      c->ops.row_c2r(c->om_s, c->om_r, nullptr, nullptr, c->geo, c->twx, c->stream);
-      LE_TRY(hipGetLastError());
-      if ((rc = download_real(c, c->om_r, omega))) return rc;
-    } else {
-      std::memset(omega, 0, c->n_real * sizeof(double));
-    }
-  }
-  if (psi) {
-    c->ops.row_c2r(c->ps_s, c->ps_r, nullptr, nullptr, c->geo, c->twx, c->stream);
-    LE_TRY(hipGetLastError());
-    if ((rc = download_real(c, c->ps_r, psi))) return rc;
-  }
-  if (step) *step = c->step;
-  if (wraps) *wraps = c->wraps;
-  return LE_OK;
-}
-
-int le_profile(le_ctx* c, int enable) {
-  if (!c) return LE_EINVAL;
-  if (enable && c->events.empty()) {
-    c->events.resize((size_t)kProfChunk * (LE_NSTAGES + 1));
-    for (auto& e : c->events) {
-      if (hipEventCreate(&e) != hipSuccess) {
-        e = nullptr;
-        return LE_EDEVICE;
-      }
-    }
-  }
-  c->profiling = enable != 0;
-  for (int s = 0; s < LE_NSTAGES; ++s) {
-    c->stage_ms[s] = 0.0;
-    c->stage_n[s] = 0;
-  }
-  return LE_OK;
-}
-
-int le_stage_times(le_ctx* c, double* ms, int64_t* launches, int32_t cap) {
-  if (!c || cap < 0) return LE_EINVAL;
-  const int n = cap < LE_NSTAGES ? cap : LE_NSTAGES;
-  for (int s = 0; s < n; ++s) {
-    if (ms) ms[s] = c->stage_ms[s];
-    if (launches) launches[s] = c->stage_n[s];
-  }
-  return LE_OK;
+  return get_state_of(c, 0, phi, omega, psi, step, wraps);
 }
 
 int le_set_state(le_ctx* c, const double* phi, const double* omega, const double* psi,
                  int64_t step, int64_t wraps) {
   if (!c || !phi || !psi || step < 0) return LE_EINVAL;
-  if (c->inertial && !omega) return LE_EINVAL;
-  if (wraps != wrap_count(c->p, step)) return LE_EINVAL;
-  int rc;
-  if ((rc = upload_real(c, phi, c->phi))) return rc;
-  if (c->inertial) {
-    if ((rc = upload_real(c, omega, c->om_r))) return rc;
-    c->ops.row_r2c(c->om_r, c->om_s, c->geo, c->twx, c->stream);
+  RunHost& r = c->runs[0];
+  if (r.inertial && !omega) return LE_EINVAL;
+  if (wraps != wrap_count(r.p, step)) return LE_EINVAL;
+  const Ops& o = c->classes[r.cls].ops;
+  LE_RC(upload_real(c, r, phi, B_PHI));
+  if (r.inertial) {
+    LE_RC(upload_real(c, r, omega, B_OM_R));
+    o.row_r2c(desc(c, r), 1, r.p.ny, B_OM_R, B_OM_S, c->stream);
   }
-  if ((rc = upload_real(c, psi, c->ps_r))) return rc;
-  c->ops.row_r2c(c->ps_r, c->ps_s, c->geo, c->twx, c->stream);
+  LE_RC(upload_real(c, r, psi, B_PS_R));
+  o.row_r2c(desc(c, r), 1, r.p.ny, B_PS_R, B_PS_S, c->stream);
   LE_TRY(hipGetLastError());
   LE_TRY(hipStreamSynchronize(c->stream));
   c->step = step;
-  c->wraps = wraps;
+  r.wraps = wraps;
   return LE_OK;
+}
+
+int le_profile(le_ctx* c, int enable) { return profile_engine(c, enable); }
+
+int le_stage_times(le_ctx* c, double* ms, int64_t* launches, int32_t cap) {
+  return stage_times_of(c, ms, launches, cap);
+}
+
+int le_batch_create(int32_t n, const le_params* ps, const double* const* phi0s,
+                    const double* const* omega0s, le_batch** out) {
+  if (!out) return LE_EINVAL;
+  *out = nullptr;
+  le_batch* b = new (std::nothrow) le_batch();
+  if (!b) return LE_ENOMEM;
+  const int rc = create_engine(n, ps, phi0s, omega0s, &b->e);
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return LE_OK;
+}
+
+int le_batch_step(le_batch* b, int64_t nsteps) {
+  return b ? step_engine(b->e, nsteps) : LE_EINVAL;
+}
+
+int le_batch_observables(le_batch* b, int32_t run, le_obs* o, double* Sk, int32_t sk_cap) {
+  if (!b || !o || run < 0 || run >= b->e->nruns) return LE_EINVAL;
+  return observables_of(b->e, b->e->runs[run], o, Sk, sk_cap);
+}
+
+int le_batch_get_state(le_batch* b, int32_t run, double* phi, double* omega, double* psi,
+                       int64_t* step, int64_t* wraps) {
+  return b ? get_state_of(b->e, run, phi, omega, psi, step, wraps) : LE_EINVAL;
+}
+
+int le_batch_profile(le_batch* b, int enable) {
+  return b ? profile_engine(b->e, enable) : LE_EINVAL;
+}
+
+int le_batch_stage_times(le_batch* b, double* ms, int64_t* launches, int32_t cap) {
+  return b ? stage_times_of(b->e, ms, launches, cap) : LE_EINVAL;
+}
+
+void le_batch_destroy(le_batch* b) {
+  if (!b) return;
+  destroy_engine(b->e);
+  delete b;
 }
 
 }  // extern "C"

@@ -22,6 +22,30 @@ struct StepArgs {
   double pad;
 };
 
+// Device buffers of one run (storage type T, as void*).
+enum Buf {
+  B_PHI = 0,  // real phi (state)
+  B_OM_S,     // row spectrum of omega (state, inertial runs)
+  B_PS_S,     // row spectrum of psi (state)
+  B_OM_R,     // real scratch: omega
+  B_PS_R,     // real scratch: psi
+  B_PHIH,     // row spectra, scratch
+  B_FH,
+  B_OMH,
+  B_GH,
+  B_PHIN,
+  B_TMP,      // real scratch (remap, downloads)
+  NBUF
+};
+
+// Descriptor of one run, read by the kernels (blockIdx.z picks the run).
+struct Run {
+  Geo g;
+  void* buf[NBUF];
+  const void* twx;   // exp(-2 pi i k / nx), k < nx
+  const void* twy;   // exp(-2 pi i k / (2 ny)), k < 2 ny
+};
+
 // Column-kernel variants (per-mode update applied between the transforms).
 enum ColMode { COL_CH = 0, COL_FLOW = 1, COL_STOKES = 2, COL_POISSON = 3 };
 

@@ -1,5 +1,7 @@
 // ops.hpp -- type-erased launchers of the stage kernels for one precision and
-// one grid, so the runtime can pick the instantiation at context creation.
+// one grid shape.  Every step launcher covers `nruns` runs of that shape at
+// once (grid z = run); `runs` is a device array of descriptors and `sa` the
+// matching per-run StepArgs of the step.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,29 +12,26 @@
 namespace le {
 
 struct Ops {
-  // forward row transform of a real field into a row spectrum
-  void (*row_r2c)(const void* x, void* X, const Geo& g, const void* twx, hipStream_t st);
-  // inverse row transform of one (X1 == nullptr) or two fields
-  void (*row_c2r)(const void* X0, void* x0, const void* X1, void* x1, const Geo& g,
-                  const void* twx, hipStream_t st);
+  void (*row_r2c)(const Run* runs, int nruns, int ny, int bin, int bout, hipStream_t st);
+  // inverse row transforms: bin0 -> bout0 and, when nfields == 2, bin1 -> bout1
+  void (*row_c2r)(const Run* runs, int nruns, int ny, int bin0, int bout0, int bin1, int bout1,
+                  int nfields, hipStream_t st);
   // stage 1a + forward row transforms (omega parts only when inertial)
-  void (*advect)(const void* phi, const void* om, const void* psi, void* phih, void* fh,
-                 void* omh, const StepArgs* sa, const Geo& g, const void* twx, bool inertial,
+  void (*advect)(const Run* runs, int nruns, int ny, const StepArgs* sa, bool inertial,
                  hipStream_t st);
   // stage 2a + forward row transform of g
-  void (*mu_source)(const void* phi, void* gh, const StepArgs* sa, const Geo& g,
-                    double inv_coef, const void* twx, hipStream_t st);
-  // column transform + per-mode update + inverse (mode: ColMode)
-  void (*column)(int mode, const void* in0, const void* in1, void* out0, void* out1,
-                 const StepArgs* sa, const Geo& g, const void* twy, hipStream_t st);
-  // spectral observable partials; returns nothing, see obs_blocks
-  void (*obs_spectral)(const void* phih, const void* psih, double* part, double* bins,
-                       double* counts, const StepArgs* sa, const Geo& g, const void* twy,
-                       hipStream_t st);
-  int (*obs_blocks)(const Geo& g);
-  void (*obs_real)(const void* phi, size_t n, double* part, int nblk, hipStream_t st);
-  void (*remap_spec)(void* X, const Geo& g, int dkr, const void* twx, hipStream_t st);
-  void (*remap_real)(const void* in, void* out, const Geo& g, int dkr, hipStream_t st);
+  void (*mu_source)(const Run* runs, int nruns, int ny, const StepArgs* sa, hipStream_t st);
+  // column transform + per-mode update (ColMode) + inverse column transform
+  void (*column)(int mode, const Run* runs, int nruns, int nx, const StepArgs* sa, int bin0,
+                 int bin1, int bout0, int bout1, hipStream_t st);
+  // one run: spectral observable partials (bpsi < 0: no psi)
+  void (*obs_spectral)(const Run* run, int nx, const StepArgs* sa, int bphi, int bpsi,
+                       double* part, double* bins, double* counts, hipStream_t st);
+  int (*obs_blocks)(int nx);
+  void (*obs_real)(const Run* run, int b, double* part, int nblk, hipStream_t st);
+  void (*remap_spec)(const Run* run, int b, int dkr, hipStream_t st);
+  void (*remap_real)(const Run* run, int bin, int bout, int dkr, hipStream_t st);
+  void (*copy_real)(const Run* run, int bin, int bout, hipStream_t st);
 };
 
 // Fill *ops for precision (0 = double, 1 = float) and the grid; false if the

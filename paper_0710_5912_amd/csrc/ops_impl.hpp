@@ -10,94 +10,77 @@ namespace le {
 template <typename T, int L>
 struct RowLaunch {
   using C = RowCfg<L>;
-  static dim3 grid(const Geo& g) { return dim3((g.ny + C::G - 1) / C::G); }
-  static void r2c(const void* x, void* X, const Geo& g, const void* tw, hipStream_t st) {
-    hipLaunchKernelGGL((k_row_r2c<T, L>), grid(g), dim3(C::THREADS), 0, st,
-                       static_cast<const T*>(x), static_cast<c2<T>*>(X), g.ny,
-                       static_cast<const c2<T>*>(tw));
+  static dim3 grid(int ny, int fields, int nruns) {
+    return dim3((ny + C::G - 1) / C::G, fields, nruns);
   }
-  static void c2r(const void* X0, void* x0, const void* X1, void* x1, const Geo& g,
-                  const void* tw, hipStream_t st) {
-    dim3 gr = grid(g);
-    gr.y = X1 ? 2 : 1;
-    hipLaunchKernelGGL((k_row_c2r<T, L>), gr, dim3(C::THREADS), 0, st,
-                       static_cast<const c2<T>*>(X0), static_cast<T*>(x0),
-                       static_cast<const c2<T>*>(X1), static_cast<T*>(x1), g.ny,
-                       static_cast<const c2<T>*>(tw));
+  static void r2c(const Run* runs, int nruns, int ny, int bin, int bout, hipStream_t st) {
+    hipLaunchKernelGGL((k_row_r2c<T, L>), grid(ny, 1, nruns), dim3(C::THREADS), 0, st, runs,
+                       bin, bout);
   }
-  static void advect(const void* phi, const void* om, const void* psi, void* phih, void* fh,
-                     void* omh, const StepArgs* sa, const Geo& g, const void* tw,
-                     bool inertial, hipStream_t st) {
-    dim3 gr = grid(g);
-    gr.y = inertial ? 3 : 2;
-    hipLaunchKernelGGL((k_advect<T, L>), gr, dim3(C::THREADS), 0, st,
-                       static_cast<const T*>(phi), static_cast<const T*>(om),
-                       static_cast<const T*>(psi), static_cast<c2<T>*>(phih),
-                       static_cast<c2<T>*>(fh), static_cast<c2<T>*>(omh), sa, g,
-                       static_cast<const c2<T>*>(tw));
+  static void c2r(const Run* runs, int nruns, int ny, int bin0, int bout0, int bin1, int bout1,
+                  int nfields, hipStream_t st) {
+    hipLaunchKernelGGL((k_row_c2r<T, L>), grid(ny, nfields, nruns), dim3(C::THREADS), 0, st,
+                       runs, bin0, bout0, bin1, bout1);
   }
-  static void mu_source(const void* phi, void* gh, const StepArgs* sa, const Geo& g,
-                        double inv, const void* tw, hipStream_t st) {
+  static void advect(const Run* runs, int nruns, int ny, const StepArgs* sa, bool inertial,
+                     hipStream_t st) {
+    hipLaunchKernelGGL((k_advect<T, L>), grid(ny, inertial ? 3 : 2, nruns), dim3(C::THREADS),
+                       0, st, runs, sa);
+  }
+  static void mu_source(const Run* runs, int nruns, int ny, const StepArgs* sa, hipStream_t st) {
     using M = MuCfg<L>;
-    hipLaunchKernelGGL((k_mu_source<T, L>), dim3((g.ny + M::G - 1) / M::G), dim3(M::THREADS),
-                       0, st, static_cast<const T*>(phi), static_cast<c2<T>*>(gh), sa, g, inv,
-                       static_cast<const c2<T>*>(tw));
+    hipLaunchKernelGGL((k_mu_source<T, L>), dim3((ny + M::G - 1) / M::G, 1, nruns),
+                       dim3(M::THREADS), 0, st, runs, sa);
   }
 };
 
 template <typename T, int L>
 struct ColLaunch {
   using C = ColCfg<L>;
-  static dim3 grid(const Geo& g) { return dim3((g.nx / 2 + 1 + C::CW - 1) / C::CW); }
-  static void column(int mode, const void* in0, const void* in1, void* out0, void* out1,
-                     const StepArgs* sa, const Geo& g, const void* tw, hipStream_t st) {
-    auto i0 = static_cast<const c2<T>*>(in0);
-    auto i1 = static_cast<const c2<T>*>(in1);
-    auto o0 = static_cast<c2<T>*>(out0);
-    auto o1 = static_cast<c2<T>*>(out1);
-    auto w = static_cast<const c2<T>*>(tw);
+  static int nblk(int nx) { return (nx / 2 + 1 + C::CW - 1) / C::CW; }
+  static void column(int mode, const Run* runs, int nruns, int nx, const StepArgs* sa,
+                     int bin0, int bin1, int bout0, int bout1, hipStream_t st) {
+    const dim3 gr(nblk(nx), 1, nruns), bl(C::THREADS);
     switch (mode) {
       case COL_CH:
-        hipLaunchKernelGGL((k_column<T, L, COL_CH>), grid(g), dim3(C::THREADS), 0, st, i0, i1,
-                           o0, o1, sa, g, w);
+        hipLaunchKernelGGL((k_column<T, L, COL_CH>), gr, bl, 0, st, runs, sa, bin0, bin1, bout0,
+                           bout1);
         break;
       case COL_FLOW:
-        hipLaunchKernelGGL((k_column<T, L, COL_FLOW>), grid(g), dim3(C::THREADS), 0, st, i0,
-                           i1, o0, o1, sa, g, w);
+        hipLaunchKernelGGL((k_column<T, L, COL_FLOW>), gr, bl, 0, st, runs, sa, bin0, bin1,
+                           bout0, bout1);
         break;
       case COL_STOKES:
-        hipLaunchKernelGGL((k_column<T, L, COL_STOKES>), grid(g), dim3(C::THREADS), 0, st, i0,
-                           i1, o0, o1, sa, g, w);
+        hipLaunchKernelGGL((k_column<T, L, COL_STOKES>), gr, bl, 0, st, runs, sa, bin0, bin1,
+                           bout0, bout1);
         break;
       default:
-        hipLaunchKernelGGL((k_column<T, L, COL_POISSON>), grid(g), dim3(C::THREADS), 0, st,
-                           i0, i1, o0, o1, sa, g, w);
+        hipLaunchKernelGGL((k_column<T, L, COL_POISSON>), gr, bl, 0, st, runs, sa, bin0, bin1,
+                           bout0, bout1);
         break;
     }
   }
-  static void obs(const void* phih, const void* psih, double* part, double* bins,
-                  double* counts, const StepArgs* sa, const Geo& g, const void* tw,
-                  hipStream_t st) {
-    hipLaunchKernelGGL((k_obs_spectral<T, L>), grid(g), dim3(C::THREADS), 0, st,
-                       static_cast<const c2<T>*>(phih), static_cast<const c2<T>*>(psih), part,
-                       bins, counts, sa, g, static_cast<const c2<T>*>(tw));
+  static void obs(const Run* run, int nx, const StepArgs* sa, int bphi, int bpsi, double* part,
+                  double* bins, double* counts, hipStream_t st) {
+    hipLaunchKernelGGL((k_obs_spectral<T, L>), dim3(nblk(nx)), dim3(C::THREADS), 0, st, run, sa,
+                       bphi, bpsi, part, bins, counts);
   }
-  static int blocks(const Geo& g) { return (int)grid(g).x; }
+  static int blocks(int nx) { return nblk(nx); }
 };
 
 template <typename T>
 struct Misc {
-  static void obs_real(const void* phi, size_t n, double* part, int nblk, hipStream_t st) {
-    hipLaunchKernelGGL((k_obs_real<T>), dim3(nblk), dim3(256), 0, st,
-                       static_cast<const T*>(phi), n, part);
+  static void obs_real(const Run* run, int b, double* part, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL((k_obs_real<T>), dim3(nblk), dim3(256), 0, st, run, b, part);
   }
-  static void remap_spec(void* X, const Geo& g, int dkr, const void* tw, hipStream_t st) {
-    hipLaunchKernelGGL((k_remap_spec<T>), dim3(1024), dim3(256), 0, st, static_cast<c2<T>*>(X),
-                       g.nx, g.ny, dkr, static_cast<const c2<T>*>(tw));
+  static void remap_spec(const Run* run, int b, int dkr, hipStream_t st) {
+    hipLaunchKernelGGL((k_remap_spec<T>), dim3(1024), dim3(256), 0, st, run, b, dkr);
   }
-  static void remap_real(const void* in, void* out, const Geo& g, int dkr, hipStream_t st) {
-    hipLaunchKernelGGL((k_remap_real<T>), dim3(1024), dim3(256), 0, st,
-                       static_cast<const T*>(in), static_cast<T*>(out), g.nx, g.ny, dkr);
+  static void remap_real(const Run* run, int bin, int bout, int dkr, hipStream_t st) {
+    hipLaunchKernelGGL((k_remap_real<T>), dim3(1024), dim3(256), 0, st, run, bin, bout, dkr);
+  }
+  static void copy_real(const Run* run, int bin, int bout, hipStream_t st) {
+    hipLaunchKernelGGL((k_copy_real<T>), dim3(1024), dim3(256), 0, st, run, bin, bout);
   }
 };
 
@@ -147,6 +130,7 @@ bool fill_ops(int nx, int ny, Ops* o) {
   o->obs_real = &Misc<T>::obs_real;
   o->remap_spec = &Misc<T>::remap_spec;
   o->remap_real = &Misc<T>::remap_real;
+  o->copy_real = &Misc<T>::copy_real;
   return true;
 }
 

@@ -62,6 +62,26 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return x * q + (x < rem ? x : rem) + (b >> 3);
 }
 
+// Logical (x, y, z) of this block: the XCD-aware map applied to the linear
+// block index, so consecutive x (rows or columns) of one field and run land
+// in one L2.
+struct BPos {
+  int x, y, z;
+};
+__device__ __forceinline__ BPos block_pos() {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int nb = gx * gy * gridDim.z;
+  const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int l = xcd_block(lin, nb);
+  const int rest = l / gx;
+  return {l % gx, rest % gy, rest / gy};
+}
+
+template <typename T>
+__device__ __forceinline__ T* bufp(const Run& R, int b) {
+  return static_cast<T*>(R.buf[b]);
+}
+
 // ---------------------------------------------------------------- helpers
 
 template <typename T, int L, int E>
@@ -138,14 +158,20 @@ __device__ __forceinline__ double lambda_of(const Modes& q, double s) {
 
 // ---------------------------------------------------------------- row kernels
 
-// Forward row transform of one real field (used at set-up and for observables).
+// Forward row transform of one real field (buffer bin -> row spectrum bout).
 template <typename T, int L>
 __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_row_r2c(
-    const T* __restrict__ x, c2<T>* __restrict__ X, int ny, const c2<T>* __restrict__ tw) {
+    const Run* __restrict__ runs, int bin, int bout) {
   using C = RowCfg<L>;
   __shared__ c2<T> lds[C::G * L];
+  const BPos bp = block_pos();
+  const Run& R = runs[bp.z];
+  const int ny = R.g.ny;
+  const T* x = bufp<T>(R, bin);
+  c2<T>* X = bufp<c2<T>>(R, bout);
+  const c2<T>* tw = static_cast<const c2<T>*>(R.twx);
   const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
-  const int j = xcd_block(blockIdx.x, gridDim.x) * C::G + g;
+  const int j = bp.x * C::G + g;
   const bool ok = j < ny;
   const c2<T>* xr = reinterpret_cast<const c2<T>*>(x + (size_t)(ok ? j : 0) * 2 * L);
   c2<T> v[C::E];
@@ -155,19 +181,23 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_row_r2c(
   if (ok) store_row_spec<T, L, C::E>(X + (size_t)j * (L + 1), v, t);
 }
 
-// Inverse row transform; blockIdx.y selects the field (X0 -> x0, X1 -> x1).
+// Inverse row transform; the block's y picks the field (bin0 -> bout0, or
+// bin1 -> bout1).
 template <typename T, int L>
 __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_row_c2r(
-    const c2<T>* __restrict__ X0, T* __restrict__ x0, const c2<T>* __restrict__ X1,
-    T* __restrict__ x1, int ny, const c2<T>* __restrict__ tw) {
+    const Run* __restrict__ runs, int bin0, int bout0, int bin1, int bout1) {
   using C = RowCfg<L>;
   __shared__ c2<T> lds[C::G * L];
+  const BPos bp = block_pos();
+  const Run& R = runs[bp.z];
+  const int ny = R.g.ny;
+  const c2<T>* X = bufp<const c2<T>>(R, bp.y == 0 ? bin0 : bin1);
+  T* x = bufp<T>(R, bp.y == 0 ? bout0 : bout1);
+  const c2<T>* tw = static_cast<const c2<T>*>(R.twx);
   const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
-  const int j = xcd_block(blockIdx.x, gridDim.x) * C::G + g;
+  const int j = bp.x * C::G + g;
   const bool ok = j < ny;
   const int jj = ok ? j : 0;
-  const c2<T>* X = blockIdx.y == 0 ? X0 : X1;
-  T* x = blockIdx.y == 0 ? x0 : x1;
   c2<T> v[C::E];
   load_row_spec<T, L, C::E>(X + (size_t)jj * (L + 1), v, t);
   row_c2r<T, L, C::E>(v, lds + g * L, tw, t);
@@ -239,20 +269,25 @@ __device__ __forceinline__ void dys_pair(const T* f, int jp, int jm, int i, int 
 // followed by the forward row transform of that field.
 template <typename T, int L>
 __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_advect(
-    const T* __restrict__ phi, const T* __restrict__ om, const T* __restrict__ psi,
-    c2<T>* __restrict__ phih, c2<T>* __restrict__ fh, c2<T>* __restrict__ omh,
-    const StepArgs* __restrict__ sa, Geo geo, const c2<T>* __restrict__ tw) {
+    const Run* __restrict__ runs, const StepArgs* __restrict__ sa) {
   using C = RowCfg<L>;
   constexpr int NX = 2 * L;
   __shared__ c2<T> lds[C::G * L];
+  const BPos bp = block_pos();
+  const Run& R = runs[bp.z];
+  const Geo& geo = R.g;
+  const T* phi = bufp<const T>(R, B_PHI);
+  const T* om = bufp<const T>(R, B_OM_R);
+  const T* psi = bufp<const T>(R, B_PS_R);
+  const c2<T>* tw = static_cast<const c2<T>*>(R.twx);
   const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
-  const int j0 = xcd_block(blockIdx.x, gridDim.x) * C::G + g;
+  const int j0 = bp.x * C::G + g;
   const bool ok = j0 < geo.ny;
   const int j = ok ? j0 : 0;
   const int jp = (j + 1 == geo.ny) ? 0 : j + 1;
   const int jm = (j == 0) ? geo.ny - 1 : j - 1;
-  const int field = blockIdx.y;
-  const Stencil<T> st = make_stencil<T>(geo, sa->s);
+  const int field = bp.y;
+  const Stencil<T> st = make_stencil<T>(geo, sa[bp.z].s);
   const T dt = T(geo.dt);
   c2<T> v[C::E];
   if (field == 1) {
@@ -278,7 +313,7 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_advect(
     }
   }
   row_r2c<T, L, C::E>(v, lds + g * L, tw, t);
-  c2<T>* out = field == 0 ? phih : (field == 1 ? fh : omh);
+  c2<T>* out = bufp<c2<T>>(R, field == 0 ? B_PHIH : (field == 1 ? B_FH : B_OMH));
   if (ok) store_row_spec<T, L, C::E>(out + (size_t)j * (L + 1), v, t);
 }
 
@@ -287,17 +322,23 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_advect(
 // (inv = 1/rho, or 1/eta on the Stokes branch) and its forward row transform.
 template <typename T, int L>
 __global__ __launch_bounds__(MuCfg<L>::THREADS) LE_OCCUPANCY void k_mu_source(
-    const T* __restrict__ phi, c2<T>* __restrict__ gh, const StepArgs* __restrict__ sa,
-    Geo geo, double inv_coef, const c2<T>* __restrict__ tw) {
+    const Run* __restrict__ runs, const StepArgs* __restrict__ sa) {
   using C = MuCfg<L>;
+  const BPos bp = block_pos();
+  const Run& R = runs[bp.z];
+  const Geo& geo = R.g;
+  const T* phi = bufp<const T>(R, B_PHI);
+  c2<T>* gh = bufp<c2<T>>(R, B_GH);
+  const c2<T>* tw = static_cast<const c2<T>*>(R.twx);
+  const double inv_coef = 1.0 / (geo.rho > 0.0 ? geo.rho : geo.eta);
   constexpr int NX = 2 * L;
   constexpr int MU_ROWS = C::G + 2;
   constexpr int LDS_T = MU_ROWS * NX;  // >= C::G * L complex
   __shared__ __attribute__((aligned(16))) T smu[LDS_T];
   c2<T>* lds = reinterpret_cast<c2<T>*>(smu);
   const int ny = geo.ny;
-  const int jbase = xcd_block(blockIdx.x, gridDim.x) * C::G;
-  const double s = sa->s;
+  const int jbase = bp.x * C::G;
+  const double s = sa[bp.z].s;
   const T cxx = T((1.0 + s * s) / (geo.dx * geo.dx));
   const T cyy = T(1.0 / (geo.dy * geo.dy));
   const T cxy = T(-2.0 * s / (4.0 * geo.dx * geo.dy));
@@ -360,10 +401,12 @@ __global__ __launch_bounds__(MuCfg<L>::THREADS) LE_OCCUPANCY void k_mu_source(
 }
 
 // Strain-wrap remap of a row spectrum: row j shifted by sh_j = (dkr * j) mod nx,
-// X[j][m] *= exp(-2 pi i m sh_j / nx).  twx: exp(-2 pi i k / nx), k < nx.
+// X[j][m] *= exp(-2 pi i m sh_j / nx).
 template <typename T>
-__global__ void k_remap_spec(c2<T>* __restrict__ X, int nx, int ny, int dkr,
-                             const c2<T>* __restrict__ twx) {
+__global__ void k_remap_spec(const Run* __restrict__ run, int b, int dkr) {
+  const int nx = run->g.nx, ny = run->g.ny;
+  c2<T>* X = bufp<c2<T>>(*run, b);
+  const c2<T>* twx = static_cast<const c2<T>*>(run->twx);
   const int S = nx / 2 + 1;
   const size_t total = (size_t)ny * S;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
@@ -377,8 +420,10 @@ __global__ void k_remap_spec(c2<T>* __restrict__ X, int nx, int ny, int dkr,
 
 // Strain-wrap remap of a real field: out[j][i] = in[j][(i - dkr j) mod nx].
 template <typename T>
-__global__ void k_remap_real(const T* __restrict__ in, T* __restrict__ out, int nx, int ny,
-                             int dkr) {
+__global__ void k_remap_real(const Run* __restrict__ run, int bin, int bout, int dkr) {
+  const int nx = run->g.nx, ny = run->g.ny;
+  const T* in = bufp<const T>(*run, bin);
+  T* out = bufp<T>(*run, bout);
   const size_t total = (size_t)ny * nx;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
@@ -386,6 +431,17 @@ __global__ void k_remap_real(const T* __restrict__ in, T* __restrict__ out, int 
     const long long sh = (((long long)dkr * j) % nx + nx) % nx;
     out[e] = in[(size_t)j * nx + (size_t)((i - sh + nx) % nx)];
   }
+}
+
+// Plain copy of a real field (bin -> bout).
+template <typename T>
+__global__ void k_copy_real(const Run* __restrict__ run, int bin, int bout) {
+  const size_t total = (size_t)run->g.ny * run->g.nx;
+  const T* in = bufp<const T>(*run, bin);
+  T* out = bufp<T>(*run, bout);
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x)
+    out[e] = in[e];
 }
 
 // ---------------------------------------------------------------- column kernels
@@ -397,16 +453,23 @@ __global__ void k_remap_real(const T* __restrict__ in, T* __restrict__ out, int 
 //  COL_POISSON omega -> psi               set-up: psi from omega
 template <typename T, int L, int MODE>
 __global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY void k_column(
-    const c2<T>* __restrict__ in0, const c2<T>* __restrict__ in1, c2<T>* __restrict__ out0,
-    c2<T>* __restrict__ out1, const StepArgs* __restrict__ sa, Geo geo,
-    const c2<T>* __restrict__ tw) {
+    const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int bin0, int bin1,
+    int bout0, int bout1) {
   using C = ColCfg<L>;
+  const BPos bp = block_pos();
+  const Run& R = runs[bp.z];
+  const Geo& geo = R.g;
+  const c2<T>* in0 = bufp<const c2<T>>(R, bin0);
+  const c2<T>* in1 = bufp<const c2<T>>(R, bin1);
+  c2<T>* out0 = bufp<c2<T>>(R, bout0);
+  c2<T>* out1 = bufp<c2<T>>(R, bout1);
+  const c2<T>* tw = static_cast<const c2<T>*>(R.twy);
   constexpr int NIN = (MODE == COL_CH || MODE == COL_FLOW) ? 2 : 1;
   constexpr int NOUT = (MODE == COL_FLOW) ? 2 : 1;
   __shared__ c2<T> lds[C::CW * L];
   const int S = geo.nx / 2 + 1;
   const int c = threadIdx.x % C::CW, t = threadIdx.x / C::CW;
-  const int m0 = xcd_block(blockIdx.x, gridDim.x) * C::CW + c;
+  const int m0 = bp.x * C::CW + c;
   const bool ok = m0 < S;
   const int m = ok ? m0 : 0;
   c2<T> v0[C::E], v1[C::E];
@@ -419,7 +482,7 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY void k_column(
     __syncthreads();
     fft_group<T, L, C::E, -1>(v1, lds + c, C::CW, tw, t);
   }
-  const double s = sa->s;
+  const double s = sa[bp.z].s;
   const double inv_ny = 1.0 / (double)geo.ny;
   const double dtnu = geo.rho > 0.0 ? geo.dt * (geo.eta / geo.rho) : 0.0;
 #pragma unroll
@@ -499,10 +562,13 @@ __device__ __forceinline__ void obs_mode(const Geo& g, int m, int n, double s, d
 // order partial sums of OBS_* and of the S(k) shells.
 template <typename T, int L>
 __global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY void k_obs_spectral(
-    const c2<T>* __restrict__ phih, const c2<T>* __restrict__ psih, double* __restrict__ part,
-    double* __restrict__ bins, double* __restrict__ counts, const StepArgs* __restrict__ sa,
-    Geo geo, const c2<T>* __restrict__ tw) {
+    const Run* __restrict__ run, const StepArgs* __restrict__ sa, int bphi, int bpsi,
+    double* __restrict__ part, double* __restrict__ bins, double* __restrict__ counts) {
   using C = ColCfg<L>;
+  const Geo& geo = run->g;
+  const c2<T>* phih = bufp<const c2<T>>(*run, bphi);
+  const c2<T>* psih = bpsi >= 0 ? bufp<const c2<T>>(*run, bpsi) : nullptr;
+  const c2<T>* tw = static_cast<const c2<T>*>(run->twy);
   constexpr int NB = L / 2;  // shells 1 .. ny/2
   constexpr int NBT = (NB + C::THREADS - 1) / C::THREADS;
   constexpr int NE = C::CW * L;
@@ -629,9 +695,11 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY void k_obs_spectra
 
 // Real-space partial sums: sum phi, sum phi^2 (FP64) and the non-finite count.
 template <typename T>
-__global__ __launch_bounds__(256) void k_obs_real(const T* __restrict__ phi, size_t n,
+__global__ __launch_bounds__(256) void k_obs_real(const Run* __restrict__ run, int bphi,
                                                   double* __restrict__ part) {
   __shared__ double red[3][256];
+  const T* phi = bufp<const T>(*run, bphi);
+  const size_t n = (size_t)run->g.nx * run->g.ny;
   const size_t per = (n + gridDim.x - 1) / gridDim.x;
   const size_t lo = blockIdx.x * per, hi = lo + per < n ? lo + per : n;
   double a = 0.0, b = 0.0, bad = 0.0;

@@ -18,7 +18,9 @@ LE_OK, LE_EINVAL, LE_ENOMEM, LE_EDEVICE, LE_ENONFINITE, LE_ESTATE = 0, -1, -2, -
 LE_FP64, LE_FP32 = 0, 1
 
 SYMBOLS = ("le_create", "le_step", "le_observables", "le_destroy", "le_get_state",
-           "le_set_state", "le_strerror", "le_profile", "le_stage_times", "le_last_error")
+           "le_set_state", "le_strerror", "le_profile", "le_stage_times", "le_last_error",
+           "le_batch_create", "le_batch_step", "le_batch_observables", "le_batch_get_state",
+           "le_batch_profile", "le_batch_stage_times", "le_batch_destroy")
 LE_NSTAGES = 6
 STAGES = ("row_inv_flow", "advect", "column_ch", "row_inv_phi", "mu_source", "column_flow")
 
@@ -79,6 +81,24 @@ def lib():
         L.le_profile.restype = C.c_int
         L.le_stage_times.argtypes = [C.c_void_p, _DP, C.POINTER(C.c_int64), C.c_int32]
         L.le_stage_times.restype = C.c_int
+        _PP = C.POINTER(_DP)
+        L.le_batch_create.argtypes = [C.c_int32, C.POINTER(LeParams), _PP, _PP,
+                                      C.POINTER(C.c_void_p)]
+        L.le_batch_create.restype = C.c_int
+        L.le_batch_step.argtypes = [C.c_void_p, C.c_int64]
+        L.le_batch_step.restype = C.c_int
+        L.le_batch_observables.argtypes = [C.c_void_p, C.c_int32, C.POINTER(LeObs), _DP,
+                                           C.c_int32]
+        L.le_batch_observables.restype = C.c_int
+        L.le_batch_get_state.argtypes = [C.c_void_p, C.c_int32, _DP, _DP, _DP,
+                                         C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.le_batch_get_state.restype = C.c_int
+        L.le_batch_profile.argtypes = [C.c_void_p, C.c_int]
+        L.le_batch_profile.restype = C.c_int
+        L.le_batch_stage_times.argtypes = [C.c_void_p, _DP, C.POINTER(C.c_int64), C.c_int32]
+        L.le_batch_stage_times.restype = C.c_int
+        L.le_batch_destroy.argtypes = [C.c_void_p]
+        L.le_batch_destroy.restype = None
         L.le_last_error.argtypes = []
         L.le_last_error.restype = C.c_char_p
         L.le_strerror.argtypes = [C.c_int]
@@ -210,3 +230,86 @@ class Context:
         except Exception:
             pass
 
+
+
+class Batch:
+    """Many independent runs advanced together (one launch per stage and shape)."""
+
+    def __init__(self, params_list, phi0s, omega0s=None, precisions=None, stream=None):
+        n = len(params_list)
+        if n < 1 or len(phi0s) != n:
+            raise ValueError("need one phi0 per run")
+        precisions = precisions or ["fp64"] * n
+        self.shapes = [(int(p["ny"]), int(p["nx"])) for p in params_list]
+        arr = (LeParams * n)()
+        for i, p in enumerate(params_list):
+            arr[i] = make_params(p, precisions[i], stream)
+        self._keep = [_f64(a, self.shapes[i]) for i, a in enumerate(phi0s)]
+        phis = (_DP * n)(*[_dp(a) for a in self._keep])
+        oms = None
+        if omega0s is not None:
+            self._keep_om = [None if a is None else _f64(a, self.shapes[i])
+                             for i, a in enumerate(omega0s)]
+            oms = (_DP * n)(*[_dp(a) if a is not None else None for a in self._keep_om])
+        h = C.c_void_p()
+        rc = lib().le_batch_create(n, arr, phis, oms, C.byref(h))
+        if rc != LE_OK:
+            raise LeError(rc, "le_batch_create")
+        self._h = h
+        self.n = n
+        self._keep = None
+        self._keep_om = None
+
+    def step(self, nsteps: int) -> None:
+        rc = lib().le_batch_step(self._h, int(nsteps))
+        if rc != LE_OK:
+            raise LeError(rc, "le_batch_step")
+
+    def observables(self, run: int, sk: bool = True):
+        o = LeObs()
+        nb = self.shapes[run][0] // 2
+        Sk = np.zeros(nb) if sk else None
+        rc = lib().le_batch_observables(self._h, int(run), C.byref(o), _dp(Sk), nb if sk else 0)
+        if rc != LE_OK:
+            raise LeError(rc, "le_batch_observables")
+        return {name: getattr(o, name) for name, _ in LeObs._fields_}, Sk
+
+    def get_state(self, run: int):
+        shape = self.shapes[run]
+        phi, om, psi = np.empty(shape), np.empty(shape), np.empty(shape)
+        step, wraps = C.c_int64(), C.c_int64()
+        rc = lib().le_batch_get_state(self._h, int(run), _dp(phi), _dp(om), _dp(psi),
+                                      C.byref(step), C.byref(wraps))
+        if rc != LE_OK:
+            raise LeError(rc, "le_batch_get_state")
+        return dict(phi=phi, omega=om, psi=psi, step=step.value, wraps=wraps.value)
+
+    def profile(self, enable: bool) -> None:
+        rc = lib().le_batch_profile(self._h, 1 if enable else 0)
+        if rc != LE_OK:
+            raise LeError(rc, "le_batch_profile")
+
+    def stage_times(self):
+        ms = np.zeros(LE_NSTAGES)
+        n = (C.c_int64 * LE_NSTAGES)()
+        rc = lib().le_batch_stage_times(self._h, _dp(ms), n, LE_NSTAGES)
+        if rc != LE_OK:
+            raise LeError(rc, "le_batch_stage_times")
+        return {STAGES[k]: (float(ms[k]), int(n[k])) for k in range(LE_NSTAGES)}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().le_batch_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
