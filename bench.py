@@ -89,6 +89,53 @@ def run_variant(le, torch, params, precision, steps, warmup, obs_every, seed=0,
     return dict(wall=wall, gpu_ms=gpu_ms, times=times, series=series)
 
 
+def batch_workload():
+    """96 runs: 32 each of 128^2, 256^2, 512^2; gdot log-uniform in [1e-3, 1e-1]
+    (seed 1000); rho alternating 0 / 1; phi0 seed 2000 + r; FP32 bulk."""
+    from paper_0710_5912_amd import configs, inputs
+
+    gd = inputs.batch_draws(96, seed=1000)
+    params, phis = [], []
+    for r in range(96):
+        n = (128, 256, 512)[r // 32]
+        params.append(configs.model_h(n, n, gdot=float(gd[r]), rho=float(r % 2)))
+        phis.append(inputs.noise_phi0(n, n, 2000 + r, amp=0.05))
+    return params, phis
+
+
+def run_batch(le, torch, steps, warmup, seq_steps):
+    params, phis = batch_workload()
+    sites = sum(p["nx"] * p["ny"] for p in params)
+    stream = torch.cuda.Stream()
+    b = le.Batch(params, phis, precisions=["fp32"] * len(params), stream=stream.cuda_stream)
+    b.step(warmup)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batched = sites * steps / (e0.elapsed_time(e1) * 1e-3)
+    b.close()
+    # the same runs one after another through the single-run path
+    total_ms = 0.0
+    for p, phi0 in zip(params, phis):
+        c = le.Context(p, phi0, precision="fp32", stream=stream.cuda_stream)
+        c.step(10)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        c.step(seq_steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        total_ms += e0.elapsed_time(e1)
+        c.close()
+    sequential = sites * seq_steps / (total_ms * 1e-3)
+    return dict(value=batched, sequential_value=sequential, gain=batched / sequential,
+                runs=len(params), sites=sites, steps=steps,
+                error="each run bit-identical to its single-run result (tests)")
+
+
 def roofline_of(params, precision, times):
     b = stage_bytes(params, precision)
     rows = {}
@@ -200,6 +247,8 @@ def main():
             var[name] = dict(value=sites * n / (rv["gpu_ms"] * 1e-3),
                              ms_per_step=rv["gpu_ms"] / n,
                              dominant=d, dominant_frac=rw[d]["gbs"] / HBM_PEAK_GBS)
+        print("bench: variant batched_96", file=sys.stderr, flush=True)
+        var["batched_96_fp32"] = run_batch(le, torch, 500, 50, 100)
         # the large single-GPU grid
         p = configs.LARGE_4096["params"]
         print("bench: variant fp64_4096", file=sys.stderr, flush=True)

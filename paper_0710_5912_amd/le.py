@@ -267,6 +267,9 @@ class Batch:
 
     def observables(self, run: int, sk: bool = True):
         o = LeObs()
+        if not 0 <= run < self.n:
+            rc = lib().le_batch_observables(self._h, int(run), C.byref(o), None, 0)
+            raise LeError(rc, "le_batch_observables")
         nb = self.shapes[run][0] // 2
         Sk = np.zeros(nb) if sk else None
         rc = lib().le_batch_observables(self._h, int(run), C.byref(o), _dp(Sk), nb if sk else 0)
@@ -275,6 +278,9 @@ class Batch:
         return {name: getattr(o, name) for name, _ in LeObs._fields_}, Sk
 
     def get_state(self, run: int):
+        if not 0 <= run < self.n:   # let the library reject it
+            rc = lib().le_batch_get_state(self._h, int(run), None, None, None, None, None)
+            raise LeError(rc, "le_batch_get_state")
         shape = self.shapes[run]
         phi, om, psi = np.empty(shape), np.empty(shape), np.empty(shape)
         step, wraps = C.c_int64(), C.c_int64()
