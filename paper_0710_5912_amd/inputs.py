@@ -31,3 +31,21 @@ def batch_draws(nruns: int, seed: int = 1000):
     """Per-run shear rates log-uniform in [1e-3, 1e-1] for the batched workload."""
     rng = np.random.default_rng(seed)
     return 10.0 ** rng.uniform(-3.0, -1.0, nruns)
+
+
+CNN_LAYERS = ((2, 32), (32, 32), (32, 32), (32, 2))
+
+
+def cnn_init_params(seed: int = 0) -> np.ndarray:
+    """Seeded initial weights of the corrector network (float64 vector).
+
+    Layout per layer: W[co][ci][ky][kx] then b[co]; W uniform in
+    +-0.5 sqrt(6 / (9 ci)), b = 0.
+    """
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in CNN_LAYERS:
+        bound = np.sqrt(6.0 / (9 * ci)) * 0.5
+        parts.append(rng.uniform(-bound, bound, co * ci * 9))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts)
