@@ -182,6 +182,65 @@ int le_batch_profile(le_batch* b, int enable);
 int le_batch_stage_times(le_batch* b, double* ms, int64_t* launches, int32_t cap);
 void le_batch_destroy(le_batch* b);  /* NULL-safe */
 
+/*
+ * Learned coarse-step corrector (single inertial run).  After every plain
+ * step the network maps the state (phi, omega) to a residual r, applied as
+ *   phi += r_phi - mean(r_phi),  omega += r_omega,
+ * and psi is re-solved from the corrected omega (Poisson solve at the step's
+ * strain offset).  The mean-phi projection keeps the conserved mean exact.
+ *
+ * le_corrector_load: params = the network's FP32 weight vector (length
+ *   le_cnn_nparams(); per layer W[co][ci][ky][kx] then b[co], layers
+ *   2->32->32->32->2); scales = {in_phi, in_omega, out_phi, out_omega}.
+ *   Needs rho > 0, nx, ny >= 16 and nx*ny a multiple of 256 (LE_EINVAL).
+ * le_step_corrected: ncoarse corrected steps (LE_EINVAL before a load).
+ * le_restrict: factor x factor block means of phi and omega (real space) into
+ *   host arrays of (ny/factor)*(nx/factor) doubles (either may be NULL).
+ * le_set_fields: replace phi and omega (NULL: zero) and the step counter;
+ *   psi is re-solved from the flow constraint at that step.
+ */
+int le_corrector_load(le_ctx* c, const float* params, int32_t nparams, const float* scales);
+int le_step_corrected(le_ctx* c, int64_t ncoarse);
+int le_restrict(le_ctx* c, int32_t factor, double* phi_out, double* omega_out);
+int le_set_fields(le_ctx* c, const double* phi, const double* omega, int64_t step);
+
+/*
+ * Training the corrector network on the GPU (BF16 matrix-core kernels, FP32
+ * accumulation and master weights, Adam).  Pointers named *_dev are device
+ * memory (e.g. torch tensors); planes are [channel][H][W] FP32 with channel 0
+ * = phi and 1 = omega; batches stack planes: [B][2][H][W].  H, W: powers of
+ * two >= 16 with H*W a multiple of 256.  stream: hipStream_t or NULL.
+ *
+ * le_cnn_grad: loss = mean over the batch, channels and pixels of (r - t)^2
+ *   with r the network's output on x, t the target residual; its gradient
+ *   replaces the stored one (and is copied to grad_host when non-NULL).
+ * le_cnn_adam: one Adam step with the stored gradient.
+ * le_cnn_layer_fwd / le_cnn_layer_bwd (layer 0..3) run one convolution on
+ *   pixel-major BF16 inputs a_in_dev [H*W][Cin] (bit patterns): forward gives
+ *   the FP32 pre-activation [H*W][Cout] (and BF16 SiLU output for layers
+ *   0..2); backward takes dz_dev [H*W][Cout] FP32 and gives the weight and
+ *   bias gradient dw_dev (that layer's slice of the weight vector) and, for
+ *   layers 1..3 when dzprev_dev is given, the input gradient times silu'(zprev)
+ *   (zprev_dev NULL: the plain input gradient).
+ * le_cnn_mfma_probe: one 32x32x16 BF16 matrix product c = a b on host arrays
+ *   (row-major a 32x16, b 16x32 BF16 bit patterns, c 32x32 FP32).
+ */
+typedef struct le_cnn le_cnn;
+int le_cnn_nparams(void);
+int le_cnn_create(int32_t H, int32_t W, le_cnn** out);
+void le_cnn_destroy(le_cnn* c);  /* NULL-safe */
+int le_cnn_set_params(le_cnn* c, const float* params, int32_t n, const float* scales);
+int le_cnn_get_params(le_cnn* c, float* params, int32_t n);
+int le_cnn_forward(le_cnn* c, const float* x_dev, float* r_dev, void* stream);
+int le_cnn_grad(le_cnn* c, const float* x_dev, const float* t_dev, int32_t batch, double* loss,
+                float* grad_host, void* stream);
+int le_cnn_adam(le_cnn* c, float lr, float beta1, float beta2, float eps, void* stream);
+int le_cnn_layer_fwd(le_cnn* c, int32_t layer, const uint16_t* a_in_dev, float* z_out_dev,
+                     uint16_t* a_out_dev, void* stream);
+int le_cnn_layer_bwd(le_cnn* c, int32_t layer, const float* dz_dev, const uint16_t* a_in_dev,
+                     const float* zprev_dev, float* dzprev_dev, float* dw_dev, void* stream);
+int le_cnn_mfma_probe(const uint16_t* a, const uint16_t* b, float* c);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/le.h"
+#include "cnn.hpp"
 #include "common.hpp"
 #include "ops.hpp"
 
@@ -147,6 +148,13 @@ struct le_ctx {
   std::vector<hipEvent_t> events;  // kProfChunk * (LE_NSTAGES + 1)
   double stage_ms[LE_NSTAGES] = {0};
   int64_t stage_n[LE_NSTAGES] = {0};
+  Net* net = nullptr;              // learned corrector (single inertial run)
+  double* d_restrict = nullptr;    // restriction output
+};
+
+// Network with training state, driven through device pointers.
+struct le_cnn {
+  Net net;
 };
 
 // A batch handle owns an engine of many runs.
@@ -181,6 +189,12 @@ void release(Engine* e) {
   if (e->h_args) (void)hipHostFree(e->h_args);
   if (e->h_out) (void)hipHostFree(e->h_out);
   if (e->h_stage) (void)hipHostFree(e->h_stage);
+  if (e->net) {
+    net_destroy(e->net);
+    delete e->net;
+    e->net = nullptr;
+  }
+  if (e->d_restrict) (void)hipFree(e->d_restrict);
   if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
 }
 
@@ -695,6 +709,58 @@ int stage_times_of(Engine* e, double* ms, int64_t* launches, int32_t cap) {
   return LE_OK;
 }
 
+// Coarse steps each followed by the learned correction: omega to real
+// space, phi += r_phi - mean(r_phi), omega += r_omega, then psi from the
+// corrected omega by the Poisson solve at the step's strain offset.
+int step_corrected(Engine* e, int64_t ncoarse) {
+  if (!e || ncoarse < 0 || !e->net || e->nruns != 1) return LE_EINVAL;
+  RunHost& r = e->runs[0];
+  const Ops& o = e->classes[r.cls].ops;
+  const Run* d = desc(e, r);
+  int64_t remaining = ncoarse;
+  while (remaining > 0) {
+    const int64_t n0 = e->step;
+    int64_t count = remaining < kChunkCap ? remaining : kChunkCap;
+    for (int64_t k = 0; k < count; ++k) {
+      e->h_args[k].s = strain_offset(r.p, n0 + k);
+      e->h_args[k].pad = 0.0;
+      if (wrap_count(r.p, n0 + k + 1) != wrap_count(r.p, n0 + k)) {
+        count = k + 1;
+        break;
+      }
+    }
+    LE_TRY(hipMemcpyAsync(e->d_args, e->h_args, (size_t)count * sizeof(StepArgs),
+                          hipMemcpyHostToDevice, e->stream));
+    for (int64_t k = 0; k < count; ++k) {
+      const StepArgs* sa = e->d_args + k;
+      enqueue_step(e, sa, nullptr);
+      o.row_c2r(d, 1, r.p.ny, B_OM_S, B_OM_R, B_OM_S, B_OM_R, 1, e->stream);
+      int rc = r.tsize == sizeof(double)
+                   ? net_correct_fields<double>(e->net, static_cast<double*>(r.buf[B_PHI]),
+                                                static_cast<double*>(r.buf[B_OM_R]), e->stream)
+                   : net_correct_fields<float>(e->net, static_cast<float*>(r.buf[B_PHI]),
+                                               static_cast<float*>(r.buf[B_OM_R]), e->stream);
+      if (rc) return LE_EDEVICE;
+      o.row_r2c(d, 1, r.p.ny, B_OM_R, B_OM_S, e->stream);
+      o.column(COL_POISSON, d, 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, e->stream);
+    }
+    e->step = n0 + count;
+    const int64_t k_new = wrap_count(r.p, e->step);
+    if (k_new != r.wraps) {
+      enqueue_remap(e, r, k_new - r.wraps);
+      r.wraps = k_new;
+    }
+    LE_TRY(hipGetLastError());
+    LE_TRY(hipStreamSynchronize(e->stream));
+    remaining -= count;
+  }
+  if (ncoarse > 0) {
+    LE_RC(reduce_observables(e, r, false));
+    if (e->h_out[OBS_NONFINITE] != 0.0) return LE_ENONFINITE;
+  }
+  return LE_OK;
+}
+
 void destroy_engine(Engine* e) {
   if (!e) return;
   if (e->stream) (void)hipStreamSynchronize(e->stream);
@@ -803,6 +869,172 @@ int le_batch_profile(le_batch* b, int enable) {
 
 int le_batch_stage_times(le_batch* b, double* ms, int64_t* launches, int32_t cap) {
   return b ? stage_times_of(b->e, ms, launches, cap) : LE_EINVAL;
+}
+
+int le_corrector_load(le_ctx* c, const float* params, int32_t nparams, const float* scales) {
+  if (!c || !params || !scales || nparams != kCnnParams || c->nruns != 1) return LE_EINVAL;
+  RunHost& r = c->runs[0];
+  if (!r.inertial) return LE_EINVAL;
+  if (!c->net) {
+    Net* n = new (std::nothrow) Net();
+    if (!n) return LE_ENOMEM;
+    if (net_create(n, r.p.ny, r.p.nx, false)) {
+      delete n;
+      return LE_EINVAL;
+    }
+    c->net = n;
+  }
+  for (int k = 0; k < 4; ++k) c->net->scales[k] = scales[k];
+  if (net_set_params(c->net, params, c->stream)) return LE_EDEVICE;
+  LE_TRY(hipStreamSynchronize(c->stream));
+  return LE_OK;
+}
+
+int le_step_corrected(le_ctx* c, int64_t ncoarse) { return step_corrected(c, ncoarse); }
+
+int le_restrict(le_ctx* c, int32_t factor, double* phi_out, double* omega_out) {
+  if (!c || factor < 1) return LE_EINVAL;
+  RunHost& r = c->runs[0];
+  if (r.p.nx % factor || r.p.ny % factor) return LE_EINVAL;
+  const Ops& o = c->classes[r.cls].ops;
+  const size_t nc = r.n_real / ((size_t)factor * factor);
+  if (!c->d_restrict) LE_RC(alloc((void**)&c->d_restrict, r.n_real * sizeof(double)));
+  if (phi_out) {
+    o.restrict_real(desc(c, r), B_PHI, factor, c->d_restrict, c->stream);
+    LE_TRY(hipMemcpyAsync(phi_out, c->d_restrict, nc * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    LE_TRY(hipStreamSynchronize(c->stream));
+  }
+  if (omega_out) {
+    if (r.inertial) {
+      o.row_c2r(desc(c, r), 1, r.p.ny, B_OM_S, B_OM_R, B_OM_S, B_OM_R, 1, c->stream);
+      o.restrict_real(desc(c, r), B_OM_R, factor, c->d_restrict, c->stream);
+      LE_TRY(hipMemcpyAsync(omega_out, c->d_restrict, nc * sizeof(double),
+                            hipMemcpyDeviceToHost, c->stream));
+      LE_TRY(hipStreamSynchronize(c->stream));
+    } else {
+      std::memset(omega_out, 0, nc * sizeof(double));
+    }
+  }
+  return LE_OK;
+}
+
+int le_set_fields(le_ctx* c, const double* phi, const double* omega, int64_t step) {
+  if (!c || !phi || step < 0) return LE_EINVAL;
+  RunHost& r = c->runs[0];
+  const Ops& o = c->classes[r.cls].ops;
+  LE_RC(upload_real(c, r, phi, B_PHI));
+  c->step = step;
+  r.wraps = wrap_count(r.p, step);
+  if (r.inertial) {
+    if (omega) {
+      LE_RC(upload_real(c, r, omega, B_OM_R));
+    } else {
+      LE_TRY(hipMemsetAsync(r.buf[B_OM_R], 0, r.n_real * r.tsize, c->stream));
+    }
+    o.row_r2c(desc(c, r), 1, r.p.ny, B_OM_R, B_OM_S, c->stream);
+  }
+  LE_RC(solve_psi(c, r));
+  LE_TRY(hipStreamSynchronize(c->stream));
+  return LE_OK;
+}
+
+int le_cnn_nparams(void) { return kCnnParams; }
+
+int le_cnn_create(int32_t H, int32_t W, le_cnn** out) {
+  if (!out) return LE_EINVAL;
+  *out = nullptr;
+  int dev_count = 0;
+  if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) return LE_EDEVICE;
+  le_cnn* c = new (std::nothrow) le_cnn();
+  if (!c) return LE_ENOMEM;
+  const int rc = net_create(&c->net, H, W, true);
+  if (rc) {
+    delete c;
+    return rc == -1 ? LE_EINVAL : (rc == -2 ? LE_ENOMEM : LE_EDEVICE);
+  }
+  *out = c;
+  return LE_OK;
+}
+
+void le_cnn_destroy(le_cnn* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  net_destroy(&c->net);
+  delete c;
+}
+
+int le_cnn_set_params(le_cnn* c, const float* params, int32_t n, const float* scales) {
+  if (!c || !params || !scales || n != kCnnParams) return LE_EINVAL;
+  for (int k = 0; k < 4; ++k) c->net.scales[k] = scales[k];
+  if (net_set_params(&c->net, params, nullptr)) return LE_EDEVICE;
+  LE_TRY(hipMemset(c->net.m, 0, kCnnParams * sizeof(float)));
+  LE_TRY(hipMemset(c->net.v, 0, kCnnParams * sizeof(float)));
+  LE_TRY(hipDeviceSynchronize());
+  return LE_OK;
+}
+
+int le_cnn_get_params(le_cnn* c, float* params, int32_t n) {
+  if (!c || !params || n != kCnnParams) return LE_EINVAL;
+  LE_TRY(hipDeviceSynchronize());
+  LE_TRY(hipMemcpy(params, c->net.params, kCnnParams * sizeof(float), hipMemcpyDeviceToHost));
+  return LE_OK;
+}
+
+int le_cnn_forward(le_cnn* c, const float* x, float* r, void* stream) {
+  if (!c || !x || !r) return LE_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (net_forward_planes(&c->net, x, r, st)) return LE_EDEVICE;
+  LE_TRY(hipStreamSynchronize(st));
+  return LE_OK;
+}
+
+int le_cnn_grad(le_cnn* c, const float* xs, const float* ts, int32_t batch, double* loss,
+                float* grad_host, void* stream) {
+  if (!c || !xs || !ts || batch < 1) return LE_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  LE_TRY(hipMemsetAsync(c->net.grad, 0, kCnnParams * sizeof(float), st));
+  if (net_grad(&c->net, xs, ts, batch, loss, st)) return LE_EDEVICE;
+  if (grad_host) {
+    LE_TRY(hipMemcpyAsync(grad_host, c->net.grad, kCnnParams * sizeof(float),
+                          hipMemcpyDeviceToHost, st));
+    LE_TRY(hipStreamSynchronize(st));
+  }
+  return LE_OK;
+}
+
+int le_cnn_adam(le_cnn* c, float lr, float beta1, float beta2, float eps, void* stream) {
+  if (!c || !(lr >= 0.f)) return LE_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (net_adam(&c->net, lr, beta1, beta2, eps, st)) return LE_EDEVICE;
+  LE_TRY(hipStreamSynchronize(st));
+  return LE_OK;
+}
+
+int le_cnn_layer_fwd(le_cnn* c, int32_t layer, const uint16_t* a_in, float* z_out,
+                     uint16_t* a_out, void* stream) {
+  if (!c || !a_in || !z_out || layer < 0 || layer > 3 || (layer < 3 && !a_out))
+    return LE_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (net_layer_fwd(&c->net, layer, a_in, z_out, a_out, st)) return LE_EDEVICE;
+  LE_TRY(hipStreamSynchronize(st));
+  return LE_OK;
+}
+
+int le_cnn_layer_bwd(le_cnn* c, int32_t layer, const float* dz, const uint16_t* a_in,
+                     const float* zprev, float* dzprev, float* dw, void* stream) {
+  if (!c || !dz || !a_in || layer < 0 || layer > 3) return LE_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (net_layer_bwd(&c->net, layer, dz, a_in, zprev, dzprev, dw, st)) return LE_EDEVICE;
+  LE_TRY(hipStreamSynchronize(st));
+  return LE_OK;
+}
+
+int le_cnn_mfma_probe(const uint16_t* a, const uint16_t* b, float* c) {
+  if (!a || !b || !c) return LE_EINVAL;
+  int dev_count = 0;
+  if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) return LE_EDEVICE;
+  return mfma_probe(a, b, c, nullptr) ? LE_EDEVICE : LE_OK;
 }
 
 void le_batch_destroy(le_batch* b) {

@@ -32,6 +32,7 @@ struct Ops {
   void (*remap_spec)(const Run* run, int b, int dkr, hipStream_t st);
   void (*remap_real)(const Run* run, int bin, int bout, int dkr, hipStream_t st);
   void (*copy_real)(const Run* run, int bin, int bout, hipStream_t st);
+  void (*restrict_real)(const Run* run, int bin, int f, double* out, hipStream_t st);
 };
 
 // Fill *ops for precision (0 = double, 1 = float) and the grid; false if the

@@ -82,6 +82,9 @@ struct Misc {
   static void copy_real(const Run* run, int bin, int bout, hipStream_t st) {
     hipLaunchKernelGGL((k_copy_real<T>), dim3(1024), dim3(256), 0, st, run, bin, bout);
   }
+  static void restrict_real(const Run* run, int bin, int f, double* out, hipStream_t st) {
+    hipLaunchKernelGGL((k_restrict<T>), dim3(256), dim3(256), 0, st, run, bin, f, out);
+  }
 };
 
 template <typename T, int L>
@@ -131,6 +134,7 @@ bool fill_ops(int nx, int ny, Ops* o) {
   o->remap_spec = &Misc<T>::remap_spec;
   o->remap_real = &Misc<T>::remap_real;
   o->copy_real = &Misc<T>::copy_real;
+  o->restrict_real = &Misc<T>::restrict_real;
   return true;
 }
 

@@ -433,6 +433,21 @@ __global__ void k_remap_real(const Run* __restrict__ run, int bin, int bout, int
   }
 }
 
+// f x f block means of a real field into out[(ny/f)][(nx/f)] (FP64).
+template <typename T>
+__global__ void k_restrict(const Run* __restrict__ run, int bin, int f, double* __restrict__ out) {
+  const int nx = run->g.nx, ny = run->g.ny, cx = nx / f, cy = ny / f;
+  const T* in = bufp<const T>(*run, bin);
+  const double inv = 1.0 / ((double)f * f);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cx * cy; e += gridDim.x * blockDim.x) {
+    const int J = e / cx, I = e % cx;
+    double acc = 0.0;
+    for (int a = 0; a < f; ++a)
+      for (int b = 0; b < f; ++b) acc += (double)in[(size_t)(J * f + a) * nx + I * f + b];
+    out[e] = acc * inv;
+  }
+}
+
 // Plain copy of a real field (bin -> bout).
 template <typename T>
 __global__ void k_copy_real(const Run* __restrict__ run, int bin, int bout) {

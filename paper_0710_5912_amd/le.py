@@ -20,7 +20,11 @@ LE_FP64, LE_FP32 = 0, 1
 SYMBOLS = ("le_create", "le_step", "le_observables", "le_destroy", "le_get_state",
            "le_set_state", "le_strerror", "le_profile", "le_stage_times", "le_last_error",
            "le_batch_create", "le_batch_step", "le_batch_observables", "le_batch_get_state",
-           "le_batch_profile", "le_batch_stage_times", "le_batch_destroy")
+           "le_batch_profile", "le_batch_stage_times", "le_batch_destroy",
+           "le_corrector_load", "le_step_corrected", "le_restrict", "le_set_fields",
+           "le_cnn_nparams", "le_cnn_create", "le_cnn_destroy", "le_cnn_set_params",
+           "le_cnn_get_params", "le_cnn_forward", "le_cnn_grad", "le_cnn_adam",
+           "le_cnn_layer_fwd", "le_cnn_layer_bwd", "le_cnn_mfma_probe")
 LE_NSTAGES = 6
 STAGES = ("row_inv_flow", "advect", "column_ch", "row_inv_phi", "mu_source", "column_flow")
 
@@ -99,6 +103,42 @@ def lib():
         L.le_batch_stage_times.restype = C.c_int
         L.le_batch_destroy.argtypes = [C.c_void_p]
         L.le_batch_destroy.restype = None
+        _FP = C.POINTER(C.c_float)
+        _U16 = C.POINTER(C.c_uint16)
+        L.le_corrector_load.argtypes = [C.c_void_p, _FP, C.c_int32, _FP]
+        L.le_corrector_load.restype = C.c_int
+        L.le_step_corrected.argtypes = [C.c_void_p, C.c_int64]
+        L.le_step_corrected.restype = C.c_int
+        L.le_restrict.argtypes = [C.c_void_p, C.c_int32, _DP, _DP]
+        L.le_restrict.restype = C.c_int
+        L.le_set_fields.argtypes = [C.c_void_p, _DP, _DP, C.c_int64]
+        L.le_set_fields.restype = C.c_int
+        L.le_cnn_nparams.argtypes = []
+        L.le_cnn_nparams.restype = C.c_int
+        L.le_cnn_create.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_void_p)]
+        L.le_cnn_create.restype = C.c_int
+        L.le_cnn_destroy.argtypes = [C.c_void_p]
+        L.le_cnn_destroy.restype = None
+        L.le_cnn_set_params.argtypes = [C.c_void_p, _FP, C.c_int32, _FP]
+        L.le_cnn_set_params.restype = C.c_int
+        L.le_cnn_get_params.argtypes = [C.c_void_p, _FP, C.c_int32]
+        L.le_cnn_get_params.restype = C.c_int
+        L.le_cnn_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.le_cnn_forward.restype = C.c_int
+        L.le_cnn_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                  C.POINTER(C.c_double), _FP, C.c_void_p]
+        L.le_cnn_grad.restype = C.c_int
+        L.le_cnn_adam.argtypes = [C.c_void_p, C.c_float, C.c_float, C.c_float, C.c_float,
+                                  C.c_void_p]
+        L.le_cnn_adam.restype = C.c_int
+        L.le_cnn_layer_fwd.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p]
+        L.le_cnn_layer_fwd.restype = C.c_int
+        L.le_cnn_layer_bwd.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.le_cnn_layer_bwd.restype = C.c_int
+        L.le_cnn_mfma_probe.argtypes = [_U16, _U16, _FP]
+        L.le_cnn_mfma_probe.restype = C.c_int
         L.le_last_error.argtypes = []
         L.le_last_error.restype = C.c_char_p
         L.le_strerror.argtypes = [C.c_int]
@@ -213,6 +253,40 @@ class Context:
             raise LeError(rc, "le_stage_times")
         return {STAGES[k]: (float(ms[k]), int(n[k])) for k in range(LE_NSTAGES)}
 
+    def corrector_load(self, params, scales) -> None:
+        """Install the corrector network (FP32 weight vector, 4 scales)."""
+        self._check()
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        sc = np.ascontiguousarray(scales, dtype=np.float32)
+        rc = lib().le_corrector_load(self._h, p.ctypes.data_as(C.POINTER(C.c_float)), p.size,
+                                     sc.ctypes.data_as(C.POINTER(C.c_float)))
+        if rc != LE_OK:
+            raise LeError(rc, "le_corrector_load")
+
+    def step_corrected(self, ncoarse: int) -> None:
+        self._check()
+        rc = lib().le_step_corrected(self._h, int(ncoarse))
+        if rc != LE_OK:
+            raise LeError(rc, "le_step_corrected")
+
+    def restrict(self, factor: int):
+        """(phi, omega) block means over factor x factor cells."""
+        self._check()
+        shape = (self.shape[0] // factor, self.shape[1] // factor)
+        phi, om = np.empty(shape), np.empty(shape)
+        rc = lib().le_restrict(self._h, int(factor), _dp(phi), _dp(om))
+        if rc != LE_OK:
+            raise LeError(rc, "le_restrict")
+        return phi, om
+
+    def set_fields(self, phi, omega, step: int) -> None:
+        self._check()
+        phi = _f64(phi, self.shape)
+        omega = _f64(omega, self.shape)
+        rc = lib().le_set_fields(self._h, _dp(phi), _dp(omega), int(step))
+        if rc != LE_OK:
+            raise LeError(rc, "le_set_fields")
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
             lib().le_destroy(self._h)
@@ -319,3 +393,101 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Net:
+    """The corrector network with training state on the GPU.
+
+    Tensors passed in are torch device tensors (FP32 planes [B][2][H][W], or
+    the per-layer BF16 bit patterns as int16); the library reads and writes
+    them in place.
+    """
+
+    def __init__(self, H: int, W: int):
+        h = C.c_void_p()
+        rc = lib().le_cnn_create(int(H), int(W), C.byref(h))
+        if rc != LE_OK:
+            raise LeError(rc, "le_cnn_create")
+        self._h = h
+        self.H, self.W = H, W
+
+    @staticmethod
+    def nparams() -> int:
+        return lib().le_cnn_nparams()
+
+    def set_params(self, params, scales) -> None:
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        sc = np.ascontiguousarray(scales, dtype=np.float32)
+        rc = lib().le_cnn_set_params(self._h, p.ctypes.data_as(C.POINTER(C.c_float)), p.size,
+                                     sc.ctypes.data_as(C.POINTER(C.c_float)))
+        if rc != LE_OK:
+            raise LeError(rc, "le_cnn_set_params")
+
+    def get_params(self) -> np.ndarray:
+        p = np.empty(self.nparams(), dtype=np.float32)
+        rc = lib().le_cnn_get_params(self._h, p.ctypes.data_as(C.POINTER(C.c_float)), p.size)
+        if rc != LE_OK:
+            raise LeError(rc, "le_cnn_get_params")
+        return p
+
+    def forward(self, x, r, stream=None) -> None:
+        rc = lib().le_cnn_forward(self._h, _ptr(x), _ptr(r), stream)
+        if rc != LE_OK:
+            raise LeError(rc, "le_cnn_forward")
+
+    def grad(self, xs, ts, batch: int, want_grad: bool = False, stream=None):
+        loss = C.c_double()
+        g = np.empty(self.nparams(), dtype=np.float32) if want_grad else None
+        rc = lib().le_cnn_grad(self._h, _ptr(xs), _ptr(ts), int(batch), C.byref(loss),
+                               None if g is None else g.ctypes.data_as(C.POINTER(C.c_float)),
+                               stream)
+        if rc != LE_OK:
+            raise LeError(rc, "le_cnn_grad")
+        return loss.value, g
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+             stream=None) -> None:
+        rc = lib().le_cnn_adam(self._h, lr, beta1, beta2, eps, stream)
+        if rc != LE_OK:
+            raise LeError(rc, "le_cnn_adam")
+
+    def layer_fwd(self, layer, a_in, z_out, a_out=None, stream=None) -> None:
+        rc = lib().le_cnn_layer_fwd(self._h, int(layer), _ptr(a_in), _ptr(z_out), _ptr(a_out),
+                                    stream)
+        if rc != LE_OK:
+            raise LeError(rc, "le_cnn_layer_fwd")
+
+    def layer_bwd(self, layer, dz, a_in, zprev=None, dzprev=None, dw=None, stream=None) -> None:
+        rc = lib().le_cnn_layer_bwd(self._h, int(layer), _ptr(dz), _ptr(a_in), _ptr(zprev),
+                                    _ptr(dzprev), _ptr(dw), stream)
+        if rc != LE_OK:
+            raise LeError(rc, "le_cnn_layer_bwd")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().le_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mfma_probe(a_bits: np.ndarray, b_bits: np.ndarray) -> np.ndarray:
+    """c = a b on one matrix-core tile (BF16 bit patterns in, FP32 out)."""
+    a = np.ascontiguousarray(a_bits, dtype=np.uint16)
+    b = np.ascontiguousarray(b_bits, dtype=np.uint16)
+    c = np.empty((32, 32), dtype=np.float32)
+    rc = lib().le_cnn_mfma_probe(a.ctypes.data_as(C.POINTER(C.c_uint16)),
+                                 b.ctypes.data_as(C.POINTER(C.c_uint16)),
+                                 c.ctypes.data_as(C.POINTER(C.c_float)))
+    if rc != LE_OK:
+        raise LeError(rc, "le_cnn_mfma_probe")
+    return c

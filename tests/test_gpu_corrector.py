@@ -1,0 +1,91 @@
+"""The corrected coarse step in the engine, and the restriction/set-up calls."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import cnn
+from oracle import model_h as mh
+from paper_0710_5912_amd import configs, inputs
+
+pytestmark = pytest.mark.gpu
+
+le = pytest.importorskip("paper_0710_5912_amd.le")
+
+
+def test_restrict_is_block_mean():
+    p = configs.model_h(64, 64, gdot=0.1)
+    phi0 = inputs.noise_phi0(64, 64, 3, amp=0.5)
+    om0 = inputs.noise_omega0(64, 64, 3)
+    with le.Context(p, phi0, om0) as c:
+        c.step(20)
+        st = c.get_state()
+        phi_c, om_c = c.restrict(4)
+    assert np.max(np.abs(phi_c - cnn.restrict4(st["phi"]))) <= 1e-15
+    assert np.max(np.abs(om_c - cnn.restrict4(st["omega"]))) <= 1e-15
+    assert abs(phi_c.mean() - st["phi"].mean()) <= 1e-15
+
+
+def test_set_fields_resolves_psi():
+    p = configs.model_h(32, 32, gdot=0.2)
+    phi0 = inputs.noise_phi0(32, 32, 4, amp=0.5)
+    om0 = inputs.noise_omega0(32, 32, 4)
+    with le.Context(p, np.zeros((32, 32))) as c:
+        c.set_fields(phi0, om0, 137)
+        g = c.get_state()
+    op = mh.Params(**p)
+    s = mh.strain_offset(op, 137)
+    _, psi = mh.stage_flow(mh.Params(**dict(p, dt=0.0)), om0 - om0.mean(), np.zeros_like(om0), s)
+    assert g["step"] == 137 and g["wraps"] == mh.wrap_count(op, 137)
+    assert np.max(np.abs(g["psi"] - psi)) <= 1e-12 * np.max(np.abs(psi))
+
+
+def test_zero_network_leaves_the_plain_step():
+    """With the last layer zeroed the residual vanishes: corrected = plain."""
+    p = configs.model_h(64, 64, gdot=0.5, rho=1.0)
+    phi0 = inputs.noise_phi0(64, 64, 5, amp=0.5)
+    params = inputs.cnn_init_params(1)
+    params[19104:] = 0.0
+    with le.Context(p, phi0) as a, le.Context(p, phi0) as b:
+        a.corrector_load(params, [1.0, 10.0, 1.0, 1.0])
+        a.step_corrected(220)          # crosses the wrap at strain 0.5 (step 200)
+        b.step(220)
+        ga, gb = a.get_state(), b.get_state()
+    assert ga["wraps"] == gb["wraps"] == 1
+    for k in ("phi", "omega", "psi"):
+        assert np.max(np.abs(ga[k] - gb[k])) <= 1e-12 * np.max(np.abs(gb[k])), k
+
+
+def test_corrected_step_applies_the_network():
+    """One corrected step = plain step + network residual (mean-free in phi)."""
+    p = configs.model_h(64, 64, gdot=0.1, rho=1.0)
+    phi0 = inputs.noise_phi0(64, 64, 6, amp=0.6)
+    params = inputs.cnn_init_params(2) * 3.0
+    scales = [1.0, 10.0, 0.05, 0.01]
+    with le.Context(p, phi0) as a, le.Context(p, phi0) as b:
+        a.corrector_load(params, scales)
+        a.step_corrected(1)
+        b.step(1)
+        ga, gb = a.get_state(), b.get_state()
+    x = np.stack([gb["phi"], gb["omega"]])
+    rparams = np.concatenate([np.concatenate([cnn.bf16_round(Wl).ravel(),
+                                              np.asarray(bb, np.float32).astype(np.float64)])
+                              for Wl, bb in cnn.unpack(np.asarray(params, np.float32))])
+    r = cnn.forward(rparams, x, scales, round_act=cnn.bf16_round)
+    d_phi = ga["phi"] - gb["phi"]
+    d_om = ga["omega"] - gb["omega"]
+    assert abs(d_phi.mean()) <= 1e-15
+    assert abs(ga["phi"].mean() - phi0.mean()) <= 1e-14
+    assert np.max(np.abs(d_phi - (r[0] - r[0].mean()))) <= 2e-2 * np.max(np.abs(r[0]))
+    assert np.max(np.abs(d_om - r[1])) <= 2e-2 * np.max(np.abs(r[1]))
+
+
+def test_corrector_needs_inertia_and_a_load():
+    p = configs.model_h(32, 32, rho=0.0)
+    with le.Context(p, inputs.noise_phi0(32, 32, 0)) as c:
+        with pytest.raises(le.LeError):
+            c.corrector_load(inputs.cnn_init_params(0), [1, 1, 1, 1])
+    p = configs.model_h(32, 32, rho=1.0)
+    with le.Context(p, inputs.noise_phi0(32, 32, 0)) as c:
+        with pytest.raises(le.LeError):
+            c.step_corrected(1)
