@@ -249,6 +249,16 @@ def main():
                              dominant=d, dominant_frac=rw[d]["gbs"] / HBM_PEAK_GBS)
         print("bench: variant batched_96", file=sys.stderr, flush=True)
         var["batched_96_fp32"] = run_batch(le, torch, 500, 50, 100)
+        print("bench: variant corrector", file=sys.stderr, flush=True)
+        from paper_0710_5912_amd import corrector
+        cp, cs, meta = corrector.load()
+        ev = corrector.evaluate(cp, cs, gdot=0.01, seed=99, log=lambda m: None)
+        var["corrector_256_from_1024"] = dict(
+            value=ev["corrected_fine_equiv_rate"], plain_fine_value=ev["fine_rate"],
+            gain=ev["gain"], L_err_mean=ev["err_mean_corrected"],
+            L_err_max=ev["err_max_corrected"], L_err_mean_plain_coarse=ev["err_mean_coarse"],
+            note="fine-equivalent site-updates/s of 256^2 corrected steps at 4 dt against "
+                 "the 1024^2 FP64 plain run, t = 5..50, gdot = 0.01, held-out seed")
         # the large single-GPU grid
         p = configs.LARGE_4096["params"]
         print("bench: variant fp64_4096", file=sys.stderr, flush=True)

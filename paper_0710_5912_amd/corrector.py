@@ -1,0 +1,224 @@
+"""Data generation, training and evaluation of the learned coarse-step corrector.
+
+Orchestration only: every step, restriction, network pass and optimiser
+update runs in the HIP library (paper_0710_5912_amd.le); torch holds the
+training tensors in device memory.
+
+Workload (the corrector configuration): fine runs on a 1024 x 1024 grid
+(spacing 1, FP64, rho = eta = 1, dt = 0.005) at shear rates in [0.003, 0.03]
+are sampled after t = 5; each sample is restricted by 4 x 4 block means to the
+256 x 256 coarse grid (spacing 4), advanced by one plain coarse step of
+4 dt = 0.02, and paired with the restricted fine state 4 fine steps later.
+The network learns the residual between the two; at inference it corrects
+each coarse step.
+
+    python -m paper_0710_5912_amd.corrector train --out weights.npz
+    python -m paper_0710_5912_amd.corrector eval --weights weights.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import configs, inputs, le
+
+FINE_N = 1024
+FACTOR = 4
+DT = 0.005
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "corrector_c4.npz")
+
+
+def fine_params(gdot, n=FINE_N):
+    return configs.model_h(n, n, gdot=gdot, rho=1.0, dt=DT)
+
+
+def coarse_params(gdot, n=FINE_N, factor=FACTOR):
+    nc = n // factor
+    return configs.model_h(nc, nc, gdot=gdot, rho=1.0, dt=DT * factor, lx=float(n),
+                           ly=float(n))
+
+
+def _wraps(params, n):
+    c = params["lx"] / params["ly"]
+    X = params["gdot"] * (float(n) * params["dt"])
+    return math.floor((X + 0.5 * c) / c)
+
+
+def generate_pairs(n_pairs=2000, gdots=(0.003, 0.005, 0.008, 0.012, 0.018, 0.03),
+                   seeds=(11, 12, 13, 14, 15, 16), t_start=5.0, t_end=50.0, n=FINE_N,
+                   factor=FACTOR, log=print):
+    """(x, t) pairs: x = coarse-stepped restricted state, t = target residual."""
+    per_run = -(-n_pairs // len(gdots))
+    k0 = int(round(t_start / DT))
+    k1 = int(round(t_end / DT))
+    stride = max(factor, ((k1 - k0) // per_run) // factor * factor)
+    xs, ts = [], []
+    for gdot, seed in zip(gdots, seeds):
+        fp = fine_params(gdot, n)
+        cp = coarse_params(gdot, n, factor)
+        nc = n // factor
+        fine = le.Context(fp, inputs.noise_phi0(n, n, seed, amp=0.05))
+        coarse = le.Context(cp, np.zeros((nc, nc)))
+        fine.step(k0)
+        step = k0
+        got = 0
+        t0 = time.time()
+        while got < per_run and step + factor <= k1:
+            phi_c, om_c = fine.restrict(factor)
+            fine.step(factor)
+            phi_n, om_n = fine.restrict(factor)
+            if _wraps(fp, step) == _wraps(fp, step + factor):   # skip steps across a wrap
+                coarse.set_fields(phi_c, om_c, step // factor)
+                coarse.step(1)
+                g = coarse.get_state()
+                xs.append(np.stack([g["phi"], g["omega"]]).astype(np.float32))
+                ts.append(np.stack([phi_n - g["phi"], om_n - g["omega"]]).astype(np.float32))
+                got += 1
+            fine.step(stride - factor)
+            step += stride
+        fine.close()
+        coarse.close()
+        log(f"corrector data: gdot={gdot} seed={seed} pairs={got} ({time.time() - t0:.1f} s)")
+    return np.stack(xs[:n_pairs]), np.stack(ts[:n_pairs])
+
+
+def scales_from(xs, ts):
+    """Per-channel input and output scales: inputs and targets at unit RMS."""
+    def rms(a):
+        return float(np.sqrt(np.mean(a.astype(np.float64) ** 2))) or 1.0
+    return np.array([1.0 / rms(xs[:, 0]), 1.0 / rms(xs[:, 1]), rms(ts[:, 0]), rms(ts[:, 1])],
+                    dtype=np.float32)
+
+
+def train(xs, ts, epochs=20, batch=16, lr=1e-3, seed=0, log=print):
+    import torch
+
+    nc = xs.shape[-1]
+    scales = scales_from(xs, ts)
+    net = le.Net(nc, nc)
+    net.set_params(inputs.cnn_init_params(seed).astype(np.float32), scales)
+    X = torch.tensor(xs, device="cuda")
+    T = torch.tensor(ts, device="cuda")
+    rng = np.random.default_rng(seed)
+    n = xs.shape[0]
+    history = []
+    for ep in range(epochs):
+        order = rng.permutation(n)
+        tot = 0.0
+        for b in range(0, n - batch + 1, batch):
+            idx = torch.tensor(order[b:b + batch], device="cuda")
+            loss, _ = net.grad(X[idx].contiguous(), T[idx].contiguous(), batch)
+            net.adam(lr * (0.5 ** (ep // 8)))
+            tot += loss
+        mean = tot / (n // batch)
+        history.append(mean)
+        log(f"corrector train: epoch {ep} loss {mean:.4e} (relative {mean:.3e})")
+    params = net.get_params()
+    net.close()
+    return params, scales, history
+
+
+def evaluate(params, scales, gdot=0.01, seed=99, t0=5.0, t_end=50.0, every=0.5, n=FINE_N,
+             factor=FACTOR, log=print):
+    """L(t) of the plain fine run, the corrected coarse run and the plain
+    coarse run from the same restricted state at t0, with wall times."""
+    import torch
+
+    fp, cp = fine_params(gdot, n), coarse_params(gdot, n, factor)
+    nc = n // factor
+    fine = le.Context(fp, inputs.noise_phi0(n, n, seed, amp=0.05))
+    k0 = int(round(t0 / DT))
+    fine.step(k0)
+    phi_c, om_c = fine.restrict(factor)
+    nsamp = int(round((t_end - t0) / every))
+    kf, kc = int(round(every / DT)), int(round(every / (DT * factor)))
+    out = {"t": [], "fine": [], "corrected": [], "coarse": []}
+    torch.cuda.synchronize()
+    t_a = time.perf_counter()
+    for i in range(nsamp):
+        fine.step(kf)
+        o, _ = fine.observables(sk=False)
+        out["t"].append(o["t"])
+        out["fine"].append(o["Ls"])
+    wall_fine = time.perf_counter() - t_a
+    fine.close()
+    for name in ("corrected", "coarse"):
+        c = le.Context(cp, np.zeros((nc, nc)))
+        c.set_fields(phi_c, om_c, k0 // factor)
+        if name == "corrected":
+            c.corrector_load(params, scales)
+        t_a = time.perf_counter()
+        for i in range(nsamp):
+            if name == "corrected":
+                c.step_corrected(kc)
+            else:
+                c.step(kc)
+            o, _ = c.observables(sk=False)
+            out[name].append(o["Ls"])
+        out["wall_" + name] = time.perf_counter() - t_a
+        c.close()
+    out["wall_fine"] = wall_fine
+    f = np.array(out["fine"])
+    for name in ("corrected", "coarse"):
+        e = np.abs(np.array(out[name]) - f) / f
+        out["err_mean_" + name] = float(e.mean())
+        out["err_max_" + name] = float(e.max())
+    sites_fine = n * n * (t_end - t0) / DT
+    out["fine_rate"] = sites_fine / wall_fine
+    out["corrected_fine_equiv_rate"] = sites_fine / out["wall_corrected"]
+    out["gain"] = wall_fine / out["wall_corrected"]
+    log(f"corrector eval gdot={gdot}: L err mean corrected {out['err_mean_corrected']:.3f} "
+        f"plain coarse {out['err_mean_coarse']:.3f}, gain {out['gain']:.1f}x")
+    return out
+
+
+def save(path, params, scales, history, meta):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    np.savez(path, params=np.asarray(params, np.float32), scales=np.asarray(scales, np.float32),
+             history=np.asarray(history), meta=json.dumps(meta))
+
+
+def load(path=WEIGHTS):
+    with np.load(path, allow_pickle=False) as z:
+        return z["params"], z["scales"], json.loads(str(z["meta"]))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=("train", "eval"))
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--weights", default=WEIGHTS)
+    ap.add_argument("--pairs", type=int, default=2000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--seeds", type=int, nargs="*", default=[99, 98, 97])
+    ap.add_argument("--gdots", type=float, nargs="*", default=[0.003, 0.01, 0.03])
+    args = ap.parse_args(argv)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    if args.cmd == "train":
+        t0 = time.time()
+        xs, ts = generate_pairs(args.pairs, log=log)
+        t1 = time.time()
+        params, scales, hist = train(xs, ts, epochs=args.epochs, log=log)
+        t2 = time.time()
+        meta = dict(pairs=int(xs.shape[0]), epochs=args.epochs, data_s=t1 - t0,
+                    train_s=t2 - t1, fine=FINE_N, factor=FACTOR)
+        save(args.out, params, scales, hist, meta)
+        print(json.dumps(dict(meta, final_loss=hist[-1], first_loss=hist[0])))
+    else:
+        params, scales, _ = load(args.weights)
+        res = []
+        for g in args.gdots:
+            for s in args.seeds:
+                r = evaluate(params, scales, gdot=g, seed=s, log=log)
+                res.append({k: v for k, v in r.items() if not isinstance(v, list)})
+        print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -64,6 +64,15 @@ def lib():
     """Load the HIP library once; raise if it is missing."""
     global _LIB
     if _LIB is None:
+        # torch carries its own HIP runtime next to the system one this
+        # library links; both work in one process only when torch has
+        # initialised the device first, so let it do so before loading.
+        try:
+            import torch
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with `python -m paper_0710_5912_amd.build`")
