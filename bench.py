@@ -183,6 +183,10 @@ def main():
     ap.add_argument("--obs-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="short pass for hardware counters: a 512 MiB device copy "
+                         "(calibration of FETCH_SIZE/WRITE_SIZE) then 50 directly launched "
+                         "steps of the 1024^2 FP64 workload; prints no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -197,6 +201,18 @@ def main():
     from paper_0710_5912_amd import configs, le
 
     params = configs.single_1024(rho=1.0, gdot=0.01)["params"]
+    if args.profile_pass:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        from paper_0710_5912_amd import inputs
+        ctx = le.Context(params, inputs.noise_phi0(1024, 1024, 0), precision="fp64")
+        ctx.profile(True)      # direct launches: one dispatch per stage and step
+        ctx.step(50)
+        print(json.dumps({"profile_pass": ctx.stage_times()}))
+        ctx.close()
+        return
     print(f"bench: 1024x1024 fp64 inertial, {args.warmup} warmup + {args.steps} timed steps",
           file=sys.stderr, flush=True)
     r = run_variant(le, torch, params, "fp64", args.steps, args.warmup, args.obs_every)
