@@ -150,6 +150,30 @@ def roofline_of(params, precision, times):
     return dom, rows
 
 
+def traffic_of(kernel, precision, nx):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter record,
+    or None when there is none for this workload or the kernel sources changed since."""
+    import glob
+    import hashlib
+
+    if precision != "fp64" or nx != 1024:
+        return None
+    path = os.path.join(ROOT, "profiles", "modelh_1024x1024_fp64_traffic.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("traffic-record: "):
+            rec = json.loads(line[len("traffic-record: "):])
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_0710_5912_amd", "csrc", "*"))):
+        h.update(open(p, "rb").read())
+    if rec is None or rec["source_hash"] != h.hexdigest()[:16] or kernel not in rec["kernels"]:
+        return None
+    k = rec["kernels"][kernel]
+    return (k["fetch_kib"] * rec["fetch_factor"] + k["write_kib"] * rec["write_factor"]) * 1024.0
+
+
 def cpu_baseline(params, budget_s=15.0):
     """The FP64 oracle, untuned, on a bounded number of steps of the same workload."""
     import numpy as np
@@ -242,7 +266,8 @@ def main():
                      "timing": "HIP events around each stage launch, 1000 directly launched "
                                "steps after the timed region, same stream", "achieved": rows[dom]["gbs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": rows[dom]["gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": rows[dom]["gbs"] / HBM_PEAK_GBS,
+                     "traffic": traffic_of(dom, "fp64", 1024),
                      "bytes_per_launch": rows[dom]["bytes"],
                      "avg_launch_us": rows[dom]["avg_us"]},
         "stages": {k: {"avg_us": round(v["avg_us"], 2), "GBs": round(v["gbs"], 1)}
@@ -278,11 +303,14 @@ def main():
         # the large single-GPU grid
         p = configs.LARGE_4096["params"]
         print("bench: variant fp64_4096", file=sys.stderr, flush=True)
-        rv = run_variant(le, torch, p, "fp64", 200, 20, 100)
+        rv = run_variant(le, torch, p, "fp64", 200, 20, 100, prof_steps=100)
         d, rw = roofline_of(p, "fp64", rv["times"])
         var["fp64_4096_inertial"] = dict(value=4096 * 4096 * 200 / (rv["gpu_ms"] * 1e-3),
                                          ms_per_step=rv["gpu_ms"] / 200, dominant=d,
-                                         dominant_frac=rw[d]["gbs"] / HBM_PEAK_GBS)
+                                         dominant_frac=rw[d]["gbs"] / HBM_PEAK_GBS,
+                                         stages={k: {"avg_us": round(v["avg_us"], 1),
+                                                     "GBs": round(v["gbs"], 1)}
+                                                 for k, v in rw.items()})
         out["variants"] = var
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
