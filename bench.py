@@ -207,6 +207,7 @@ def main():
     ap.add_argument("--obs-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--profile-size", type=int, default=1024)
     ap.add_argument("--profile-pass", action="store_true",
                     help="short pass for hardware counters: a 512 MiB device copy "
                          "(calibration of FETCH_SIZE/WRITE_SIZE) then 50 directly launched "
@@ -231,9 +232,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         from paper_0710_5912_amd import inputs
-        ctx = le.Context(params, inputs.noise_phi0(1024, 1024, 0), precision="fp64")
+        n = args.profile_size
+        pp = configs.model_h(n, n, gdot=0.01, rho=1.0)
+        ctx = le.Context(pp, inputs.noise_phi0(n, n, 0), precision="fp64")
         ctx.profile(True)      # direct launches: one dispatch per stage and step
-        ctx.step(50)
+        ctx.step(50 if n <= 1024 else 10)
         print(json.dumps({"profile_pass": ctx.stage_times()}))
         ctx.close()
         return

@@ -538,22 +538,16 @@ int create_engine(int32_t n, const le_params* ps, const double* const* phi0s,
       rc = rc ? rc : alloc(&r.buf[B_OM_S], sb);
       rc = rc ? rc : alloc(&r.buf[B_OMH], sb);
     }
-    rc = rc ? rc : alloc(&r.twx, (size_t)r.p.nx * 2 * r.tsize);
-    rc = rc ? rc : alloc(&r.twy, (size_t)r.p.ny * 4 * r.tsize);
+    // twiddle tables are FP64 for both precisions (FP32 runs round each
+    // twiddle once, from FP64)
+    rc = rc ? rc : alloc(&r.twx, (size_t)r.p.nx * 2 * sizeof(double));
+    rc = rc ? rc : alloc(&r.twy, (size_t)r.p.ny * 4 * sizeof(double));
     if (!rc) {
-      if (r.tsize == sizeof(double)) {
-        auto a = twiddles<double>(r.p.nx);
-        auto b = twiddles<double>(2 * r.p.ny);
-        if (hipMemcpy(r.twx, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice) ||
-            hipMemcpy(r.twy, b.data(), b.size() * sizeof(double), hipMemcpyHostToDevice))
-          rc = LE_EDEVICE;
-      } else {
-        auto a = twiddles<float>(r.p.nx);
-        auto b = twiddles<float>(2 * r.p.ny);
-        if (hipMemcpy(r.twx, a.data(), a.size() * sizeof(float), hipMemcpyHostToDevice) ||
-            hipMemcpy(r.twy, b.data(), b.size() * sizeof(float), hipMemcpyHostToDevice))
-          rc = LE_EDEVICE;
-      }
+      auto a = twiddles<double>(r.p.nx);
+      auto b = twiddles<double>(2 * r.p.ny);
+      if (hipMemcpy(r.twx, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice) ||
+          hipMemcpy(r.twy, b.data(), b.size() * sizeof(double), hipMemcpyHostToDevice))
+        rc = LE_EDEVICE;
     }
     const Ops& o = e->classes[r.cls].ops;
     e->nsblk_max = std::max(e->nsblk_max, o.obs_blocks(r.p.nx));

@@ -42,8 +42,8 @@ enum Buf {
 struct Run {
   Geo g;
   void* buf[NBUF];
-  const void* twx;   // exp(-2 pi i k / nx), k < nx
-  const void* twy;   // exp(-2 pi i k / (2 ny)), k < 2 ny
+  const void* twx;   // FP64 complex exp(-2 pi i k / nx), k < nx
+  const void* twy;   // FP64 complex exp(-2 pi i k / (2 ny)), k < 2 ny
 };
 
 // Column-kernel variants (per-mode update applied between the transforms).

@@ -25,6 +25,35 @@ struct alignas(2 * sizeof(T)) c2 {
   T x, y;
 };
 
+// Pointer into device global memory.  The run descriptors hold plain
+// pointers; giving them the global address space lets every access compile
+// to global_load/store, which (unlike flat accesses) do not share the LDS
+// wait counter, so LDS passes do not wait on outstanding memory traffic.
+template <typename T>
+using gp = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gp<T> to_global(const void* p) {
+  return (gp<T>)(p);
+}
+
+// Whole-value load and store of a complex through a global pointer (one
+// 8- or 16-byte access).
+template <typename T>
+using vec2 = T __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ c2<T> ldg(gp<const c2<T>> p) {
+  const vec2<T> v = *reinterpret_cast<gp<const vec2<T>>>(p);
+  return {v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ c2<T> ldg(gp<c2<T>> p) {
+  return ldg<T>(static_cast<gp<const c2<T>>>(p));
+}
+template <typename T>
+__device__ __forceinline__ void stg(gp<c2<T>> p, c2<T> a) {
+  *reinterpret_cast<gp<vec2<T>>>(p) = vec2<T>{a.x, a.y};
+}
+
 template <typename T>
 __device__ __forceinline__ c2<T> cadd(c2<T> a, c2<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>
@@ -110,15 +139,62 @@ constexpr int first_radix(int L, int E) {
 // Elements per thread used for a transform of length L.
 constexpr int elems_for(int L) { return L >= 1024 ? 16 : (L >= 8 ? 8 : L); }
 
+// Number of LDS passes (twiddled radix-E passes) of a length-L transform.
+constexpr int fft_passes(int L, int E) {
+  int n = 0;
+  for (int Ns = first_radix(L, E); Ns < L; Ns *= E) ++n;
+  return n;
+}
+
+// v[r] *= w^r (r = 1 .. E-1; conj(w)^r for DIR > 0).  The powers come from
+// a product tree of depth <= 3 in FP64 (error ~1e-15), each rounded once to T.
+template <typename T, int DIR, int E>
+__device__ __forceinline__ void twiddle_powers(c2<T>* v, c2<double> w1) {
+  auto app = [&](int r, c2<double> wd) {
+    const c2<T> w = {static_cast<T>(wd.x), static_cast<T>(wd.y)};
+    v[r] = DIR < 0 ? cmul(v[r], w) : cmulc(v[r], w);
+  };
+  if constexpr (E >= 2) app(1, w1);
+  if constexpr (E >= 4) {
+    const c2<double> w2 = cmul(w1, w1);
+    app(2, w2);
+    app(3, cmul(w2, w1));
+    if constexpr (E >= 8) {
+      const c2<double> w4 = cmul(w2, w2);
+      app(4, w4);
+      app(5, cmul(w4, w1));
+      app(6, cmul(w4, w2));
+      app(7, cmul(w4, cmul(w2, w1)));
+      if constexpr (E >= 16) {
+        const c2<double> w8 = cmul(w4, w4);
+        app(8, w8);
+#pragma unroll
+        for (int r = 9; r < 16; ++r) {
+          // w^r = w^8 w^(r-8), r - 8 in 1 .. 7
+          const int a = r - 8;
+          c2<double> wa = (a & 4) ? w4 : c2<double>{1.0, 0.0};
+          if (a & 2) wa = (a & 4) ? cmul(wa, w2) : w2;
+          if (a & 1) wa = (a & 6) ? cmul(wa, w1) : w1;
+          app(r, cmul(w8, wa));
+        }
+      }
+    }
+  }
+}
+
 // Length-L complex FFT by a group of P = L/E threads; thread t in [0, P).
 // On entry v[q] = x[t + q P]; on exit v[q] = X[t + q P].
-// lds: the group's LDS area, element i at lds[i * LS].  tw: table of
-// exp(-2 pi i k / (2L)), k < 2L.  Every thread of the block must call this
-// with the same L (the passes contain __syncthreads()).  On return other
-// threads may still read lds: barrier before reusing it.
+// lds: the group's LDS area, element i at lds[i * LS].  tw: the FP64 table
+// exp(-2 pi i k / (2L)), k < 2L.  Pass p (stride Ns = R0 E^p) needs w^r,
+// w = exp(-2 pi i k / (Ns E)), k = t mod Ns, r = 1 .. E-1: w is read from
+// the table one pass ahead (its latency hides behind the pass before), the
+// powers are formed in FP64 and rounded once to T.  Every thread of the
+// block must call this with the same L (the passes contain
+// __syncthreads()).  On return other threads may still read lds: barrier
+// before reusing it.
 template <typename T, int L, int E, int DIR>
 __device__ __forceinline__ void fft_group(c2<T>* v, c2<T>* lds, int LS,
-                                          const c2<T>* __restrict__ tw, int t) {
+                                          gp<const c2<double>> __restrict__ tw, int t) {
   constexpr int P = L / E;
   constexpr int R0 = first_radix(L, E);
   constexpr int Q = E / R0;
@@ -140,23 +216,22 @@ __device__ __forceinline__ void fft_group(c2<T>* v, c2<T>* lds, int LS,
     }
   }
   if constexpr (L > R0) {
+    constexpr int NP = fft_passes(L, E);
+    auto tw_of = [&](int Ns) { return ldg<double>(tw + (2 * L / E) / Ns * (t & (Ns - 1))); };
+    c2<double> wn = tw_of(R0);
     int Ns = R0;
 #pragma unroll
-    for (int pass = 1; pass < 8; ++pass) {
+    for (int pass = 0; pass < NP; ++pass) {
+      const c2<double> w = wn;
+      if (pass + 1 < NP) wn = tw_of(Ns * E);
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < E; ++r) v[r] = lds[(t + r * P) * LS];
-      const int k = t & (Ns - 1);
-      // twiddle exp(DIR 2 pi i r k / (Ns E)) = tw[r k (2L / (Ns E))]
-      const int step = (2 * L / E) / Ns * k;
-#pragma unroll
-      for (int r = 1; r < E; ++r) {
-        const c2<T> w = tw[r * step];
-        v[r] = DIR < 0 ? cmul(v[r], w) : cmulc(v[r], w);
-      }
+      twiddle_powers<T, DIR, E>(v, w);
       dft_reg<T, DIR, E>(v);
-      if (Ns * E == L) break;
+      if (pass + 1 == NP) break;
       __syncthreads();
+      const int k = t & (Ns - 1);
       const int idxD = (t / Ns) * Ns * E + k;
 #pragma unroll
       for (int r = 0; r < E; ++r) lds[(idxD + r * Ns) * LS] = v[r];
@@ -168,10 +243,11 @@ __device__ __forceinline__ void fft_group(c2<T>* v, c2<T>* lds, int LS,
 // Real row x[0 .. 2L) to its packed half spectrum.
 // On entry v[q] = (x[2m], x[2m+1]) for m = t + q P.  On exit v[q] = X[m]
 // for m >= 1 and v[q] = (X[0], X[L]) for m = 0 (DC and Nyquist are real).
-// lds must hold L values (stride 1); tw: exp(-2 pi i k / (2L)), k < 2L.
+// lds must hold L values (stride 1); tw: the FP64 table exp(-2 pi i k / (2L)),
+// k < 2L.
 template <typename T, int L, int E>
-__device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* lds,
-                                        const c2<T>* __restrict__ tw, int t) {
+__device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* lds, gp<const c2<double>> __restrict__ tw,
+                                        int t) {
   constexpr int P = L / E;
   fft_group<T, L, E, -1>(v, lds, 1, tw, t);
   __syncthreads();
@@ -189,7 +265,8 @@ __device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* lds,
       const T h = static_cast<T>(0.5);
       const c2<T> e = {h * (z.x + zc.x), h * (z.y - zc.y)};
       const c2<T> o = {h * (z.y + zc.y), -h * (z.x - zc.x)};
-      v[q] = cadd(e, cmul(o, tw[m]));
+      const c2<double> wd = ldg<double>(tw + m);
+      v[q] = cadd(e, cmul(o, c2<T>{static_cast<T>(wd.x), static_cast<T>(wd.y)}));
     }
   }
 }
@@ -198,8 +275,8 @@ __device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* lds,
 // row_c2r(row_r2c(x)) = x.  On entry v[q] = packed X[m], m = t + q P; on exit
 // v[q] = (x[2m], x[2m+1]).
 template <typename T, int L, int E>
-__device__ __forceinline__ void row_c2r(c2<T>* v, c2<T>* lds,
-                                        const c2<T>* __restrict__ tw, int t) {
+__device__ __forceinline__ void row_c2r(c2<T>* v, c2<T>* lds, gp<const c2<double>> __restrict__ tw,
+                                        int t) {
   constexpr int P = L / E;
 #pragma unroll
   for (int q = 0; q < E; ++q) lds[t + q * P] = v[q];
@@ -214,7 +291,8 @@ __device__ __forceinline__ void row_c2r(c2<T>* v, c2<T>* lds,
       const c2<T> Xc = lds[L - m];
       const c2<T> a = {X.x + Xc.x, X.y - Xc.y};          // X + conj(Xc)
       const c2<T> d = {X.x - Xc.x, X.y + Xc.y};          // X - conj(Xc)
-      const c2<T> b = cmulc(d, tw[m]);                    // times exp(+2 pi i m / 2L)
+      const c2<double> wd = ldg<double>(tw + m);
+      const c2<T> b = cmulc(d, c2<T>{static_cast<T>(wd.x), static_cast<T>(wd.y)});                   // times exp(+2 pi i m / 2L)
       v[q] = {a.x - b.y, a.y + b.x};                      // a + i b
     }
   }

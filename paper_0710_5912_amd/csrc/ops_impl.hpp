@@ -5,6 +5,7 @@
 #include "ops.hpp"
 #include "stages.hpp"
 
+
 namespace le {
 
 template <typename T, int L>
@@ -22,15 +23,30 @@ struct RowLaunch {
     hipLaunchKernelGGL((k_row_c2r<T, L>), grid(ny, nfields, nruns), dim3(C::THREADS), 0, st,
                        runs, bin0, bout0, bin1, bout1);
   }
+  // the r = 1 (square cell grid, nx = ny) form when it applies
+  static void bracket(const Run* runs, int nruns, int ny, const StepArgs* sa, const Jobs& jobs,
+                      int njobs, hipStream_t st) {
+    if (ny == 2 * L)
+      hipLaunchKernelGGL((k_bracket<T, L, true>), grid(ny, njobs, nruns), dim3(C::THREADS), 0,
+                         st, runs, sa, jobs);
+    else
+      hipLaunchKernelGGL((k_bracket<T, L, false>), grid(ny, njobs, nruns), dim3(C::THREADS), 0,
+                         st, runs, sa, jobs);
+  }
   static void advect(const Run* runs, int nruns, int ny, const StepArgs* sa, bool inertial,
                      hipStream_t st) {
-    hipLaunchKernelGGL((k_advect<T, L>), grid(ny, inertial ? 3 : 2, nruns), dim3(C::THREADS),
-                       0, st, runs, sa);
+    Jobs jobs{{{JOB_ADVECT, B_PHI, B_PS_R, B_PHIH},
+               {JOB_CUBE, B_PHI, B_PHI, B_FH},
+               {JOB_ADVECT, B_OM_R, B_PS_R, B_OMH}}};
+    bracket(runs, nruns, ny, sa, jobs, inertial ? 3 : 2, st);
   }
+  // mu into the real scratch field, then the source bracket and its row
+  // transform
   static void mu_source(const Run* runs, int nruns, int ny, const StepArgs* sa, hipStream_t st) {
-    using M = MuCfg<L>;
-    hipLaunchKernelGGL((k_mu_source<T, L>), dim3((ny + M::G - 1) / M::G, 1, nruns),
-                       dim3(M::THREADS), 0, st, runs, sa);
+    hipLaunchKernelGGL((k_mu<T, L>), grid(ny, 1, nruns), dim3(C::THREADS), 0, st, runs, sa,
+                       (int)B_PHI, (int)B_TMP);
+    Jobs jobs{{{JOB_SOURCE, B_PHI, B_TMP, B_GH}, {}, {}}};
+    bracket(runs, nruns, ny, sa, jobs, 1, st);
   }
 };
 

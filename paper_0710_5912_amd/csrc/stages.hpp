@@ -24,7 +24,14 @@ constexpr int col_elems(int L) { return L >= 8 ? 8 : L; }
 
 // Occupancy hint for the stage kernels (waves per SIMD the register
 // allocation must allow).
-#define LE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(2)))
+#ifndef LE_WAVES
+#define LE_WAVES 2
+#endif
+#ifndef LE_WAVES_COL
+#define LE_WAVES_COL LE_WAVES
+#endif
+#define LE_OCCUPANCY __attribute__((amdgpu_waves_per_eu(LE_WAVES)))
+#define LE_OCCUPANCY_COL __attribute__((amdgpu_waves_per_eu(LE_WAVES_COL)))
 // Keep the scheduler from interleaving consecutive unrolled iterations (which
 // would hoist every iteration's loads and blow the register budget).
 #define LE_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
@@ -35,14 +42,6 @@ struct RowCfg {
   static constexpr int E = row_elems(L);
   static constexpr int P = L / E;
   static constexpr int G = clampi(128 / P, 1, 16);
-  static constexpr int THREADS = G * P;
-};
-
-template <int L>
-struct MuCfg {
-  static constexpr int E = row_elems(L);
-  static constexpr int P = L / E;
-  static constexpr int G = clampi(256 / P, 1, 16);
   static constexpr int THREADS = G * P;
 };
 
@@ -78,34 +77,35 @@ __device__ __forceinline__ BPos block_pos() {
 }
 
 template <typename T>
-__device__ __forceinline__ T* bufp(const Run& R, int b) {
-  return static_cast<T*>(R.buf[b]);
+__device__ __forceinline__ gp<T> bufp(const Run& R, int b) {
+  return to_global<T>(R.buf[b]);
 }
 
 // ---------------------------------------------------------------- helpers
 
 template <typename T, int L, int E>
-__device__ __forceinline__ void store_row_spec(c2<T>* __restrict__ X, const c2<T>* v, int t) {
+__device__ __forceinline__ void store_row_spec(gp<c2<T>> __restrict__ X, const c2<T>* v, int t) {
   constexpr int P = L / E;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int m = t + q * P;
     if (m == 0) {
-      X[0] = {v[q].x, T(0)};
-      X[L] = {v[q].y, T(0)};
+      stg<T>(X, {v[q].x, T(0)});
+      stg<T>(X + L, {v[q].y, T(0)});
     } else {
-      X[m] = v[q];
+      stg<T>(X + m, v[q]);
     }
   }
 }
 
 template <typename T, int L, int E>
-__device__ __forceinline__ void load_row_spec(const c2<T>* __restrict__ X, c2<T>* v, int t) {
+__device__ __forceinline__ void load_row_spec(gp<const c2<T>> __restrict__ X, c2<T>* v, int t) {
   constexpr int P = L / E;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int m = t + q * P;
-    v[q] = (m == 0) ? c2<T>{X[0].x, X[L].x} : X[m];
+    const c2<T> xm = ldg<T>(X + m);
+    v[q] = (m == 0) ? c2<T>{xm.x, X[L].x} : xm;
   }
 }
 
@@ -167,16 +167,16 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_row_r2c(
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
   const int ny = R.g.ny;
-  const T* x = bufp<T>(R, bin);
-  c2<T>* X = bufp<c2<T>>(R, bout);
-  const c2<T>* tw = static_cast<const c2<T>*>(R.twx);
+  auto x = bufp<T>(R, bin);
+  auto X = bufp<c2<T>>(R, bout);
+  auto tw = to_global<const c2<double>>(R.twx);
   const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
   const int j = bp.x * C::G + g;
   const bool ok = j < ny;
-  const c2<T>* xr = reinterpret_cast<const c2<T>*>(x + (size_t)(ok ? j : 0) * 2 * L);
+  auto xr = reinterpret_cast<gp<const c2<T>>>(x + (size_t)(ok ? j : 0) * 2 * L);
   c2<T> v[C::E];
 #pragma unroll
-  for (int q = 0; q < C::E; ++q) v[q] = xr[t + q * C::P];
+  for (int q = 0; q < C::E; ++q) v[q] = ldg<T>(xr + t + q * C::P);
   row_r2c<T, L, C::E>(v, lds + g * L, tw, t);
   if (ok) store_row_spec<T, L, C::E>(X + (size_t)j * (L + 1), v, t);
 }
@@ -191,9 +191,9 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_row_c2r(
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
   const int ny = R.g.ny;
-  const c2<T>* X = bufp<const c2<T>>(R, bp.y == 0 ? bin0 : bin1);
-  T* x = bufp<T>(R, bp.y == 0 ? bout0 : bout1);
-  const c2<T>* tw = static_cast<const c2<T>*>(R.twx);
+  auto X = bufp<const c2<T>>(R, bp.y == 0 ? bin0 : bin1);
+  auto x = bufp<T>(R, bp.y == 0 ? bout0 : bout1);
+  auto tw = to_global<const c2<double>>(R.twx);
   const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
   const int j = bp.x * C::G + g;
   const bool ok = j < ny;
@@ -202,16 +202,10 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_row_c2r(
   load_row_spec<T, L, C::E>(X + (size_t)jj * (L + 1), v, t);
   row_c2r<T, L, C::E>(v, lds + g * L, tw, t);
   if (ok) {
-    c2<T>* xr = reinterpret_cast<c2<T>*>(x + (size_t)j * 2 * L);
+    auto xr = reinterpret_cast<gp<c2<T>>>(x + (size_t)j * 2 * L);
 #pragma unroll
-    for (int q = 0; q < C::E; ++q) xr[t + q * C::P] = v[q];
+    for (int q = 0; q < C::E; ++q) stg<T>(xr + t + q * C::P, v[q]);
   }
-}
-
-// Periodic read of a real field at (row jj, column i), nx a power of two.
-template <typename T>
-__device__ __forceinline__ T at(const T* __restrict__ f, int jj, int i, int nx) {
-  return f[(size_t)jj * nx + (i & (nx - 1))];
 }
 
 // Stencil coefficients of one step, in the storage precision.
@@ -219,7 +213,6 @@ template <typename T>
 struct Stencil {
   T inv2dx, inv2dy, w, wm;  // 1/(2dx), 1/(2dy), |s|/c, 1 - |s|/c
   int off;                  // sign(s) * r: x offset of the diagonal y difference
-  bool sheared;             // w != 0
 };
 
 template <typename T>
@@ -231,173 +224,233 @@ __device__ __forceinline__ Stencil<T> make_stencil(const Geo& g, double s) {
   st.w = T(w);
   st.wm = T(1.0 - w);
   st.off = s >= 0.0 ? g.r : -g.r;
-  st.sheared = w != 0.0;
   return st;
 }
 
-// Central x difference at (j, i) and (j, i+1) from a field in global memory.
-template <typename T>
-__device__ __forceinline__ void dx_pair(const T* f, int j, int i, int nx, T inv2dx, T& d0, T& d1) {
-  const T a = at(f, j, i - 1, nx), b = at(f, j, i, nx), c = at(f, j, i + 1, nx),
-          d = at(f, j, i + 2, nx);
-  d0 = (c - a) * inv2dx;
-  d1 = (d - b) * inv2dx;
+// ------------------------------------------------ x-pair access for row stencils
+//
+// The row kernels give thread t of a row the x pairs (x, x+1), x = 2(t + qP),
+// q = 0 .. E-1: the layout the row transform consumes.  A stencil needs the
+// values at x-1 and x+2 too; they are the neighbouring lanes' pairs, moved
+// across the wavefront with DPP (wave_shr:1 / wave_shl:1), and only the
+// lanes whose neighbour is not the adjacent lane (first/last of a row group
+// or of the wavefront) read them from memory.
+
+constexpr int kDppWaveShr1 = 0x138;  // lane i receives lane i-1 (lane 0 keeps its own)
+constexpr int kDppWaveShl1 = 0x130;  // lane i receives lane i+1 (lane 63 keeps its own)
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  const int b = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  int lo = (int)b, hi = (int)(b >> 32);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (long long)(((unsigned long long)(unsigned)hi << 32) |
+                                                (unsigned)lo));
 }
 
-// Shear-interpolated y difference (Eq. p1y, offsets +-r, weight |s|/c) at
-// (j, i) and (j, i+1); jp = j+1, jm = j-1 (periodic).
+// f[x-1], f[x], f[x+1], f[x+2] of one row.
 template <typename T>
-__device__ __forceinline__ void dys_pair(const T* f, int jp, int jm, int i, int nx,
-                                         const Stencil<T>& st, T& d0, T& d1) {
-  const T p0 = at(f, jp, i, nx), p1 = at(f, jp, i + 1, nx);
-  const T m0 = at(f, jm, i, nx), m1 = at(f, jm, i + 1, nx);
-  if (st.sheared) {
-    const T pd0 = at(f, jp, i - st.off, nx), pd1 = at(f, jp, i + 1 - st.off, nx);
-    const T md0 = at(f, jm, i + st.off, nx), md1 = at(f, jm, i + 1 + st.off, nx);
-    d0 = (st.wm * (p0 - m0) + st.w * (pd0 - md0)) * st.inv2dy;
-    d1 = (st.wm * (p1 - m1) + st.w * (pd1 - md1)) * st.inv2dy;
-  } else {
-    d0 = (p0 - m0) * st.inv2dy;
-    d1 = (p1 - m1) * st.inv2dy;
+struct Quad {
+  T l, a0, a1, r;
+};
+
+// Row `row` (NX values), pair at even x.  Lanes with edge_l / edge_r take
+// x-1 / x+2 from the halo values at xl / xr (the values left of the first and
+// right of the last pair of the lane's run of adjacent lanes), which every
+// lane reads: one address per run, so the reads cost no extra traffic and no
+// branch.  Every lane of the wavefront must execute this (DPP reads the
+// neighbours' registers).
+template <typename T, int NX>
+__device__ __forceinline__ Quad<T> load_quad(gp<const T> __restrict__ row, int x, int xl, int xr,
+                                             bool edge_l, bool edge_r) {
+  const c2<T> p = ldg<T>(reinterpret_cast<gp<const c2<T>>>(row + x));
+  const T hl = row[xl & (NX - 1)];
+  const T hr = row[xr & (NX - 1)];
+  const T nl = dpp_mov<kDppWaveShr1>(p.y);
+  const T nr = dpp_mov<kDppWaveShl1>(p.x);
+  return {edge_l ? hl : nl, p.x, p.y, edge_r ? hr : nr};
+}
+
+// Lanes of a row group: thread t of P; runs of adjacent lanes are whole
+// wavefronts when P >= 64, else the whole group.
+template <int P>
+struct LaneRun {
+  int tl, tr;          // first and last t of the lane's run
+  bool edge_l, edge_r;
+  __device__ __forceinline__ LaneRun(int t) {
+    tl = P >= 64 ? (t & ~63) : 0;
+    tr = P >= 64 ? (t | 63) : P - 1;
+    edge_l = t == tl;
+    edge_r = t == tr;
   }
+  // halo positions of pair slot q
+  __device__ __forceinline__ int xl(int q) const { return 2 * (tl + q * P) - 1; }
+  __device__ __forceinline__ int xr(int q) const { return 2 * (tr + q * P) + 2; }
+};
+
+// Aligned pair (f[x], f[x+1]) of a row, x even, taken periodically.
+template <typename T, int NX>
+__device__ __forceinline__ c2<T> load_pair(gp<const T> __restrict__ row, int x) {
+  return ldg<T>(reinterpret_cast<gp<const c2<T>>>(row + (x & (NX - 1))));
 }
 
-// Stage 1a (Eq. advective), one output field per blockIdx.y:
-//   0: phi_h = phi - dt [Dys psi Dx phi - Dx psi Dys phi]
-//   1: f = phi^3
-//   2: omega_h = omega - dt [Dys psi Dx omega - Dx psi Dys omega]  (inertial)
-// followed by the forward row transform of that field.
-template <typename T, int L>
-__global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_advect(
-    const Run* __restrict__ runs, const StepArgs* __restrict__ sa) {
+// Central x difference at x and x+1.
+template <typename T>
+__device__ __forceinline__ void quad_dx(const Quad<T>& q, T inv2dx, T& d0, T& d1) {
+  d0 = (q.a1 - q.l) * inv2dx;
+  d1 = (q.r - q.a0) * inv2dx;
+}
+
+// Sheared y difference (Eq. p1y) at x and x+1 from rows j+1 (up) and j-1
+// (dn): plain part up(x) - dn(x) weighted 1 - |s|/c, diagonal part
+// up(x - off) - dn(x + off) weighted |s|/c, off = sign(s) r (unsheared:
+// weights 1 and 0, the same value).  R1: r = 1, the diagonal values are the
+// quads' own neighbours; otherwise r is even and they are aligned pairs read
+// from the rows.  Branch-free.
+template <typename T, int NX, bool R1>
+__device__ __forceinline__ void quad_dys(const Quad<T>& up, const Quad<T>& dn,
+                                         gp<const T> __restrict__ rowu, gp<const T> __restrict__ rowd,
+                                         int x, const Stencil<T>& st, T& d0, T& d1) {
+  T u0, u1, m0, m1;  // up(x - off), up(x + 1 - off), dn(x + off), dn(x + 1 + off)
+  if constexpr (R1) {
+    const bool pos = st.off > 0;
+    u0 = pos ? up.l : up.a1;
+    u1 = pos ? up.a0 : up.r;
+    m0 = pos ? dn.a1 : dn.l;
+    m1 = pos ? dn.r : dn.a0;
+  } else {
+    const c2<T> pu = load_pair<T, NX>(rowu, x - st.off);
+    const c2<T> pd = load_pair<T, NX>(rowd, x + st.off);
+    u0 = pu.x; u1 = pu.y; m0 = pd.x; m1 = pd.y;
+  }
+  d0 = (st.wm * (up.a0 - dn.a0) + st.w * (u0 - m0)) * st.inv2dy;
+  d1 = (st.wm * (up.a1 - dn.a1) + st.w * (u1 - m1)) * st.inv2dy;
+}
+
+// One output field of a bracket row kernel.
+//   JOB_ADVECT: out = a - dt [Dx a Dys b - Dys a Dx b]   (stage 1a, b = psi)
+//   JOB_CUBE:   out = a^3                                  (stage 1a, f)
+//   JOB_SOURCE: out = -[Dx a Dys b - Dys a Dx b] / c       (stage 2a, a = phi,
+//               b = mu, c = rho, or eta on the Stokes branch)
+enum JobKind { JOB_ADVECT = 0, JOB_CUBE = 1, JOB_SOURCE = 2 };
+struct Job {
+  int kind, a, b, out;  // Buf indices
+};
+struct Jobs {
+  Job j[3];
+};
+
+// Bracket jobs of a row: blockIdx.y picks the job, each computed on x pairs
+// and passed through the forward row transform into a row spectrum.
+template <typename T, int L, bool R1>
+__global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_bracket(
+    const Run* __restrict__ runs, const StepArgs* __restrict__ sa, Jobs jobs) {
   using C = RowCfg<L>;
   constexpr int NX = 2 * L;
   __shared__ c2<T> lds[C::G * L];
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
   const Geo& geo = R.g;
-  const T* phi = bufp<const T>(R, B_PHI);
-  const T* om = bufp<const T>(R, B_OM_R);
-  const T* psi = bufp<const T>(R, B_PS_R);
-  const c2<T>* tw = static_cast<const c2<T>*>(R.twx);
+  const Job job = jobs.j[bp.y];
+  auto tw = to_global<const c2<double>>(R.twx);
   const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
+  const LaneRun<C::P> lr(t);
   const int j0 = bp.x * C::G + g;
   const bool ok = j0 < geo.ny;
   const int j = ok ? j0 : 0;
   const int jp = (j + 1 == geo.ny) ? 0 : j + 1;
   const int jm = (j == 0) ? geo.ny - 1 : j - 1;
-  const int field = bp.y;
-  const Stencil<T> st = make_stencil<T>(geo, sa[bp.z].s);
-  const T dt = T(geo.dt);
+  auto fa = bufp<const T>(R, job.a);
+  auto a_c = fa + (size_t)j * NX;
   c2<T> v[C::E];
-  if (field == 1) {
+  if (job.kind == JOB_CUBE) {
 #pragma unroll
     for (int q = 0; q < C::E; ++q) {
-      const int i = 2 * (t + q * C::P);
-      const T p0 = phi[(size_t)j * NX + i], p1 = phi[(size_t)j * NX + i + 1];
-      v[q] = {p0 * p0 * p0, p1 * p1 * p1};
+      const c2<T> p = load_pair<T, NX>(a_c, 2 * (t + q * C::P));
+      v[q] = {p.x * p.x * p.x, p.y * p.y * p.y};
     }
   } else {
-    const T* a = field == 0 ? phi : om;
+    const Stencil<T> st = make_stencil<T>(geo, sa[bp.z].s);
+    auto fb = bufp<const T>(R, job.b);
+    auto a_p = fa + (size_t)jp * NX;
+    auto a_m = fa + (size_t)jm * NX;
+    auto b_c = fb + (size_t)j * NX;
+    auto b_p = fb + (size_t)jp * NX;
+    auto b_m = fb + (size_t)jm * NX;
+    const bool adv = job.kind == JOB_ADVECT;
+    const T alpha = adv ? T(1) : T(0);
+    const T beta = adv ? T(-geo.dt) : T(-1.0 / (geo.rho > 0.0 ? geo.rho : geo.eta));
 #pragma unroll
     for (int q = 0; q < C::E; ++q) {
-      const int i = 2 * (t + q * C::P);
-      T sx0, sx1, sy0, sy1, ax0, ax1, ay0, ay1;
-      dx_pair(psi, j, i, NX, st.inv2dx, sx0, sx1);
-      dys_pair(psi, jp, jm, i, NX, st, sy0, sy1);
-      dx_pair(a, j, i, NX, st.inv2dx, ax0, ax1);
-      dys_pair(a, jp, jm, i, NX, st, ay0, ay1);
-      const T a0 = a[(size_t)j * NX + i], a1 = a[(size_t)j * NX + i + 1];
-      v[q] = {a0 - dt * (sy0 * ax0 - sx0 * ay0), a1 - dt * (sy1 * ax1 - sx1 * ay1)};
+      const int x = 2 * (t + q * C::P);
+      const Quad<T> A = load_quad<T, NX>(a_c, x, lr.xl(q), lr.xr(q), lr.edge_l, lr.edge_r);
+      const Quad<T> Ap = load_quad<T, NX>(a_p, x, lr.xl(q), lr.xr(q), lr.edge_l, lr.edge_r);
+      const Quad<T> Am = load_quad<T, NX>(a_m, x, lr.xl(q), lr.xr(q), lr.edge_l, lr.edge_r);
+      const Quad<T> B = load_quad<T, NX>(b_c, x, lr.xl(q), lr.xr(q), lr.edge_l, lr.edge_r);
+      const Quad<T> Bp = load_quad<T, NX>(b_p, x, lr.xl(q), lr.xr(q), lr.edge_l, lr.edge_r);
+      const Quad<T> Bm = load_quad<T, NX>(b_m, x, lr.xl(q), lr.xr(q), lr.edge_l, lr.edge_r);
+      T ax0, ax1, ay0, ay1, bx0, bx1, by0, by1;
+      quad_dx(A, st.inv2dx, ax0, ax1);
+      quad_dx(B, st.inv2dx, bx0, bx1);
+      quad_dys<T, NX, R1>(Ap, Am, a_p, a_m, x, st, ay0, ay1);
+      quad_dys<T, NX, R1>(Bp, Bm, b_p, b_m, x, st, by0, by1);
+      v[q] = {alpha * A.a0 + beta * (by0 * ax0 - bx0 * ay0),
+              alpha * A.a1 + beta * (by1 * ax1 - bx1 * ay1)};
       LE_SCHED_FENCE();
     }
   }
   row_r2c<T, L, C::E>(v, lds + g * L, tw, t);
-  c2<T>* out = bufp<c2<T>>(R, field == 0 ? B_PHIH : (field == 1 ? B_FH : B_OMH));
+  auto out = bufp<c2<T>>(R, job.out);
   if (ok) store_row_spec<T, L, C::E>(out + (size_t)j * (L + 1), v, t);
 }
 
-// Stage 2a: mu = B phi^3 - A phi - kappa [(1+s^2) Dxx + Dyy - 2 s Dxy] phi on
-// rows j0-1 .. j0+G (into LDS), then g = -[Dx phi Dys mu - Dys phi Dx mu] * inv
-// (inv = 1/rho, or 1/eta on the Stokes branch) and its forward row transform.
+// Chemical potential (Eq. mu, stage 2a) on x pairs into a real field:
+//   mu = B phi^3 - A phi - kappa [(1+s^2) Dxx + Dyy - 2 s Dxy] phi.
 template <typename T, int L>
-__global__ __launch_bounds__(MuCfg<L>::THREADS) LE_OCCUPANCY void k_mu_source(
-    const Run* __restrict__ runs, const StepArgs* __restrict__ sa) {
-  using C = MuCfg<L>;
+__global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_mu(
+    const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int bin, int bout) {
+  using C = RowCfg<L>;
+  constexpr int NX = 2 * L;
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
   const Geo& geo = R.g;
-  const T* phi = bufp<const T>(R, B_PHI);
-  c2<T>* gh = bufp<c2<T>>(R, B_GH);
-  const c2<T>* tw = static_cast<const c2<T>*>(R.twx);
-  const double inv_coef = 1.0 / (geo.rho > 0.0 ? geo.rho : geo.eta);
-  constexpr int NX = 2 * L;
-  constexpr int MU_ROWS = C::G + 2;
-  constexpr int LDS_T = MU_ROWS * NX;  // >= C::G * L complex
-  __shared__ __attribute__((aligned(16))) T smu[LDS_T];
-  c2<T>* lds = reinterpret_cast<c2<T>*>(smu);
-  const int ny = geo.ny;
-  const int jbase = bp.x * C::G;
+  const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
+  const LaneRun<C::P> lr(t);
+  const int j0 = bp.x * C::G + g;
+  const bool ok = j0 < geo.ny;
+  const int j = ok ? j0 : 0;
+  const int jp = (j + 1 == geo.ny) ? 0 : j + 1;
+  const int jm = (j == 0) ? geo.ny - 1 : j - 1;
+  auto phi = bufp<const T>(R, bin);
+  auto mu = bufp<T>(R, bout) + (size_t)j * NX;
   const double s = sa[bp.z].s;
   const T cxx = T((1.0 + s * s) / (geo.dx * geo.dx));
   const T cyy = T(1.0 / (geo.dy * geo.dy));
   const T cxy = T(-2.0 * s / (4.0 * geo.dx * geo.dy));
   const T A = T(geo.A), B = T(geo.B), kap = T(geo.kappa);
   const T two = T(2);
-  for (int e = threadIdx.x; e < MU_ROWS * NX; e += C::THREADS) {
-    const int k = e / NX, i = e % NX;
-    int jj = jbase - 1 + k;
-    jj = (jj % ny + ny) % ny;
-    const int jp = (jj + 1 == ny) ? 0 : jj + 1;
-    const int jm = (jj == 0) ? ny - 1 : jj - 1;
-    const T c = at(phi, jj, i, NX);
-    const T dxx = at(phi, jj, i + 1, NX) - two * c + at(phi, jj, i - 1, NX);
-    const T dyy = at(phi, jp, i, NX) - two * c + at(phi, jm, i, NX);
-    const T dxy = at(phi, jp, i + 1, NX) - at(phi, jm, i + 1, NX) - at(phi, jp, i - 1, NX) +
-                  at(phi, jm, i - 1, NX);
-    smu[e] = B * c * c * c - A * c - kap * (cxx * dxx + cyy * dyy + cxy * dxy);
-  }
-  __syncthreads();
-  const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
-  const int j0 = jbase + g;
-  const bool ok = j0 < ny;
-  const int j = ok ? j0 : 0;
-  const int jp = (j + 1 == ny) ? 0 : j + 1;
-  const int jm = (j == 0) ? ny - 1 : j - 1;
-  const Stencil<T> st = make_stencil<T>(geo, s);
-  const T* mu_c = smu + (g + 1) * NX;   // row j
-  const T* mu_p = smu + (g + 2) * NX;   // row j + 1
-  const T* mu_m = smu + g * NX;         // row j - 1
-  const T neg_inv = T(-inv_coef);
-  c2<T> v[C::E];
+  auto p_c = phi + (size_t)j * NX;
+  auto p_p = phi + (size_t)jp * NX;
+  auto p_m = phi + (size_t)jm * NX;
 #pragma unroll
   for (int q = 0; q < C::E; ++q) {
-    const int i = 2 * (t + q * C::P);
-    T px0, px1, py0, py1;
-    dx_pair(phi, j, i, NX, st.inv2dx, px0, px1);
-    dys_pair(phi, jp, jm, i, NX, st, py0, py1);
-    const T mx0 = (mu_c[(i + 1) & (NX - 1)] - mu_c[(i - 1) & (NX - 1)]) * st.inv2dx;
-    const T mx1 = (mu_c[(i + 2) & (NX - 1)] - mu_c[i]) * st.inv2dx;
-    T my0, my1;
-    {
-      const T p0 = mu_p[i], p1 = mu_p[i + 1];
-      const T m0 = mu_m[i], m1 = mu_m[i + 1];
-      if (st.sheared) {
-        const T pd0 = mu_p[(i - st.off) & (NX - 1)], pd1 = mu_p[(i + 1 - st.off) & (NX - 1)];
-        const T md0 = mu_m[(i + st.off) & (NX - 1)], md1 = mu_m[(i + 1 + st.off) & (NX - 1)];
-        my0 = (st.wm * (p0 - m0) + st.w * (pd0 - md0)) * st.inv2dy;
-        my1 = (st.wm * (p1 - m1) + st.w * (pd1 - md1)) * st.inv2dy;
-      } else {
-        my0 = (p0 - m0) * st.inv2dy;
-        my1 = (p1 - m1) * st.inv2dy;
-      }
-    }
-    v[q] = {neg_inv * (px0 * my0 - py0 * mx0), neg_inv * (px1 * my1 - py1 * mx1)};
-    LE_SCHED_FENCE();
+    const int x = 2 * (t + q * C::P);
+    const Quad<T> c = load_quad<T, NX>(p_c, x, lr.xl(q), lr.xr(q), lr.edge_l, lr.edge_r);
+    const Quad<T> u = load_quad<T, NX>(p_p, x, lr.xl(q), lr.xr(q), lr.edge_l, lr.edge_r);
+    const Quad<T> d = load_quad<T, NX>(p_m, x, lr.xl(q), lr.xr(q), lr.edge_l, lr.edge_r);
+    const T dxx0 = c.a1 - two * c.a0 + c.l, dxx1 = c.r - two * c.a1 + c.a0;
+    const T dyy0 = u.a0 - two * c.a0 + d.a0, dyy1 = u.a1 - two * c.a1 + d.a1;
+    const T dxy0 = u.a1 - d.a1 - u.l + d.l, dxy1 = u.r - d.r - u.a0 + d.a0;
+    const T m0 = B * c.a0 * c.a0 * c.a0 - A * c.a0 - kap * (cxx * dxx0 + cyy * dyy0 + cxy * dxy0);
+    const T m1 = B * c.a1 * c.a1 * c.a1 - A * c.a1 - kap * (cxx * dxx1 + cyy * dyy1 + cxy * dxy1);
+    if (ok) stg<T>(reinterpret_cast<gp<c2<T>>>(mu + x), {m0, m1});
   }
-  __syncthreads();  // mu is dead; its LDS becomes the transform's
-  row_r2c<T, L, C::E>(v, lds + g * L, tw, t);
-  if (ok) store_row_spec<T, L, C::E>(gh + (size_t)j * (L + 1), v, t);
 }
 
 // Strain-wrap remap of a row spectrum: row j shifted by sh_j = (dkr * j) mod nx,
@@ -405,8 +458,8 @@ __global__ __launch_bounds__(MuCfg<L>::THREADS) LE_OCCUPANCY void k_mu_source(
 template <typename T>
 __global__ void k_remap_spec(const Run* __restrict__ run, int b, int dkr) {
   const int nx = run->g.nx, ny = run->g.ny;
-  c2<T>* X = bufp<c2<T>>(*run, b);
-  const c2<T>* twx = static_cast<const c2<T>*>(run->twx);
+  auto X = bufp<c2<T>>(*run, b);
+  auto twx = to_global<const c2<double>>(run->twx);
   const int S = nx / 2 + 1;
   const size_t total = (size_t)ny * S;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
@@ -414,7 +467,8 @@ __global__ void k_remap_spec(const Run* __restrict__ run, int b, int dkr) {
     const int j = (int)(e / S), m = (int)(e % S);
     const long long sh = (((long long)dkr * j) % nx + nx) % nx;
     const int idx = (int)(((long long)m * sh) % nx);
-    X[e] = cmul(X[e], twx[idx]);
+    const c2<double> w = ldg<double>(twx + idx);
+    stg<T>(X + e, cmul(ldg<T>(X + e), c2<T>{static_cast<T>(w.x), static_cast<T>(w.y)}));
   }
 }
 
@@ -422,8 +476,8 @@ __global__ void k_remap_spec(const Run* __restrict__ run, int b, int dkr) {
 template <typename T>
 __global__ void k_remap_real(const Run* __restrict__ run, int bin, int bout, int dkr) {
   const int nx = run->g.nx, ny = run->g.ny;
-  const T* in = bufp<const T>(*run, bin);
-  T* out = bufp<T>(*run, bout);
+  auto in = bufp<const T>(*run, bin);
+  auto out = bufp<T>(*run, bout);
   const size_t total = (size_t)ny * nx;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
@@ -437,7 +491,7 @@ __global__ void k_remap_real(const Run* __restrict__ run, int bin, int bout, int
 template <typename T>
 __global__ void k_restrict(const Run* __restrict__ run, int bin, int f, double* __restrict__ out) {
   const int nx = run->g.nx, ny = run->g.ny, cx = nx / f, cy = ny / f;
-  const T* in = bufp<const T>(*run, bin);
+  auto in = bufp<const T>(*run, bin);
   const double inv = 1.0 / ((double)f * f);
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cx * cy; e += gridDim.x * blockDim.x) {
     const int J = e / cx, I = e % cx;
@@ -452,8 +506,8 @@ __global__ void k_restrict(const Run* __restrict__ run, int bin, int f, double* 
 template <typename T>
 __global__ void k_copy_real(const Run* __restrict__ run, int bin, int bout) {
   const size_t total = (size_t)run->g.ny * run->g.nx;
-  const T* in = bufp<const T>(*run, bin);
-  T* out = bufp<T>(*run, bout);
+  auto in = bufp<const T>(*run, bin);
+  auto out = bufp<T>(*run, bout);
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x)
     out[e] = in[e];
@@ -467,18 +521,18 @@ __global__ void k_copy_real(const Run* __restrict__ run, int bin, int bout) {
 //  COL_STOKES  g -> psi'                  zero-Reynolds solve
 //  COL_POISSON omega -> psi               set-up: psi from omega
 template <typename T, int L, int MODE>
-__global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY void k_column(
+__global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY_COL void k_column(
     const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int bin0, int bin1,
     int bout0, int bout1) {
   using C = ColCfg<L>;
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
   const Geo& geo = R.g;
-  const c2<T>* in0 = bufp<const c2<T>>(R, bin0);
-  const c2<T>* in1 = bufp<const c2<T>>(R, bin1);
-  c2<T>* out0 = bufp<c2<T>>(R, bout0);
-  c2<T>* out1 = bufp<c2<T>>(R, bout1);
-  const c2<T>* tw = static_cast<const c2<T>*>(R.twy);
+  auto in0 = bufp<const c2<T>>(R, bin0);
+  auto in1 = bufp<const c2<T>>(R, bin1);
+  auto out0 = bufp<c2<T>>(R, bout0);
+  auto out1 = bufp<c2<T>>(R, bout1);
+  auto tw = to_global<const c2<double>>(R.twy);
   constexpr int NIN = (MODE == COL_CH || MODE == COL_FLOW) ? 2 : 1;
   constexpr int NOUT = (MODE == COL_FLOW) ? 2 : 1;
   __shared__ c2<T> lds[C::CW * L];
@@ -489,11 +543,11 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY void k_column(
   const int m = ok ? m0 : 0;
   c2<T> v0[C::E], v1[C::E];
 #pragma unroll
-  for (int q = 0; q < C::E; ++q) v0[q] = in0[(size_t)(t + q * C::P) * S + m];
+  for (int q = 0; q < C::E; ++q) v0[q] = ldg<T>(in0 + (size_t)(t + q * C::P) * S + m);
   fft_group<T, L, C::E, -1>(v0, lds + c, C::CW, tw, t);
   if constexpr (NIN == 2) {
 #pragma unroll
-    for (int q = 0; q < C::E; ++q) v1[q] = in1[(size_t)(t + q * C::P) * S + m];
+    for (int q = 0; q < C::E; ++q) v1[q] = ldg<T>(in1 + (size_t)(t + q * C::P) * S + m);
     __syncthreads();
     fft_group<T, L, C::E, -1>(v1, lds + c, C::CW, tw, t);
   }
@@ -544,14 +598,14 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY void k_column(
   fft_group<T, L, C::E, +1>(v0, lds + c, C::CW, tw, t);
   if (ok) {
 #pragma unroll
-    for (int q = 0; q < C::E; ++q) out0[(size_t)(t + q * C::P) * S + m] = v0[q];
+    for (int q = 0; q < C::E; ++q) stg<T>(out0 + (size_t)(t + q * C::P) * S + m, v0[q]);
   }
   if constexpr (NOUT == 2) {
     __syncthreads();
     fft_group<T, L, C::E, +1>(v1, lds + c, C::CW, tw, t);
     if (ok) {
 #pragma unroll
-      for (int q = 0; q < C::E; ++q) out1[(size_t)(t + q * C::P) * S + m] = v1[q];
+      for (int q = 0; q < C::E; ++q) stg<T>(out1 + (size_t)(t + q * C::P) * S + m, v1[q]);
     }
   }
 }
@@ -581,9 +635,9 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY void k_obs_spectra
     double* __restrict__ part, double* __restrict__ bins, double* __restrict__ counts) {
   using C = ColCfg<L>;
   const Geo& geo = run->g;
-  const c2<T>* phih = bufp<const c2<T>>(*run, bphi);
-  const c2<T>* psih = bpsi >= 0 ? bufp<const c2<T>>(*run, bpsi) : nullptr;
-  const c2<T>* tw = static_cast<const c2<T>*>(run->twy);
+  auto phih = bufp<const c2<T>>(*run, bphi);
+  gp<const c2<T>> psih = bpsi >= 0 ? bufp<const c2<T>>(*run, bpsi) : nullptr;
+  auto tw = to_global<const c2<double>>(run->twy);
   constexpr int NB = L / 2;  // shells 1 .. ny/2
   constexpr int NBT = (NB + C::THREADS - 1) / C::THREADS;
   constexpr int NE = C::CW * L;
@@ -603,12 +657,12 @@ __global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY void k_obs_spectra
   const int m = ok ? m0 : 0;
   c2<T> v0[C::E], v1[C::E];
 #pragma unroll
-  for (int q = 0; q < C::E; ++q) v0[q] = phih[(size_t)(t + q * C::P) * S + m];
+  for (int q = 0; q < C::E; ++q) v0[q] = ldg<T>(phih + (size_t)(t + q * C::P) * S + m);
   fft_group<T, L, C::E, -1>(v0, lds + c, C::CW, tw, t);
   const bool has_psi = psih != nullptr;
   if (has_psi) {
 #pragma unroll
-    for (int q = 0; q < C::E; ++q) v1[q] = psih[(size_t)(t + q * C::P) * S + m];
+    for (int q = 0; q < C::E; ++q) v1[q] = ldg<T>(psih + (size_t)(t + q * C::P) * S + m);
     __syncthreads();
     fft_group<T, L, C::E, -1>(v1, lds + c, C::CW, tw, t);
   }
@@ -713,7 +767,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_obs_real(const Run* __restrict__ run, int bphi,
                                                   double* __restrict__ part) {
   __shared__ double red[3][256];
-  const T* phi = bufp<const T>(*run, bphi);
+  auto phi = bufp<const T>(*run, bphi);
   const size_t n = (size_t)run->g.nx * run->g.ny;
   const size_t per = (n + gridDim.x - 1) / gridDim.x;
   const size_t lo = blockIdx.x * per, hi = lo + per < n ? lo + per : n;
