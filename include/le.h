@@ -156,6 +156,23 @@ int le_profile(le_ctx* c, int enable);
 int le_stage_times(le_ctx* c, double* ms, int64_t* launches, int32_t cap);
 
 /*
+ * Kernel variants (not part of the method: how its stages are laid out on
+ * the GPU).  At creation every group of runs sharing (nx, ny, precision,
+ * rho > 0) times the candidate kernel variants of its stages on its own
+ * buffers and keeps the fastest; every variant computes the same stage (to
+ * rounding).  le_tuning writes, per group, LE_TUNING_FIELDS int32 values
+ *   nx, ny, precision, inertial, advect, mu_source, column_ch, column_flow
+ * (advect / mu_source: 0 = one fused stencil-and-row-transform kernel,
+ * k > 0 = a stencil kernel over k-row strips then in-place row transforms;
+ * column_*: block shape 0 .. 3), at most cap values in all, and returns the
+ * number of groups (LE_EINVAL for NULL c, cap < 0 or out NULL with cap > 0).
+ * The environment variables LE_TUNE_ADV, LE_TUNE_MU, LE_TUNE_COL_CH and
+ * LE_TUNE_COL_FLOW, when set, fix the corresponding variant at creation.
+ */
+enum { LE_TUNING_FIELDS = 8 };
+int le_tuning(le_ctx* c, int32_t* out, int32_t cap);
+
+/*
  * Batched runs.  Many independent runs (each with its own grid, shear rate,
  * density, precision and initial state) advance together: every stage of a
  * step is one launch per group of runs sharing (nx, ny, precision, rho > 0),
@@ -170,6 +187,7 @@ int le_stage_times(le_ctx* c, double* ms, int64_t* launches, int32_t cap);
  *   le_get_state for run index 0 <= run < n (LE_EINVAL otherwise).
  * le_batch_profile / le_batch_stage_times: as le_profile / le_stage_times,
  *   each stage timed across all runs.
+ * le_batch_tuning: as le_tuning, one record per group of runs.
  */
 typedef struct le_batch le_batch;
 int le_batch_create(int32_t n, const le_params* ps, const double* const* phi0s,
@@ -180,6 +198,7 @@ int le_batch_get_state(le_batch* b, int32_t run, double* phi, double* omega, dou
                        int64_t* step, int64_t* wraps);
 int le_batch_profile(le_batch* b, int enable);
 int le_batch_stage_times(le_batch* b, double* ms, int64_t* launches, int32_t cap);
+int le_batch_tuning(le_batch* b, int32_t* out, int32_t cap);
 void le_batch_destroy(le_batch* b);  /* NULL-safe */
 
 /*

@@ -116,6 +116,11 @@ struct Class {
   int nx, ny, prec;
   bool inertial;
   Ops ops;
+  // kernel variants, chosen by autotune() at creation
+  int adv_variant = 0;       // Ops::advect
+  int mu_variant = 0;        // Ops::mu_source
+  int col_ch_variant = 0;    // Ops::column, Cahn-Hilliard pass
+  int col_flow_variant = 0;  // Ops::column, flow (or Stokes) pass
   std::vector<int> members;  // run ids
   int first = 0;             // internal index of members[0]
 };
@@ -245,11 +250,12 @@ int solve_psi(Engine* e, const RunHost& r) {
   const Class& k = e->classes[r.cls];
   const StepArgs* sa = e->d_args + r.internal;
   if (r.inertial) {
-    k.ops.column(COL_POISSON, desc(e, r), 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S,
+    k.ops.column(COL_POISSON, desc(e, r), 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0,
                  e->stream);
   } else {
-    k.ops.mu_source(desc(e, r), 1, r.p.ny, sa, e->stream);
-    k.ops.column(COL_STOKES, desc(e, r), 1, r.p.nx, sa, B_GH, B_GH, B_PS_S, B_PS_S, e->stream);
+    k.ops.mu_source(desc(e, r), 1, r.p.ny, sa, k.mu_variant, e->stream);
+    k.ops.column(COL_STOKES, desc(e, r), 1, r.p.nx, sa, B_GH, B_GH, B_PS_S, B_PS_S,
+                 k.col_flow_variant, e->stream);
   }
   LE_TRY(hipGetLastError());
   return LE_OK;
@@ -274,26 +280,27 @@ void enqueue_step(Engine* e, const StepArgs* sa, hipEvent_t* ev) {
   mark(1);
   for (const Class& k : e->classes)
     k.ops.advect(e->d_desc + k.first, (int)k.members.size(), k.ny, sa + k.first, k.inertial,
-                 st);
+                 k.adv_variant, st);
   mark(2);
   for (const Class& k : e->classes)
     k.ops.column(COL_CH, e->d_desc + k.first, (int)k.members.size(), k.nx, sa + k.first,
-                 B_PHIH, B_FH, B_PHIN, B_PHIN, st);
+                 B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant, st);
   mark(3);
   for (const Class& k : e->classes)
     k.ops.row_c2r(e->d_desc + k.first, (int)k.members.size(), k.ny, B_PHIN, B_PHI, B_PHIN,
                   B_PHI, 1, st);
   mark(4);
   for (const Class& k : e->classes)
-    k.ops.mu_source(e->d_desc + k.first, (int)k.members.size(), k.ny, sa + k.first, st);
+    k.ops.mu_source(e->d_desc + k.first, (int)k.members.size(), k.ny, sa + k.first,
+                    k.mu_variant, st);
   mark(5);
   for (const Class& k : e->classes) {
     if (k.inertial)
       k.ops.column(COL_FLOW, e->d_desc + k.first, (int)k.members.size(), k.nx, sa + k.first,
-                   B_OMH, B_GH, B_OM_S, B_PS_S, st);
+                   B_OMH, B_GH, B_OM_S, B_PS_S, k.col_flow_variant, st);
     else
       k.ops.column(COL_STOKES, e->d_desc + k.first, (int)k.members.size(), k.nx,
-                   sa + k.first, B_GH, B_GH, B_PS_S, B_PS_S, st);
+                   sa + k.first, B_GH, B_GH, B_PS_S, B_PS_S, k.col_flow_variant, st);
   }
   mark(6);
 }
@@ -437,6 +444,95 @@ int observables_of(Engine* e, const RunHost& r, le_obs* o, double* Sk, int32_t s
 }
 
 // Build an engine for n runs; on failure everything is released.
+// ---------------------------------------------------------------- autotuner
+//
+// Each class (runs sharing nx, ny, precision, inertia) picks its kernel
+// variants by timing every candidate on its own buffers at creation: the
+// advect and mu/source variants (fused kernel vs strip stencil over 4 .. 32
+// row strips) and the column block shapes of both column passes.  The timed
+// launches read the state and write only step temporaries (the flow pass is
+// timed into the spectral scratch buffers), so the state is untouched.
+// LE_TUNE_<STAGE>=v (ADV, MU, COL_CH, COL_FLOW) fixes a variant instead, for
+// tests that exercise every path.
+namespace {
+
+constexpr int kAdvCand[] = {0, 4, 8, 16, 32};
+constexpr int kMuCand[] = {0, 4, 8, 16, 32};
+constexpr int kColCand[] = {0, 1, 2, 3};
+
+int env_variant(const char* name) {
+  const char* v = std::getenv(name);
+  return v ? std::atoi(v) : -1;
+}
+
+// Milliseconds of `reps` launches of f after one untimed launch.
+template <typename F>
+int time_launches(Engine* e, hipEvent_t a, hipEvent_t b, F&& f, float* ms) {
+  f();
+  LE_TRY(hipEventRecord(a, e->stream));
+  for (int i = 0; i < 3; ++i) f();
+  LE_TRY(hipEventRecord(b, e->stream));
+  LE_TRY(hipEventSynchronize(b));
+  LE_TRY(hipGetLastError());
+  LE_TRY(hipEventElapsedTime(ms, a, b));
+  return LE_OK;
+}
+
+template <size_t N, typename F>
+int pick(Engine* e, hipEvent_t a, hipEvent_t b, const int (&cand)[N], const char* env, int* out,
+         F&& launch) {
+  const int forced = env_variant(env);
+  if (forced >= 0) {
+    *out = forced;
+    return LE_OK;
+  }
+  float best = 0.0f;
+  for (size_t i = 0; i < N; ++i) {
+    float ms = 0.0f;
+    LE_RC(time_launches(e, a, b, [&] { launch(cand[i]); }, &ms));
+    if (i == 0 || ms < best) {
+      best = ms;
+      *out = cand[i];
+    }
+  }
+  return LE_OK;
+}
+
+int autotune(Engine* e) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return LE_EDEVICE;
+  }
+  int rc = LE_OK;
+  for (Class& k : e->classes) {
+    const Run* d = e->d_desc + k.first;
+    const int n = (int)k.members.size();
+    const StepArgs* sa = e->d_args + k.first;
+    hipStream_t st = e->stream;
+    rc = rc ? rc : pick(e, a, b, kAdvCand, "LE_TUNE_ADV", &k.adv_variant, [&](int v) {
+      k.ops.advect(d, n, k.ny, sa, k.inertial, v, st);
+    });
+    rc = rc ? rc : pick(e, a, b, kMuCand, "LE_TUNE_MU", &k.mu_variant, [&](int v) {
+      k.ops.mu_source(d, n, k.ny, sa, v, st);
+    });
+    rc = rc ? rc : pick(e, a, b, kColCand, "LE_TUNE_COL_CH", &k.col_ch_variant, [&](int v) {
+      k.ops.column(COL_CH, d, n, k.nx, sa, B_PHIH, B_FH, B_PHIN, B_PHIN, v, st);
+    });
+    rc = rc ? rc : pick(e, a, b, kColCand, "LE_TUNE_COL_FLOW", &k.col_flow_variant, [&](int v) {
+      if (k.inertial)
+        k.ops.column(COL_FLOW, d, n, k.nx, sa, B_OMH, B_GH, B_PHIH, B_FH, v, st);
+      else
+        k.ops.column(COL_STOKES, d, n, k.nx, sa, B_GH, B_GH, B_PHIN, B_PHIN, v, st);
+    });
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
+}  // namespace
+
 int create_engine(int32_t n, const le_params* ps, const double* const* phi0s,
                   const double* const* omega0s, Engine** out) {
   if (!out || n < 1 || !ps || !phi0s) return LE_EINVAL;
@@ -597,6 +693,7 @@ int create_engine(int32_t n, const le_params* ps, const double* const* phi0s,
     }
     if (!rc) rc = solve_psi(e, r);
   }
+  if (!rc) rc = autotune(e);
   if (!rc && hipStreamSynchronize(e->stream) != hipSuccess) rc = LE_EDEVICE;
   if (rc) {
     release(e);
@@ -736,7 +833,7 @@ int step_corrected(Engine* e, int64_t ncoarse) {
                                                static_cast<float*>(r.buf[B_OM_R]), e->stream);
       if (rc) return LE_EDEVICE;
       o.row_r2c(d, 1, r.p.ny, B_OM_R, B_OM_S, e->stream);
-      o.column(COL_POISSON, d, 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, e->stream);
+      o.column(COL_POISSON, d, 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0, e->stream);
     }
     e->step = n0 + count;
     const int64_t k_new = wrap_count(r.p, e->step);
@@ -824,6 +921,18 @@ int le_set_state(le_ctx* c, const double* phi, const double* omega, const double
 
 int le_profile(le_ctx* c, int enable) { return profile_engine(c, enable); }
 
+int tuning_of(le_ctx* c, int32_t* out, int32_t cap) {
+  if (!c || cap < 0 || (cap > 0 && !out)) return LE_EINVAL;
+  int32_t w = 0;
+  for (const Class& k : c->classes) {
+    const int32_t rec[LE_TUNING_FIELDS] = {k.nx, k.ny, k.prec, k.inertial ? 1 : 0,
+                                           k.adv_variant, k.mu_variant, k.col_ch_variant,
+                                           k.col_flow_variant};
+    for (int i = 0; i < LE_TUNING_FIELDS && w < cap; ++i) out[w++] = rec[i];
+  }
+  return (int)c->classes.size();
+}
+
 int le_stage_times(le_ctx* c, double* ms, int64_t* launches, int32_t cap) {
   return stage_times_of(c, ms, launches, cap);
 }
@@ -859,6 +968,12 @@ int le_batch_get_state(le_batch* b, int32_t run, double* phi, double* omega, dou
 
 int le_batch_profile(le_batch* b, int enable) {
   return b ? profile_engine(b->e, enable) : LE_EINVAL;
+}
+
+int le_tuning(le_ctx* c, int32_t* out, int32_t cap) { return tuning_of(c, out, cap); }
+
+int le_batch_tuning(le_batch* b, int32_t* out, int32_t cap) {
+  return b ? tuning_of(b->e, out, cap) : LE_EINVAL;
 }
 
 int le_batch_stage_times(le_batch* b, double* ms, int64_t* launches, int32_t cap) {

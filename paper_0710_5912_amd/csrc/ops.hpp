@@ -16,14 +16,19 @@ struct Ops {
   // inverse row transforms: bin0 -> bout0 and, when nfields == 2, bin1 -> bout1
   void (*row_c2r)(const Run* runs, int nruns, int ny, int bin0, int bout0, int bin1, int bout1,
                   int nfields, hipStream_t st);
-  // stage 1a + forward row transforms (omega parts only when inertial)
+  // stage 1a + forward row transforms (omega parts only when inertial);
+  // variant: 0 fused, k > 0 strip stencil over k-row strips + in-place
+  // transforms
   void (*advect)(const Run* runs, int nruns, int ny, const StepArgs* sa, bool inertial,
-                 hipStream_t st);
-  // stage 2a + forward row transform of g
-  void (*mu_source)(const Run* runs, int nruns, int ny, const StepArgs* sa, hipStream_t st);
-  // column transform + per-mode update (ColMode) + inverse column transform
+                 int variant, hipStream_t st);
+  // stage 2a + forward row transform of g; variant: 0 two kernels through
+  // the real scratch, k > 0 strip stencil over k-row strips (square cells)
+  void (*mu_source)(const Run* runs, int nruns, int ny, const StepArgs* sa, int variant,
+                    hipStream_t st);
+  // column transform + per-mode update (ColMode) + inverse column transform;
+  // variant 0 .. kColVariants-1 picks the block shape
   void (*column)(int mode, const Run* runs, int nruns, int nx, const StepArgs* sa, int bin0,
-                 int bin1, int bout0, int bout1, hipStream_t st);
+                 int bin1, int bout0, int bout1, int variant, hipStream_t st);
   // one run: spectral observable partials (bpsi < 0: no psi)
   void (*obs_spectral)(const Run* run, int nx, const StepArgs* sa, int bphi, int bpsi,
                        double* part, double* bins, double* counts, hipStream_t st);

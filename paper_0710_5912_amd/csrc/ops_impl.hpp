@@ -15,8 +15,9 @@ struct RowLaunch {
     return dim3((ny + C::G - 1) / C::G, fields, nruns);
   }
   static void r2c(const Run* runs, int nruns, int ny, int bin, int bout, hipStream_t st) {
+    R2cJobs jobs{{{bin, bout, 2 * L}, {}, {}}};
     hipLaunchKernelGGL((k_row_r2c<T, L>), grid(ny, 1, nruns), dim3(C::THREADS), 0, st, runs,
-                       bin, bout);
+                       jobs);
   }
   static void c2r(const Run* runs, int nruns, int ny, int bin0, int bout0, int bin1, int bout1,
                   int nfields, hipStream_t st) {
@@ -33,55 +34,102 @@ struct RowLaunch {
       hipLaunchKernelGGL((k_bracket<T, L, false>), grid(ny, njobs, nruns), dim3(C::THREADS), 0,
                          st, runs, sa, jobs);
   }
+  // variant 0: the fused bracket kernel (stencil and row transform per
+  // block); variant k > 0: the strip stencil over k-row strips into the
+  // spectral buffers, then in-place row transforms
   static void advect(const Run* runs, int nruns, int ny, const StepArgs* sa, bool inertial,
-                     hipStream_t st) {
-    Jobs jobs{{{JOB_ADVECT, B_PHI, B_PS_R, B_PHIH},
-               {JOB_CUBE, B_PHI, B_PHI, B_FH},
-               {JOB_ADVECT, B_OM_R, B_PS_R, B_OMH}}};
-    bracket(runs, nruns, ny, sa, jobs, inertial ? 3 : 2, st);
+                     int variant, hipStream_t st) {
+    if (variant <= 0) {
+      Jobs jobs{{{JOB_ADVECT, B_PHI, B_PS_R, B_PHIH},
+                 {JOB_CUBE, B_PHI, B_PHI, B_FH},
+                 {JOB_ADVECT, B_OM_R, B_PS_R, B_OMH}}};
+      bracket(runs, nruns, ny, sa, jobs, inertial ? 3 : 2, st);
+      return;
+    }
+    constexpr int NX = 2 * L, TPB = strip_threads(NX);
+    const dim3 gs(NX / 2 / TPB, (ny + variant - 1) / variant, nruns);
+    if (ny == NX)
+      hipLaunchKernelGGL((k_adv_strip<T, NX, true>), gs, dim3(TPB), 0, st, runs, sa, variant,
+                         inertial ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_adv_strip<T, NX, false>), gs, dim3(TPB), 0, st, runs, sa, variant,
+                         inertial ? 1 : 0);
+    R2cJobs jobs{{{B_PHIH, B_PHIH, NX + 2}, {B_FH, B_FH, NX + 2}, {B_OMH, B_OMH, NX + 2}}};
+    hipLaunchKernelGGL((k_row_r2c<T, L>), grid(ny, inertial ? 3 : 2, nruns), dim3(C::THREADS), 0,
+                       st, runs, jobs);
   }
-  // mu into the real scratch field, then the source bracket and its row
+  // variant 0: mu into the real scratch field, then the source bracket and
+  // its row transform; variant k > 0 (square cells only): the strip stencil
+  // (mu in registers) over k-row strips into B_GH, then its in-place row
   // transform
-  static void mu_source(const Run* runs, int nruns, int ny, const StepArgs* sa, hipStream_t st) {
-    hipLaunchKernelGGL((k_mu<T, L>), grid(ny, 1, nruns), dim3(C::THREADS), 0, st, runs, sa,
-                       (int)B_PHI, (int)B_TMP);
-    Jobs jobs{{{JOB_SOURCE, B_PHI, B_TMP, B_GH}, {}, {}}};
-    bracket(runs, nruns, ny, sa, jobs, 1, st);
+  static void mu_source(const Run* runs, int nruns, int ny, const StepArgs* sa, int variant,
+                        hipStream_t st) {
+    constexpr int NX = 2 * L, TPB = strip_threads(NX);
+    if (variant <= 0 || ny != NX) {
+      hipLaunchKernelGGL((k_mu<T, L>), grid(ny, 1, nruns), dim3(C::THREADS), 0, st, runs, sa,
+                         (int)B_PHI, (int)B_TMP);
+      Jobs jobs{{{JOB_SOURCE, B_PHI, B_TMP, B_GH}, {}, {}}};
+      bracket(runs, nruns, ny, sa, jobs, 1, st);
+      return;
+    }
+    const dim3 gs(NX / 2 / TPB, (ny + variant - 1) / variant, nruns);
+    hipLaunchKernelGGL((k_mug_strip<T, NX>), gs, dim3(TPB), 0, st, runs, sa, variant);
+    R2cJobs jobs{{{B_GH, B_GH, NX + 2}, {}, {}}};
+    hipLaunchKernelGGL((k_row_r2c<T, L>), grid(ny, 1, nruns), dim3(C::THREADS), 0, st, runs,
+                       jobs);
   }
 };
 
 template <typename T, int L>
 struct ColLaunch {
-  using C = ColCfg<L>;
-  static int nblk(int nx) { return (nx / 2 + 1 + C::CW - 1) / C::CW; }
+  template <int MODE, int VAR>
+  static void launch(const Run* runs, int nruns, int nx, const StepArgs* sa, int bin0, int bin1,
+                     int bout0, int bout1, hipStream_t st) {
+    using C = ColCfg<T, L, VAR>;
+    const dim3 gr((nx / 2 + 1 + C::CW - 1) / C::CW, 1, nruns), bl(C::THREADS);
+    hipLaunchKernelGGL((k_column<T, L, MODE, VAR>), gr, bl, 0, st, runs, sa, bin0, bin1, bout0,
+                       bout1);
+  }
+  template <int MODE>
+  static void by_variant(int variant, const Run* runs, int nruns, int nx, const StepArgs* sa,
+                         int bin0, int bin1, int bout0, int bout1, hipStream_t st) {
+    // lengths below 512 are latency bound: one shape
+    if constexpr (L < 512) {
+      launch<MODE, 0>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st);
+    } else {
+      switch (variant) {
+        case 1: launch<MODE, 1>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
+        case 2: launch<MODE, 2>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
+        case 3: launch<MODE, 3>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
+        default: launch<MODE, 0>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
+      }
+    }
+  }
   static void column(int mode, const Run* runs, int nruns, int nx, const StepArgs* sa,
-                     int bin0, int bin1, int bout0, int bout1, hipStream_t st) {
-    const dim3 gr(nblk(nx), 1, nruns), bl(C::THREADS);
+                     int bin0, int bin1, int bout0, int bout1, int variant, hipStream_t st) {
     switch (mode) {
       case COL_CH:
-        hipLaunchKernelGGL((k_column<T, L, COL_CH>), gr, bl, 0, st, runs, sa, bin0, bin1, bout0,
-                           bout1);
+        by_variant<COL_CH>(variant, runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st);
         break;
       case COL_FLOW:
-        hipLaunchKernelGGL((k_column<T, L, COL_FLOW>), gr, bl, 0, st, runs, sa, bin0, bin1,
-                           bout0, bout1);
+        by_variant<COL_FLOW>(variant, runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st);
         break;
       case COL_STOKES:
-        hipLaunchKernelGGL((k_column<T, L, COL_STOKES>), gr, bl, 0, st, runs, sa, bin0, bin1,
-                           bout0, bout1);
+        by_variant<COL_STOKES>(variant, runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st);
         break;
       default:
-        hipLaunchKernelGGL((k_column<T, L, COL_POISSON>), gr, bl, 0, st, runs, sa, bin0, bin1,
-                           bout0, bout1);
+        launch<COL_POISSON, 0>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st);
         break;
     }
   }
+  using O = ObsCfg<L>;
+  static int obs_nblk(int nx) { return (nx / 2 + 1 + O::CW - 1) / O::CW; }
   static void obs(const Run* run, int nx, const StepArgs* sa, int bphi, int bpsi, double* part,
                   double* bins, double* counts, hipStream_t st) {
-    hipLaunchKernelGGL((k_obs_spectral<T, L>), dim3(nblk(nx)), dim3(C::THREADS), 0, st, run, sa,
-                       bphi, bpsi, part, bins, counts);
+    hipLaunchKernelGGL((k_obs_spectral<T, L>), dim3(obs_nblk(nx)), dim3(O::THREADS), 0, st, run,
+                       sa, bphi, bpsi, part, bins, counts);
   }
-  static int blocks(int nx) { return nblk(nx); }
+  static int blocks(int nx) { return obs_nblk(nx); }
 };
 
 template <typename T>

@@ -45,8 +45,27 @@ struct RowCfg {
   static constexpr int THREADS = G * P;
 };
 
-template <int L>
+// Column kernel shapes, VAR (a tuning choice, 0 .. 3): bit 0 doubles the
+// columns per block (where threads <= 1024 and LDS <= 160 KB allow), bit 1
+// uses 16 values per thread (FP32 only: fewer LDS passes; FP64 would not fit
+// the registers).
+template <typename T, int L, int VAR>
 struct ColCfg {
+  static constexpr bool WIDE_E = (VAR & 2) != 0 && sizeof(T) == 4 && L >= 16;
+  static constexpr int E = WIDE_E ? 16 : col_elems(L);
+  static constexpr int P = L / E;
+  static constexpr int CW0 = clampi(256 / P, 1, 64);
+  static constexpr int CWD = (VAR & 1) ? 2 * CW0 : CW0;
+  static constexpr bool FITS =
+      CWD <= 64 && CWD * P <= 1024 && (long)CWD * L * (long)sizeof(c2<T>) <= 160L * 1024;
+  static constexpr int CW = FITS ? CWD : CW0;
+  static constexpr int THREADS = CW * P;
+};
+constexpr int kColVariants = 4;
+
+// Observables' column kernel (its LDS also holds the shell partials).
+template <int L>
+struct ObsCfg {
   static constexpr int E = col_elems(L);
   static constexpr int P = L / E;
   static constexpr int CW = clampi(256 / P, 1, 64);
@@ -158,22 +177,33 @@ __device__ __forceinline__ double lambda_of(const Modes& q, double s) {
 
 // ---------------------------------------------------------------- row kernels
 
-// Forward row transform of one real field (buffer bin -> row spectrum bout).
+// Forward row transforms: blockIdx.y picks the job (real buffer bin, row
+// stride rs elements -> row spectrum bout).  With rs = nx + 2 the real rows
+// sit at the spectral rows' offsets and the transform may run in place
+// (bin == bout): a block reads its whole row before it writes any of it.
+struct R2cJob {
+  int bin, bout, rs;
+};
+struct R2cJobs {
+  R2cJob j[3];
+};
+
 template <typename T, int L>
 __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_row_r2c(
-    const Run* __restrict__ runs, int bin, int bout) {
+    const Run* __restrict__ runs, R2cJobs jobs) {
   using C = RowCfg<L>;
   __shared__ c2<T> lds[C::G * L];
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
+  const R2cJob job = jobs.j[bp.y];
   const int ny = R.g.ny;
-  auto x = bufp<T>(R, bin);
-  auto X = bufp<c2<T>>(R, bout);
+  auto x = bufp<T>(R, job.bin);
+  auto X = bufp<c2<T>>(R, job.bout);
   auto tw = to_global<const c2<double>>(R.twx);
   const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
   const int j = bp.x * C::G + g;
   const bool ok = j < ny;
-  auto xr = reinterpret_cast<gp<const c2<T>>>(x + (size_t)(ok ? j : 0) * 2 * L);
+  auto xr = reinterpret_cast<gp<const c2<T>>>(x + (size_t)(ok ? j : 0) * job.rs);
   c2<T> v[C::E];
 #pragma unroll
   for (int q = 0; q < C::E; ++q) v[q] = ldg<T>(xr + t + q * C::P);
@@ -410,6 +440,228 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_bracket(
   if (ok) store_row_spec<T, L, C::E>(out + (size_t)j * (L + 1), v, t);
 }
 
+// Stage 1a (Eq. advective) as a stencil over row strips, no transform:
+//   phi_h = phi - dt [Dx phi Dys psi - Dys phi Dx psi],  f = phi^3,
+//   omega_h = omega - dt [Dx omega Dys psi - Dys omega Dx psi]  (inertial)
+// into B_PHIH, B_FH, B_OMH as real rows at the spectral row offsets (row
+// stride nx + 2), for the in-place forward row transforms that follow.
+// Thread: one x pair of a row, walking `rows` consecutive rows; it keeps the
+// quads of rows j-1, j, j+1 in registers and reads one new row per field and
+// step (row j+2, requested a step ahead).
+constexpr int strip_threads(int nx) { return nx / 2 < 256 ? nx / 2 : 256; }
+
+template <typename T, int NX>
+struct StripLanes {
+  static constexpr int TPB = strip_threads(NX);
+  int x, xl, xr;  // pair position; halo positions of the lane's run
+  bool edge_l, edge_r;
+  __device__ __forceinline__ StripLanes(int bx) {
+    const int p = bx * TPB + (int)threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int first = TPB >= 64 ? p - lane : bx * TPB;
+    const int last = TPB >= 64 ? first + 63 : bx * TPB + TPB - 1;
+    x = 2 * p;
+    xl = 2 * first - 1;
+    xr = 2 * last + 2;
+    edge_l = p == first;
+    edge_r = p == last;
+  }
+};
+
+// Raw values of a row for a quad: the pair and the halo this lane may need.
+template <typename T>
+struct RawQuad {
+  c2<T> p;
+  T h;
+};
+template <typename T, int NX>
+__device__ __forceinline__ RawQuad<T> load_raw(gp<const T> __restrict__ row,
+                                               const StripLanes<T, NX>& sl) {
+  RawQuad<T> r;
+  r.p = ldg<T>(reinterpret_cast<gp<const c2<T>>>(row + sl.x));
+  r.h = row[(sl.edge_r ? sl.xr : sl.xl) & (NX - 1)];
+  return r;
+}
+// Every lane of the wavefront must execute this (DPP).
+template <typename T, int NX>
+__device__ __forceinline__ Quad<T> to_quad(const RawQuad<T>& r, const StripLanes<T, NX>& sl) {
+  const T nl = dpp_mov<kDppWaveShr1>(r.p.y);
+  const T nr = dpp_mov<kDppWaveShl1>(r.p.x);
+  return {sl.edge_l ? r.h : nl, r.p.x, r.p.y, sl.edge_r ? r.h : nr};
+}
+
+template <typename T, int NX, bool R1>
+__global__ __launch_bounds__(strip_threads(NX)) void k_adv_strip(
+    const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int rows, int inertial) {
+  const BPos bp = block_pos();
+  const Run& R = runs[bp.z];
+  const Geo& geo = R.g;
+  const int ny = geo.ny;
+  const StripLanes<T, NX> sl(bp.x);
+  const int j0 = bp.y * rows;
+  const int j1 = min(j0 + rows, ny);
+  auto phi = bufp<const T>(R, B_PHI);
+  auto psi = bufp<const T>(R, B_PS_R);
+  auto om = bufp<const T>(R, B_OM_R);
+  auto o_phi = bufp<T>(R, B_PHIH);
+  auto o_f = bufp<T>(R, B_FH);
+  auto o_om = bufp<T>(R, B_OMH);
+  const Stencil<T> st = make_stencil<T>(geo, sa[bp.z].s);
+  const T dt = T(geo.dt);
+  const bool inr = inertial != 0;
+  auto row = [&](gp<const T> f, int j) { return f + (size_t)(j < 0 ? j + ny : (j >= ny ? j - ny : j)) * NX; };
+  Quad<T> Fm = to_quad(load_raw(row(phi, j0 - 1), sl), sl);
+  Quad<T> Fc = to_quad(load_raw(row(phi, j0), sl), sl);
+  Quad<T> Sm = to_quad(load_raw(row(psi, j0 - 1), sl), sl);
+  Quad<T> Sc = to_quad(load_raw(row(psi, j0), sl), sl);
+  Quad<T> Wm = Fm, Wc = Fc;
+  if (inr) {
+    Wm = to_quad(load_raw(row(om, j0 - 1), sl), sl);
+    Wc = to_quad(load_raw(row(om, j0), sl), sl);
+  }
+  RawQuad<T> rF = load_raw(row(phi, j0 + 1), sl);
+  RawQuad<T> rS = load_raw(row(psi, j0 + 1), sl);
+  RawQuad<T> rW = inr ? load_raw(row(om, j0 + 1), sl) : rF;
+  for (int j = j0; j < j1; ++j) {
+    const Quad<T> Fp = to_quad(rF, sl);
+    const Quad<T> Sp = to_quad(rS, sl);
+    const Quad<T> Wp = inr ? to_quad(rW, sl) : Fp;
+    if (j + 1 < j1) {  // row j+2, a step ahead
+      rF = load_raw(row(phi, j + 2), sl);
+      rS = load_raw(row(psi, j + 2), sl);
+      if (inr) rW = load_raw(row(om, j + 2), sl);
+    }
+    T sx0, sx1, sy0, sy1, ax0, ax1, ay0, ay1;
+    quad_dx(Sc, st.inv2dx, sx0, sx1);
+    quad_dys<T, NX, R1>(Sp, Sm, row(psi, j + 1), row(psi, j - 1), sl.x, st, sy0, sy1);
+    quad_dx(Fc, st.inv2dx, ax0, ax1);
+    quad_dys<T, NX, R1>(Fp, Fm, row(phi, j + 1), row(phi, j - 1), sl.x, st, ay0, ay1);
+    const size_t o = (size_t)j * (NX + 2) + sl.x;
+    stg<T>(reinterpret_cast<gp<c2<T>>>(o_phi + o),
+           {Fc.a0 - dt * (ax0 * sy0 - ay0 * sx0), Fc.a1 - dt * (ax1 * sy1 - ay1 * sx1)});
+    stg<T>(reinterpret_cast<gp<c2<T>>>(o_f + o),
+           {Fc.a0 * Fc.a0 * Fc.a0, Fc.a1 * Fc.a1 * Fc.a1});
+    if (inr) {
+      quad_dx(Wc, st.inv2dx, ax0, ax1);
+      quad_dys<T, NX, R1>(Wp, Wm, row(om, j + 1), row(om, j - 1), sl.x, st, ay0, ay1);
+      stg<T>(reinterpret_cast<gp<c2<T>>>(o_om + o),
+             {Wc.a0 - dt * (ax0 * sy0 - ay0 * sx0), Wc.a1 - dt * (ax1 * sy1 - ay1 * sx1)});
+    }
+    Fm = Fc; Fc = Fp;
+    Sm = Sc; Sc = Sp;
+    Wm = Wc; Wc = Wp;
+  }
+}
+
+// Stage 2a as a stencil over row strips (square cells, r = 1), no transform:
+//   mu = B phi^3 - A phi - kappa [(1+s^2) Dxx + Dyy - 2 s Dxy] phi,
+//   g = -[Dx phi Dys mu - Dys phi Dx mu] / c   (c = rho, or eta for Stokes)
+// into B_GH as real rows at the spectral row offsets (row stride nx + 2).
+// mu never leaves the registers: a thread walks its strip keeping the phi
+// quads of rows j-1 .. j+2 and the mu quads of rows j-1 .. j+1; mu at x-1 /
+// x+2 for the first / last lane of a run is computed by that lane from one
+// more phi value per row (x-2 / x+3).
+template <typename T>
+struct PhiRow {
+  Quad<T> q;
+  T e;  // phi at x-2 (first lane of a run) or x+3 (last lane)
+};
+template <typename T>
+struct RawPhi {
+  RawQuad<T> r;
+  T e;
+};
+template <typename T, int NX>
+__device__ __forceinline__ RawPhi<T> load_phi(gp<const T> __restrict__ row,
+                                              const StripLanes<T, NX>& sl) {
+  RawPhi<T> o;
+  o.r = load_raw<T, NX>(row, sl);
+  o.e = row[(sl.edge_r ? sl.xr + 1 : sl.xl - 1) & (NX - 1)];
+  return o;
+}
+template <typename T, int NX>
+__device__ __forceinline__ PhiRow<T> to_phirow(const RawPhi<T>& r, const StripLanes<T, NX>& sl) {
+  return {to_quad<T, NX>(r.r, sl), r.e};
+}
+
+template <typename T>
+struct MuCoef {
+  T cxx, cyy, cxy, A, B, kap;
+};
+// mu at one point from the 3x3 phi neighbourhood (rows d, c, u = j-1, j, j+1;
+// columns w, m, e = x-1, x, x+1).
+template <typename T>
+__device__ __forceinline__ T mu_at(const MuCoef<T>& k, T dw, T dm, T de, T cw, T cm, T ce, T uw,
+                                   T um, T ue) {
+  const T two = T(2);
+  const T dxx = ce - two * cm + cw;
+  const T dyy = um - two * cm + dm;
+  const T dxy = ue - de - uw + dw;
+  return k.B * cm * cm * cm - k.A * cm - k.kap * (k.cxx * dxx + k.cyy * dyy + k.cxy * dxy);
+}
+// mu quad of row j from the phi rows j-1 (d), j (c), j+1 (u).  Every lane of
+// the wavefront must execute this (DPP).
+template <typename T, int NX>
+__device__ __forceinline__ Quad<T> mu_quad(const MuCoef<T>& k, const PhiRow<T>& d,
+                                           const PhiRow<T>& c, const PhiRow<T>& u,
+                                           const StripLanes<T, NX>& sl) {
+  const T m0 = mu_at(k, d.q.l, d.q.a0, d.q.a1, c.q.l, c.q.a0, c.q.a1, u.q.l, u.q.a0, u.q.a1);
+  const T m1 = mu_at(k, d.q.a0, d.q.a1, d.q.r, c.q.a0, c.q.a1, c.q.r, u.q.a0, u.q.a1, u.q.r);
+  // halo mu: at x-1 (neighbourhood x-2 .. x) or at x+2 (x+1 .. x+3)
+  const T mh = sl.edge_r
+                   ? mu_at(k, d.q.a1, d.q.r, d.e, c.q.a1, c.q.r, c.e, u.q.a1, u.q.r, u.e)
+                   : mu_at(k, d.e, d.q.l, d.q.a0, c.e, c.q.l, c.q.a0, u.e, u.q.l, u.q.a0);
+  const T nl = dpp_mov<kDppWaveShr1>(m1);
+  const T nr = dpp_mov<kDppWaveShl1>(m0);
+  return {sl.edge_l ? mh : nl, m0, m1, sl.edge_r ? mh : nr};
+}
+
+template <typename T, int NX>
+__global__ __launch_bounds__(strip_threads(NX)) void k_mug_strip(
+    const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int rows) {
+  const BPos bp = block_pos();
+  const Run& R = runs[bp.z];
+  const Geo& geo = R.g;
+  const int ny = geo.ny;
+  const StripLanes<T, NX> sl(bp.x);
+  const int j0 = bp.y * rows;
+  const int j1 = min(j0 + rows, ny);
+  auto phi = bufp<const T>(R, B_PHI);
+  auto o_g = bufp<T>(R, B_GH);
+  const double s = sa[bp.z].s;
+  const MuCoef<T> k = {T((1.0 + s * s) / (geo.dx * geo.dx)), T(1.0 / (geo.dy * geo.dy)),
+                       T(-2.0 * s / (4.0 * geo.dx * geo.dy)), T(geo.A), T(geo.B), T(geo.kappa)};
+  const Stencil<T> st = make_stencil<T>(geo, s);
+  const T neg_inv = T(-1.0 / (geo.rho > 0.0 ? geo.rho : geo.eta));
+  auto row = [&](int j) {
+    j = j % ny;
+    return phi + (size_t)(j < 0 ? j + ny : j) * NX;
+  };
+  PhiRow<T> F0 = to_phirow(load_phi(row(j0 - 2), sl), sl);  // rows j-2 .. j+1 at j = j0
+  PhiRow<T> F1 = to_phirow(load_phi(row(j0 - 1), sl), sl);
+  PhiRow<T> F2 = to_phirow(load_phi(row(j0), sl), sl);
+  PhiRow<T> F3 = to_phirow(load_phi(row(j0 + 1), sl), sl);
+  Quad<T> Mm = mu_quad(k, F0, F1, F2, sl);  // mu rows j-1, j
+  Quad<T> Mc = mu_quad(k, F1, F2, F3, sl);
+  RawPhi<T> rn = load_phi(row(j0 + 2), sl);
+  for (int j = j0; j < j1; ++j) {
+    // window: F1 = phi(j-1), F2 = phi(j), F3 = phi(j+1); rn = phi(j+2)
+    const PhiRow<T> F4 = to_phirow(rn, sl);
+    if (j + 1 < j1) rn = load_phi(row(j + 3), sl);
+    const Quad<T> Mp = mu_quad(k, F2, F3, F4, sl);  // mu(j+1)
+    T px0, px1, py0, py1, mx0, mx1, my0, my1;
+    quad_dx(F2.q, st.inv2dx, px0, px1);
+    quad_dys<T, NX, true>(F3.q, F1.q, row(j + 1), row(j - 1), sl.x, st, py0, py1);
+    quad_dx(Mc, st.inv2dx, mx0, mx1);
+    quad_dys<T, NX, true>(Mp, Mm, row(j + 1), row(j - 1), sl.x, st, my0, my1);
+    const size_t o = (size_t)j * (NX + 2) + sl.x;
+    stg<T>(reinterpret_cast<gp<c2<T>>>(o_g + o),
+           {neg_inv * (px0 * my0 - py0 * mx0), neg_inv * (px1 * my1 - py1 * mx1)});
+    F1 = F2; F2 = F3; F3 = F4;
+    Mm = Mc; Mc = Mp;
+  }
+}
+
 // Chemical potential (Eq. mu, stage 2a) on x pairs into a real field:
 //   mu = B phi^3 - A phi - kappa [(1+s^2) Dxx + Dyy - 2 s Dxy] phi.
 template <typename T, int L>
@@ -520,11 +772,11 @@ __global__ void k_copy_real(const Run* __restrict__ run, int bin, int bout) {
 //  COL_FLOW    (omega_h, g) -> (omega', psi')   stages 2b and 3
 //  COL_STOKES  g -> psi'                  zero-Reynolds solve
 //  COL_POISSON omega -> psi               set-up: psi from omega
-template <typename T, int L, int MODE>
-__global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY_COL void k_column(
+template <typename T, int L, int MODE, int VAR>
+__global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void k_column(
     const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int bin0, int bin1,
     int bout0, int bout1) {
-  using C = ColCfg<L>;
+  using C = ColCfg<T, L, VAR>;
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
   const Geo& geo = R.g;
@@ -630,10 +882,10 @@ __device__ __forceinline__ void obs_mode(const Geo& g, int m, int n, double s, d
 // Spectral observables: column transforms of phi (and psi), per-block fixed
 // order partial sums of OBS_* and of the S(k) shells.
 template <typename T, int L>
-__global__ __launch_bounds__(ColCfg<L>::THREADS) LE_OCCUPANCY void k_obs_spectral(
+__global__ __launch_bounds__(ObsCfg<L>::THREADS) LE_OCCUPANCY void k_obs_spectral(
     const Run* __restrict__ run, const StepArgs* __restrict__ sa, int bphi, int bpsi,
     double* __restrict__ part, double* __restrict__ bins, double* __restrict__ counts) {
-  using C = ColCfg<L>;
+  using C = ObsCfg<L>;
   const Geo& geo = run->g;
   auto phih = bufp<const c2<T>>(*run, bphi);
   gp<const c2<T>> psih = bpsi >= 0 ? bufp<const c2<T>>(*run, bpsi) : nullptr;

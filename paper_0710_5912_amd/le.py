@@ -21,12 +21,16 @@ SYMBOLS = ("le_create", "le_step", "le_observables", "le_destroy", "le_get_state
            "le_set_state", "le_strerror", "le_profile", "le_stage_times", "le_last_error",
            "le_batch_create", "le_batch_step", "le_batch_observables", "le_batch_get_state",
            "le_batch_profile", "le_batch_stage_times", "le_batch_destroy",
+           "le_tuning", "le_batch_tuning",
            "le_corrector_load", "le_step_corrected", "le_restrict", "le_set_fields",
            "le_cnn_nparams", "le_cnn_create", "le_cnn_destroy", "le_cnn_set_params",
            "le_cnn_get_params", "le_cnn_forward", "le_cnn_grad", "le_cnn_adam",
            "le_cnn_layer_fwd", "le_cnn_layer_bwd", "le_cnn_mfma_probe")
 LE_NSTAGES = 6
 STAGES = ("row_inv_flow", "advect", "column_ch", "row_inv_phi", "mu_source", "column_flow")
+LE_TUNING_FIELDS = 8
+TUNING_KEYS = ("nx", "ny", "precision", "inertial", "advect", "mu_source", "column_ch",
+               "column_flow")
 
 
 class LeParams(C.Structure):
@@ -45,6 +49,19 @@ class LeObs(C.Structure):
                 ("L_perp", C.c_double), ("sigma_xy", C.c_double),
                 ("sigma_xy_re", C.c_double), ("nbins", C.c_int32), ("dk", C.c_double),
                 ("finite", C.c_int32)]
+
+
+def _tuning(fn, h, what):
+    """Per-group kernel variants chosen at creation (list of dicts)."""
+    n = fn(h, None, 0)
+    if n < 0:
+        raise LeError(n, what)
+    buf = (C.c_int32 * (n * LE_TUNING_FIELDS))()
+    rc = fn(h, buf, n * LE_TUNING_FIELDS)
+    if rc < 0:
+        raise LeError(rc, what)
+    return [dict(zip(TUNING_KEYS, buf[i * LE_TUNING_FIELDS:(i + 1) * LE_TUNING_FIELDS]))
+            for i in range(n)]
 
 
 class LeError(RuntimeError):
@@ -110,6 +127,9 @@ def lib():
         L.le_batch_profile.restype = C.c_int
         L.le_batch_stage_times.argtypes = [C.c_void_p, _DP, C.POINTER(C.c_int64), C.c_int32]
         L.le_batch_stage_times.restype = C.c_int
+        for f in (L.le_tuning, L.le_batch_tuning):
+            f.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.c_int32]
+            f.restype = C.c_int
         L.le_batch_destroy.argtypes = [C.c_void_p]
         L.le_batch_destroy.restype = None
         _FP = C.POINTER(C.c_float)
@@ -262,6 +282,11 @@ class Context:
             raise LeError(rc, "le_stage_times")
         return {STAGES[k]: (float(ms[k]), int(n[k])) for k in range(LE_NSTAGES)}
 
+    def tuning(self):
+        """Kernel variants the autotuner chose for this run (list of one dict)."""
+        self._check()
+        return _tuning(lib().le_tuning, self._h, "le_tuning")
+
     def corrector_load(self, params, scales) -> None:
         """Install the corrector network (FP32 weight vector, 4 scales)."""
         self._check()
@@ -377,6 +402,10 @@ class Batch:
         rc = lib().le_batch_profile(self._h, 1 if enable else 0)
         if rc != LE_OK:
             raise LeError(rc, "le_batch_profile")
+
+    def tuning(self):
+        """Kernel variants the autotuner chose, one dict per group of runs."""
+        return _tuning(lib().le_batch_tuning, self._h, "le_batch_tuning")
 
     def stage_times(self):
         ms = np.zeros(LE_NSTAGES)

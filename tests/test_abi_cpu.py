@@ -78,4 +78,6 @@ def test_null_arguments_rejected():
     assert lib.le_create(C.byref(p), None, None, C.byref(h)) == le.LE_EINVAL
     assert lib.le_step(None, 1) == le.LE_EINVAL
     assert lib.le_observables(None, None, None, 0) == le.LE_EINVAL
+    assert lib.le_tuning(None, None, 0) == le.LE_EINVAL
+    assert lib.le_batch_tuning(None, None, 0) == le.LE_EINVAL
     lib.le_destroy(None)   # NULL-safe

@@ -1,0 +1,110 @@
+"""Every kernel variant the autotuner may pick computes the same step.
+
+The variants of a stage (fused stencil-and-transform kernel or strip stencil
+plus in-place row transforms; column block shapes) are forced one by one
+through LE_TUNE_* at creation and each run is checked against the FP64 oracle
+(1e-10 relative, max norm) at sizes where the column shapes differ (512^2)
+and across a strain wrap.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import model_h as mh
+from paper_0710_5912_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+le = pytest.importorskip("paper_0710_5912_amd.le")
+
+KEYS = ("LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH", "LE_TUNE_COL_FLOW")
+# (advect, mu_source, column_ch, column_flow)
+COMBOS = [(0, 0, 0, 0), (4, 4, 1, 1), (32, 32, 2, 2), (8, 16, 3, 3)]
+
+
+def params(nx, ny, **kw):
+    base = dict(nx=nx, ny=ny, lx=float(nx), ly=float(ny), gdot=0.3, A=1.0, B=1.0,
+                kappa=1.0, M=1.0, eta=1.0, rho=1.0, dt=0.005)
+    base.update(kw)
+    return base
+
+
+def rel(a, b):
+    den = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0))
+
+
+_ORACLE = {}
+
+
+def oracle(p, steps, seed):
+    key = (tuple(sorted(p.items())), steps, seed)
+    if key not in _ORACLE:
+        phi0 = inputs.noise_phi0(p["ny"], p["nx"], seed, amp=0.5)
+        om0 = inputs.noise_omega0(p["ny"], p["nx"], seed) if p["rho"] > 0 else None
+        op = mh.Params(**p)
+        _ORACLE[key] = (phi0, om0, mh.run(op, mh.initial_state(op, phi0, om0), steps))
+    return _ORACLE[key]
+
+
+def run_forced(monkeypatch, p, steps, seed, combo, precision="fp64"):
+    for k, v in zip(KEYS, combo):
+        monkeypatch.setenv(k, str(v))
+    phi0, om0, st = oracle(p, steps, seed)
+    print(f"case nx={p['nx']} ny={p['ny']} rho={p['rho']} steps={steps} combo={combo} "
+          f"{precision}", flush=True)
+    with le.Context(p, phi0, om0, precision=precision) as c:
+        t = c.tuning()[0]
+        c.step(steps)
+        g = c.get_state()
+    assert (t["advect"], t["mu_source"], t["column_ch"], t["column_flow"]) == combo
+    return g, st
+
+
+@pytest.mark.parametrize("combo", COMBOS)
+@pytest.mark.parametrize("rho", [1.0, 0.0])
+def test_variants_512_fp64(monkeypatch, combo, rho):
+    p = params(512, 512, rho=rho)
+    g, st = run_forced(monkeypatch, p, 3, 21, combo)
+    for k in ("phi", "psi") + (("omega",) if rho > 0 else ()):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k
+
+
+@pytest.mark.parametrize("combo", [(4, 4, 1, 3), (32, 8, 3, 1)])
+def test_variants_512_fp32(monkeypatch, combo):
+    """FP32 shapes (16 values per thread in shapes 2 and 3) within the FP32 bound."""
+    p = params(512, 512)
+    g, st = run_forced(monkeypatch, p, 3, 22, combo, precision="fp32")
+    assert rel(g["phi"], st.phi) <= 2e-5
+    assert rel(g["psi"], st.psi) <= 2e-4
+
+
+@pytest.mark.parametrize("combo", [(4, 4, 0, 0), (16, 32, 0, 0)])
+def test_strip_variants_across_a_wrap(monkeypatch, combo):
+    """64^2, gdot = 0.5: the strain wraps at step 200; 220 steps."""
+    p = params(64, 64, gdot=0.5)
+    g, st = run_forced(monkeypatch, p, 220, 23, combo)
+    assert g["wraps"] == st.wraps == 1
+    for k in ("phi", "omega", "psi"):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k
+
+
+def test_strip_variants_non_square_cells(monkeypatch):
+    """nx = 4 ny (r = 4): the strip advect reads the diagonal pairs; the mu
+    strip applies to square cells only and falls back."""
+    p = params(256, 64, gdot=0.2, lx=256.0, ly=64.0)
+    g, st = run_forced(monkeypatch, p, 20, 24, (8, 8, 0, 0))
+    for k in ("phi", "omega", "psi"):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k
+
+
+def test_autotuner_reports_valid_choices():
+    p = params(256, 256)
+    with le.Context(p, inputs.noise_phi0(256, 256, 0)) as c:
+        t = c.tuning()
+    assert len(t) == 1
+    t = t[0]
+    assert (t["nx"], t["ny"], t["precision"], t["inertial"]) == (256, 256, 0, 1)
+    assert t["advect"] in (0, 4, 8, 16, 32) and t["mu_source"] in (0, 4, 8, 16, 32)
+    assert t["column_ch"] in range(4) and t["column_flow"] in range(4)
