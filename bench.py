@@ -85,8 +85,24 @@ def run_variant(le, torch, params, precision, steps, warmup, obs_every, seed=0,
         ctx.step(prof_steps)
         times = ctx.stage_times()
         ctx.profile(False)
+    tuning = ctx.tuning()[0]
     ctx.close()
-    return dict(wall=wall, gpu_ms=gpu_ms, times=times, series=series)
+    return dict(wall=wall, gpu_ms=gpu_ms, times=times, series=series, tuning=tuning)
+
+
+def step_bytes(params, precision):
+    return sum(stage_bytes(params, precision).values())
+
+
+def stage_kernels(tuning, inertial):
+    """Kernels each stage launches under the autotuned variants."""
+    adv = ("k_bracket" if tuning["advect"] == 0 else "k_adv_strip + k_row_r2c")
+    sq = tuning["nx"] == tuning["ny"]
+    mu = ("k_mu + k_bracket" if tuning["mu_source"] == 0 or not sq
+          else "k_mug_strip + k_row_r2c")
+    return {"row_inv_flow": "k_row_c2r", "advect": adv, "column_ch": "k_column<COL_CH>",
+            "row_inv_phi": "k_row_c2r", "mu_source": mu,
+            "column_flow": "k_column<COL_FLOW>" if inertial else "k_column<COL_STOKES>"}
 
 
 def batch_workload():
@@ -265,7 +281,8 @@ def main():
                                "plain FP64 step, observables every 100 steps",
                    "grid": [1024, 1024], "precision": "fp64", "rho": 1.0, "gdot": 0.01,
                    "obs_every": args.obs_every},
-        "roofline": {"bound": "hbm", "kernel": dom,
+        "roofline": {"bound": "hbm", "stage": dom,
+                     "kernels": stage_kernels(r["tuning"], True)[dom],
                      "timing": "HIP events around each stage launch, 1000 directly launched "
                                "steps after the timed region, same stream", "achieved": rows[dom]["gbs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -275,6 +292,10 @@ def main():
                      "avg_launch_us": rows[dom]["avg_us"]},
         "stages": {k: {"avg_us": round(v["avg_us"], 2), "GBs": round(v["gbs"], 1)}
                    for k, v in rows.items()},
+        "step_roofline": {"bytes_per_step": step_bytes(params, "fp64"),
+                          "frac": step_bytes(params, "fp64") / (r["gpu_ms"] / args.steps * 1e-3)
+                          / 1e9 / HBM_PEAK_GBS},
+        "tuning": r["tuning"],
         "wall_s": r["wall"],
         "hip_note": le.lib().le_last_error().decode(),
         "parity": "FP64 path within 1e-10 of the FP64 oracle after 100 steps (tests)",
@@ -290,7 +311,8 @@ def main():
             d, rw = roofline_of(p, prec, rv["times"])
             var[name] = dict(value=sites * n / (rv["gpu_ms"] * 1e-3),
                              ms_per_step=rv["gpu_ms"] / n,
-                             dominant=d, dominant_frac=rw[d]["gbs"] / HBM_PEAK_GBS)
+                             dominant=d, dominant_frac=rw[d]["gbs"] / HBM_PEAK_GBS,
+                             tuning=rv["tuning"])
         print("bench: variant batched_96", file=sys.stderr, flush=True)
         var["batched_96_fp32"] = run_batch(le, torch, 500, 50, 100)
         print("bench: variant corrector", file=sys.stderr, flush=True)
@@ -303,17 +325,20 @@ def main():
             L_err_max=ev["err_max_corrected"], L_err_mean_plain_coarse=ev["err_mean_coarse"],
             note="fine-equivalent site-updates/s of 256^2 corrected steps at 4 dt against "
                  "the 1024^2 FP64 plain run, t = 5..50, gdot = 0.01, held-out seed")
-        # the large single-GPU grid
-        p = configs.LARGE_4096["params"]
-        print("bench: variant fp64_4096", file=sys.stderr, flush=True)
-        rv = run_variant(le, torch, p, "fp64", 200, 20, 100, prof_steps=100)
-        d, rw = roofline_of(p, "fp64", rv["times"])
-        var["fp64_4096_inertial"] = dict(value=4096 * 4096 * 200 / (rv["gpu_ms"] * 1e-3),
-                                         ms_per_step=rv["gpu_ms"] / 200, dominant=d,
-                                         dominant_frac=rw[d]["gbs"] / HBM_PEAK_GBS,
-                                         stages={k: {"avg_us": round(v["avg_us"], 1),
-                                                     "GBs": round(v["gbs"], 1)}
-                                                 for k, v in rw.items()})
+        # the large single-GPU grid, FP64 and FP32 bulk
+        for prec in ("fp64", "fp32"):
+            p = configs.LARGE_4096["params"]
+            print(f"bench: variant {prec}_4096", file=sys.stderr, flush=True)
+            rv = run_variant(le, torch, p, prec, 200, 20, 100, prof_steps=100)
+            d, rw = roofline_of(p, prec, rv["times"])
+            ms = rv["gpu_ms"] / 200
+            var[f"{prec}_4096_inertial"] = dict(
+                value=4096 * 4096 * 200 / (rv["gpu_ms"] * 1e-3), ms_per_step=ms, dominant=d,
+                dominant_frac=rw[d]["gbs"] / HBM_PEAK_GBS,
+                step_frac=step_bytes(p, prec) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                tuning=rv["tuning"],
+                stages={k: {"avg_us": round(v["avg_us"], 1), "GBs": round(v["gbs"], 1)}
+                        for k, v in rw.items()})
         out["variants"] = var
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
