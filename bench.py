@@ -323,8 +323,14 @@ def main():
             value=ev["corrected_fine_equiv_rate"], plain_fine_value=ev["fine_rate"],
             gain=ev["gain"], L_err_mean=ev["err_mean_corrected"],
             L_err_max=ev["err_max_corrected"], L_err_mean_plain_coarse=ev["err_mean_coarse"],
-            note="fine-equivalent site-updates/s of 256^2 corrected steps at 4 dt against "
-                 "the 1024^2 FP64 plain run, t = 5..50, gdot = 0.01, held-out seed")
+            L_err_mean_vs_restricted=ev["err_mean_corrected_vs_restricted"],
+            L_err_max_vs_restricted=ev["err_max_corrected_vs_restricted"],
+            L_err_mean_plain_coarse_vs_restricted=ev["err_mean_coarse_vs_restricted"],
+            L_restriction_bias=ev["err_mean_restriction"],
+            note=f"fine-equivalent site-updates/s of 256^2 corrected steps at 4 dt against "
+                 f"the 1024^2 FP64 plain run, t = {corrector.T_START:g}..{corrector.T_END:g}, "
+                 f"gdot = 0.01, held-out seed; errors of L(t) against the fine run and "
+                 f"against the fine field restricted to the coarse grid")
         # the large single-GPU grid, FP64 and FP32 bulk
         for prec in ("fp64", "fp32"):
             p = configs.LARGE_4096["params"]

@@ -183,3 +183,19 @@ def test_graph_replays_match_eager_launches(monkeypatch):
         assert oa["Ls"] == ob_["Ls"]
     eager.close()
     graph.close()
+
+
+@pytest.mark.parametrize("kw", [
+    dict(A=0.7, B=1.3, kappa=4.0, M=2.0, eta=0.5, rho=2.0),
+    dict(kappa=16.0, M=16.0),
+    dict(A=0.7, B=1.3, kappa=4.0, M=2.0, eta=3.0, rho=0.0),
+])
+def test_parity_other_material_parameters(kw):
+    """Free-energy, mobility, viscosity and density constants other than 1."""
+    p = params(64, 64, gdot=0.05, **kw)
+    ctx, g, st, _ = run_pair(p, 100, seed=5, amp=0.3)
+    assert rel(g["phi"], st.phi) <= 1e-10
+    assert rel(g["psi"], st.psi) <= 1e-10
+    if kw.get("rho", 1.0) > 0:
+        assert rel(g["omega"], st.omega) <= 1e-10
+    ctx.close()
