@@ -310,10 +310,13 @@ void enqueue_step(Engine* e, const StepArgs* sa, hipEvent_t* ev) {
 // and replayed (the strain offsets stay in device memory, so one graph
 // serves every chunk of that length).  Stage timing brackets direct launches
 // with events, so timed chunks are never captured.
-int enqueue_steps(Engine* e, int64_t count) {
-  const size_t row = (size_t)e->nruns;
+// Enqueue `count` steps through enqueue_one(k, events): replayed from the
+// graph cached under `key` when there is one, else captured (chunks of at
+// least kGraphMin steps, when not timing stages) or launched directly.
+template <typename F>
+int enqueue_chunk(Engine* e, int64_t key, int64_t count, F&& enqueue_one) {
   const bool graph_ok = e->use_graphs && count >= kGraphMin && !e->profiling;
-  auto it = graph_ok ? e->graphs.find(count) : e->graphs.end();
+  auto it = graph_ok ? e->graphs.find(key) : e->graphs.end();
   if (graph_ok && it == e->graphs.end()) {
     if (e->graphs.size() >= kGraphCacheMax) {
       auto old = e->graphs.begin();
@@ -323,10 +326,12 @@ int enqueue_steps(Engine* e, int64_t count) {
     }
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
+    int rc = LE_OK;
     hipError_t err = hipStreamBeginCapture(e->stream, hipStreamCaptureModeRelaxed);
     if (err == hipSuccess) {
-      for (int64_t k = 0; k < count; ++k) enqueue_step(e, e->d_args + k * row, nullptr);
+      for (int64_t k = 0; k < count && rc == LE_OK; ++k) rc = enqueue_one(k, nullptr);
       err = hipStreamEndCapture(e->stream, &g);
+      if (rc != LE_OK && err == hipSuccess) err = hipErrorUnknown;
     }
     if (err == hipSuccess) err = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
     if (err != hipSuccess) {
@@ -343,7 +348,7 @@ int enqueue_steps(Engine* e, int64_t count) {
       fail_hip(err, "graph capture (falling back to direct launches)", __LINE__);
       e->use_graphs = false;
     } else {
-      it = e->graphs.emplace(count, std::make_pair(g, ge)).first;
+      it = e->graphs.emplace(key, std::make_pair(g, ge)).first;
     }
   }
   if (it != e->graphs.end()) {
@@ -351,9 +356,20 @@ int enqueue_steps(Engine* e, int64_t count) {
     return LE_OK;
   }
   for (int64_t k = 0; k < count; ++k)
-    enqueue_step(e, e->d_args + k * row,
-                 e->profiling ? &e->events[(size_t)k * (LE_NSTAGES + 1)] : nullptr);
+    LE_RC(enqueue_one(k, e->profiling ? &e->events[(size_t)k * (LE_NSTAGES + 1)] : nullptr));
   return LE_OK;
+}
+
+// Enqueue `count` plain steps whose StepArgs rows are d_args[0 .. count)
+// (one graph per chunk length serves every chunk of that length: the strain
+// offsets stay in device memory).  Stage timing brackets direct launches
+// with events, so timed chunks are never captured.
+int enqueue_steps(Engine* e, int64_t count) {
+  const size_t row = (size_t)e->nruns;
+  return enqueue_chunk(e, count, count, [&](int64_t k, hipEvent_t* ev) {
+    enqueue_step(e, e->d_args + k * row, ev);
+    return LE_OK;
+  });
 }
 
 // Re-express run r's state after its strain offset jumped by -dk c.
@@ -465,10 +481,9 @@ int env_variant(const char* name) {
   return v ? std::atoi(v) : -1;
 }
 
-// Milliseconds of `reps` launches of f after one untimed launch.
+// Milliseconds of 3 launches of f.
 template <typename F>
 int time_launches(Engine* e, hipEvent_t a, hipEvent_t b, F&& f, float* ms) {
-  f();
   LE_TRY(hipEventRecord(a, e->stream));
   for (int i = 0; i < 3; ++i) f();
   LE_TRY(hipEventRecord(b, e->stream));
@@ -478,6 +493,8 @@ int time_launches(Engine* e, hipEvent_t a, hipEvent_t b, F&& f, float* ms) {
   return LE_OK;
 }
 
+// Every candidate is launched once untimed (code loading, clocks), then
+// timed in two rounds in opposite orders; the smallest time wins.
 template <size_t N, typename F>
 int pick(Engine* e, hipEvent_t a, hipEvent_t b, const int (&cand)[N], const char* env, int* out,
          F&& launch) {
@@ -486,15 +503,21 @@ int pick(Engine* e, hipEvent_t a, hipEvent_t b, const int (&cand)[N], const char
     *out = forced;
     return LE_OK;
   }
-  float best = 0.0f;
-  for (size_t i = 0; i < N; ++i) {
-    float ms = 0.0f;
-    LE_RC(time_launches(e, a, b, [&] { launch(cand[i]); }, &ms));
-    if (i == 0 || ms < best) {
-      best = ms;
-      *out = cand[i];
+  for (size_t i = 0; i < N; ++i) launch(cand[i]);
+  float best[N];
+  for (size_t i = 0; i < N; ++i) best[i] = 3.4e38f;
+  for (int round = 0; round < 2; ++round) {
+    for (size_t j = 0; j < N; ++j) {
+      const size_t i = round == 0 ? j : N - 1 - j;
+      float ms = 0.0f;
+      LE_RC(time_launches(e, a, b, [&] { launch(cand[i]); }, &ms));
+      if (ms < best[i]) best[i] = ms;
     }
   }
+  size_t w = 0;
+  for (size_t i = 1; i < N; ++i)
+    if (best[i] < best[w]) w = i;
+  *out = cand[w];
   return LE_OK;
 }
 
@@ -822,19 +845,21 @@ int step_corrected(Engine* e, int64_t ncoarse) {
     }
     LE_TRY(hipMemcpyAsync(e->d_args, e->h_args, (size_t)count * sizeof(StepArgs),
                           hipMemcpyHostToDevice, e->stream));
-    for (int64_t k = 0; k < count; ++k) {
+    // corrected chunks share the graph cache under negative keys
+    LE_RC(enqueue_chunk(e, -count, count, [&](int64_t k, hipEvent_t* ev) {
       const StepArgs* sa = e->d_args + k;
-      enqueue_step(e, sa, nullptr);
+      enqueue_step(e, sa, ev);
       o.row_c2r(d, 1, r.p.ny, B_OM_S, B_OM_R, B_OM_S, B_OM_R, 1, e->stream);
       int rc = r.tsize == sizeof(double)
                    ? net_correct_fields<double>(e->net, static_cast<double*>(r.buf[B_PHI]),
                                                 static_cast<double*>(r.buf[B_OM_R]), e->stream)
                    : net_correct_fields<float>(e->net, static_cast<float*>(r.buf[B_PHI]),
                                                static_cast<float*>(r.buf[B_OM_R]), e->stream);
-      if (rc) return LE_EDEVICE;
+      if (rc) return (int)LE_EDEVICE;
       o.row_r2c(d, 1, r.p.ny, B_OM_R, B_OM_S, e->stream);
       o.column(COL_POISSON, d, 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0, e->stream);
-    }
+      return (int)LE_OK;
+    }));
     e->step = n0 + count;
     const int64_t k_new = wrap_count(r.p, e->step);
     if (k_new != r.wraps) {
@@ -995,6 +1020,16 @@ int le_corrector_load(le_ctx* c, const float* params, int32_t nparams, const flo
   }
   for (int k = 0; k < 4; ++k) c->net->scales[k] = scales[k];
   if (net_set_params(c->net, params, c->stream)) return LE_EDEVICE;
+  // captured corrected chunks hold the old scales as launch arguments
+  for (auto it = c->graphs.begin(); it != c->graphs.end();) {
+    if (it->first < 0) {
+      (void)hipGraphExecDestroy(it->second.second);
+      (void)hipGraphDestroy(it->second.first);
+      it = c->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
   LE_TRY(hipStreamSynchronize(c->stream));
   return LE_OK;
 }

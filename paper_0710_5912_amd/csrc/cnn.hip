@@ -64,14 +64,18 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ a
   const int p0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
   const int p = p0 + i;
   f32x16 acc = {};
-#pragma unroll 2
-  for (int ks = 0; ks < KP / 16; ++ks) {
+  // every operand of the tile is requested before the first product: at
+  // 32 pixels per wavefront a 256^2 grid gives only ~2 wavefronts per SIMD,
+  // too few to hide a load per k step
+  constexpr int NKS = KP / 16;
+  u16x8 av[NKS], bv[NKS];
+#pragma unroll
+  for (int ks = 0; ks < NKS; ++ks) {
     const int k0 = ks * 16 + half * 8;
-    u16x8 av;
     if constexpr (CIN % 8 == 0) {
       const int tap = k0 / CIN, ci0 = k0 % CIN;
       const int q = nb(p, tap / 3 - 1, tap % 3 - 1, H, W, lgW);
-      av = *reinterpret_cast<const u16x8*>(a_in + (size_t)q * CIN + ci0);
+      av[ks] = *reinterpret_cast<const u16x8*>(a_in + (size_t)q * CIN + ci0);
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
@@ -81,12 +85,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ a
           const int tap = k / CIN, ci = k % CIN;
           v = a_in[(size_t)nb(p, tap / 3 - 1, tap % 3 - 1, H, W, lgW) * CIN + ci];
         }
-        av[e] = v;
+        av[ks][e] = v;
       }
     }
-    const u16x8 bv = *reinterpret_cast<const u16x8*>(wt + (size_t)i * KP + k0);
-    acc = mfma(av, bv, acc);
+    bv[ks] = *reinterpret_cast<const u16x8*>(wt + (size_t)i * KP + k0);
   }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int ks = 0; ks < NKS; ++ks) acc = mfma(av[ks], bv[ks], acc);
   const int co = i;
   if (co < COUT) {
     const float bc = bias[co];
@@ -244,12 +250,21 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ z4,
 }
 
 // out[slot] += sum of n partials (one thread, fixed order).
-__global__ void k_sum_into(const double* __restrict__ part, int n, double* __restrict__ out) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int k = 0; k < n; ++k) s += part[k];
-    out[0] += s;
+// out[0] (+)= sum of part[0 .. n), n <= 1024, as one block's fixed-order
+// tree; acc = 0 overwrites (no clearing launch needed, so the call may sit
+// in a captured graph).  Launch with 256 threads.
+__global__ __launch_bounds__(256) void k_sum_into(const double* __restrict__ part, int n,
+                                                  double* __restrict__ out, int acc) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) s += part[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) out[0] = (acc ? out[0] : 0.0) + red[0];
 }
 
 template <typename T>
@@ -505,7 +520,7 @@ int net_grad(Net* n, const float* xs, const float* ts, int B, double* loss, hipS
       launch_fwd(n, l, n->act[l], n->z[l], l < 3 ? n->act[l + 1] : nullptr, st);
     hipLaunchKernelGGL(k_loss, dim3(256), dim3(256), 0, st, n->z[3], t, P, n->scales[2],
                        n->scales[3], scale, n->dz[0], n->red);
-    hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, st, n->red, 256, n->red + 1024);
+    hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(256), 0, st, n->red, 256, n->red + 1024, 1);
     int cur = 0;
     for (int l = kCnnLayers - 1; l >= 0; --l) {
       launch_bwd(n, l, n->dz[cur], n->act[l], l > 0 ? n->z[l - 1] : nullptr,
@@ -563,8 +578,7 @@ int net_correct_fields(Net* n, T* phi, T* omega, hipStream_t st) {
   for (int l = 0; l < kCnnLayers; ++l)
     launch_fwd(n, l, n->act[l], n->z[l], l < 3 ? n->act[l + 1] : nullptr, st);
   hipLaunchKernelGGL(k_rphi_sum, dim3(256), dim3(256), 0, st, n->z[3], P, n->red);
-  CNN_TRY(hipMemsetAsync(n->red + 1024, 0, sizeof(double), st));
-  hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(64), 0, st, n->red, 256, n->red + 1024);
+  hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(256), 0, st, n->red, 256, n->red + 1024, 0);
   hipLaunchKernelGGL((k_apply_correction<T>), dim3(256), dim3(256), 0, st, phi, omega, n->z[3],
                      P, n->scales[2], n->scales[3], n->red + 1024);
   CNN_TRY(hipGetLastError());

@@ -89,3 +89,28 @@ def test_corrector_needs_inertia_and_a_load():
     with le.Context(p, inputs.noise_phi0(32, 32, 0)) as c:
         with pytest.raises(le.LeError):
             c.step_corrected(1)
+
+
+def test_corrected_graph_replays_match_eager(monkeypatch):
+    """Corrected chunks replayed from a captured graph equal direct launches,
+    replay after replay, and a reload with new scales is not replayed stale."""
+    p = configs.model_h(64, 64, gdot=0.1, rho=1.0)
+    phi0 = inputs.noise_phi0(64, 64, 8, amp=0.6)
+    params = inputs.cnn_init_params(3) * 2.0
+    a = le.Context(p, phi0)
+    monkeypatch.setenv("LE_GRAPHS", "0")
+    b = le.Context(p, phi0)
+    monkeypatch.delenv("LE_GRAPHS")
+    try:
+        for scales in ([1.0, 10.0, 0.02, 0.005], [0.5, 5.0, 0.04, 0.001]):
+            a.corrector_load(params, scales)
+            b.corrector_load(params, scales)
+            for rep in range(3):
+                a.step_corrected(16)
+                b.step_corrected(16)
+                ga, gb = a.get_state(), b.get_state()
+                for k in ("phi", "omega", "psi"):
+                    assert np.array_equal(ga[k], gb[k]), (scales, rep, k)
+    finally:
+        a.close()
+        b.close()
