@@ -50,10 +50,10 @@ def stage_bytes(params, precision):
 
 
 def run_variant(le, torch, params, precision, steps, warmup, obs_every, seed=0,
-                prof_steps=1000):
+                stage_reps=200):
     """Timed region (graph-replayed steps, observables every obs_every steps),
-    then a pass of prof_steps steps with HIP events around every stage launch
-    on the same stream, for the per-kernel durations."""
+    then each stage timed on its own: stage_reps back-to-back launches of its
+    (autotuned) kernels between HIP events on the same stream."""
     from paper_0710_5912_amd import inputs
 
     nx, ny = params["nx"], params["ny"]
@@ -80,11 +80,8 @@ def run_variant(le, torch, params, precision, steps, warmup, obs_every, seed=0,
     wall = time.perf_counter() - t0
     gpu_ms = e0.elapsed_time(e1)
     times = {}
-    if prof_steps:
-        ctx.profile(True)
-        ctx.step(prof_steps)
-        times = ctx.stage_times()
-        ctx.profile(False)
+    if stage_reps:
+        times = {s: ctx.time_stage(s, stage_reps) for s in le.STAGES}
     tuning = ctx.tuning()[0]
     ctx.close()
     return dict(wall=wall, gpu_ms=gpu_ms, times=times, series=series, tuning=tuning)
@@ -153,22 +150,24 @@ def run_batch(le, torch, steps, warmup, seq_steps):
 
 
 def roofline_of(params, precision, times):
+    """Per stage: average launch us, algorithmic bytes and GB/s; the dominant stage."""
     b = stage_bytes(params, precision)
-    rows = {}
-    for k, (ms, n) in times.items():
-        if n == 0:
-            continue
-        avg_s = ms / n * 1e-3
-        rows[k] = dict(avg_us=avg_s * 1e6, bytes=b[k], gbs=b[k] / avg_s / 1e9)
+    rows = {k: dict(avg_us=us, bytes=b[k], gbs=b[k] / (us * 1e-6) / 1e9)
+            for k, us in times.items()}
     if not rows:
         return None, {}
     dom = max(rows, key=lambda k: rows[k]["avg_us"])
     return dom, rows
 
 
-def traffic_of(kernel, precision, nx):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter record,
-    or None when there is none for this workload or the kernel sources changed since."""
+VARIANT_OF = {"advect": "advect", "mu_source": "mu_source", "column_ch": "column_ch",
+              "column_flow": "column_flow"}
+
+
+def traffic_of(stage, precision, nx, tuning):
+    """HBM bytes per launch of `stage` from the committed rocprofv3 counter record,
+    or None when there is none for this workload, the kernel sources changed
+    since, or the record was taken with another variant of the stage."""
     import glob
     import hashlib
 
@@ -184,9 +183,12 @@ def traffic_of(kernel, precision, nx):
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(ROOT, "paper_0710_5912_amd", "csrc", "*"))):
         h.update(open(p, "rb").read())
-    if rec is None or rec["source_hash"] != h.hexdigest()[:16] or kernel not in rec["kernels"]:
+    if rec is None or rec["source_hash"] != h.hexdigest()[:16] or stage not in rec["stages"]:
         return None
-    k = rec["kernels"][kernel]
+    v = VARIANT_OF.get(stage)
+    if v is not None and rec["tuning"][v] != tuning[v]:
+        return None
+    k = rec["stages"][stage]
     return (k["fetch_kib"] * rec["fetch_factor"] + k["write_kib"] * rec["write_factor"]) * 1024.0
 
 
@@ -224,6 +226,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--profile-size", type=int, default=1024)
+    ap.add_argument("--profile-precision", default="fp64", choices=("fp64", "fp32"))
     ap.add_argument("--profile-pass", action="store_true",
                     help="short pass for hardware counters: a 512 MiB device copy "
                          "(calibration of FETCH_SIZE/WRITE_SIZE) then 50 directly launched "
@@ -250,10 +253,10 @@ def main():
         from paper_0710_5912_amd import inputs
         n = args.profile_size
         pp = configs.model_h(n, n, gdot=0.01, rho=1.0)
-        ctx = le.Context(pp, inputs.noise_phi0(n, n, 0), precision="fp64")
+        ctx = le.Context(pp, inputs.noise_phi0(n, n, 0), precision=args.profile_precision)
         ctx.profile(True)      # direct launches: one dispatch per stage and step
         ctx.step(50 if n <= 1024 else 10)
-        print(json.dumps({"profile_pass": ctx.stage_times()}))
+        print(json.dumps({"profile_pass": ctx.stage_times(), "tuning": ctx.tuning()}))
         ctx.close()
         return
     print(f"bench: 1024x1024 fp64 inertial, {args.warmup} warmup + {args.steps} timed steps",
@@ -283,11 +286,12 @@ def main():
                    "obs_every": args.obs_every},
         "roofline": {"bound": "hbm", "stage": dom,
                      "kernels": stage_kernels(r["tuning"], True)[dom],
-                     "timing": "HIP events around each stage launch, 1000 directly launched "
-                               "steps after the timed region, same stream", "achieved": rows[dom]["gbs"],
+                     "timing": "HIP events around 200 back-to-back launches of the stage's "
+                               "kernels after the timed region, on the library's stream",
+                     "achieved": rows[dom]["gbs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": rows[dom]["gbs"] / HBM_PEAK_GBS,
-                     "traffic": traffic_of(dom, "fp64", 1024),
+                     "traffic": traffic_of(dom, "fp64", 1024, r["tuning"]),
                      "bytes_per_launch": rows[dom]["bytes"],
                      "avg_launch_us": rows[dom]["avg_us"]},
         "stages": {k: {"avg_us": round(v["avg_us"], 2), "GBs": round(v["gbs"], 1)}
@@ -335,7 +339,7 @@ def main():
         for prec in ("fp64", "fp32"):
             p = configs.LARGE_4096["params"]
             print(f"bench: variant {prec}_4096", file=sys.stderr, flush=True)
-            rv = run_variant(le, torch, p, prec, 200, 20, 100, prof_steps=100)
+            rv = run_variant(le, torch, p, prec, 200, 20, 100, stage_reps=20)
             d, rw = roofline_of(p, prec, rv["times"])
             ms = rv["gpu_ms"] / 200
             var[f"{prec}_4096_inertial"] = dict(

@@ -156,6 +156,17 @@ int le_profile(le_ctx* c, int enable);
 int le_stage_times(le_ctx* c, double* ms, int64_t* launches, int32_t cap);
 
 /*
+ * le_time_stage: the average duration (milliseconds) of one launch of stage
+ * `stage` (numbered as above, with the autotuned variant) over `reps`
+ * back-to-back launches on the context's stream, after one untimed launch.
+ * The launches read the current state and write only scratch buffers, so
+ * the state is neither advanced nor changed.
+ * LE_EINVAL for a bad stage, reps < 1 or NULL; LE_ESTATE while le_profile
+ * timing is enabled.
+ */
+int le_time_stage(le_ctx* c, int32_t stage, int32_t reps, double* ms_per_launch);
+
+/*
  * Kernel variants (not part of the method: how its stages are laid out on
  * the GPU).  At creation every group of runs sharing (nx, ny, precision,
  * rho > 0) times the candidate kernel variants of its stages on its own

@@ -944,6 +944,71 @@ int le_set_state(le_ctx* c, const double* phi, const double* omega, const double
   return LE_OK;
 }
 
+int time_stage_of(Engine* e, int32_t stage, int32_t reps, double* ms_per_launch) {
+  if (!e || stage < 0 || stage >= LE_NSTAGES || reps < 1 || !ms_per_launch) return LE_EINVAL;
+  if (e->profiling) return LE_ESTATE;
+  for (const RunHost& r : e->runs) LE_RC(set_args_one(e, r, e->step));
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return LE_EDEVICE;
+  }
+  // each launch covers every class, as one stage of a step does
+  auto launch = [&]() {
+    hipStream_t st = e->stream;
+    for (const Class& k : e->classes) {
+      const Run* d = e->d_desc + k.first;
+      const int n = (int)k.members.size();
+      const StepArgs* sa = e->d_args + k.first;
+      switch (stage) {
+        case 0:  // inverse row transforms of the state spectra, into the real scratch
+          if (k.inertial)
+            k.ops.row_c2r(d, n, k.ny, B_OM_S, B_TMP, B_PS_S, B_TMP, 2, st);
+          else
+            k.ops.row_c2r(d, n, k.ny, B_PS_S, B_TMP, B_PS_S, B_TMP, 1, st);
+          break;
+        case 1:
+          k.ops.advect(d, n, k.ny, sa, k.inertial, k.adv_variant, st);
+          break;
+        case 2:
+          k.ops.column(COL_CH, d, n, k.nx, sa, B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant,
+                       st);
+          break;
+        case 3:  // into the real scratch
+          k.ops.row_c2r(d, n, k.ny, B_PHIN, B_TMP, B_PHIN, B_TMP, 1, st);
+          break;
+        case 4:
+          k.ops.mu_source(d, n, k.ny, sa, k.mu_variant, st);
+          break;
+        default:  // outputs into the spectral scratch, the state untouched
+          if (k.inertial)
+            k.ops.column(COL_FLOW, d, n, k.nx, sa, B_OMH, B_GH, B_PHIH, B_FH,
+                         k.col_flow_variant, st);
+          else
+            k.ops.column(COL_STOKES, d, n, k.nx, sa, B_GH, B_GH, B_PHIN, B_PHIN,
+                         k.col_flow_variant, st);
+          break;
+      }
+    }
+  };
+  int rc = LE_OK;
+  launch();
+  float ms = 0.0f;
+  if (hipEventRecord(a, e->stream) != hipSuccess) rc = LE_EDEVICE;
+  for (int i = 0; i < reps && !rc; ++i) launch();
+  if (!rc && (hipEventRecord(b, e->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+              hipGetLastError() != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))
+    rc = LE_EDEVICE;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (!rc) *ms_per_launch = (double)ms / reps;
+  return rc;
+}
+
+int le_time_stage(le_ctx* c, int32_t stage, int32_t reps, double* ms_per_launch) {
+  return time_stage_of(c, stage, reps, ms_per_launch);
+}
+
 int le_profile(le_ctx* c, int enable) { return profile_engine(c, enable); }
 
 int tuning_of(le_ctx* c, int32_t* out, int32_t cap) {

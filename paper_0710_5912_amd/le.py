@@ -21,7 +21,7 @@ SYMBOLS = ("le_create", "le_step", "le_observables", "le_destroy", "le_get_state
            "le_set_state", "le_strerror", "le_profile", "le_stage_times", "le_last_error",
            "le_batch_create", "le_batch_step", "le_batch_observables", "le_batch_get_state",
            "le_batch_profile", "le_batch_stage_times", "le_batch_destroy",
-           "le_tuning", "le_batch_tuning",
+           "le_tuning", "le_batch_tuning", "le_time_stage",
            "le_corrector_load", "le_step_corrected", "le_restrict", "le_set_fields",
            "le_cnn_nparams", "le_cnn_create", "le_cnn_destroy", "le_cnn_set_params",
            "le_cnn_get_params", "le_cnn_forward", "le_cnn_grad", "le_cnn_adam",
@@ -127,6 +127,8 @@ def lib():
         L.le_batch_profile.restype = C.c_int
         L.le_batch_stage_times.argtypes = [C.c_void_p, _DP, C.POINTER(C.c_int64), C.c_int32]
         L.le_batch_stage_times.restype = C.c_int
+        L.le_time_stage.argtypes = [C.c_void_p, C.c_int32, C.c_int32, _DP]
+        L.le_time_stage.restype = C.c_int
         for f in (L.le_tuning, L.le_batch_tuning):
             f.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.c_int32]
             f.restype = C.c_int
@@ -281,6 +283,16 @@ class Context:
         if rc != LE_OK:
             raise LeError(rc, "le_stage_times")
         return {STAGES[k]: (float(ms[k]), int(n[k])) for k in range(LE_NSTAGES)}
+
+    def time_stage(self, stage: str, reps: int = 100) -> float:
+        """Average microseconds of one launch of `stage` (back-to-back launches;
+        the state is not advanced)."""
+        self._check()
+        ms = C.c_double()
+        rc = lib().le_time_stage(self._h, STAGES.index(stage), reps, C.byref(ms))
+        if rc != LE_OK:
+            raise LeError(rc, "le_time_stage")
+        return ms.value * 1e3
 
     def tuning(self):
         """Kernel variants the autotuner chose for this run (list of one dict)."""

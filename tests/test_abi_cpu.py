@@ -81,3 +81,9 @@ def test_null_arguments_rejected():
     assert lib.le_tuning(None, None, 0) == le.LE_EINVAL
     assert lib.le_batch_tuning(None, None, 0) == le.LE_EINVAL
     lib.le_destroy(None)   # NULL-safe
+
+
+def test_stage_timer_validates_arguments():
+    lib = le.lib()
+    ms = C.c_double()
+    assert lib.le_time_stage(None, 0, 1, C.byref(ms)) == le.LE_EINVAL

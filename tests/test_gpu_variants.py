@@ -108,3 +108,28 @@ def test_autotuner_reports_valid_choices():
     assert (t["nx"], t["ny"], t["precision"], t["inertial"]) == (256, 256, 0, 1)
     assert t["advect"] in (0, 4, 8, 16, 32) and t["mu_source"] in (0, 4, 8, 16, 32)
     assert t["column_ch"] in range(4) and t["column_flow"] in range(4)
+
+
+@pytest.mark.parametrize("rho", [1.0, 0.0])
+def test_stage_timer_leaves_the_state(monkeypatch, rho):
+    """le_time_stage launches each stage back to back without touching the
+    state: the run continues bit for bit as its untimed twin (both with the
+    same variants, fixed here)."""
+    for k, v in zip(KEYS, (4, 4, 0, 0)):
+        monkeypatch.setenv(k, str(v))
+    p = params(128, 128, rho=rho)
+    phi0 = inputs.noise_phi0(128, 128, 31, amp=0.5)
+    with le.Context(p, phi0) as a, le.Context(p, phi0) as b:
+        for ctx in (a, b):
+            ctx.step(5)
+        before = a.get_state()
+        for s in le.STAGES:
+            assert a.time_stage(s, 3) > 0.0
+        after = a.get_state()
+        for k in ("phi", "omega", "psi"):
+            assert np.array_equal(before[k], after[k]), k
+        a.step(7)
+        b.step(7)
+        ga, gb = a.get_state(), b.get_state()
+        for k in ("phi", "omega", "psi"):
+            assert np.array_equal(ga[k], gb[k]), k
