@@ -171,16 +171,20 @@ int le_time_stage(le_ctx* c, int32_t stage, int32_t reps, double* ms_per_launch)
  * the GPU).  At creation every group of runs sharing (nx, ny, precision,
  * rho > 0) times the candidate kernel variants of its stages on its own
  * buffers and keeps the fastest; every variant computes the same stage (to
- * rounding).  le_tuning writes, per group, LE_TUNING_FIELDS int32 values
- *   nx, ny, precision, inertial, advect, mu_source, column_ch, column_flow
+ * rounding; runs are bit-identical only between equal variants).  le_tuning
+ * writes, per group, LE_TUNING_FIELDS int32 values
+ *   nx, ny, precision, inertial, advect, mu_source, column_ch, column_flow,
+ *   row
  * (advect / mu_source: 0 = one fused stencil-and-row-transform kernel,
  * k > 0 = a stencil kernel over k-row strips then in-place row transforms;
- * column_*: block shape 0 .. 3), at most cap values in all, and returns the
- * number of groups (LE_EINVAL for NULL c, cap < 0 or out NULL with cap > 0).
- * The environment variables LE_TUNE_ADV, LE_TUNE_MU, LE_TUNE_COL_CH and
- * LE_TUNE_COL_FLOW, when set, fix the corresponding variant at creation.
+ * column_*: block shape 0 .. 3; row: row transforms with 8 (0) or 4 (1)
+ * values per thread), at most cap values in all, and returns the number of
+ * groups (LE_EINVAL for NULL c, cap < 0 or out NULL with cap > 0).  The
+ * environment variables LE_TUNE_ADV, LE_TUNE_MU, LE_TUNE_COL_CH,
+ * LE_TUNE_COL_FLOW and LE_TUNE_ROW, when set, fix the corresponding variant
+ * at creation.
  */
-enum { LE_TUNING_FIELDS = 8 };
+enum { LE_TUNING_FIELDS = 9 };
 int le_tuning(le_ctx* c, int32_t* out, int32_t cap);
 
 /*

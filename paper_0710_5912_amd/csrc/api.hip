@@ -121,6 +121,7 @@ struct Class {
   int mu_variant = 0;        // Ops::mu_source
   int col_ch_variant = 0;    // Ops::column, Cahn-Hilliard pass
   int col_flow_variant = 0;  // Ops::column, flow (or Stokes) pass
+  int row_variant = 0;       // Ops::row_r2c / row_c2r (and the strip variants' transforms)
   std::vector<int> members;  // run ids
   int first = 0;             // internal index of members[0]
 };
@@ -253,7 +254,7 @@ int solve_psi(Engine* e, const RunHost& r) {
     k.ops.column(COL_POISSON, desc(e, r), 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0,
                  e->stream);
   } else {
-    k.ops.mu_source(desc(e, r), 1, r.p.ny, sa, k.mu_variant, e->stream);
+    k.ops.mu_source(desc(e, r), 1, r.p.ny, sa, k.mu_variant, k.row_variant, e->stream);
     k.ops.column(COL_STOKES, desc(e, r), 1, r.p.nx, sa, B_GH, B_GH, B_PS_S, B_PS_S,
                  k.col_flow_variant, e->stream);
   }
@@ -273,14 +274,14 @@ void enqueue_step(Engine* e, const StepArgs* sa, hipEvent_t* ev) {
     const Run* d = e->d_desc + k.first;
     const int n = (int)k.members.size();
     if (k.inertial)
-      k.ops.row_c2r(d, n, k.ny, B_OM_S, B_OM_R, B_PS_S, B_PS_R, 2, st);
+      k.ops.row_c2r(d, n, k.ny, B_OM_S, B_OM_R, B_PS_S, B_PS_R, 2, k.row_variant, st);
     else
-      k.ops.row_c2r(d, n, k.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1, st);
+      k.ops.row_c2r(d, n, k.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1, k.row_variant, st);
   }
   mark(1);
   for (const Class& k : e->classes)
     k.ops.advect(e->d_desc + k.first, (int)k.members.size(), k.ny, sa + k.first, k.inertial,
-                 k.adv_variant, st);
+                 k.adv_variant, k.row_variant, st);
   mark(2);
   for (const Class& k : e->classes)
     k.ops.column(COL_CH, e->d_desc + k.first, (int)k.members.size(), k.nx, sa + k.first,
@@ -288,11 +289,11 @@ void enqueue_step(Engine* e, const StepArgs* sa, hipEvent_t* ev) {
   mark(3);
   for (const Class& k : e->classes)
     k.ops.row_c2r(e->d_desc + k.first, (int)k.members.size(), k.ny, B_PHIN, B_PHI, B_PHIN,
-                  B_PHI, 1, st);
+                  B_PHI, 1, k.row_variant, st);
   mark(4);
   for (const Class& k : e->classes)
     k.ops.mu_source(e->d_desc + k.first, (int)k.members.size(), k.ny, sa + k.first,
-                    k.mu_variant, st);
+                    k.mu_variant, k.row_variant, st);
   mark(5);
   for (const Class& k : e->classes) {
     if (k.inertial)
@@ -402,7 +403,7 @@ int reduce_observables(Engine* e, const RunHost& r, bool spectral) {
   int nsblk = 0;
   if (spectral) {
     LE_RC(set_args_one(e, r, e->step));
-    o.row_r2c(desc(e, r), 1, r.p.ny, B_PHI, B_PHIH, e->stream);
+    o.row_r2c(desc(e, r), 1, r.p.ny, B_PHI, B_PHIH, e->classes[r.cls].row_variant, e->stream);
     o.obs_spectral(desc(e, r), r.p.nx, e->d_args + r.internal, B_PHIH,
                    r.inertial ? B_PS_S : -1, e->d_spart, e->d_bins, e->d_counts, e->stream);
     nsblk = o.obs_blocks(r.p.nx);
@@ -472,8 +473,9 @@ int observables_of(Engine* e, const RunHost& r, le_obs* o, double* Sk, int32_t s
 // tests that exercise every path.
 namespace {
 
-constexpr int kAdvCand[] = {0, 4, 8, 16, 32};
-constexpr int kMuCand[] = {0, 4, 8, 16, 32};
+constexpr int kRowCand[] = {0, 1};
+constexpr int kAdvCand[] = {0, 2, 4, 8, 16, 32};
+constexpr int kMuCand[] = {0, 2, 4, 8, 16, 32};
 constexpr int kColCand[] = {0, 1, 2, 3};
 
 int env_variant(const char* name) {
@@ -533,11 +535,17 @@ int autotune(Engine* e) {
     const int n = (int)k.members.size();
     const StepArgs* sa = e->d_args + k.first;
     hipStream_t st = e->stream;
+    // row transforms first (the strip variants below use them); timed on the
+    // inverse transforms of stages 0 and 3, into the real scratch
+    rc = rc ? rc : pick(e, a, b, kRowCand, "LE_TUNE_ROW", &k.row_variant, [&](int v) {
+      k.ops.row_c2r(d, n, k.ny, B_PS_S, B_TMP, B_PS_S, B_TMP, 2, v, st);
+      k.ops.row_c2r(d, n, k.ny, B_PHIN, B_TMP, B_PHIN, B_TMP, 1, v, st);
+    });
     rc = rc ? rc : pick(e, a, b, kAdvCand, "LE_TUNE_ADV", &k.adv_variant, [&](int v) {
-      k.ops.advect(d, n, k.ny, sa, k.inertial, v, st);
+      k.ops.advect(d, n, k.ny, sa, k.inertial, v, k.row_variant, st);
     });
     rc = rc ? rc : pick(e, a, b, kMuCand, "LE_TUNE_MU", &k.mu_variant, [&](int v) {
-      k.ops.mu_source(d, n, k.ny, sa, v, st);
+      k.ops.mu_source(d, n, k.ny, sa, v, k.row_variant, st);
     });
     rc = rc ? rc : pick(e, a, b, kColCand, "LE_TUNE_COL_CH", &k.col_ch_variant, [&](int v) {
       k.ops.column(COL_CH, d, n, k.nx, sa, B_PHIH, B_FH, B_PHIN, B_PHIN, v, st);
@@ -712,7 +720,9 @@ int create_engine(int32_t n, const le_params* ps, const double* const* phi0s,
                  hipSuccess) {
         rc = LE_EDEVICE;
       }
-      if (!rc) e->classes[r.cls].ops.row_r2c(desc(e, r), 1, r.p.ny, B_OM_R, B_OM_S, e->stream);
+      if (!rc)
+        e->classes[r.cls].ops.row_r2c(desc(e, r), 1, r.p.ny, B_OM_R, B_OM_S,
+                                      e->classes[r.cls].row_variant, e->stream);
     }
     if (!rc) rc = solve_psi(e, r);
   }
@@ -782,7 +792,8 @@ int get_state_of(Engine* e, int run, double* phi, double* omega, double* psi, in
   if (phi) LE_RC(download_real(e, r, B_PHI, phi));
   if (omega) {
     if (r.inertial) {
-      o.row_c2r(desc(e, r), 1, r.p.ny, B_OM_S, B_OM_R, B_OM_S, B_OM_R, 1, e->stream);
+      o.row_c2r(desc(e, r), 1, r.p.ny, B_OM_S, B_OM_R, B_OM_S, B_OM_R, 1,
+                e->classes[r.cls].row_variant, e->stream);
       LE_TRY(hipGetLastError());
       LE_RC(download_real(e, r, B_OM_R, omega));
     } else {
@@ -790,7 +801,8 @@ int get_state_of(Engine* e, int run, double* phi, double* omega, double* psi, in
     }
   }
   if (psi) {
-    o.row_c2r(desc(e, r), 1, r.p.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1, e->stream);
+    o.row_c2r(desc(e, r), 1, r.p.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1,
+              e->classes[r.cls].row_variant, e->stream);
     LE_TRY(hipGetLastError());
     LE_RC(download_real(e, r, B_PS_R, psi));
   }
@@ -849,14 +861,15 @@ int step_corrected(Engine* e, int64_t ncoarse) {
     LE_RC(enqueue_chunk(e, -count, count, [&](int64_t k, hipEvent_t* ev) {
       const StepArgs* sa = e->d_args + k;
       enqueue_step(e, sa, ev);
-      o.row_c2r(d, 1, r.p.ny, B_OM_S, B_OM_R, B_OM_S, B_OM_R, 1, e->stream);
+      o.row_c2r(d, 1, r.p.ny, B_OM_S, B_OM_R, B_OM_S, B_OM_R, 1, e->classes[r.cls].row_variant,
+                e->stream);
       int rc = r.tsize == sizeof(double)
                    ? net_correct_fields<double>(e->net, static_cast<double*>(r.buf[B_PHI]),
                                                 static_cast<double*>(r.buf[B_OM_R]), e->stream)
                    : net_correct_fields<float>(e->net, static_cast<float*>(r.buf[B_PHI]),
                                                static_cast<float*>(r.buf[B_OM_R]), e->stream);
       if (rc) return (int)LE_EDEVICE;
-      o.row_r2c(d, 1, r.p.ny, B_OM_R, B_OM_S, e->stream);
+      o.row_r2c(d, 1, r.p.ny, B_OM_R, B_OM_S, e->classes[r.cls].row_variant, e->stream);
       o.column(COL_POISSON, d, 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0, e->stream);
       return (int)LE_OK;
     }));
@@ -933,10 +946,12 @@ int le_set_state(le_ctx* c, const double* phi, const double* omega, const double
   LE_RC(upload_real(c, r, phi, B_PHI));
   if (r.inertial) {
     LE_RC(upload_real(c, r, omega, B_OM_R));
-    o.row_r2c(desc(c, r), 1, r.p.ny, B_OM_R, B_OM_S, c->stream);
+    o.row_r2c(desc(c, r), 1, r.p.ny, B_OM_R, B_OM_S, c->classes[r.cls].row_variant,
+              c->stream);
   }
   LE_RC(upload_real(c, r, psi, B_PS_R));
-  o.row_r2c(desc(c, r), 1, r.p.ny, B_PS_R, B_PS_S, c->stream);
+  o.row_r2c(desc(c, r), 1, r.p.ny, B_PS_R, B_PS_S, c->classes[r.cls].row_variant,
+            c->stream);
   LE_TRY(hipGetLastError());
   LE_TRY(hipStreamSynchronize(c->stream));
   c->step = step;
@@ -963,22 +978,22 @@ int time_stage_of(Engine* e, int32_t stage, int32_t reps, double* ms_per_launch)
       switch (stage) {
         case 0:  // inverse row transforms of the state spectra, into the real scratch
           if (k.inertial)
-            k.ops.row_c2r(d, n, k.ny, B_OM_S, B_TMP, B_PS_S, B_TMP, 2, st);
+            k.ops.row_c2r(d, n, k.ny, B_OM_S, B_TMP, B_PS_S, B_TMP, 2, k.row_variant, st);
           else
-            k.ops.row_c2r(d, n, k.ny, B_PS_S, B_TMP, B_PS_S, B_TMP, 1, st);
+            k.ops.row_c2r(d, n, k.ny, B_PS_S, B_TMP, B_PS_S, B_TMP, 1, k.row_variant, st);
           break;
         case 1:
-          k.ops.advect(d, n, k.ny, sa, k.inertial, k.adv_variant, st);
+          k.ops.advect(d, n, k.ny, sa, k.inertial, k.adv_variant, k.row_variant, st);
           break;
         case 2:
           k.ops.column(COL_CH, d, n, k.nx, sa, B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant,
                        st);
           break;
         case 3:  // into the real scratch
-          k.ops.row_c2r(d, n, k.ny, B_PHIN, B_TMP, B_PHIN, B_TMP, 1, st);
+          k.ops.row_c2r(d, n, k.ny, B_PHIN, B_TMP, B_PHIN, B_TMP, 1, k.row_variant, st);
           break;
         case 4:
-          k.ops.mu_source(d, n, k.ny, sa, k.mu_variant, st);
+          k.ops.mu_source(d, n, k.ny, sa, k.mu_variant, k.row_variant, st);
           break;
         default:  // outputs into the spectral scratch, the state untouched
           if (k.inertial)
@@ -1017,7 +1032,7 @@ int tuning_of(le_ctx* c, int32_t* out, int32_t cap) {
   for (const Class& k : c->classes) {
     const int32_t rec[LE_TUNING_FIELDS] = {k.nx, k.ny, k.prec, k.inertial ? 1 : 0,
                                            k.adv_variant, k.mu_variant, k.col_ch_variant,
-                                           k.col_flow_variant};
+                                           k.col_flow_variant, k.row_variant};
     for (int i = 0; i < LE_TUNING_FIELDS && w < cap; ++i) out[w++] = rec[i];
   }
   return (int)c->classes.size();
@@ -1116,7 +1131,8 @@ int le_restrict(le_ctx* c, int32_t factor, double* phi_out, double* omega_out) {
   }
   if (omega_out) {
     if (r.inertial) {
-      o.row_c2r(desc(c, r), 1, r.p.ny, B_OM_S, B_OM_R, B_OM_S, B_OM_R, 1, c->stream);
+      o.row_c2r(desc(c, r), 1, r.p.ny, B_OM_S, B_OM_R, B_OM_S, B_OM_R, 1,
+                c->classes[r.cls].row_variant, c->stream);
       o.restrict_real(desc(c, r), B_OM_R, factor, c->d_restrict, c->stream);
       LE_TRY(hipMemcpyAsync(omega_out, c->d_restrict, nc * sizeof(double),
                             hipMemcpyDeviceToHost, c->stream));
@@ -1141,7 +1157,8 @@ int le_set_fields(le_ctx* c, const double* phi, const double* omega, int64_t ste
     } else {
       LE_TRY(hipMemsetAsync(r.buf[B_OM_R], 0, r.n_real * r.tsize, c->stream));
     }
-    o.row_r2c(desc(c, r), 1, r.p.ny, B_OM_R, B_OM_S, c->stream);
+    o.row_r2c(desc(c, r), 1, r.p.ny, B_OM_R, B_OM_S, c->classes[r.cls].row_variant,
+              c->stream);
   }
   LE_RC(solve_psi(c, r));
   LE_TRY(hipStreamSynchronize(c->stream));

@@ -12,19 +12,21 @@
 namespace le {
 
 struct Ops {
-  void (*row_r2c)(const Run* runs, int nruns, int ny, int bin, int bout, hipStream_t st);
+  // row transforms; variant (a tuning choice): 0 = 8 values per thread, 1 = 4
+  void (*row_r2c)(const Run* runs, int nruns, int ny, int bin, int bout, int variant,
+                  hipStream_t st);
   // inverse row transforms: bin0 -> bout0 and, when nfields == 2, bin1 -> bout1
   void (*row_c2r)(const Run* runs, int nruns, int ny, int bin0, int bout0, int bin1, int bout1,
-                  int nfields, hipStream_t st);
+                  int nfields, int variant, hipStream_t st);
   // stage 1a + forward row transforms (omega parts only when inertial);
   // variant: 0 fused, k > 0 strip stencil over k-row strips + in-place
   // transforms
   void (*advect)(const Run* runs, int nruns, int ny, const StepArgs* sa, bool inertial,
-                 int variant, hipStream_t st);
+                 int variant, int row_variant, hipStream_t st);
   // stage 2a + forward row transform of g; variant: 0 two kernels through
   // the real scratch, k > 0 strip stencil over k-row strips (square cells)
   void (*mu_source)(const Run* runs, int nruns, int ny, const StepArgs* sa, int variant,
-                    hipStream_t st);
+                    int row_variant, hipStream_t st);
   // column transform + per-mode update (ColMode) + inverse column transform;
   // variant 0 .. kColVariants-1 picks the block shape
   void (*column)(int mode, const Run* runs, int nruns, int nx, const StepArgs* sa, int bin0,

@@ -8,21 +8,49 @@
 
 namespace le {
 
+// Row transform shape: variant 0 = 8 values per thread, 1 = 4 (twice the
+// threads per row: shorter chains for latency-bound grids).
+constexpr int row_e_of(int L, int variant) {
+  return (variant == 1 && L >= 16) ? 4 : row_elems(L);
+}
+
 template <typename T, int L>
 struct RowLaunch {
   using C = RowCfg<L>;
   static dim3 grid(int ny, int fields, int nruns) {
     return dim3((ny + C::G - 1) / C::G, fields, nruns);
   }
-  static void r2c(const Run* runs, int nruns, int ny, int bin, int bout, hipStream_t st) {
+  template <int E>
+  static dim3 grid_e(int ny, int fields, int nruns) {
+    using CE = RowCfg<L, E>;
+    return dim3((ny + CE::G - 1) / CE::G, fields, nruns);
+  }
+  static void r2c_jobs(const Run* runs, int nruns, int ny, const R2cJobs& jobs, int njobs,
+                       int variant, hipStream_t st) {
+    if (variant == 1 && L >= 16) {
+      constexpr int E = row_e_of(L, 1);
+      hipLaunchKernelGGL((k_row_r2c<T, L, E>), grid_e<E>(ny, njobs, nruns),
+                         dim3(RowCfg<L, E>::THREADS), 0, st, runs, jobs);
+    } else {
+      hipLaunchKernelGGL((k_row_r2c<T, L>), grid(ny, njobs, nruns), dim3(C::THREADS), 0, st,
+                         runs, jobs);
+    }
+  }
+  static void r2c(const Run* runs, int nruns, int ny, int bin, int bout, int variant,
+                  hipStream_t st) {
     R2cJobs jobs{{{bin, bout, 2 * L}, {}, {}}};
-    hipLaunchKernelGGL((k_row_r2c<T, L>), grid(ny, 1, nruns), dim3(C::THREADS), 0, st, runs,
-                       jobs);
+    r2c_jobs(runs, nruns, ny, jobs, 1, variant, st);
   }
   static void c2r(const Run* runs, int nruns, int ny, int bin0, int bout0, int bin1, int bout1,
-                  int nfields, hipStream_t st) {
-    hipLaunchKernelGGL((k_row_c2r<T, L>), grid(ny, nfields, nruns), dim3(C::THREADS), 0, st,
-                       runs, bin0, bout0, bin1, bout1);
+                  int nfields, int variant, hipStream_t st) {
+    if (variant == 1 && L >= 16) {
+      constexpr int E = row_e_of(L, 1);
+      hipLaunchKernelGGL((k_row_c2r<T, L, E>), grid_e<E>(ny, nfields, nruns),
+                         dim3(RowCfg<L, E>::THREADS), 0, st, runs, bin0, bout0, bin1, bout1);
+    } else {
+      hipLaunchKernelGGL((k_row_c2r<T, L>), grid(ny, nfields, nruns), dim3(C::THREADS), 0, st,
+                         runs, bin0, bout0, bin1, bout1);
+    }
   }
   // the r = 1 (square cell grid, nx = ny) form when it applies
   static void bracket(const Run* runs, int nruns, int ny, const StepArgs* sa, const Jobs& jobs,
@@ -38,7 +66,7 @@ struct RowLaunch {
   // block); variant k > 0: the strip stencil over k-row strips into the
   // spectral buffers, then in-place row transforms
   static void advect(const Run* runs, int nruns, int ny, const StepArgs* sa, bool inertial,
-                     int variant, hipStream_t st) {
+                     int variant, int row_variant, hipStream_t st) {
     if (variant <= 0) {
       Jobs jobs{{{JOB_ADVECT, B_PHI, B_PS_R, B_PHIH},
                  {JOB_CUBE, B_PHI, B_PHI, B_FH},
@@ -55,15 +83,14 @@ struct RowLaunch {
       hipLaunchKernelGGL((k_adv_strip<T, NX, false>), gs, dim3(TPB), 0, st, runs, sa, variant,
                          inertial ? 1 : 0);
     R2cJobs jobs{{{B_PHIH, B_PHIH, NX + 2}, {B_FH, B_FH, NX + 2}, {B_OMH, B_OMH, NX + 2}}};
-    hipLaunchKernelGGL((k_row_r2c<T, L>), grid(ny, inertial ? 3 : 2, nruns), dim3(C::THREADS), 0,
-                       st, runs, jobs);
+    r2c_jobs(runs, nruns, ny, jobs, inertial ? 3 : 2, row_variant, st);
   }
   // variant 0: mu into the real scratch field, then the source bracket and
   // its row transform; variant k > 0 (square cells only): the strip stencil
   // (mu in registers) over k-row strips into B_GH, then its in-place row
   // transform
   static void mu_source(const Run* runs, int nruns, int ny, const StepArgs* sa, int variant,
-                        hipStream_t st) {
+                        int row_variant, hipStream_t st) {
     constexpr int NX = 2 * L, TPB = strip_threads(NX);
     if (variant <= 0 || ny != NX) {
       hipLaunchKernelGGL((k_mu<T, L>), grid(ny, 1, nruns), dim3(C::THREADS), 0, st, runs, sa,
@@ -75,8 +102,7 @@ struct RowLaunch {
     const dim3 gs(NX / 2 / TPB, (ny + variant - 1) / variant, nruns);
     hipLaunchKernelGGL((k_mug_strip<T, NX>), gs, dim3(TPB), 0, st, runs, sa, variant);
     R2cJobs jobs{{{B_GH, B_GH, NX + 2}, {}, {}}};
-    hipLaunchKernelGGL((k_row_r2c<T, L>), grid(ny, 1, nruns), dim3(C::THREADS), 0, st, runs,
-                       jobs);
+    r2c_jobs(runs, nruns, ny, jobs, 1, row_variant, st);
   }
 };
 

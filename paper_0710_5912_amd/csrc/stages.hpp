@@ -37,25 +37,30 @@ constexpr int col_elems(int L) { return L >= 8 ? 8 : L; }
 #define LE_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-template <int L>
+template <int L, int E_ = row_elems(L)>
 struct RowCfg {
-  static constexpr int E = row_elems(L);
+  static constexpr int E = E_;
   static constexpr int P = L / E;
   static constexpr int G = clampi(128 / P, 1, 16);
   static constexpr int THREADS = G * P;
 };
 
-// Column kernel shapes, VAR (a tuning choice, 0 .. 3): bit 0 doubles the
-// columns per block (where threads <= 1024 and LDS <= 160 KB allow), bit 1
-// uses 16 values per thread (FP32 only: fewer LDS passes; FP64 would not fit
-// the registers).
+// Column kernel shapes, VAR (a tuning choice, 0 .. 3).  8 values per thread
+// and CW0 = 256/P columns per block, except: VAR 1 doubles the columns per
+// block (where threads <= 1024 and LDS <= 160 KB allow); in FP32, VAR 2 and
+// 3 use 16 values per thread (fewer LDS passes; 3 also doubles the
+// columns); in FP64 (where 16 values would not fit the registers), VAR 2
+// halves the columns per block (more, shorter blocks) and VAR 3 uses 4
+// values per thread.
 template <typename T, int L, int VAR>
 struct ColCfg {
-  static constexpr bool WIDE_E = (VAR & 2) != 0 && sizeof(T) == 4 && L >= 16;
-  static constexpr int E = WIDE_E ? 16 : col_elems(L);
+  static constexpr bool F32 = sizeof(T) == 4;
+  static constexpr bool ALT_E = L >= 16 && (F32 ? VAR >= 2 : VAR == 3);
+  static constexpr int E = !ALT_E ? col_elems(L) : (F32 ? 16 : 4);
   static constexpr int P = L / E;
   static constexpr int CW0 = clampi(256 / P, 1, 64);
-  static constexpr int CWD = (VAR & 1) ? 2 * CW0 : CW0;
+  static constexpr int CWD = (VAR == 1 || (F32 && VAR == 3)) ? 2 * CW0
+                             : (!F32 && VAR == 2 ? (CW0 > 1 ? CW0 / 2 : 1) : CW0);
   static constexpr bool FITS =
       CWD <= 64 && CWD * P <= 1024 && (long)CWD * L * (long)sizeof(c2<T>) <= 160L * 1024;
   static constexpr int CW = FITS ? CWD : CW0;
@@ -188,10 +193,10 @@ struct R2cJobs {
   R2cJob j[3];
 };
 
-template <typename T, int L>
-__global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_row_r2c(
+template <typename T, int L, int E = row_elems(L)>
+__global__ __launch_bounds__((RowCfg<L, E>::THREADS)) LE_OCCUPANCY void k_row_r2c(
     const Run* __restrict__ runs, R2cJobs jobs) {
-  using C = RowCfg<L>;
+  using C = RowCfg<L, E>;
   __shared__ c2<T> lds[C::G * L];
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
@@ -213,10 +218,10 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_row_r2c(
 
 // Inverse row transform; the block's y picks the field (bin0 -> bout0, or
 // bin1 -> bout1).
-template <typename T, int L>
-__global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_row_c2r(
+template <typename T, int L, int E = row_elems(L)>
+__global__ __launch_bounds__((RowCfg<L, E>::THREADS)) LE_OCCUPANCY void k_row_c2r(
     const Run* __restrict__ runs, int bin0, int bout0, int bin1, int bout1) {
-  using C = RowCfg<L>;
+  using C = RowCfg<L, E>;
   __shared__ c2<T> lds[C::G * L];
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];

@@ -34,7 +34,7 @@ def mixed_runs():
     return runs
 
 
-def test_batch_equals_single_runs_bitwise():
+def test_batch_equals_single_runs_bitwise(fixed_variants):
     runs = mixed_runs()
     print(f"batch of {len(runs)} runs, 130 steps", flush=True)
     b = le.Batch([r[0] for r in runs], [r[2] for r in runs],

@@ -91,7 +91,8 @@ def test_corrector_needs_inertia_and_a_load():
             c.step_corrected(1)
 
 
-def test_corrected_graph_replays_match_eager(monkeypatch):
+def test_corrected_graph_replays_match_eager(fixed_variants):
+    monkeypatch = fixed_variants
     """Corrected chunks replayed from a captured graph equal direct launches,
     replay after replay, and a reload with new scales is not replayed stale."""
     p = configs.model_h(64, 64, gdot=0.1, rho=1.0)

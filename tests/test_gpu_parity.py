@@ -106,7 +106,7 @@ def test_observables_match_oracle():
     ctx.close()
 
 
-def test_mean_phi_conserved_and_deterministic():
+def test_mean_phi_conserved_and_deterministic(fixed_variants):
     p = params(128, 128, gdot=0.2, rho=1.0)
     phi0 = inputs.noise_phi0(128, 128, 9, amp=0.3, mean=0.1)
     runs = []
@@ -121,7 +121,7 @@ def test_mean_phi_conserved_and_deterministic():
     assert np.array_equal(runs[0]["psi"], runs[1]["psi"])
 
 
-def test_checkpoint_resume_is_bitwise():
+def test_checkpoint_resume_is_bitwise(fixed_variants):
     p = params(64, 64, gdot=1.0, rho=1.0)    # a wrap at strain 0.5 (step 100)
     phi0 = inputs.noise_phi0(64, 64, 2, amp=0.5)
     a = le.Context(p, phi0)
@@ -162,7 +162,8 @@ def test_fp32_error_bound(rho):
     ctx.close()
 
 
-def test_graph_replays_match_eager_launches(monkeypatch):
+def test_graph_replays_match_eager_launches(fixed_variants):
+    monkeypatch = fixed_variants
     """Captured step graphs replayed many times, with eager work between the
     replays, give bit-identical states to plain launches."""
     p = params(128, 64, lx=256.0, ly=128.0, gdot=0.5, rho=1.0)   # wraps every 200 steps
