@@ -177,8 +177,9 @@ int le_time_stage(le_ctx* c, int32_t stage, int32_t reps, double* ms_per_launch)
  *   row
  * (advect / mu_source: 0 = one fused stencil-and-row-transform kernel,
  * k > 0 = a stencil kernel over k-row strips then in-place row transforms;
- * column_*: block shape 0 .. 3; row: row transforms with 8 (0) or 4 (1)
- * values per thread), at most cap values in all, and returns the number of
+ * column_*: block shape 0 .. 3; row: row-transform shape 0 .. 3, 8 or 4
+ * values per thread, all or a quarter of the rows per block), at most cap
+ * values in all, and returns the number of
  * groups (LE_EINVAL for NULL c, cap < 0 or out NULL with cap > 0).  The
  * environment variables LE_TUNE_ADV, LE_TUNE_MU, LE_TUNE_COL_CH,
  * LE_TUNE_COL_FLOW and LE_TUNE_ROW, when set, fix the corresponding variant

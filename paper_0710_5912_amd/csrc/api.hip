@@ -473,7 +473,7 @@ int observables_of(Engine* e, const RunHost& r, le_obs* o, double* Sk, int32_t s
 // tests that exercise every path.
 namespace {
 
-constexpr int kRowCand[] = {0, 1};
+constexpr int kRowCand[] = {0, 1, 2, 3};
 constexpr int kAdvCand[] = {0, 2, 4, 8, 16, 32};
 constexpr int kMuCand[] = {0, 2, 4, 8, 16, 32};
 constexpr int kColCand[] = {0, 1, 2, 3};

@@ -8,32 +8,39 @@
 
 namespace le {
 
-// Row transform shape: variant 0 = 8 values per thread, 1 = 4 (twice the
-// threads per row: shorter chains for latency-bound grids).
-constexpr int row_e_of(int L, int variant) {
-  return (variant == 1 && L >= 16) ? 4 : row_elems(L);
-}
-
+// Row transform shapes (variant, a tuning choice): 0 = 8 values per thread,
+// 1 = 4 (twice the threads per row: shorter chains for latency-bound grids),
+// 2 and 3 = the same with a quarter of the rows per block (more blocks for
+// small grids).
 template <typename T, int L>
 struct RowLaunch {
   using C = RowCfg<L>;
   static dim3 grid(int ny, int fields, int nruns) {
     return dim3((ny + C::G - 1) / C::G, fields, nruns);
   }
-  template <int E>
-  static dim3 grid_e(int ny, int fields, int nruns) {
-    using CE = RowCfg<L, E>;
-    return dim3((ny + CE::G - 1) / CE::G, fields, nruns);
+  template <int E, int GD>
+  static void r2c_shape(const Run* runs, int nruns, int ny, const R2cJobs& jobs, int njobs,
+                        hipStream_t st) {
+    using CE = RowCfg<L, E, GD>;
+    hipLaunchKernelGGL((k_row_r2c<T, L, E, GD>), dim3((ny + CE::G - 1) / CE::G, njobs, nruns),
+                       dim3(CE::THREADS), 0, st, runs, jobs);
   }
+  template <int E, int GD>
+  static void c2r_shape(const Run* runs, int nruns, int ny, int bin0, int bout0, int bin1,
+                        int bout1, int nfields, hipStream_t st) {
+    using CE = RowCfg<L, E, GD>;
+    hipLaunchKernelGGL((k_row_c2r<T, L, E, GD>),
+                       dim3((ny + CE::G - 1) / CE::G, nfields, nruns), dim3(CE::THREADS), 0, st,
+                       runs, bin0, bout0, bin1, bout1);
+  }
+  static constexpr int E4 = L >= 16 ? 4 : row_elems(L);
   static void r2c_jobs(const Run* runs, int nruns, int ny, const R2cJobs& jobs, int njobs,
                        int variant, hipStream_t st) {
-    if (variant == 1 && L >= 16) {
-      constexpr int E = row_e_of(L, 1);
-      hipLaunchKernelGGL((k_row_r2c<T, L, E>), grid_e<E>(ny, njobs, nruns),
-                         dim3(RowCfg<L, E>::THREADS), 0, st, runs, jobs);
-    } else {
-      hipLaunchKernelGGL((k_row_r2c<T, L>), grid(ny, njobs, nruns), dim3(C::THREADS), 0, st,
-                         runs, jobs);
+    switch (variant) {
+      case 1: r2c_shape<E4, 1>(runs, nruns, ny, jobs, njobs, st); break;
+      case 2: r2c_shape<row_elems(L), 4>(runs, nruns, ny, jobs, njobs, st); break;
+      case 3: r2c_shape<E4, 4>(runs, nruns, ny, jobs, njobs, st); break;
+      default: r2c_shape<row_elems(L), 1>(runs, nruns, ny, jobs, njobs, st); break;
     }
   }
   static void r2c(const Run* runs, int nruns, int ny, int bin, int bout, int variant,
@@ -43,13 +50,15 @@ struct RowLaunch {
   }
   static void c2r(const Run* runs, int nruns, int ny, int bin0, int bout0, int bin1, int bout1,
                   int nfields, int variant, hipStream_t st) {
-    if (variant == 1 && L >= 16) {
-      constexpr int E = row_e_of(L, 1);
-      hipLaunchKernelGGL((k_row_c2r<T, L, E>), grid_e<E>(ny, nfields, nruns),
-                         dim3(RowCfg<L, E>::THREADS), 0, st, runs, bin0, bout0, bin1, bout1);
-    } else {
-      hipLaunchKernelGGL((k_row_c2r<T, L>), grid(ny, nfields, nruns), dim3(C::THREADS), 0, st,
-                         runs, bin0, bout0, bin1, bout1);
+    switch (variant) {
+      case 1: c2r_shape<E4, 1>(runs, nruns, ny, bin0, bout0, bin1, bout1, nfields, st); break;
+      case 2:
+        c2r_shape<row_elems(L), 4>(runs, nruns, ny, bin0, bout0, bin1, bout1, nfields, st);
+        break;
+      case 3: c2r_shape<E4, 4>(runs, nruns, ny, bin0, bout0, bin1, bout1, nfields, st); break;
+      default:
+        c2r_shape<row_elems(L), 1>(runs, nruns, ny, bin0, bout0, bin1, bout1, nfields, st);
+        break;
     }
   }
   // the r = 1 (square cell grid, nx = ny) form when it applies
@@ -119,16 +128,11 @@ struct ColLaunch {
   template <int MODE>
   static void by_variant(int variant, const Run* runs, int nruns, int nx, const StepArgs* sa,
                          int bin0, int bin1, int bout0, int bout1, hipStream_t st) {
-    // lengths below 512 are latency bound: one shape
-    if constexpr (L < 512) {
-      launch<MODE, 0>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st);
-    } else {
-      switch (variant) {
-        case 1: launch<MODE, 1>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
-        case 2: launch<MODE, 2>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
-        case 3: launch<MODE, 3>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
-        default: launch<MODE, 0>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
-      }
+    switch (variant) {
+      case 1: launch<MODE, 1>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
+      case 2: launch<MODE, 2>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
+      case 3: launch<MODE, 3>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
+      default: launch<MODE, 0>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
     }
   }
   static void column(int mode, const Run* runs, int nruns, int nx, const StepArgs* sa,

@@ -37,30 +37,29 @@ constexpr int col_elems(int L) { return L >= 8 ? 8 : L; }
 #define LE_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-template <int L, int E_ = row_elems(L)>
+template <int L, int E_ = row_elems(L), int GDIV = 1>
 struct RowCfg {
   static constexpr int E = E_;
   static constexpr int P = L / E;
-  static constexpr int G = clampi(128 / P, 1, 16);
+  static constexpr int G0 = clampi(128 / P, 1, 16);
+  static constexpr int G = G0 / GDIV > 1 ? G0 / GDIV : 1;  // rows per block
   static constexpr int THREADS = G * P;
 };
 
-// Column kernel shapes, VAR (a tuning choice, 0 .. 3).  8 values per thread
-// and CW0 = 256/P columns per block, except: VAR 1 doubles the columns per
-// block (where threads <= 1024 and LDS <= 160 KB allow); in FP32, VAR 2 and
-// 3 use 16 values per thread (fewer LDS passes; 3 also doubles the
-// columns); in FP64 (where 16 values would not fit the registers), VAR 2
-// halves the columns per block (more, shorter blocks) and VAR 3 uses 4
-// values per thread.
+// Column kernel shapes, VAR (a tuning choice, 0 .. 3): 8 values per thread
+// and CW0 = 256/P columns per block (VAR 0), twice the columns per block
+// where threads <= 1024 and LDS <= 160 KB allow (VAR 1), a quarter (VAR 2:
+// more, smaller blocks for grids whose column pass has few blocks), and
+// other values per thread (VAR 3): 16 in FP32 (fewer LDS passes), 4 in FP64
+// (where 16 would not fit the registers).
 template <typename T, int L, int VAR>
 struct ColCfg {
   static constexpr bool F32 = sizeof(T) == 4;
-  static constexpr bool ALT_E = L >= 16 && (F32 ? VAR >= 2 : VAR == 3);
+  static constexpr bool ALT_E = L >= 16 && VAR == 3;
   static constexpr int E = !ALT_E ? col_elems(L) : (F32 ? 16 : 4);
   static constexpr int P = L / E;
   static constexpr int CW0 = clampi(256 / P, 1, 64);
-  static constexpr int CWD = (VAR == 1 || (F32 && VAR == 3)) ? 2 * CW0
-                             : (!F32 && VAR == 2 ? (CW0 > 1 ? CW0 / 2 : 1) : CW0);
+  static constexpr int CWD = VAR == 1 ? 2 * CW0 : (VAR == 2 ? (CW0 / 4 > 1 ? CW0 / 4 : 1) : CW0);
   static constexpr bool FITS =
       CWD <= 64 && CWD * P <= 1024 && (long)CWD * L * (long)sizeof(c2<T>) <= 160L * 1024;
   static constexpr int CW = FITS ? CWD : CW0;
@@ -193,10 +192,10 @@ struct R2cJobs {
   R2cJob j[3];
 };
 
-template <typename T, int L, int E = row_elems(L)>
-__global__ __launch_bounds__((RowCfg<L, E>::THREADS)) LE_OCCUPANCY void k_row_r2c(
+template <typename T, int L, int E = row_elems(L), int GDIV = 1>
+__global__ __launch_bounds__((RowCfg<L, E, GDIV>::THREADS)) LE_OCCUPANCY void k_row_r2c(
     const Run* __restrict__ runs, R2cJobs jobs) {
-  using C = RowCfg<L, E>;
+  using C = RowCfg<L, E, GDIV>;
   __shared__ c2<T> lds[C::G * L];
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
@@ -218,10 +217,10 @@ __global__ __launch_bounds__((RowCfg<L, E>::THREADS)) LE_OCCUPANCY void k_row_r2
 
 // Inverse row transform; the block's y picks the field (bin0 -> bout0, or
 // bin1 -> bout1).
-template <typename T, int L, int E = row_elems(L)>
-__global__ __launch_bounds__((RowCfg<L, E>::THREADS)) LE_OCCUPANCY void k_row_c2r(
+template <typename T, int L, int E = row_elems(L), int GDIV = 1>
+__global__ __launch_bounds__((RowCfg<L, E, GDIV>::THREADS)) LE_OCCUPANCY void k_row_c2r(
     const Run* __restrict__ runs, int bin0, int bout0, int bin1, int bout1) {
-  using C = RowCfg<L, E>;
+  using C = RowCfg<L, E, GDIV>;
   __shared__ c2<T> lds[C::G * L];
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];

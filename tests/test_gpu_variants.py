@@ -20,7 +20,7 @@ le = pytest.importorskip("paper_0710_5912_amd.le")
 
 KEYS = ("LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH", "LE_TUNE_COL_FLOW", "LE_TUNE_ROW")
 # (advect, mu_source, column_ch, column_flow, row)
-COMBOS = [(0, 0, 0, 0, 0), (4, 4, 1, 1, 1), (32, 32, 2, 2, 0), (8, 16, 3, 3, 1),
+COMBOS = [(0, 0, 0, 0, 0), (4, 4, 1, 1, 1), (32, 32, 2, 2, 2), (8, 16, 3, 3, 3),
           (2, 2, 0, 0, 1)]
 
 
@@ -72,7 +72,7 @@ def test_variants_512_fp64(monkeypatch, combo, rho):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
 
 
-@pytest.mark.parametrize("combo", [(4, 4, 1, 3, 1), (32, 8, 3, 1, 0)])
+@pytest.mark.parametrize("combo", [(4, 4, 1, 3, 1), (32, 8, 3, 2, 3)])
 def test_variants_512_fp32(monkeypatch, combo):
     """FP32 shapes (16 values per thread in shapes 2 and 3) within the FP32 bound."""
     p = params(512, 512)
@@ -81,7 +81,7 @@ def test_variants_512_fp32(monkeypatch, combo):
     assert rel(g["psi"], st.psi) <= 2e-4
 
 
-@pytest.mark.parametrize("combo", [(4, 4, 0, 0, 1), (16, 32, 0, 0, 0), (2, 2, 0, 0, 0)])
+@pytest.mark.parametrize("combo", [(4, 4, 0, 2, 1), (16, 32, 3, 0, 2), (2, 2, 2, 1, 3)])
 def test_strip_variants_across_a_wrap(monkeypatch, combo):
     """64^2, gdot = 0.5: the strain wraps at step 200; 220 steps."""
     p = params(64, 64, gdot=0.5)
@@ -95,7 +95,7 @@ def test_strip_variants_non_square_cells(monkeypatch):
     """nx = 4 ny (r = 4): the strip advect reads the diagonal pairs; the mu
     strip applies to square cells only and falls back."""
     p = params(256, 64, gdot=0.2, lx=256.0, ly=64.0)
-    g, st = run_forced(monkeypatch, p, 20, 24, (8, 8, 0, 0, 1))
+    g, st = run_forced(monkeypatch, p, 20, 24, (8, 8, 2, 3, 3))
     for k in ("phi", "omega", "psi"):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
 
@@ -108,7 +108,7 @@ def test_autotuner_reports_valid_choices():
     t = t[0]
     assert (t["nx"], t["ny"], t["precision"], t["inertial"]) == (256, 256, 0, 1)
     assert t["advect"] in (0, 2, 4, 8, 16, 32) and t["mu_source"] in (0, 2, 4, 8, 16, 32)
-    assert t["column_ch"] in range(4) and t["column_flow"] in range(4) and t["row"] in (0, 1)
+    assert t["column_ch"] in range(4) and t["column_flow"] in range(4) and t["row"] in range(4)
 
 
 @pytest.mark.parametrize("rho", [1.0, 0.0])
