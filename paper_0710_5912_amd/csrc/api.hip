@@ -32,6 +32,7 @@ constexpr int64_t kChunkCap = 1024;  // steps per host chunk
 constexpr int64_t kProfChunk = 256;  // steps per chunk while stage timing is on
 constexpr int kRealBlocks = 256;     // blocks of the real-space reduction
 constexpr int64_t kGraphMin = 8;     // shortest chunk worth capturing
+constexpr int64_t kGraphChunk = 128; // longest captured chunk (longer graphs replay slower)
 constexpr size_t kGraphCacheMax = 4;
 
 thread_local char g_last_error[256] = "";
@@ -743,7 +744,7 @@ int step_engine(Engine* e, int64_t nsteps) {
   int64_t remaining = nsteps;
   while (remaining > 0) {
     const int64_t n0 = e->step;
-    const int64_t cap = e->profiling ? kProfChunk : kChunkCap;
+    const int64_t cap = e->profiling ? kProfChunk : (e->use_graphs ? kGraphChunk : kChunkCap);
     int64_t count = remaining < cap ? remaining : cap;
     // fill the table; end the chunk after the first step on which any run wraps
     for (int64_t k = 0; k < count; ++k) {
@@ -846,7 +847,8 @@ int step_corrected(Engine* e, int64_t ncoarse) {
   int64_t remaining = ncoarse;
   while (remaining > 0) {
     const int64_t n0 = e->step;
-    int64_t count = remaining < kChunkCap ? remaining : kChunkCap;
+    const int64_t cap = e->use_graphs ? kGraphChunk : kChunkCap;
+    int64_t count = remaining < cap ? remaining : cap;
     for (int64_t k = 0; k < count; ++k) {
       e->h_args[k].s = strain_offset(r.p, n0 + k);
       e->h_args[k].pad = 0.0;
