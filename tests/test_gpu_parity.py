@@ -200,3 +200,33 @@ def test_parity_other_material_parameters(kw):
     if kw.get("rho", 1.0) > 0:
         assert rel(g["omega"], st.omega) <= 1e-10
     ctx.close()
+
+
+def test_long_run_statistics_fp64_and_fp32():
+    """8000 steps (t = 40, domains formed and sheared) at 128^2: L(t),
+    <phi^2> and the Korteweg stress of the FP64 and FP32 GPU runs against
+    the oracle every 1000 steps, within 2% (the ensemble-statistics bar)."""
+    from oracle import observables as ob
+    p = params(128, 128, gdot=0.02, rho=1.0)
+    phi0 = inputs.noise_phi0(128, 128, 5, amp=0.05)
+    op = mh.Params(**p)
+    st = mh.initial_state(op, phi0)
+    ctx = {prec: le.Context(p, phi0, precision=prec) for prec in ("fp64", "fp32")}
+    print("case 128^2 gdot=0.02 8000 steps, fp64 and fp32 vs oracle", flush=True)
+    try:
+        for k in range(8):
+            st = mh.run(op, st, 1000)
+            ro = ob.observables(op, st, 64)[0]
+            if k < 3:
+                continue          # before t = 20 the domains are still forming
+            for prec, c in ctx.items():
+                c.step(1000 if k > 3 else 4000)
+                o, _ = c.observables(sk=False)
+                assert o["step"] == st.step
+                for key in ("Ls", "phi2"):
+                    assert abs(o[key] - ro[key]) <= 0.02 * abs(ro[key]), (prec, k, key)
+                assert abs(o["sigma_xy"] - ro["sigma_xy"]) <= 0.02 * abs(ro["sigma_xy"]) + 1e-9, \
+                    (prec, k)
+    finally:
+        for c in ctx.values():
+            c.close()
