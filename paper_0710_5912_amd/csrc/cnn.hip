@@ -51,14 +51,23 @@ __device__ __forceinline__ int nb(int p, int dy, int dx, int H, int W, int lgW) 
 // ---------------------------------------------------------------- forward
 
 // z[p][co] = b[co] + sum_{tap, ci} W[co][ci][tap] a[p + tap - (1,1)][ci];
-// a_out = bf16(silu(z)) when ACT.  Block: 4 waves, each a 32-pixel tile.
-template <int CIN, int COUT, bool ACT>
+// a_out = bf16(silu(z)) when ACT; z itself is stored only where z_out is
+// given (training keeps it for the backward pass, inference does not).
+// Block: 4 waves, each a 32-pixel tile.
+// Input: the BF16 activations a_in, or (FIELDS, first layer of the
+// corrected step) the two state planes x0, x1 (T) scaled by s0, s1 and
+// rounded to BF16 here.  RSUM: also write the block's FP64 sum of z[.][0]
+// (fixed order) to rsum[blockIdx.x].
+template <int CIN, int COUT, bool ACT, typename T = float, bool FIELDS = false, bool RSUM = false>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ a_in,
                                                   const uint16_t* __restrict__ wt,
                                                   const float* __restrict__ bias,
                                                   float* __restrict__ z_out,
                                                   uint16_t* __restrict__ a_out, int H, int W,
-                                                  int lgW) {
+                                                  int lgW, const T* __restrict__ x0 = nullptr,
+                                                  const T* __restrict__ x1 = nullptr,
+                                                  float s0 = 1.f, float s1 = 1.f,
+                                                  double* __restrict__ rsum = nullptr) {
   constexpr int K = 9 * CIN, KP = pad16(K);
   const int lane = threadIdx.x & 63, half = lane >> 5, i = lane & 31;
   const int p0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
@@ -72,7 +81,19 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ a
 #pragma unroll
   for (int ks = 0; ks < NKS; ++ks) {
     const int k0 = ks * 16 + half * 8;
-    if constexpr (CIN % 8 == 0) {
+    if constexpr (FIELDS) {
+      static_assert(CIN == 2, "state planes feed the two-channel first layer");
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = k0 + e;
+        uint16_t v = 0;
+        if (k < K) {
+          const int tap = k / 2, q = nb(p, tap / 3 - 1, tap % 3 - 1, H, W, lgW);
+          v = (k & 1) ? f2bf((float)x1[q] * s1) : f2bf((float)x0[q] * s0);
+        }
+        av[ks][e] = v;
+      }
+    } else if constexpr (CIN % 8 == 0) {
       const int tap = k0 / CIN, ci0 = k0 % CIN;
       const int q = nb(p, tap / 3 - 1, tap % 3 - 1, H, W, lgW);
       av[ks] = *reinterpret_cast<const u16x8*>(a_in + (size_t)q * CIN + ci0);
@@ -94,14 +115,27 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ a
 #pragma unroll
   for (int ks = 0; ks < NKS; ++ks) acc = mfma(av[ks], bv[ks], acc);
   const int co = i;
+  double zs = 0.0;
   if (co < COUT) {
     const float bc = bias[co];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int pp = p0 + c_row(r, half);
       const float z = acc[r] + bc;
-      z_out[(size_t)pp * COUT + co] = z;
+      if (z_out) z_out[(size_t)pp * COUT + co] = z;
       if constexpr (ACT) a_out[(size_t)pp * COUT + co] = f2bf(silu(z));
+      if constexpr (RSUM) zs += (double)z;
+    }
+  }
+  if constexpr (RSUM) {
+    // lanes 0 and 32 of each wave hold channel 0 of the wave's 32 pixels
+    __shared__ double wsum[8];
+    if (co == 0) wsum[(threadIdx.x >> 6) * 2 + half] = zs;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int k = 0; k < 8; ++k) t += wsum[k];
+      rsum[blockIdx.x] = t;
     }
   }
 }
@@ -284,28 +318,26 @@ __global__ void k_unpack_out(const float* __restrict__ z4, int P, float s2, floa
   }
 }
 
-// Per-block sums of the phi residual (FP64, fixed order).
-__global__ __launch_bounds__(256) void k_rphi_sum(const float* __restrict__ z4, int P,
-                                                  double* __restrict__ part) {
+// phi += s2 (z4_phi - mean(z4_phi)); omega += s3 z4_omega.  Every block
+// first sums the nblk per-block partials of z4_phi itself, in one fixed
+// order, so all blocks use the same mean without a separate launch.
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_correction(T* __restrict__ phi,
+                                                          T* __restrict__ om,
+                                                          const float* __restrict__ z4, int P,
+                                                          float s2, float s3,
+                                                          const double* __restrict__ part,
+                                                          int nblk) {
   __shared__ double red[256];
-  double acc = 0.0;
-  for (int p = blockIdx.x * 256 + threadIdx.x; p < P; p += gridDim.x * 256)
-    acc += (double)z4[2 * (size_t)p];
-  red[threadIdx.x] = acc;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += 256) s += part[k];
+  red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h >= 1; h >>= 1) {
     if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
-
-// phi += s2 (z4_phi - mean(z4_phi)); omega += s3 z4_omega.
-template <typename T>
-__global__ void k_apply_correction(T* __restrict__ phi, T* __restrict__ om,
-                                   const float* __restrict__ z4, int P, float s2, float s3,
-                                   const double* __restrict__ sum_rphi) {
-  const double mean = sum_rphi[0] / (double)P;
+  const double mean = red[0] / (double)P;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
     phi[p] = (T)((double)phi[p] + (double)s2 * ((double)z4[2 * (size_t)p] - mean));
     om[p] = (T)((double)om[p] + (double)s3 * (double)z4[2 * (size_t)p + 1]);
@@ -457,7 +489,10 @@ int net_create(Net* n, int H, int W, bool training) {
     rc = rc ? rc : alloc_dev((void**)&n->act[l], P * kCnnCin[l] * 2);
     rc = rc ? rc : alloc_dev((void**)&n->z[l], P * kCnnCout[l] * sizeof(float));
   }
-  rc = rc ? rc : alloc_dev((void**)&n->red, 2048 * sizeof(double));
+  // reduction scratch: the corrected step's P/128 per-block partials; the
+  // loss's 256 partials and its running sum at [1024]
+  const size_t nred = (P / 128 > 2048 ? P / 128 : 2048);
+  rc = rc ? rc : alloc_dev((void**)&n->red, nred * sizeof(double));
   if (training) {
     rc = rc ? rc : alloc_dev((void**)&n->grad, kCnnParams * sizeof(float));
     rc = rc ? rc : alloc_dev((void**)&n->m, kCnnParams * sizeof(float));
@@ -573,18 +608,24 @@ int net_layer_bwd(Net* n, int li, const float* dz, const uint16_t* a_in, const f
 template <typename T>
 int net_correct_fields(Net* n, T* phi, T* omega, hipStream_t st) {
   const int P = n->P;
-  hipLaunchKernelGGL((k_pack_input<T>), dim3(256), dim3(256), 0, st, phi, omega, P,
-                     n->scales[0], n->scales[1], n->act[0]);
-  for (int l = 0; l < kCnnLayers; ++l)
-    launch_fwd(n, l, n->act[l], n->z[l], l < 3 ? n->act[l + 1] : nullptr, st);
-  hipLaunchKernelGGL(k_rphi_sum, dim3(256), dim3(256), 0, st, n->z[3], P, n->red);
-  hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(256), 0, st, n->red, 256, n->red + 1024, 0);
+  const dim3 g(P / 128), b(256);
+  const int nblk = P / 128;
+  // layer 1 reads the state planes itself; layers 1-3 keep only their
+  // activations; layer 4 leaves per-block sums of the phi residual, which the
+  // update sums for the mean-free correction
+  hipLaunchKernelGGL((k_conv_fwd<2, 32, true, T, true>), g, b, 0, st, nullptr, n->wt[0],
+                     n->params + kOffB[0], nullptr, n->act[1], n->H, n->W, n->lgW, phi, omega,
+                     n->scales[0], n->scales[1], nullptr);
+  launch_fwd(n, 1, n->act[1], nullptr, n->act[2], st);
+  launch_fwd(n, 2, n->act[2], nullptr, n->act[3], st);
+  hipLaunchKernelGGL((k_conv_fwd<32, 2, false, float, false, true>), g, b, 0, st, n->act[3],
+                     n->wt[3], n->params + kOffB[3], n->z[3], nullptr, n->H, n->W, n->lgW,
+                     nullptr, nullptr, 1.f, 1.f, n->red);
   hipLaunchKernelGGL((k_apply_correction<T>), dim3(256), dim3(256), 0, st, phi, omega, n->z[3],
-                     P, n->scales[2], n->scales[3], n->red + 1024);
+                     P, n->scales[2], n->scales[3], n->red, nblk);
   CNN_TRY(hipGetLastError());
   return 0;
 }
-
 template int net_correct_fields<double>(Net*, double*, double*, hipStream_t);
 template int net_correct_fields<float>(Net*, float*, float*, hipStream_t);
 
