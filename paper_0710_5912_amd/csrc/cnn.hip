@@ -18,12 +18,9 @@ constexpr int kOffB[kCnnLayers] = {576, 9824, 19072, 19680};
 
 constexpr int pad16(int k) { return (k + 15) / 16 * 16; }
 
-// FP32 -> BF16, round to nearest even (NaN kept quiet).
+// FP32 -> BF16, round to nearest even (the hardware conversion).
 __device__ __forceinline__ uint16_t f2bf(float f) {
-  unsigned u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((unsigned)h) << 16); }
 
@@ -36,9 +33,14 @@ __device__ __forceinline__ f32x16 mfma(u16x8 a, u16x8 b, f32x16 c) {
 }
 __device__ __forceinline__ int c_row(int r, int half) { return 8 * (r >> 2) + 4 * half + (r & 3); }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+// Logistic function from the hardware base-2 exponential and reciprocal
+// (about 1 ulp each: far below the BF16 rounding of the activations).
+__device__ __forceinline__ float sigmoid(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
+__device__ __forceinline__ float silu(float z) { return z * sigmoid(z); }
 __device__ __forceinline__ float silu_grad(float z) {
-  const float s = 1.0f / (1.0f + expf(-z));
+  const float s = sigmoid(z);
   return s * (1.0f + z * (1.0f - s));
 }
 
@@ -51,23 +53,14 @@ __device__ __forceinline__ int nb(int p, int dy, int dx, int H, int W, int lgW) 
 // ---------------------------------------------------------------- forward
 
 // z[p][co] = b[co] + sum_{tap, ci} W[co][ci][tap] a[p + tap - (1,1)][ci];
-// a_out = bf16(silu(z)) when ACT; z itself is stored only where z_out is
-// given (training keeps it for the backward pass, inference does not).
-// Block: 4 waves, each a 32-pixel tile.
-// Input: the BF16 activations a_in, or (FIELDS, first layer of the
-// corrected step) the two state planes x0, x1 (T) scaled by s0, s1 and
-// rounded to BF16 here.  RSUM: also write the block's FP64 sum of z[.][0]
-// (fixed order) to rsum[blockIdx.x].
-template <int CIN, int COUT, bool ACT, typename T = float, bool FIELDS = false, bool RSUM = false>
+// a_out = bf16(silu(z)) when ACT.  Block: 4 waves, each a 32-pixel tile.
+template <int CIN, int COUT, bool ACT>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ a_in,
                                                   const uint16_t* __restrict__ wt,
                                                   const float* __restrict__ bias,
                                                   float* __restrict__ z_out,
                                                   uint16_t* __restrict__ a_out, int H, int W,
-                                                  int lgW, const T* __restrict__ x0 = nullptr,
-                                                  const T* __restrict__ x1 = nullptr,
-                                                  float s0 = 1.f, float s1 = 1.f,
-                                                  double* __restrict__ rsum = nullptr) {
+                                                  int lgW) {
   constexpr int K = 9 * CIN, KP = pad16(K);
   const int lane = threadIdx.x & 63, half = lane >> 5, i = lane & 31;
   const int p0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
@@ -81,19 +74,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ a
 #pragma unroll
   for (int ks = 0; ks < NKS; ++ks) {
     const int k0 = ks * 16 + half * 8;
-    if constexpr (FIELDS) {
-      static_assert(CIN == 2, "state planes feed the two-channel first layer");
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = k0 + e;
-        uint16_t v = 0;
-        if (k < K) {
-          const int tap = k / 2, q = nb(p, tap / 3 - 1, tap % 3 - 1, H, W, lgW);
-          v = (k & 1) ? f2bf((float)x1[q] * s1) : f2bf((float)x0[q] * s0);
-        }
-        av[ks][e] = v;
-      }
-    } else if constexpr (CIN % 8 == 0) {
+    if constexpr (CIN % 8 == 0) {
       const int tap = k0 / CIN, ci0 = k0 % CIN;
       const int q = nb(p, tap / 3 - 1, tap % 3 - 1, H, W, lgW);
       av[ks] = *reinterpret_cast<const u16x8*>(a_in + (size_t)q * CIN + ci0);
@@ -115,28 +96,195 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ a
 #pragma unroll
   for (int ks = 0; ks < NKS; ++ks) acc = mfma(av[ks], bv[ks], acc);
   const int co = i;
-  double zs = 0.0;
   if (co < COUT) {
     const float bc = bias[co];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int pp = p0 + c_row(r, half);
       const float z = acc[r] + bc;
-      if (z_out) z_out[(size_t)pp * COUT + co] = z;
+      z_out[(size_t)pp * COUT + co] = z;
       if constexpr (ACT) a_out[(size_t)pp * COUT + co] = f2bf(silu(z));
-      if constexpr (RSUM) zs += (double)z;
     }
   }
-  if constexpr (RSUM) {
-    // lanes 0 and 32 of each wave hold channel 0 of the wave's 32 pixels
-    __shared__ double wsum[8];
-    if (co == 0) wsum[(threadIdx.x >> 6) * 2 + half] = zs;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int k = 0; k < 8; ++k) t += wsum[k];
-      rsum[blockIdx.x] = t;
+}
+
+// ---------------------------------------------------------------- fused inference
+
+// The corrected step runs the whole network over one 16 x 16 output tile per
+// block.  The state planes of the tile and a 4-pixel halo (one pixel per 3x3
+// layer) are read once; every intermediate activation stays in LDS as
+// [pixel][kFS] BF16 (32 channels and 8 of padding: an 80-byte pixel stride
+// puts the 16-byte reads of consecutive pixels on distinct banks).  Layer l
+// computes the (22 - 2l)^2 pixels the next layer needs.  Each value is formed
+// with the k order, products and roundings of the per-layer kernel above, so
+// it equals the per-layer result bit for bit.
+constexpr int kFT = 16, kFH = 4, kFR = kFT + 2 * kFH, kFS = 40, kFWaves = 8;
+
+// One layer on the tile: input region SIN x SIN (LDS), output region
+// (SIN - 2)^2, weights wt in LDS as [COUT][KP + 8] (the 8 of padding spread
+// the rows over the banks).  Hidden layers write bf16(silu(z)) to LDS; the last writes z
+// of both channels to z_out at the global pixels (tile origin gy0, gx0) and
+// adds channel 0 into zs (FP64, lanes 0 and 32 of each wavefront).
+template <int CIN, int SIN, bool LAST>
+__device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ in,
+                                            uint16_t* __restrict__ out,
+                                            const uint16_t* __restrict__ wt,
+                                            const float* __restrict__ bias,
+                                            float* __restrict__ z_out, int gy0, int gx0, int H,
+                                            int W, int lgW, double& zs) {
+  constexpr int COUT = LAST ? 2 : 32;
+  constexpr int SOUT = SIN - 2, NP = SOUT * SOUT, NT = (NP + 31) / 32;
+  constexpr int K = 9 * CIN, KP = pad16(K), NKS = KP / 16;
+  const int lane = threadIdx.x & 63, half = lane >> 5, i = lane & 31;
+  u16x8 bv[NKS];
+#pragma unroll
+  for (int ks = 0; ks < NKS; ++ks)
+    bv[ks] = i < COUT ? *reinterpret_cast<const u16x8*>(wt + i * (KP + 8) + ks * 16 + half * 8)
+                      : u16x8{};
+  const float bc = i < COUT ? bias[i] : 0.f;
+  for (int tile = (int)(threadIdx.x >> 6); tile < NT; tile += kFWaves) {
+    // rows past the region repeat its last pixel; their results are dropped
+    const int t = min(tile * 32 + i, NP - 1);
+    const int oy = t / SOUT, ox = t - oy * SOUT;
+    u16x8 av[NKS];
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int k0 = ks * 16 + half * 8;
+      if constexpr (CIN == 2) {
+#pragma unroll
+        for (int e = 0; e < 8; e += 2) {
+          const int k = k0 + e, tap = k / 2;
+          unsigned v = 0;
+          if (k < K) {
+            const int q = (oy + tap / 3) * SIN + ox + tap % 3;
+            v = *reinterpret_cast<const unsigned*>(in + 2 * q);
+          }
+          av[ks][e] = (uint16_t)(v & 0xffffu);
+          av[ks][e + 1] = (uint16_t)(v >> 16);
+        }
+      } else {
+        const int tap = k0 / CIN, ci0 = k0 % CIN;
+        const int q = (oy + tap / 3) * SIN + ox + tap % 3;
+        av[ks] = *reinterpret_cast<const u16x8*>(in + q * kFS + ci0);
+      }
     }
+    f32x16 acc = {};
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) acc = mfma(av[ks], bv[ks], acc);
+    if (i < COUT) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int tt = tile * 32 + c_row(r, half);
+        if (tt < NP) {
+          const float z = acc[r] + bc;
+          if constexpr (!LAST) {
+            out[tt * kFS + i] = f2bf(silu(z));
+          } else {
+            const int y = tt / SOUT, x = tt - y * SOUT;
+            const int gp = (((gy0 + y) & (H - 1)) << lgW) | ((gx0 + x) & (W - 1));
+            z_out[(size_t)gp * 2 + i] = z;
+            if (i == 0) zs += (double)z;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Grid: (H / 16) (W / 16) blocks of 512 threads, tile b at rows
+// 16 (b / (W / 16)), columns 16 (b % (W / 16)).  part[b] = the tile's FP64 sum
+// of z[.][0] (fixed order).
+template <typename T>
+__global__ __launch_bounds__(kFWaves * 64) void k_net_fused(
+    const T* __restrict__ phi, const T* __restrict__ om, float s0, float s1,
+    const uint16_t* __restrict__ w0, const uint16_t* __restrict__ w1,
+    const uint16_t* __restrict__ w2, const uint16_t* __restrict__ w3,
+    const float* __restrict__ params, float* __restrict__ z3, double* __restrict__ part, int H,
+    int W, int lgW) {
+  __shared__ __align__(16) uint16_t in0[kFR * kFR * 2];
+  __shared__ __align__(16) uint16_t buf_a[(kFR - 2) * (kFR - 2) * kFS];
+  __shared__ __align__(16) uint16_t buf_b[(kFR - 4) * (kFR - 4) * kFS];
+  constexpr int KP0 = pad16(18), KP = pad16(288);
+  __shared__ __align__(16) uint16_t wl0[32 * (KP0 + 8)];
+  __shared__ __align__(16) uint16_t wl1[32 * (KP + 8)];
+  __shared__ __align__(16) uint16_t wl2[32 * (KP + 8)];
+  __shared__ __align__(16) uint16_t wl3[2 * (KP + 8)];
+  __shared__ double wsum[2 * kFWaves];
+  const int tiles_x = W / kFT;
+  const int ty0 = (int)(blockIdx.x / tiles_x) * kFT, tx0 = (int)(blockIdx.x % tiles_x) * kFT;
+  // every global read of the block is issued before the first is used: the
+  // 16-byte chunks of the four weight matrices (rows past the last layer's
+  // two outputs are not needed) and the state planes of the region
+  constexpr int C0 = 32 * KP0 / 8, C1 = 32 * KP / 8, C3 = 2 * KP / 8;
+  constexpr int NCH = C0 + 2 * C1 + C3, NCH_T = (NCH + kFWaves * 64 - 1) / (kFWaves * 64);
+  u16x8 wv[NCH_T];
+#pragma unroll
+  for (int u = 0; u < NCH_T; ++u) {
+    int c = (int)threadIdx.x + u * kFWaves * 64;
+    const uint16_t* src = nullptr;
+    if (c < C0) {
+      src = w0 + c * 8;
+    } else if ((c -= C0) < C1) {
+      src = w1 + c * 8;
+    } else if ((c -= C1) < C1) {
+      src = w2 + c * 8;
+    } else if ((c -= C1) < C3) {
+      src = w3 + c * 8;
+    }
+    wv[u] = src ? *reinterpret_cast<const u16x8*>(src) : u16x8{};
+  }
+  constexpr int NPX = kFR * kFR, NPX_T = (NPX + kFWaves * 64 - 1) / (kFWaves * 64);
+  T xv[NPX_T][2];
+#pragma unroll
+  for (int u = 0; u < NPX_T; ++u) {
+    const int q = (int)threadIdx.x + u * kFWaves * 64;
+    const int ry = q / kFR, rx = q - ry * kFR;
+    const int gp = (((ty0 - kFH + ry) & (H - 1)) << lgW) | ((tx0 - kFH + rx) & (W - 1));
+    xv[u][0] = q < NPX ? phi[gp] : T(0);
+    xv[u][1] = q < NPX ? om[gp] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < NCH_T; ++u) {
+    int c = (int)threadIdx.x + u * kFWaves * 64;
+    uint16_t* dst = nullptr;
+    if (c < C0) {
+      dst = wl0 + (c / (KP0 / 8)) * (KP0 + 8) + (c % (KP0 / 8)) * 8;
+    } else if ((c -= C0) < C1) {
+      dst = wl1 + (c / (KP / 8)) * (KP + 8) + (c % (KP / 8)) * 8;
+    } else if ((c -= C1) < C1) {
+      dst = wl2 + (c / (KP / 8)) * (KP + 8) + (c % (KP / 8)) * 8;
+    } else if ((c -= C1) < C3) {
+      dst = wl3 + (c / (KP / 8)) * (KP + 8) + (c % (KP / 8)) * 8;
+    }
+    if (dst) *reinterpret_cast<u16x8*>(dst) = wv[u];
+  }
+#pragma unroll
+  for (int u = 0; u < NPX_T; ++u) {
+    const int q = (int)threadIdx.x + u * kFWaves * 64;
+    if (q < NPX) {
+      in0[2 * q] = f2bf((float)xv[u][0] * s0);
+      in0[2 * q + 1] = f2bf((float)xv[u][1] * s1);
+    }
+  }
+  __syncthreads();
+  double zs = 0.0;
+  fused_layer<2, kFR, false>(in0, buf_a, wl0, params + kOffB[0], nullptr, 0, 0, H, W, lgW, zs);
+  __syncthreads();
+  fused_layer<32, kFR - 2, false>(buf_a, buf_b, wl1, params + kOffB[1], nullptr, 0, 0, H, W,
+                                  lgW, zs);
+  __syncthreads();
+  fused_layer<32, kFR - 4, false>(buf_b, buf_a, wl2, params + kOffB[2], nullptr, 0, 0, H, W,
+                                  lgW, zs);
+  __syncthreads();
+  fused_layer<32, kFR - 6, true>(buf_a, nullptr, wl3, params + kOffB[3], z3, ty0, tx0, H, W,
+                                 lgW, zs);
+  const int lane = threadIdx.x & 63;
+  if ((lane & 31) == 0) wsum[(threadIdx.x >> 6) * 2 + (lane >> 5)] = zs;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < 2 * kFWaves; ++k) t += wsum[k];
+    part[blockIdx.x] = t;
   }
 }
 
@@ -489,9 +637,9 @@ int net_create(Net* n, int H, int W, bool training) {
     rc = rc ? rc : alloc_dev((void**)&n->act[l], P * kCnnCin[l] * 2);
     rc = rc ? rc : alloc_dev((void**)&n->z[l], P * kCnnCout[l] * sizeof(float));
   }
-  // reduction scratch: the corrected step's P/128 per-block partials; the
+  // reduction scratch: the corrected step's P/256 per-tile partials; the
   // loss's 256 partials and its running sum at [1024]
-  const size_t nred = (P / 128 > 2048 ? P / 128 : 2048);
+  const size_t nred = (P / 256 > 2048 ? P / 256 : 2048);
   rc = rc ? rc : alloc_dev((void**)&n->red, nred * sizeof(double));
   if (training) {
     rc = rc ? rc : alloc_dev((void**)&n->grad, kCnnParams * sizeof(float));
@@ -608,19 +756,10 @@ int net_layer_bwd(Net* n, int li, const float* dz, const uint16_t* a_in, const f
 template <typename T>
 int net_correct_fields(Net* n, T* phi, T* omega, hipStream_t st) {
   const int P = n->P;
-  const dim3 g(P / 128), b(256);
-  const int nblk = P / 128;
-  // layer 1 reads the state planes itself; layers 1-3 keep only their
-  // activations; layer 4 leaves per-block sums of the phi residual, which the
-  // update sums for the mean-free correction
-  hipLaunchKernelGGL((k_conv_fwd<2, 32, true, T, true>), g, b, 0, st, nullptr, n->wt[0],
-                     n->params + kOffB[0], nullptr, n->act[1], n->H, n->W, n->lgW, phi, omega,
-                     n->scales[0], n->scales[1], nullptr);
-  launch_fwd(n, 1, n->act[1], nullptr, n->act[2], st);
-  launch_fwd(n, 2, n->act[2], nullptr, n->act[3], st);
-  hipLaunchKernelGGL((k_conv_fwd<32, 2, false, float, false, true>), g, b, 0, st, n->act[3],
-                     n->wt[3], n->params + kOffB[3], n->z[3], nullptr, n->H, n->W, n->lgW,
-                     nullptr, nullptr, 1.f, 1.f, n->red);
+  const int nblk = (n->H / kFT) * (n->W / kFT);
+  hipLaunchKernelGGL((k_net_fused<T>), dim3(nblk), dim3(kFWaves * 64), 0, st, phi, omega,
+                     n->scales[0], n->scales[1], n->wt[0], n->wt[1], n->wt[2], n->wt[3],
+                     n->params, n->z[3], n->red, n->H, n->W, n->lgW);
   hipLaunchKernelGGL((k_apply_correction<T>), dim3(256), dim3(256), 0, st, phi, omega, n->z[3],
                      P, n->scales[2], n->scales[3], n->red, nblk);
   CNN_TRY(hipGetLastError());

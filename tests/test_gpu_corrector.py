@@ -80,6 +80,38 @@ def test_corrected_step_applies_the_network():
     assert np.max(np.abs(d_om - r[1])) <= 2e-2 * np.max(np.abs(r[1]))
 
 
+@pytest.mark.parametrize("n", [64, 256])
+def test_fused_network_equals_the_layer_kernels(fixed_variants, n):
+    """The corrected step runs the network as one tiled kernel (activations in
+    LDS, 4-pixel halos); its residual equals the per-layer kernels' output on
+    the same planes (unit output scales: r = z exactly), up to the FP64 sum
+    order of the mean."""
+    torch = pytest.importorskip("torch")
+    p = configs.model_h(n, n, gdot=0.1, rho=1.0)
+    phi0 = inputs.noise_phi0(n, n, 9, amp=0.6)
+    params = inputs.cnn_init_params(4) * 3.0
+    scales = [1.0, 10.0, 1.0, 1.0]
+    with le.Context(p, phi0) as a, le.Context(p, phi0) as b:
+        a.corrector_load(params, scales)
+        a.step_corrected(1)
+        b.step(1)
+        ga, gb = a.get_state(), b.get_state()
+    net = le.Net(n, n)
+    try:
+        net.set_params(params, scales)
+        x = torch.from_numpy(np.stack([gb["phi"], gb["omega"]]).astype(np.float32)[None]).cuda()
+        r = torch.empty_like(x)
+        net.forward(x, r)
+        torch.cuda.synchronize()
+        r = r.cpu().numpy()[0].astype(np.float64)
+    finally:
+        net.close()
+    d_phi = ga["phi"] - gb["phi"]
+    d_om = ga["omega"] - gb["omega"]
+    assert np.max(np.abs(d_phi - (r[0] - r[0].mean()))) <= 1e-12 * np.max(np.abs(r[0]))
+    assert np.max(np.abs(d_om - r[1])) <= 1e-12 * np.max(np.abs(r[1]))
+
+
 def test_corrector_needs_inertia_and_a_load():
     p = configs.model_h(32, 32, rho=0.0)
     with le.Context(p, inputs.noise_phi0(32, 32, 0)) as c:
