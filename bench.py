@@ -160,14 +160,10 @@ def roofline_of(params, precision, times):
     return dom, rows
 
 
-VARIANT_OF = {"advect": "advect", "mu_source": "mu_source", "column_ch": "column_ch",
-              "column_flow": "column_flow"}
-
-
 def traffic_of(stage, precision, nx, tuning):
-    """HBM bytes per launch of `stage` from the committed rocprofv3 counter record,
-    or None when there is none for this workload, the kernel sources changed
-    since, or the record was taken with another variant of the stage."""
+    """HBM bytes per launch of `stage` from the committed rocprofv3 counter record
+    (one entry per variant of each stage), or None when there is none for this
+    workload or variant, or the kernel sources changed since."""
     import glob
     import hashlib
 
@@ -185,10 +181,10 @@ def traffic_of(stage, precision, nx, tuning):
         h.update(open(p, "rb").read())
     if rec is None or rec["source_hash"] != h.hexdigest()[:16] or stage not in rec["stages"]:
         return None
-    v = VARIANT_OF.get(stage)
-    if v is not None and rec["tuning"][v] != tuning[v]:
+    key = rec.get("variant_key", {}).get(stage)
+    k = rec["stages"][stage].get(str(tuning[key])) if key in tuning else None
+    if k is None:
         return None
-    k = rec["stages"][stage]
     return (k["fetch_kib"] * rec["fetch_factor"] + k["write_kib"] * rec["write_factor"]) * 1024.0
 
 

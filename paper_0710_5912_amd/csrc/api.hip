@@ -866,12 +866,14 @@ int step_corrected(Engine* e, int64_t ncoarse) {
       o.row_c2r(d, 1, r.p.ny, B_OM_S, B_OM_R, B_OM_S, B_OM_R, 1, e->classes[r.cls].row_variant,
                 e->stream);
       int rc = r.tsize == sizeof(double)
-                   ? net_correct_fields<double>(e->net, static_cast<double*>(r.buf[B_PHI]),
-                                                static_cast<double*>(r.buf[B_OM_R]), e->stream)
-                   : net_correct_fields<float>(e->net, static_cast<float*>(r.buf[B_PHI]),
-                                               static_cast<float*>(r.buf[B_OM_R]), e->stream);
+                   ? net_residual<double>(e->net, static_cast<const double*>(r.buf[B_PHI]),
+                                          static_cast<const double*>(r.buf[B_OM_R]), e->stream)
+                   : net_residual<float>(e->net, static_cast<const float*>(r.buf[B_PHI]),
+                                         static_cast<const float*>(r.buf[B_OM_R]), e->stream);
       if (rc) return (int)LE_EDEVICE;
-      o.row_r2c(d, 1, r.p.ny, B_OM_R, B_OM_S, e->classes[r.cls].row_variant, e->stream);
+      const CorrArgs ca{net_z_out(e->net), net_partials(e->net), net_tiles(e->net),
+                        e->net->scales[2], e->net->scales[3]};
+      o.row_r2c_corr(d, r.p.ny, ca, e->classes[r.cls].row_variant, e->stream);
       o.column(COL_POISSON, d, 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0, e->stream);
       return (int)LE_OK;
     }));

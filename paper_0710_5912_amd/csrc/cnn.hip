@@ -466,32 +466,6 @@ __global__ void k_unpack_out(const float* __restrict__ z4, int P, float s2, floa
   }
 }
 
-// phi += s2 (z4_phi - mean(z4_phi)); omega += s3 z4_omega.  Every block
-// first sums the nblk per-block partials of z4_phi itself, in one fixed
-// order, so all blocks use the same mean without a separate launch.
-template <typename T>
-__global__ __launch_bounds__(256) void k_apply_correction(T* __restrict__ phi,
-                                                          T* __restrict__ om,
-                                                          const float* __restrict__ z4, int P,
-                                                          float s2, float s3,
-                                                          const double* __restrict__ part,
-                                                          int nblk) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += 256) s += part[k];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int h = 128; h >= 1; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  const double mean = red[0] / (double)P;
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
-    phi[p] = (T)((double)phi[p] + (double)s2 * ((double)z4[2 * (size_t)p] - mean));
-    om[p] = (T)((double)om[p] + (double)s3 * (double)z4[2 * (size_t)p + 1]);
-  }
-}
-
 // BF16 GEMM operands of every layer from the FP32 master weights.
 __global__ void k_pack_weights(const float* __restrict__ params, uint16_t* wt0, uint16_t* wt1,
                                uint16_t* wt2, uint16_t* wt3, uint16_t* wx1, uint16_t* wx2,
@@ -753,20 +727,18 @@ int net_layer_bwd(Net* n, int li, const float* dz, const uint16_t* a_in, const f
   return 0;
 }
 
+int net_tiles(const Net* n) { return (n->H / kFT) * (n->W / kFT); }
+
 template <typename T>
-int net_correct_fields(Net* n, T* phi, T* omega, hipStream_t st) {
-  const int P = n->P;
-  const int nblk = (n->H / kFT) * (n->W / kFT);
-  hipLaunchKernelGGL((k_net_fused<T>), dim3(nblk), dim3(kFWaves * 64), 0, st, phi, omega,
+int net_residual(Net* n, const T* phi, const T* omega, hipStream_t st) {
+  hipLaunchKernelGGL((k_net_fused<T>), dim3(net_tiles(n)), dim3(kFWaves * 64), 0, st, phi, omega,
                      n->scales[0], n->scales[1], n->wt[0], n->wt[1], n->wt[2], n->wt[3],
                      n->params, n->z[3], n->red, n->H, n->W, n->lgW);
-  hipLaunchKernelGGL((k_apply_correction<T>), dim3(256), dim3(256), 0, st, phi, omega, n->z[3],
-                     P, n->scales[2], n->scales[3], n->red, nblk);
   CNN_TRY(hipGetLastError());
   return 0;
 }
-template int net_correct_fields<double>(Net*, double*, double*, hipStream_t);
-template int net_correct_fields<float>(Net*, float*, float*, hipStream_t);
+template int net_residual<double>(Net*, const double*, const double*, hipStream_t);
+template int net_residual<float>(Net*, const float*, const float*, hipStream_t);
 
 int mfma_probe(const uint16_t* a, const uint16_t* b, float* c, hipStream_t st) {
   uint16_t *da = nullptr, *db = nullptr;

@@ -58,11 +58,15 @@ int net_layer_fwd(Net* n, int li, const uint16_t* a_in, float* z_out, uint16_t* 
 int net_layer_bwd(Net* n, int li, const float* dz, const uint16_t* a_in, const float* zprev,
                   float* dzprev, float* dw, hipStream_t st);
 
-// Inference on the engine's fields: build the BF16 input from phi/omega
-// (storage T, real planes), run the net, and add the residual in place:
-// phi += r_phi - mean(r_phi), omega += r_omega.
+// Inference on the engine's fields (storage T, real planes): the network's
+// output z ([P][2] FP32) into z_out() and the per-tile FP64 sums of z_phi
+// (net_tiles() of them) into partials(); the update itself,
+// phi += s2 (z_phi - mean) and omega += s3 z_omega, is left to the caller.
 template <typename T>
-int net_correct_fields(Net* n, T* phi, T* omega, hipStream_t st);
+int net_residual(Net* n, const T* phi, const T* omega, hipStream_t st);
+int net_tiles(const Net* n);
+inline const float* net_z_out(const Net* n) { return n->z[3]; }
+inline const double* net_partials(const Net* n) { return n->red; }
 
 // One 32x32x16 MFMA on a single wave: c = a (32x16) b (16x32), all row-major,
 // BF16 bit patterns in, FP32 out (lane-layout check).

@@ -11,10 +11,22 @@
 
 namespace le {
 
+// The corrected step's update (row_r2c_corr): network output z ([pixel][2]
+// FP32), nblk per-tile FP64 partial sums of z_phi, output scales.
+struct CorrArgs {
+  const float* z;
+  const double* part;
+  int nblk;
+  float s2, s3;
+};
+
 struct Ops {
   // row transforms; variant (a tuning choice): 0 = 8 values per thread, 1 = 4
   void (*row_r2c)(const Run* runs, int nruns, int ny, int bin, int bout, int variant,
                   hipStream_t st);
+  // one run: the corrected step's update of phi and omega from the network
+  // output and the forward row transform of omega (B_OM_R -> B_OM_S)
+  void (*row_r2c_corr)(const Run* runs, int ny, const CorrArgs& ca, int variant, hipStream_t st);
   // inverse row transforms: bin0 -> bout0 and, when nfields == 2, bin1 -> bout1
   void (*row_c2r)(const Run* runs, int nruns, int ny, int bin0, int bout0, int bin1, int bout1,
                   int nfields, int variant, hipStream_t st);

@@ -48,6 +48,20 @@ struct RowLaunch {
     R2cJobs jobs{{{bin, bout, 2 * L}, {}, {}}};
     r2c_jobs(runs, nruns, ny, jobs, 1, variant, st);
   }
+  template <int E, int GD>
+  static void r2c_corr_shape(const Run* runs, int ny, const CorrArgs& ca, hipStream_t st) {
+    using CE = RowCfg<L, E, GD>;
+    hipLaunchKernelGGL((k_row_r2c_corr<T, L, E, GD>), dim3((ny + CE::G - 1) / CE::G),
+                       dim3(CE::THREADS), 0, st, runs, ca);
+  }
+  static void r2c_corr(const Run* runs, int ny, const CorrArgs& ca, int variant, hipStream_t st) {
+    switch (variant) {
+      case 1: r2c_corr_shape<E4, 1>(runs, ny, ca, st); break;
+      case 2: r2c_corr_shape<row_elems(L), 4>(runs, ny, ca, st); break;
+      case 3: r2c_corr_shape<E4, 4>(runs, ny, ca, st); break;
+      default: r2c_corr_shape<row_elems(L), 1>(runs, ny, ca, st); break;
+    }
+  }
   static void c2r(const Run* runs, int nruns, int ny, int bin0, int bout0, int bin1, int bout1,
                   int nfields, int variant, hipStream_t st) {
     switch (variant) {
@@ -184,6 +198,7 @@ struct Misc {
 template <typename T, int L>
 void set_row(Ops* o) {
   o->row_r2c = &RowLaunch<T, L>::r2c;
+  o->row_r2c_corr = &RowLaunch<T, L>::r2c_corr;
   o->row_c2r = &RowLaunch<T, L>::c2r;
   o->advect = &RowLaunch<T, L>::advect;
   o->mu_source = &RowLaunch<T, L>::mu_source;

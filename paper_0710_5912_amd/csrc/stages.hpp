@@ -14,6 +14,7 @@
 
 #include "common.hpp"
 #include "fft.hpp"
+#include "ops.hpp"
 
 namespace le {
 
@@ -211,6 +212,58 @@ __global__ __launch_bounds__((RowCfg<L, E, GDIV>::THREADS)) LE_OCCUPANCY void k_
   c2<T> v[C::E];
 #pragma unroll
   for (int q = 0; q < C::E; ++q) v[q] = ldg<T>(xr + t + q * C::P);
+  row_r2c<T, L, C::E>(v, lds + g * L, tw, t);
+  if (ok) store_row_spec<T, L, C::E>(X + (size_t)j * (L + 1), v, t);
+}
+
+// The corrected step's update and the vorticity's forward row transform in
+// one pass (one run): phi += s2 (z_phi - mean), omega += s3 z_omega with z
+// the network output ([pixel][2] FP32) and mean = (sum of the nblk per-tile
+// partials of z_phi) / (nx ny), formed by every block in the same fixed
+// order; the corrected real rows are stored and omega's row spectrum is
+// written to B_OM_S.
+template <typename T, int L, int E = row_elems(L), int GDIV = 1>
+__global__ __launch_bounds__((RowCfg<L, E, GDIV>::THREADS)) LE_OCCUPANCY void k_row_r2c_corr(
+    const Run* __restrict__ runs, CorrArgs ca) {
+  using C = RowCfg<L, E, GDIV>;
+  __shared__ c2<T> lds[C::G * L];
+  __shared__ double red[C::THREADS];
+  const Run& R = runs[0];
+  const int ny = R.g.ny;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < ca.nblk; k += C::THREADS) acc += ca.part[k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = C::THREADS / 2; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double mean = red[0] / ((double)ny * (double)(2 * L));
+  auto phi = reinterpret_cast<gp<c2<T>>>(bufp<T>(R, B_PHI));
+  auto om = reinterpret_cast<gp<c2<T>>>(bufp<T>(R, B_OM_R));
+  auto X = bufp<c2<T>>(R, B_OM_S);
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  auto zz = to_global<const f32x4>(reinterpret_cast<const f32x4*>(ca.z));
+  auto tw = to_global<const c2<double>>(R.twx);
+  const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
+  const int j = blockIdx.x * C::G + g;
+  const bool ok = j < ny;
+  const size_t row = (size_t)(ok ? j : 0) * L;
+  c2<T> v[C::E];
+#pragma unroll
+  for (int q = 0; q < C::E; ++q) {
+    const size_t m = row + t + q * C::P;  // the pair (2m, 2m + 1) of the field
+    const f32x4 zq = zz[m];               // z_phi, z_omega of both points
+    const c2<T> f = ldg<T>(phi + m), w = ldg<T>(om + m);
+    const c2<T> fn = {(T)((double)f.x + (double)ca.s2 * ((double)zq.x - mean)),
+                      (T)((double)f.y + (double)ca.s2 * ((double)zq.z - mean))};
+    v[q] = {(T)((double)w.x + (double)ca.s3 * (double)zq.y),
+            (T)((double)w.y + (double)ca.s3 * (double)zq.w)};
+    if (ok) {
+      stg<T>(phi + m, fn);
+      stg<T>(om + m, v[q]);
+    }
+  }
   row_r2c<T, L, C::E>(v, lds + g * L, tw, t);
   if (ok) store_row_spec<T, L, C::E>(X + (size_t)j * (L + 1), v, t);
 }
