@@ -475,7 +475,8 @@ int observables_of(Engine* e, const RunHost& r, le_obs* o, double* Sk, int32_t s
 namespace {
 
 constexpr int kRowCand[] = {0, 1, 2, 3};
-constexpr int kAdvCand[] = {0, 2, 4, 8, 16, 32};
+constexpr int kAdvCand[] = {0,  2,  4,  8,  16, 32, kStripFft + 2, kStripFft + 4,
+                             kStripFft + 8};
 constexpr int kMuCand[] = {0, 2, 4, 8, 16, 32};
 constexpr int kColCand[] = {0, 1, 2, 3};
 

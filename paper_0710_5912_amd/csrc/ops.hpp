@@ -20,6 +20,10 @@ struct CorrArgs {
   float s2, s3;
 };
 
+// Advect variants from kStripFft on: kStripFft + k = the strip stencil over
+// k-row strips with the row transforms in the same kernel.
+constexpr int kStripFft = 64;
+
 struct Ops {
   // row transforms; variant (a tuning choice): 0 = 8 values per thread, 1 = 4
   void (*row_r2c)(const Run* runs, int nruns, int ny, int bin, int bout, int variant,
@@ -31,8 +35,9 @@ struct Ops {
   void (*row_c2r)(const Run* runs, int nruns, int ny, int bin0, int bout0, int bin1, int bout1,
                   int nfields, int variant, hipStream_t st);
   // stage 1a + forward row transforms (omega parts only when inertial);
-  // variant: 0 fused, k > 0 strip stencil over k-row strips + in-place
-  // transforms
+  // variant: 0 fused, 0 < k < kStripFft strip stencil over k-row strips +
+  // in-place transforms, kStripFft + k the same strips with the transforms
+  // in one kernel
   void (*advect)(const Run* runs, int nruns, int ny, const StepArgs* sa, bool inertial,
                  int variant, int row_variant, hipStream_t st);
   // stage 2a + forward row transform of g; variant: 0 two kernels through

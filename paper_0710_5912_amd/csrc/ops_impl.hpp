@@ -86,8 +86,10 @@ struct RowLaunch {
                          st, runs, sa, jobs);
   }
   // variant 0: the fused bracket kernel (stencil and row transform per
-  // block); variant k > 0: the strip stencil over k-row strips into the
-  // spectral buffers, then in-place row transforms
+  // block); variant 0 < k < kStripFft: the strip stencil over k-row strips
+  // into the spectral buffers, then in-place row transforms; variant
+  // kStripFft + k: strip stencil and row transforms in one kernel over
+  // k-row strips (nx 256 .. 2048; elsewhere the two-kernel form)
   static void advect(const Run* runs, int nruns, int ny, const StepArgs* sa, bool inertial,
                      int variant, int row_variant, hipStream_t st) {
     if (variant <= 0) {
@@ -98,6 +100,20 @@ struct RowLaunch {
       return;
     }
     constexpr int NX = 2 * L, TPB = strip_threads(NX);
+    if (variant >= kStripFft) {
+      const int rows = variant - kStripFft;
+      if constexpr (strip_fft_ok(NX)) {
+        const dim3 gf(1, (ny + rows - 1) / rows, nruns);
+        if (ny == NX)
+          hipLaunchKernelGGL((k_adv_strip_fft<T, NX, true>), gf, dim3(NX / 4), 0, st, runs, sa,
+                             rows, inertial ? 1 : 0);
+        else
+          hipLaunchKernelGGL((k_adv_strip_fft<T, NX, false>), gf, dim3(NX / 4), 0, st, runs,
+                             sa, rows, inertial ? 1 : 0);
+        return;
+      }
+      variant = rows;  // grids outside the fused kernel's range: the two-kernel form
+    }
     const dim3 gs(NX / 2 / TPB, (ny + variant - 1) / variant, nruns);
     if (ny == NX)
       hipLaunchKernelGGL((k_adv_strip<T, NX, true>), gs, dim3(TPB), 0, st, runs, sa, variant,

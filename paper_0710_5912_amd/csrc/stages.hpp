@@ -507,9 +507,9 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_bracket(
 // step (row j+2, requested a step ahead).
 constexpr int strip_threads(int nx) { return nx / 2 < 256 ? nx / 2 : 256; }
 
-template <typename T, int NX>
+template <typename T, int NX, int TPB_ = strip_threads(NX)>
 struct StripLanes {
-  static constexpr int TPB = strip_threads(NX);
+  static constexpr int TPB = TPB_;
   int x, xl, xr;  // pair position; halo positions of the lane's run
   bool edge_l, edge_r;
   __device__ __forceinline__ StripLanes(int bx) {
@@ -531,17 +531,17 @@ struct RawQuad {
   c2<T> p;
   T h;
 };
-template <typename T, int NX>
+template <typename T, int NX, int TPB>
 __device__ __forceinline__ RawQuad<T> load_raw(gp<const T> __restrict__ row,
-                                               const StripLanes<T, NX>& sl) {
+                                               const StripLanes<T, NX, TPB>& sl) {
   RawQuad<T> r;
   r.p = ldg<T>(reinterpret_cast<gp<const c2<T>>>(row + sl.x));
   r.h = row[(sl.edge_r ? sl.xr : sl.xl) & (NX - 1)];
   return r;
 }
 // Every lane of the wavefront must execute this (DPP).
-template <typename T, int NX>
-__device__ __forceinline__ Quad<T> to_quad(const RawQuad<T>& r, const StripLanes<T, NX>& sl) {
+template <typename T, int NX, int TPB>
+__device__ __forceinline__ Quad<T> to_quad(const RawQuad<T>& r, const StripLanes<T, NX, TPB>& sl) {
   const T nl = dpp_mov<kDppWaveShr1>(r.p.y);
   const T nr = dpp_mov<kDppWaveShl1>(r.p.x);
   return {sl.edge_l ? r.h : nl, r.p.x, r.p.y, sl.edge_r ? r.h : nr};
@@ -607,6 +607,103 @@ __global__ __launch_bounds__(strip_threads(NX)) void k_adv_strip(
     Fm = Fc; Fc = Fp;
     Sm = Sc; Sc = Sp;
     Wm = Wc; Wc = Wp;
+  }
+}
+
+// Stage 1a over row strips with the forward row transforms in the same
+// kernel (no real rows written and read back).  The block owns whole rows:
+// NX/4 threads, thread t the x pairs t and t + NX/4, each walked down the
+// strip as in k_adv_strip.  Each output row goes through LDS to four groups
+// of NX/16 threads (8 values each); groups 0, 1, 2 transform phi_h, f and
+// omega_h and store their row spectra (group 3, and group 2 without
+// inertia, transform nothing useful and store nothing).
+constexpr bool strip_fft_ok(int nx) { return nx >= 256 && nx <= 2048; }
+
+template <typename T, int NX, bool R1>
+__global__ __launch_bounds__(NX / 4) void k_adv_strip_fft(const Run* __restrict__ runs,
+                                                         const StepArgs* __restrict__ sa,
+                                                         int rows, int inertial) {
+  constexpr int L = NX / 2, TPB = NX / 4, EF = 8, PF = L / EF;
+  static_assert(TPB == 4 * PF && TPB >= 64, "four transform groups of whole wavefronts");
+  __shared__ c2<T> buf[4 * L];
+  const BPos bp = block_pos();
+  const Run& R = runs[bp.z];
+  const Geo& geo = R.g;
+  const int ny = geo.ny;
+  const StripLanes<T, NX, TPB> sl0(0), sl1(1);
+  const int j0 = bp.y * rows;
+  const int j1 = min(j0 + rows, ny);
+  auto phi = bufp<const T>(R, B_PHI);
+  auto psi = bufp<const T>(R, B_PS_R);
+  auto om = bufp<const T>(R, B_OM_R);
+  auto tw = to_global<const c2<double>>(R.twx);
+  const Stencil<T> st = make_stencil<T>(geo, sa[bp.z].s);
+  const T dt = T(geo.dt);
+  const bool inr = inertial != 0;
+  const int grp = threadIdx.x / PF, tt = threadIdx.x % PF;
+  auto out = bufp<c2<T>>(R, grp == 0 ? B_PHIH : (grp == 1 ? B_FH : B_OMH));
+  const bool store = grp < (inr ? 3 : 2);
+  auto row = [&](gp<const T> f, int j) {
+    return f + (size_t)(j < 0 ? j + ny : (j >= ny ? j - ny : j)) * NX;
+  };
+  // rolling quads of rows j-1 (m), j (c) and the raw row j+1, per x segment
+  Quad<T> Fm[2], Fc[2], Sm[2], Sc[2], Wm[2], Wc[2];
+  RawQuad<T> rF[2], rS[2], rW[2];
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const StripLanes<T, NX, TPB>& sl = g ? sl1 : sl0;
+    Fm[g] = to_quad(load_raw(row(phi, j0 - 1), sl), sl);
+    Fc[g] = to_quad(load_raw(row(phi, j0), sl), sl);
+    Sm[g] = to_quad(load_raw(row(psi, j0 - 1), sl), sl);
+    Sc[g] = to_quad(load_raw(row(psi, j0), sl), sl);
+    Wm[g] = Fm[g];
+    Wc[g] = Fc[g];
+    if (inr) {
+      Wm[g] = to_quad(load_raw(row(om, j0 - 1), sl), sl);
+      Wc[g] = to_quad(load_raw(row(om, j0), sl), sl);
+    }
+    rF[g] = load_raw(row(phi, j0 + 1), sl);
+    rS[g] = load_raw(row(psi, j0 + 1), sl);
+    rW[g] = inr ? load_raw(row(om, j0 + 1), sl) : rF[g];
+  }
+  for (int j = j0; j < j1; ++j) {
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const StripLanes<T, NX, TPB>& sl = g ? sl1 : sl0;
+      const Quad<T> Fp = to_quad(rF[g], sl);
+      const Quad<T> Sp = to_quad(rS[g], sl);
+      const Quad<T> Wp = inr ? to_quad(rW[g], sl) : Fp;
+      if (j + 1 < j1) {  // row j+2, a step ahead
+        rF[g] = load_raw(row(phi, j + 2), sl);
+        rS[g] = load_raw(row(psi, j + 2), sl);
+        if (inr) rW[g] = load_raw(row(om, j + 2), sl);
+      }
+      T sx0, sx1, sy0, sy1, ax0, ax1, ay0, ay1;
+      quad_dx(Sc[g], st.inv2dx, sx0, sx1);
+      quad_dys<T, NX, R1>(Sp, Sm[g], row(psi, j + 1), row(psi, j - 1), sl.x, st, sy0, sy1);
+      quad_dx(Fc[g], st.inv2dx, ax0, ax1);
+      quad_dys<T, NX, R1>(Fp, Fm[g], row(phi, j + 1), row(phi, j - 1), sl.x, st, ay0, ay1);
+      const int pr = sl.x / 2;
+      buf[pr] = {Fc[g].a0 - dt * (ax0 * sy0 - ay0 * sx0), Fc[g].a1 - dt * (ax1 * sy1 - ay1 * sx1)};
+      buf[L + pr] = {Fc[g].a0 * Fc[g].a0 * Fc[g].a0, Fc[g].a1 * Fc[g].a1 * Fc[g].a1};
+      if (inr) {
+        quad_dx(Wc[g], st.inv2dx, ax0, ax1);
+        quad_dys<T, NX, R1>(Wp, Wm[g], row(om, j + 1), row(om, j - 1), sl.x, st, ay0, ay1);
+        buf[2 * L + pr] = {Wc[g].a0 - dt * (ax0 * sy0 - ay0 * sx0),
+                           Wc[g].a1 - dt * (ax1 * sy1 - ay1 * sx1)};
+      }
+      Fm[g] = Fc[g]; Fc[g] = Fp;
+      Sm[g] = Sc[g]; Sc[g] = Sp;
+      Wm[g] = Wc[g]; Wc[g] = Wp;
+    }
+    __syncthreads();
+    c2<T> v[EF];
+#pragma unroll
+    for (int q = 0; q < EF; ++q) v[q] = buf[grp * L + tt + q * PF];
+    __syncthreads();
+    row_r2c<T, L, EF>(v, buf + grp * L, tw, tt);
+    if (store) store_row_spec<T, L, EF>(out + (size_t)j * (L + 1), v, tt);
+    __syncthreads();
   }
 }
 

@@ -20,8 +20,9 @@ le = pytest.importorskip("paper_0710_5912_amd.le")
 
 KEYS = ("LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH", "LE_TUNE_COL_FLOW", "LE_TUNE_ROW")
 # (advect, mu_source, column_ch, column_flow, row)
+# advect 64 + k: strip stencil and row transforms in one kernel (k-row strips)
 COMBOS = [(0, 0, 0, 0, 0), (4, 4, 1, 1, 1), (32, 32, 2, 2, 2), (8, 16, 3, 3, 3),
-          (2, 2, 0, 0, 1)]
+          (2, 2, 0, 0, 1), (66, 4, 0, 1, 2), (72, 8, 2, 0, 0)]
 
 
 def params(nx, ny, **kw):
@@ -72,7 +73,7 @@ def test_variants_512_fp64(monkeypatch, combo, rho):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
 
 
-@pytest.mark.parametrize("combo", [(4, 4, 1, 3, 1), (32, 8, 3, 2, 3)])
+@pytest.mark.parametrize("combo", [(4, 4, 1, 3, 1), (32, 8, 3, 2, 3), (68, 4, 0, 0, 1)])
 def test_variants_512_fp32(monkeypatch, combo):
     """FP32 shapes (16 values per thread in shapes 2 and 3) within the FP32 bound."""
     p = params(512, 512)
@@ -81,7 +82,8 @@ def test_variants_512_fp32(monkeypatch, combo):
     assert rel(g["psi"], st.psi) <= 2e-4
 
 
-@pytest.mark.parametrize("combo", [(4, 4, 0, 2, 1), (16, 32, 3, 0, 2), (2, 2, 2, 1, 3)])
+@pytest.mark.parametrize("combo", [(4, 4, 0, 2, 1), (16, 32, 3, 0, 2), (2, 2, 2, 1, 3),
+                                   (68, 4, 0, 0, 0)])
 def test_strip_variants_across_a_wrap(monkeypatch, combo):
     """64^2, gdot = 0.5: the strain wraps at step 200; 220 steps."""
     p = params(64, 64, gdot=0.5)
@@ -91,11 +93,12 @@ def test_strip_variants_across_a_wrap(monkeypatch, combo):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
 
 
-def test_strip_variants_non_square_cells(monkeypatch):
+@pytest.mark.parametrize("combo", [(8, 8, 2, 3, 3), (66, 8, 0, 1, 0)])
+def test_strip_variants_non_square_cells(monkeypatch, combo):
     """nx = 4 ny (r = 4): the strip advect reads the diagonal pairs; the mu
     strip applies to square cells only and falls back."""
     p = params(256, 64, gdot=0.2, lx=256.0, ly=64.0)
-    g, st = run_forced(monkeypatch, p, 20, 24, (8, 8, 2, 3, 3))
+    g, st = run_forced(monkeypatch, p, 20, 24, combo)
     for k in ("phi", "omega", "psi"):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
 
@@ -107,7 +110,8 @@ def test_autotuner_reports_valid_choices():
     assert len(t) == 1
     t = t[0]
     assert (t["nx"], t["ny"], t["precision"], t["inertial"]) == (256, 256, 0, 1)
-    assert t["advect"] in (0, 2, 4, 8, 16, 32) and t["mu_source"] in (0, 2, 4, 8, 16, 32)
+    assert t["advect"] in (0, 2, 4, 8, 16, 32, 66, 68, 72)
+    assert t["mu_source"] in (0, 2, 4, 8, 16, 32)
     assert t["column_ch"] in range(4) and t["column_flow"] in range(4) and t["row"] in range(4)
 
 
