@@ -21,8 +21,9 @@ struct CorrArgs {
 };
 
 // Advect variants from kStripFft on: kStripFft + k = the strip stencil over
-// k-row strips with the row transforms in the same kernel.
-constexpr int kStripFft = 64;
+// k-row strips with the row transforms in the same kernel, two x pairs per
+// thread; kStripFft1 + k the same with one pair per thread.
+constexpr int kStripFft = 64, kStripFft1 = 96;
 
 struct Ops {
   // row transforms; variant (a tuning choice): 0 = 8 values per thread, 1 = 4

@@ -85,11 +85,23 @@ struct RowLaunch {
       hipLaunchKernelGGL((k_bracket<T, L, false>), grid(ny, njobs, nruns), dim3(C::THREADS), 0,
                          st, runs, sa, jobs);
   }
+  template <int SEG>
+  static void strip_fft(const Run* runs, const StepArgs* sa, int ny, dim3 gf, int rows,
+                        bool inertial, hipStream_t st) {
+    constexpr int NX = 2 * L;
+    if (ny == NX)
+      hipLaunchKernelGGL((k_adv_strip_fft<T, NX, true, SEG>), gf, dim3(L / SEG), 0, st, runs,
+                         sa, rows, inertial ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_adv_strip_fft<T, NX, false, SEG>), gf, dim3(L / SEG), 0, st, runs,
+                         sa, rows, inertial ? 1 : 0);
+  }
   // variant 0: the fused bracket kernel (stencil and row transform per
   // block); variant 0 < k < kStripFft: the strip stencil over k-row strips
   // into the spectral buffers, then in-place row transforms; variant
-  // kStripFft + k: strip stencil and row transforms in one kernel over
-  // k-row strips (nx 256 .. 2048; elsewhere the two-kernel form)
+  // kStripFft + k (two x pairs per thread) and kStripFft1 + k (one): strip
+  // stencil and row transforms in one kernel over k-row strips (nx 256 ..
+  // 2048; elsewhere the two-kernel form)
   static void advect(const Run* runs, int nruns, int ny, const StepArgs* sa, bool inertial,
                      int variant, int row_variant, hipStream_t st) {
     if (variant <= 0) {
@@ -101,15 +113,14 @@ struct RowLaunch {
     }
     constexpr int NX = 2 * L, TPB = strip_threads(NX);
     if (variant >= kStripFft) {
-      const int rows = variant - kStripFft;
+      const bool two = variant < kStripFft1;
+      const int rows = variant - (two ? kStripFft : kStripFft1);
       if constexpr (strip_fft_ok(NX)) {
         const dim3 gf(1, (ny + rows - 1) / rows, nruns);
-        if (ny == NX)
-          hipLaunchKernelGGL((k_adv_strip_fft<T, NX, true>), gf, dim3(NX / 4), 0, st, runs, sa,
-                             rows, inertial ? 1 : 0);
+        if (two)
+          strip_fft<2>(runs, sa, ny, gf, rows, inertial, st);
         else
-          hipLaunchKernelGGL((k_adv_strip_fft<T, NX, false>), gf, dim3(NX / 4), 0, st, runs,
-                             sa, rows, inertial ? 1 : 0);
+          strip_fft<1>(runs, sa, ny, gf, rows, inertial, st);
         return;
       }
       variant = rows;  // grids outside the fused kernel's range: the two-kernel form

@@ -612,25 +612,27 @@ __global__ __launch_bounds__(strip_threads(NX)) void k_adv_strip(
 
 // Stage 1a over row strips with the forward row transforms in the same
 // kernel (no real rows written and read back).  The block owns whole rows:
-// NX/4 threads, thread t the x pairs t and t + NX/4, each walked down the
-// strip as in k_adv_strip.  Each output row goes through LDS to four groups
-// of NX/16 threads (8 values each); groups 0, 1, 2 transform phi_h, f and
-// omega_h and store their row spectra (group 3, and group 2 without
-// inertia, transform nothing useful and store nothing).
+// NX/(2 SEG) threads, thread t the SEG x pairs t + g NX/(2 SEG), each walked
+// down the strip as in k_adv_strip.  Each output row goes through LDS to
+// four groups of threads (4 SEG values each); groups 0, 1, 2 transform
+// phi_h, f and omega_h and store their row spectra (group 3, and group 2
+// without inertia, transform nothing useful and store nothing).  SEG = 2
+// halves the threads and doubles each one's registers.
 constexpr bool strip_fft_ok(int nx) { return nx >= 256 && nx <= 2048; }
 
-template <typename T, int NX, bool R1>
-__global__ __launch_bounds__(NX / 4) void k_adv_strip_fft(const Run* __restrict__ runs,
-                                                         const StepArgs* __restrict__ sa,
-                                                         int rows, int inertial) {
-  constexpr int L = NX / 2, TPB = NX / 4, EF = 8, PF = L / EF;
-  static_assert(TPB == 4 * PF && TPB >= 64, "four transform groups of whole wavefronts");
+template <typename T, int NX, bool R1, int SEG>
+__global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __restrict__ runs,
+                                                               const StepArgs* __restrict__ sa,
+                                                               int rows, int inertial) {
+  constexpr int L = NX / 2, TPB = L / SEG, EF = 4 * SEG, PF = L / EF;
+  static_assert(TPB == 4 * PF && TPB >= 64, "four transform groups, whole wavefronts");
   __shared__ c2<T> buf[4 * L];
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
   const Geo& geo = R.g;
   const int ny = geo.ny;
-  const StripLanes<T, NX, TPB> sl0(0), sl1(1);
+  static_assert(SEG == 1 || SEG == 2, "one or two x pairs per thread");
+  const StripLanes<T, NX, TPB> sl0(0), sl1(SEG - 1);
   const int j0 = bp.y * rows;
   const int j1 = min(j0 + rows, ny);
   auto phi = bufp<const T>(R, B_PHI);
@@ -647,10 +649,10 @@ __global__ __launch_bounds__(NX / 4) void k_adv_strip_fft(const Run* __restrict_
     return f + (size_t)(j < 0 ? j + ny : (j >= ny ? j - ny : j)) * NX;
   };
   // rolling quads of rows j-1 (m), j (c) and the raw row j+1, per x segment
-  Quad<T> Fm[2], Fc[2], Sm[2], Sc[2], Wm[2], Wc[2];
-  RawQuad<T> rF[2], rS[2], rW[2];
+  Quad<T> Fm[SEG], Fc[SEG], Sm[SEG], Sc[SEG], Wm[SEG], Wc[SEG];
+  RawQuad<T> rF[SEG], rS[SEG], rW[SEG];
 #pragma unroll
-  for (int g = 0; g < 2; ++g) {
+  for (int g = 0; g < SEG; ++g) {
     const StripLanes<T, NX, TPB>& sl = g ? sl1 : sl0;
     Fm[g] = to_quad(load_raw(row(phi, j0 - 1), sl), sl);
     Fc[g] = to_quad(load_raw(row(phi, j0), sl), sl);
@@ -668,7 +670,7 @@ __global__ __launch_bounds__(NX / 4) void k_adv_strip_fft(const Run* __restrict_
   }
   for (int j = j0; j < j1; ++j) {
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < SEG; ++g) {
       const StripLanes<T, NX, TPB>& sl = g ? sl1 : sl0;
       const Quad<T> Fp = to_quad(rF[g], sl);
       const Quad<T> Sp = to_quad(rS[g], sl);

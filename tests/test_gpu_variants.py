@@ -20,9 +20,10 @@ le = pytest.importorskip("paper_0710_5912_amd.le")
 
 KEYS = ("LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH", "LE_TUNE_COL_FLOW", "LE_TUNE_ROW")
 # (advect, mu_source, column_ch, column_flow, row)
-# advect 64 + k: strip stencil and row transforms in one kernel (k-row strips)
+# advect 64 + k / 96 + k: strip stencil and row transforms in one kernel
+# (k-row strips, two / one x pairs per thread)
 COMBOS = [(0, 0, 0, 0, 0), (4, 4, 1, 1, 1), (32, 32, 2, 2, 2), (8, 16, 3, 3, 3),
-          (2, 2, 0, 0, 1), (66, 4, 0, 1, 2), (72, 8, 2, 0, 0)]
+          (2, 2, 0, 0, 1), (66, 4, 0, 1, 2), (72, 8, 2, 0, 0), (100, 2, 1, 3, 0)]
 
 
 def params(nx, ny, **kw):
@@ -73,7 +74,8 @@ def test_variants_512_fp64(monkeypatch, combo, rho):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
 
 
-@pytest.mark.parametrize("combo", [(4, 4, 1, 3, 1), (32, 8, 3, 2, 3), (68, 4, 0, 0, 1)])
+@pytest.mark.parametrize("combo", [(4, 4, 1, 3, 1), (32, 8, 3, 2, 3), (68, 4, 0, 0, 1),
+                                   (98, 8, 2, 1, 2)])
 def test_variants_512_fp32(monkeypatch, combo):
     """FP32 shapes (16 values per thread in shapes 2 and 3) within the FP32 bound."""
     p = params(512, 512)
@@ -93,7 +95,7 @@ def test_strip_variants_across_a_wrap(monkeypatch, combo):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
 
 
-@pytest.mark.parametrize("combo", [(8, 8, 2, 3, 3), (66, 8, 0, 1, 0)])
+@pytest.mark.parametrize("combo", [(8, 8, 2, 3, 3), (66, 8, 0, 1, 0), (104, 4, 1, 0, 1)])
 def test_strip_variants_non_square_cells(monkeypatch, combo):
     """nx = 4 ny (r = 4): the strip advect reads the diagonal pairs; the mu
     strip applies to square cells only and falls back."""
@@ -110,7 +112,7 @@ def test_autotuner_reports_valid_choices():
     assert len(t) == 1
     t = t[0]
     assert (t["nx"], t["ny"], t["precision"], t["inertial"]) == (256, 256, 0, 1)
-    assert t["advect"] in (0, 2, 4, 8, 16, 32, 66, 68, 72)
+    assert t["advect"] in (0, 2, 4, 8, 16, 32, 66, 68, 72, 98, 100, 104)
     assert t["mu_source"] in (0, 2, 4, 8, 16, 32)
     assert t["column_ch"] in range(4) and t["column_flow"] in range(4) and t["row"] in range(4)
 
