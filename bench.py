@@ -93,7 +93,10 @@ def step_bytes(params, precision):
 
 def stage_kernels(tuning, inertial):
     """Kernels each stage launches under the autotuned variants."""
-    adv = ("k_bracket" if tuning["advect"] == 0 else "k_adv_strip + k_row_r2c")
+    a = tuning["advect"]
+    fused_strip = a >= 64 and 256 <= tuning["nx"] <= 2048
+    adv = ("k_bracket" if a == 0 else
+           ("k_adv_strip_fft" if fused_strip else "k_adv_strip + k_row_r2c"))
     sq = tuning["nx"] == tuning["ny"]
     mu = ("k_mu + k_bracket" if tuning["mu_source"] == 0 or not sq
           else "k_mug_strip + k_row_r2c")
