@@ -477,7 +477,7 @@ namespace {
 constexpr int kRowCand[] = {0, 1, 2, 3};
 constexpr int kAdvCand[] = {0,  2,  4,  8,  16, 32, kStripFft + 2, kStripFft + 4,
                              kStripFft + 8, kStripFft1 + 2, kStripFft1 + 4, kStripFft1 + 8};
-constexpr int kMuCand[] = {0, 2, 4, 8, 16, 32};
+constexpr int kMuCand[] = {0, 2, 4, 8, 16, 32, kStripFft + 2, kStripFft + 4, kStripFft + 8};
 constexpr int kColCand[] = {0, 1, 2, 3};
 
 int env_variant(const char* name) {

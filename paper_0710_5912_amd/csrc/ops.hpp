@@ -42,7 +42,9 @@ struct Ops {
   void (*advect)(const Run* runs, int nruns, int ny, const StepArgs* sa, bool inertial,
                  int variant, int row_variant, hipStream_t st);
   // stage 2a + forward row transform of g; variant: 0 two kernels through
-  // the real scratch, k > 0 strip stencil over k-row strips (square cells)
+  // the real scratch, 0 < k < kStripFft strip stencil over k-row strips
+  // (square cells) + in-place transform, kStripFft + k the same strips with
+  // the transform in one kernel
   void (*mu_source)(const Run* runs, int nruns, int ny, const StepArgs* sa, int variant,
                     int row_variant, hipStream_t st);
   // column transform + per-mode update (ColMode) + inverse column transform;

@@ -136,9 +136,10 @@ struct RowLaunch {
     r2c_jobs(runs, nruns, ny, jobs, inertial ? 3 : 2, row_variant, st);
   }
   // variant 0: mu into the real scratch field, then the source bracket and
-  // its row transform; variant k > 0 (square cells only): the strip stencil
-  // (mu in registers) over k-row strips into B_GH, then its in-place row
-  // transform
+  // its row transform; variant 0 < k < kStripFft (square cells only): the
+  // strip stencil (mu in registers) over k-row strips into B_GH, then its
+  // in-place row transform; kStripFft + k: the same strips with the row
+  // transforms in one kernel (nx 256 .. 2048; elsewhere the two-kernel form)
   static void mu_source(const Run* runs, int nruns, int ny, const StepArgs* sa, int variant,
                         int row_variant, hipStream_t st) {
     constexpr int NX = 2 * L, TPB = strip_threads(NX);
@@ -148,6 +149,15 @@ struct RowLaunch {
       Jobs jobs{{{JOB_SOURCE, B_PHI, B_TMP, B_GH}, {}, {}}};
       bracket(runs, nruns, ny, sa, jobs, 1, st);
       return;
+    }
+    if (variant >= kStripFft) {
+      const int rows = variant - kStripFft;
+      if constexpr (strip_fft_ok(NX)) {
+        hipLaunchKernelGGL((k_mug_strip_fft<T, NX>), dim3(1, (ny + rows - 1) / rows, nruns),
+                           dim3(NX / 2), 0, st, runs, sa, rows);
+        return;
+      }
+      variant = rows;  // grids outside the fused kernel's range: the two-kernel form
     }
     const dim3 gs(NX / 2 / TPB, (ny + variant - 1) / variant, nruns);
     hipLaunchKernelGGL((k_mug_strip<T, NX>), gs, dim3(TPB), 0, st, runs, sa, variant);

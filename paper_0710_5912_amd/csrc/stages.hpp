@@ -727,16 +727,16 @@ struct RawPhi {
   RawQuad<T> r;
   T e;
 };
-template <typename T, int NX>
+template <typename T, int NX, int TPB>
 __device__ __forceinline__ RawPhi<T> load_phi(gp<const T> __restrict__ row,
-                                              const StripLanes<T, NX>& sl) {
+                                              const StripLanes<T, NX, TPB>& sl) {
   RawPhi<T> o;
   o.r = load_raw<T, NX>(row, sl);
   o.e = row[(sl.edge_r ? sl.xr + 1 : sl.xl - 1) & (NX - 1)];
   return o;
 }
-template <typename T, int NX>
-__device__ __forceinline__ PhiRow<T> to_phirow(const RawPhi<T>& r, const StripLanes<T, NX>& sl) {
+template <typename T, int NX, int TPB>
+__device__ __forceinline__ PhiRow<T> to_phirow(const RawPhi<T>& r, const StripLanes<T, NX, TPB>& sl) {
   return {to_quad<T, NX>(r.r, sl), r.e};
 }
 
@@ -757,10 +757,10 @@ __device__ __forceinline__ T mu_at(const MuCoef<T>& k, T dw, T dm, T de, T cw, T
 }
 // mu quad of row j from the phi rows j-1 (d), j (c), j+1 (u).  Every lane of
 // the wavefront must execute this (DPP).
-template <typename T, int NX>
+template <typename T, int NX, int TPB>
 __device__ __forceinline__ Quad<T> mu_quad(const MuCoef<T>& k, const PhiRow<T>& d,
                                            const PhiRow<T>& c, const PhiRow<T>& u,
-                                           const StripLanes<T, NX>& sl) {
+                                           const StripLanes<T, NX, TPB>& sl) {
   const T m0 = mu_at(k, d.q.l, d.q.a0, d.q.a1, c.q.l, c.q.a0, c.q.a1, u.q.l, u.q.a0, u.q.a1);
   const T m1 = mu_at(k, d.q.a0, d.q.a1, d.q.r, c.q.a0, c.q.a1, c.q.r, u.q.a0, u.q.a1, u.q.r);
   // halo mu: at x-1 (neighbourhood x-2 .. x) or at x+2 (x+1 .. x+3)
@@ -815,6 +815,73 @@ __global__ __launch_bounds__(strip_threads(NX)) void k_mug_strip(
            {neg_inv * (px0 * my0 - py0 * mx0), neg_inv * (px1 * my1 - py1 * mx1)});
     F1 = F2; F2 = F3; F3 = F4;
     Mm = Mc; Mc = Mp;
+  }
+}
+
+// Stage 2a over row strips with the forward row transform of g in the same
+// kernel (square cells, as k_mug_strip).  The block owns whole rows: NX/2
+// threads, one x pair each, walking the strip as k_mug_strip does.  The g
+// rows collect in LDS four at a time; each batch goes through the row
+// transform by four groups of NX/8 threads (4 values each), group k taking
+// row k of the batch, and is stored as row spectra of B_GH.
+template <typename T, int NX>
+__global__ __launch_bounds__(NX / 2) void k_mug_strip_fft(const Run* __restrict__ runs,
+                                                         const StepArgs* __restrict__ sa,
+                                                         int rows) {
+  constexpr int L = NX / 2, TPB = L, EF = 4, PF = L / EF;
+  static_assert(TPB == 4 * PF && TPB >= 64, "four transform groups, whole wavefronts");
+  __shared__ c2<T> buf[4 * L];
+  const BPos bp = block_pos();
+  const Run& R = runs[bp.z];
+  const Geo& geo = R.g;
+  const int ny = geo.ny;
+  const StripLanes<T, NX, TPB> sl(0);
+  const int j0 = bp.y * rows;
+  const int j1 = min(j0 + rows, ny);
+  auto phi = bufp<const T>(R, B_PHI);
+  auto out = bufp<c2<T>>(R, B_GH);
+  auto tw = to_global<const c2<double>>(R.twx);
+  const double s = sa[bp.z].s;
+  const MuCoef<T> k = {T((1.0 + s * s) / (geo.dx * geo.dx)), T(1.0 / (geo.dy * geo.dy)),
+                       T(-2.0 * s / (4.0 * geo.dx * geo.dy)), T(geo.A), T(geo.B), T(geo.kappa)};
+  const Stencil<T> st = make_stencil<T>(geo, s);
+  const T neg_inv = T(-1.0 / (geo.rho > 0.0 ? geo.rho : geo.eta));
+  const int grp = threadIdx.x / PF, tt = threadIdx.x % PF;
+  auto row = [&](int j) {
+    j = j % ny;
+    return phi + (size_t)(j < 0 ? j + ny : j) * NX;
+  };
+  PhiRow<T> F0 = to_phirow(load_phi(row(j0 - 2), sl), sl);  // rows j-2 .. j+1 at j = j0
+  PhiRow<T> F1 = to_phirow(load_phi(row(j0 - 1), sl), sl);
+  PhiRow<T> F2 = to_phirow(load_phi(row(j0), sl), sl);
+  PhiRow<T> F3 = to_phirow(load_phi(row(j0 + 1), sl), sl);
+  Quad<T> Mm = mu_quad(k, F0, F1, F2, sl);  // mu rows j-1, j
+  Quad<T> Mc = mu_quad(k, F1, F2, F3, sl);
+  RawPhi<T> rn = load_phi(row(j0 + 2), sl);
+  for (int j = j0; j < j1; ++j) {
+    const PhiRow<T> F4 = to_phirow(rn, sl);
+    if (j + 1 < j1) rn = load_phi(row(j + 3), sl);
+    const Quad<T> Mp = mu_quad(k, F2, F3, F4, sl);  // mu(j+1)
+    T px0, px1, py0, py1, mx0, mx1, my0, my1;
+    quad_dx(F2.q, st.inv2dx, px0, px1);
+    quad_dys<T, NX, true>(F3.q, F1.q, row(j + 1), row(j - 1), sl.x, st, py0, py1);
+    quad_dx(Mc, st.inv2dx, mx0, mx1);
+    quad_dys<T, NX, true>(Mp, Mm, row(j + 1), row(j - 1), sl.x, st, my0, my1);
+    const int slot = (j - j0) & 3;
+    buf[slot * L + sl.x / 2] = {neg_inv * (px0 * my0 - py0 * mx0),
+                                neg_inv * (px1 * my1 - py1 * mx1)};
+    F1 = F2; F2 = F3; F3 = F4;
+    Mm = Mc; Mc = Mp;
+    if (slot == 3 || j + 1 == j1) {  // a batch of up to four rows is complete
+      __syncthreads();
+      c2<T> v[EF];
+#pragma unroll
+      for (int q = 0; q < EF; ++q) v[q] = buf[grp * L + tt + q * PF];
+      __syncthreads();
+      row_r2c<T, L, EF>(v, buf + grp * L, tw, tt);
+      if (grp <= slot) store_row_spec<T, L, EF>(out + (size_t)(j - slot + grp) * (L + 1), v, tt);
+      __syncthreads();
+    }
   }
 }
 

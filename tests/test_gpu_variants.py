@@ -20,10 +20,11 @@ le = pytest.importorskip("paper_0710_5912_amd.le")
 
 KEYS = ("LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH", "LE_TUNE_COL_FLOW", "LE_TUNE_ROW")
 # (advect, mu_source, column_ch, column_flow, row)
-# advect 64 + k / 96 + k: strip stencil and row transforms in one kernel
-# (k-row strips, two / one x pairs per thread)
+# advect 64 + k / 96 + k, mu_source 64 + k: strip stencil and row transforms
+# in one kernel (k-row strips; advect with two / one x pairs per thread)
 COMBOS = [(0, 0, 0, 0, 0), (4, 4, 1, 1, 1), (32, 32, 2, 2, 2), (8, 16, 3, 3, 3),
-          (2, 2, 0, 0, 1), (66, 4, 0, 1, 2), (72, 8, 2, 0, 0), (100, 2, 1, 3, 0)]
+          (2, 2, 0, 0, 1), (66, 4, 0, 1, 2), (72, 8, 2, 0, 0), (100, 2, 1, 3, 0),
+          (98, 66, 0, 0, 3), (4, 68, 1, 1, 0), (100, 72, 3, 2, 1)]
 
 
 def params(nx, ny, **kw):
@@ -75,7 +76,7 @@ def test_variants_512_fp64(monkeypatch, combo, rho):
 
 
 @pytest.mark.parametrize("combo", [(4, 4, 1, 3, 1), (32, 8, 3, 2, 3), (68, 4, 0, 0, 1),
-                                   (98, 8, 2, 1, 2)])
+                                   (98, 8, 2, 1, 2), (66, 68, 1, 1, 2)])
 def test_variants_512_fp32(monkeypatch, combo):
     """FP32 shapes (16 values per thread in shapes 2 and 3) within the FP32 bound."""
     p = params(512, 512)
@@ -85,7 +86,7 @@ def test_variants_512_fp32(monkeypatch, combo):
 
 
 @pytest.mark.parametrize("combo", [(4, 4, 0, 2, 1), (16, 32, 3, 0, 2), (2, 2, 2, 1, 3),
-                                   (68, 4, 0, 0, 0)])
+                                   (68, 68, 0, 0, 0)])
 def test_strip_variants_across_a_wrap(monkeypatch, combo):
     """64^2, gdot = 0.5: the strain wraps at step 200; 220 steps."""
     p = params(64, 64, gdot=0.5)
@@ -113,7 +114,7 @@ def test_autotuner_reports_valid_choices():
     t = t[0]
     assert (t["nx"], t["ny"], t["precision"], t["inertial"]) == (256, 256, 0, 1)
     assert t["advect"] in (0, 2, 4, 8, 16, 32, 66, 68, 72, 98, 100, 104)
-    assert t["mu_source"] in (0, 2, 4, 8, 16, 32)
+    assert t["mu_source"] in (0, 2, 4, 8, 16, 32, 66, 68, 72)
     assert t["column_ch"] in range(4) and t["column_flow"] in range(4) and t["row"] in range(4)
 
 
