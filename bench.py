@@ -94,12 +94,14 @@ def step_bytes(params, precision):
 def stage_kernels(tuning, inertial):
     """Kernels each stage launches under the autotuned variants."""
     a = tuning["advect"]
-    fused_strip = a >= 64 and 256 <= tuning["nx"] <= 2048
+    fused_strip = a >= 64 and 256 <= tuning["nx"] <= 1024
     adv = ("k_bracket" if a == 0 else
            ("k_adv_strip_fft" if fused_strip else "k_adv_strip + k_row_r2c"))
     sq = tuning["nx"] == tuning["ny"]
-    mu = ("k_mu + k_bracket" if tuning["mu_source"] == 0 or not sq
-          else "k_mug_strip + k_row_r2c")
+    m = tuning["mu_source"]
+    mu = ("k_mu + k_bracket" if m == 0 or not sq else
+          ("k_mug_strip_fft" if m >= 64 and 256 <= tuning["nx"] <= 2048
+           else "k_mug_strip + k_row_r2c"))
     return {"row_inv_flow": "k_row_c2r", "advect": adv, "column_ch": "k_column<COL_CH>",
             "row_inv_phi": "k_row_c2r", "mu_source": mu,
             "column_flow": "k_column<COL_FLOW>" if inertial else "k_column<COL_STOKES>"}

@@ -177,9 +177,9 @@ int le_time_stage(le_ctx* c, int32_t stage, int32_t reps, double* ms_per_launch)
  *   row
  * (advect / mu_source: 0 = one fused stencil-and-row-transform kernel,
  * 0 < k < 64 = a stencil kernel over k-row strips then in-place row
- * transforms; advect 64 + k and 96 + k (two or one x pairs per thread) and
- * mu_source 64 + k = the k-row strip stencil and the row transforms in one
- * kernel, for nx 256 .. 2048 (other nx: as k);
+ * transforms; advect 64 + k and 96 + k (two or one x pairs per thread, nx
+ * 256 .. 1024) and mu_source 64 + k (nx 256 .. 2048) = the k-row strip
+ * stencil and the row transforms in one kernel (other nx: as k);
  * column_*: block shape 0 .. 3; row: row-transform shape 0 .. 3, 8 or 4
  * values per thread, all or a quarter of the rows per block), at most cap
  * values in all, and returns the number of

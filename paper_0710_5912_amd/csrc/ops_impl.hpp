@@ -101,7 +101,7 @@ struct RowLaunch {
   // into the spectral buffers, then in-place row transforms; variant
   // kStripFft + k (two x pairs per thread) and kStripFft1 + k (one): strip
   // stencil and row transforms in one kernel over k-row strips (nx 256 ..
-  // 2048; elsewhere the two-kernel form)
+  // 1024; elsewhere the two-kernel form)
   static void advect(const Run* runs, int nruns, int ny, const StepArgs* sa, bool inertial,
                      int variant, int row_variant, hipStream_t st) {
     if (variant <= 0) {
@@ -115,7 +115,7 @@ struct RowLaunch {
     if (variant >= kStripFft) {
       const bool two = variant < kStripFft1;
       const int rows = variant - (two ? kStripFft : kStripFft1);
-      if constexpr (strip_fft_ok(NX)) {
+      if constexpr (adv_strip_fft_ok(NX)) {
         const dim3 gf(1, (ny + rows - 1) / rows, nruns);
         if (two)
           strip_fft<2>(runs, sa, ny, gf, rows, inertial, st);

@@ -613,12 +613,15 @@ __global__ __launch_bounds__(strip_threads(NX)) void k_adv_strip(
 // Stage 1a over row strips with the forward row transforms in the same
 // kernel (no real rows written and read back).  The block owns whole rows:
 // NX/(2 SEG) threads, thread t the SEG x pairs t + g NX/(2 SEG), each walked
-// down the strip as in k_adv_strip.  Each output row goes through LDS to
-// four groups of threads (4 SEG values each); groups 0, 1, 2 transform
-// phi_h, f and omega_h and store their row spectra (group 3, and group 2
-// without inertia, transform nothing useful and store nothing).  SEG = 2
-// halves the threads and doubles each one's registers.
+// down the strip as in k_adv_strip.  The output rows go through LDS to four
+// groups of threads (4 SEG values each) for the row transforms and are
+// stored as row spectra: strips of four or more rows collect four rows and
+// transform them in one round per field (phi_h, f and, with inertia,
+// omega_h), group k taking row k; shorter strips transform every row in one
+// round, group k taking field k (group 3 idles).  SEG = 2 halves the
+// threads and doubles each one's registers.
 constexpr bool strip_fft_ok(int nx) { return nx >= 256 && nx <= 2048; }
+constexpr bool adv_strip_fft_ok(int nx) { return nx >= 256 && nx <= 1024; }
 
 template <typename T, int NX, bool R1, int SEG>
 __global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __restrict__ runs,
@@ -626,7 +629,7 @@ __global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __res
                                                                int rows, int inertial) {
   constexpr int L = NX / 2, TPB = L / SEG, EF = 4 * SEG, PF = L / EF;
   static_assert(TPB == 4 * PF && TPB >= 64, "four transform groups, whole wavefronts");
-  __shared__ c2<T> buf[4 * L];
+  __shared__ c2<T> buf[3 * 4 * L];  // [field][batch row][pair]
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
   const Geo& geo = R.g;
@@ -643,8 +646,10 @@ __global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __res
   const T dt = T(geo.dt);
   const bool inr = inertial != 0;
   const int grp = threadIdx.x / PF, tt = threadIdx.x % PF;
-  auto out = bufp<c2<T>>(R, grp == 0 ? B_PHIH : (grp == 1 ? B_FH : B_OMH));
-  const bool store = grp < (inr ? 3 : 2);
+  const int nf = inr ? 3 : 2;
+  // strips of four or more rows transform in batches of four rows, one
+  // round per field; shorter strips transform every row in one round
+  const bool batch = rows >= 4;
   auto row = [&](gp<const T> f, int j) {
     return f + (size_t)(j < 0 ? j + ny : (j >= ny ? j - ny : j)) * NX;
   };
@@ -669,6 +674,7 @@ __global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __res
     rW[g] = inr ? load_raw(row(om, j0 + 1), sl) : rF[g];
   }
   for (int j = j0; j < j1; ++j) {
+    const int slot = batch ? (j - j0) & 3 : 0;
 #pragma unroll
     for (int g = 0; g < SEG; ++g) {
       const StripLanes<T, NX, TPB>& sl = g ? sl1 : sl0;
@@ -685,27 +691,48 @@ __global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __res
       quad_dys<T, NX, R1>(Sp, Sm[g], row(psi, j + 1), row(psi, j - 1), sl.x, st, sy0, sy1);
       quad_dx(Fc[g], st.inv2dx, ax0, ax1);
       quad_dys<T, NX, R1>(Fp, Fm[g], row(phi, j + 1), row(phi, j - 1), sl.x, st, ay0, ay1);
-      const int pr = sl.x / 2;
+      const int pr = slot * L + sl.x / 2;
       buf[pr] = {Fc[g].a0 - dt * (ax0 * sy0 - ay0 * sx0), Fc[g].a1 - dt * (ax1 * sy1 - ay1 * sx1)};
-      buf[L + pr] = {Fc[g].a0 * Fc[g].a0 * Fc[g].a0, Fc[g].a1 * Fc[g].a1 * Fc[g].a1};
+      buf[4 * L + pr] = {Fc[g].a0 * Fc[g].a0 * Fc[g].a0, Fc[g].a1 * Fc[g].a1 * Fc[g].a1};
       if (inr) {
         quad_dx(Wc[g], st.inv2dx, ax0, ax1);
         quad_dys<T, NX, R1>(Wp, Wm[g], row(om, j + 1), row(om, j - 1), sl.x, st, ay0, ay1);
-        buf[2 * L + pr] = {Wc[g].a0 - dt * (ax0 * sy0 - ay0 * sx0),
+        buf[8 * L + pr] = {Wc[g].a0 - dt * (ax0 * sy0 - ay0 * sx0),
                            Wc[g].a1 - dt * (ax1 * sy1 - ay1 * sx1)};
       }
       Fm[g] = Fc[g]; Fc[g] = Fp;
       Sm[g] = Sc[g]; Sc[g] = Sp;
       Wm[g] = Wc[g]; Wc[g] = Wp;
     }
-    __syncthreads();
-    c2<T> v[EF];
+    if (!batch) {  // one round per row: group k transforms field k (group 3 idles)
+      c2<T>* area = buf + (grp < 3 ? grp * 4 : 1) * L;
+      __syncthreads();
+      c2<T> v[EF];
 #pragma unroll
-    for (int q = 0; q < EF; ++q) v[q] = buf[grp * L + tt + q * PF];
-    __syncthreads();
-    row_r2c<T, L, EF>(v, buf + grp * L, tw, tt);
-    if (store) store_row_spec<T, L, EF>(out + (size_t)j * (L + 1), v, tt);
-    __syncthreads();
+      for (int q = 0; q < EF; ++q) v[q] = area[tt + q * PF];
+      __syncthreads();
+      row_r2c<T, L, EF>(v, area, tw, tt);
+      if (grp < nf) {
+        auto out = bufp<c2<T>>(R, grp == 0 ? B_PHIH : (grp == 1 ? B_FH : B_OMH));
+        store_row_spec<T, L, EF>(out + (size_t)j * (L + 1), v, tt);
+      }
+      __syncthreads();
+    } else if (slot == 3 || j + 1 == j1) {  // a batch of up to four rows is complete
+      for (int f = 0; f < nf; ++f) {
+        c2<T>* area = buf + (f * 4 + grp) * L;
+        __syncthreads();
+        c2<T> v[EF];
+#pragma unroll
+        for (int q = 0; q < EF; ++q) v[q] = area[tt + q * PF];
+        __syncthreads();
+        row_r2c<T, L, EF>(v, area, tw, tt);
+        if (grp <= slot) {
+          auto out = bufp<c2<T>>(R, f == 0 ? B_PHIH : (f == 1 ? B_FH : B_OMH));
+          store_row_spec<T, L, EF>(out + (size_t)(j - slot + grp) * (L + 1), v, tt);
+        }
+      }
+      __syncthreads();
+    }
   }
 }
 
