@@ -57,6 +57,33 @@ def test_batch_equals_single_runs_bitwise(fixed_variants):
     b.close()
 
 
+@pytest.mark.parametrize("adv,mu", [(98, 66), (68, 72)])
+def test_batch_one_kernel_strips_equal_single_runs(monkeypatch, adv, mu):
+    """The one-kernel strip stages (whole rows per block, grid z = run) over a
+    batch of 256^2 and 512^2 runs (two runs per class, inertial and Stokes)
+    reproduce each run alone with the same variants bit for bit."""
+    for k, v in (("LE_TUNE_ADV", adv), ("LE_TUNE_MU", mu), ("LE_TUNE_COL_CH", 0),
+                 ("LE_TUNE_COL_FLOW", 0), ("LE_TUNE_ROW", 0)):
+        monkeypatch.setenv(k, str(v))
+    runs = []
+    for k, (n, rho, gdot) in enumerate([(256, 1.0, 0.3), (256, 1.0, -0.2), (512, 0.0, 0.1),
+                                        (512, 0.0, 0.05)]):
+        runs.append((configs.model_h(n, n, gdot=gdot, rho=rho),
+                     inputs.noise_phi0(n, n, 300 + k, amp=0.4)))
+    print(f"batch of {len(runs)} runs, advect {adv}, mu {mu}, 30 steps", flush=True)
+    b = le.Batch([r[0] for r in runs], [r[1] for r in runs])
+    assert all(t["advect"] == adv and t["mu_source"] == mu for t in b.tuning())
+    b.step(30)
+    for i, (p, phi0) in enumerate(runs):
+        with le.Context(p, phi0) as c:
+            c.step(30)
+            ref = c.get_state()
+        got = b.get_state(i)
+        for k in ("phi", "omega", "psi"):
+            assert np.array_equal(got[k], ref[k]), (i, k)
+    b.close()
+
+
 def test_batch_fp64_runs_match_oracle():
     runs = [r for r in mixed_runs() if r[1] == "fp64"][:4]
     b = le.Batch([r[0] for r in runs], [r[2] for r in runs])
