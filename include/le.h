@@ -195,6 +195,9 @@ int le_tuning(le_ctx* c, int32_t* out, int32_t cap);
  * Batched runs.  Many independent runs (each with its own grid, shear rate,
  * density, precision and initial state) advance together: every stage of a
  * step is one launch per group of runs sharing (nx, ny, precision, rho > 0),
+ * each group runs a chunk of steps on a stream of its own (forked from and
+ * joined back into the batch's stream, so the groups' kernels overlap;
+ * LE_CLASS_STREAMS=0 at creation keeps every group on the batch's stream),
  * and chunks of steps are replayed from captured HIP graphs.  Each run's
  * result is the one le_create/le_step would give for it alone.
  *

@@ -157,6 +157,12 @@ struct le_ctx {
   int64_t stage_n[LE_NSTAGES] = {0};
   Net* net = nullptr;              // learned corrector (single inertial run)
   double* d_restrict = nullptr;    // restriction output
+  // engines of several grid classes: one stream per class (default priority)
+  // so that the classes' independent kernels overlap, forked from and joined
+  // back into `stream` around every chunk of steps
+  std::vector<hipStream_t> cls_streams;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;
 };
 
 // Network with training state, driven through device pointers.
@@ -202,6 +208,13 @@ void release(Engine* e) {
     e->net = nullptr;
   }
   if (e->d_restrict) (void)hipFree(e->d_restrict);
+  for (hipStream_t cs : e->cls_streams)
+    if (cs) (void)hipStreamDestroy(cs);
+  e->cls_streams.clear();
+  for (hipEvent_t ev : e->join_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  e->join_ev.clear();
+  if (e->fork_ev) (void)hipEventDestroy(e->fork_ev);
   if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
 }
 
@@ -362,12 +375,55 @@ int enqueue_chunk(Engine* e, int64_t key, int64_t count, F&& enqueue_one) {
   return LE_OK;
 }
 
+// One step of one class on stream st (the stages of enqueue_step).
+void enqueue_class_step(const Engine* e, const Class& k, const StepArgs* sa, hipStream_t st) {
+  const Run* d = e->d_desc + k.first;
+  const int n = (int)k.members.size();
+  const StepArgs* a = sa + k.first;
+  if (k.inertial)
+    k.ops.row_c2r(d, n, k.ny, B_OM_S, B_OM_R, B_PS_S, B_PS_R, 2, k.row_variant, st);
+  else
+    k.ops.row_c2r(d, n, k.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1, k.row_variant, st);
+  k.ops.advect(d, n, k.ny, a, k.inertial, k.adv_variant, k.row_variant, st);
+  k.ops.column(COL_CH, d, n, k.nx, a, B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant, st);
+  k.ops.row_c2r(d, n, k.ny, B_PHIN, B_PHI, B_PHIN, B_PHI, 1, k.row_variant, st);
+  k.ops.mu_source(d, n, k.ny, a, k.mu_variant, k.row_variant, st);
+  if (k.inertial)
+    k.ops.column(COL_FLOW, d, n, k.nx, a, B_OMH, B_GH, B_OM_S, B_PS_S, k.col_flow_variant, st);
+  else
+    k.ops.column(COL_STOKES, d, n, k.nx, a, B_GH, B_GH, B_PS_S, B_PS_S, k.col_flow_variant,
+                 st);
+}
+
 // Enqueue `count` plain steps whose StepArgs rows are d_args[0 .. count)
 // (one graph per chunk length serves every chunk of that length: the strain
 // offsets stay in device memory).  Stage timing brackets direct launches
-// with events, so timed chunks are never captured.
+// with events, so timed chunks are never captured.  With several classes
+// (and no stage timing) each class runs the whole chunk on its own stream
+// between a fork and a join on the engine's stream.
 int enqueue_steps(Engine* e, int64_t count) {
   const size_t row = (size_t)e->nruns;
+  if (!e->cls_streams.empty() && !e->profiling) {
+    return enqueue_chunk(e, count, count, [&](int64_t k, hipEvent_t*) {
+      const size_t nc = e->classes.size();
+      if (k == 0) {
+        if (hipEventRecord(e->fork_ev, e->stream) != hipSuccess) return (int)LE_EDEVICE;
+        for (size_t c = 0; c < nc; ++c)
+          if (hipStreamWaitEvent(e->cls_streams[c], e->fork_ev, 0) != hipSuccess)
+            return (int)LE_EDEVICE;
+      }
+      for (size_t c = 0; c < nc; ++c)
+        enqueue_class_step(e, e->classes[c], e->d_args + k * row, e->cls_streams[c]);
+      if (k + 1 == count) {
+        for (size_t c = 0; c < nc; ++c) {
+          if (hipEventRecord(e->join_ev[c], e->cls_streams[c]) != hipSuccess ||
+              hipStreamWaitEvent(e->stream, e->join_ev[c], 0) != hipSuccess)
+            return (int)LE_EDEVICE;
+        }
+      }
+      return (int)LE_OK;
+    });
+  }
   return enqueue_chunk(e, count, count, [&](int64_t k, hipEvent_t* ev) {
     enqueue_step(e, e->d_args + k * row, ev);
     return LE_OK;
@@ -729,6 +785,25 @@ int create_engine(int32_t n, const le_params* ps, const double* const* phi0s,
     if (!rc) rc = solve_psi(e, r);
   }
   if (!rc) rc = autotune(e);
+  if (!rc && e->classes.size() > 1 && !(std::getenv("LE_CLASS_STREAMS") &&
+                                        std::getenv("LE_CLASS_STREAMS")[0] == '0')) {
+    if (hipEventCreateWithFlags(&e->fork_ev, hipEventDisableTiming) != hipSuccess)
+      rc = LE_EDEVICE;
+    for (size_t c = 0; c < e->classes.size() && !rc; ++c) {
+      hipStream_t cs = nullptr;
+      hipEvent_t ev = nullptr;
+      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        rc = LE_EDEVICE;
+        break;
+      }
+      e->cls_streams.push_back(cs);
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        rc = LE_EDEVICE;
+        break;
+      }
+      e->join_ev.push_back(ev);
+    }
+  }
   if (!rc && hipStreamSynchronize(e->stream) != hipSuccess) rc = LE_EDEVICE;
   if (rc) {
     release(e);
