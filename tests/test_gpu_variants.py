@@ -106,6 +106,16 @@ def test_strip_variants_non_square_cells(monkeypatch, combo):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
 
 
+@pytest.mark.parametrize("combo", [(68, 4, 0, 0, 0), (100, 8, 1, 1, 3), (66, 2, 2, 3, 1)])
+def test_one_kernel_strips_flat_grid(monkeypatch, combo):
+    """nx = 64 ny (512 x 8, r = 64): strips longer than the grid, every row a
+    halo row of the next, the diagonal pairs read r = 64 columns away."""
+    p = params(512, 8, gdot=0.05, lx=512.0, ly=8.0)
+    g, st = run_forced(monkeypatch, p, 30, 26, combo)
+    for k in ("phi", "omega", "psi"):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k
+
+
 def test_autotuner_reports_valid_choices():
     p = params(256, 256)
     with le.Context(p, inputs.noise_phi0(256, 256, 0)) as c:
