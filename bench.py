@@ -193,6 +193,25 @@ def traffic_of(stage, precision, nx, tuning):
     return (k["fetch_kib"] * rec["fetch_factor"] + k["write_kib"] * rec["write_factor"]) * 1024.0
 
 
+def copy_bandwidth(torch, mib=512, reps=20):
+    """Measured device-to-device copy bandwidth (GB/s, bytes read + written):
+    the second denominator of the roofline fractions."""
+    src = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * src.numel() * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
 def cpu_baseline(params, budget_s=15.0):
     """The FP64 oracle, untuned, on a bounded number of steps of the same workload."""
     import numpy as np
@@ -264,6 +283,7 @@ def main():
           file=sys.stderr, flush=True)
     r = run_variant(le, torch, params, "fp64", args.steps, args.warmup, args.obs_every)
     sites = params["nx"] * params["ny"]
+    copy_gbs = copy_bandwidth(torch)
     sec = r["gpu_ms"] * 1e-3
     value = sites * args.steps / sec
     dom, rows = roofline_of(params, "fp64", r["times"])
@@ -294,11 +314,18 @@ def main():
                      "frac": rows[dom]["gbs"] / HBM_PEAK_GBS,
                      "traffic": traffic_of(dom, "fp64", 1024, r["tuning"]),
                      "bytes_per_launch": rows[dom]["bytes"],
-                     "avg_launch_us": rows[dom]["avg_us"]},
+                     "avg_launch_us": rows[dom]["avg_us"],
+                     "copy_gbs": copy_gbs,
+                     "copy_note": "512 MiB device-to-device tensor copy (runtime copy kernel), "
+                                  "bytes read + written, timed after the bench",
+                     "frac_of_copy": rows[dom]["gbs"] / copy_gbs},
         "stages": {k: {"avg_us": round(v["avg_us"], 2), "GBs": round(v["gbs"], 1)}
                    for k, v in rows.items()},
         "step_roofline": {"bytes_per_step": step_bytes(params, "fp64"),
+                          "bytes_per_step_four_pass_minimum": 128 * sites,
                           "frac": step_bytes(params, "fp64") / (r["gpu_ms"] / args.steps * 1e-3)
+                          / 1e9 / HBM_PEAK_GBS,
+                          "frac_four_pass_minimum": 128 * sites / (r["gpu_ms"] / args.steps * 1e-3)
                           / 1e9 / HBM_PEAK_GBS},
         "tuning": r["tuning"],
         "wall_s": r["wall"],
