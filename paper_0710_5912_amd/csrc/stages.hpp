@@ -226,19 +226,11 @@ template <typename T, int L, int E = row_elems(L), int GDIV = 1>
 __global__ __launch_bounds__((RowCfg<L, E, GDIV>::THREADS)) LE_OCCUPANCY void k_row_r2c_corr(
     const Run* __restrict__ runs, CorrArgs ca) {
   using C = RowCfg<L, E, GDIV>;
+  constexpr int NW = (C::THREADS + 63) / 64;
   __shared__ c2<T> lds[C::G * L];
-  __shared__ double red[C::THREADS];
+  __shared__ double wred[NW];
   const Run& R = runs[0];
   const int ny = R.g.ny;
-  double acc = 0.0;
-  for (int k = threadIdx.x; k < ca.nblk; k += C::THREADS) acc += ca.part[k];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int h = C::THREADS / 2; h >= 1; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  const double mean = red[0] / ((double)ny * (double)(2 * L));
   auto phi = reinterpret_cast<gp<c2<T>>>(bufp<T>(R, B_PHI));
   auto om = reinterpret_cast<gp<c2<T>>>(bufp<T>(R, B_OM_R));
   auto X = bufp<c2<T>>(R, B_OM_S);
@@ -249,16 +241,38 @@ __global__ __launch_bounds__((RowCfg<L, E, GDIV>::THREADS)) LE_OCCUPANCY void k_
   const int j = blockIdx.x * C::G + g;
   const bool ok = j < ny;
   const size_t row = (size_t)(ok ? j : 0) * L;
-  c2<T> v[C::E];
+  // the row's operands are requested before the mean is formed
+  c2<T> f[C::E], w[C::E];
+  f32x4 zq[C::E];
 #pragma unroll
   for (int q = 0; q < C::E; ++q) {
     const size_t m = row + t + q * C::P;  // the pair (2m, 2m + 1) of the field
-    const f32x4 zq = zz[m];               // z_phi, z_omega of both points
-    const c2<T> f = ldg<T>(phi + m), w = ldg<T>(om + m);
-    const c2<T> fn = {(T)((double)f.x + (double)ca.s2 * ((double)zq.x - mean)),
-                      (T)((double)f.y + (double)ca.s2 * ((double)zq.z - mean))};
-    v[q] = {(T)((double)w.x + (double)ca.s3 * (double)zq.y),
-            (T)((double)w.y + (double)ca.s3 * (double)zq.w)};
+    zq[q] = zz[m];                        // z_phi, z_omega of both points
+    f[q] = ldg<T>(phi + m);
+    w[q] = ldg<T>(om + m);
+  }
+  // sum of the partials: per thread a strided sum, a butterfly within each
+  // wavefront, then the wavefront sums in order (the same order in every
+  // block)
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < ca.nblk; k += C::THREADS) acc += ca.part[k];
+  constexpr int WS = C::THREADS < 64 ? C::THREADS : 64;  // lanes of a (partial) wavefront
+#pragma unroll
+  for (int off = WS / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, WS);
+  if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  double total = 0.0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) total += wred[k];
+  const double mean = total / ((double)ny * (double)(2 * L));
+  c2<T> v[C::E];
+#pragma unroll
+  for (int q = 0; q < C::E; ++q) {
+    const size_t m = row + t + q * C::P;
+    const c2<T> fn = {(T)((double)f[q].x + (double)ca.s2 * ((double)zq[q].x - mean)),
+                      (T)((double)f[q].y + (double)ca.s2 * ((double)zq[q].z - mean))};
+    v[q] = {(T)((double)w[q].x + (double)ca.s3 * (double)zq[q].y),
+            (T)((double)w[q].y + (double)ca.s3 * (double)zq[q].w)};
     if (ok) {
       stg<T>(phi + m, fn);
       stg<T>(om + m, v[q]);
