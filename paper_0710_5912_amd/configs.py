@@ -30,3 +30,23 @@ def paper_units(l, eta, rho, gdot, lx, nx, ny, dt):
     """Table I parameters mapped to A = B = 1, kappa = M = l^2, Ly = 1."""
     return dict(nx=nx, ny=ny, lx=float(lx), ly=1.0, gdot=gdot, A=1.0, B=1.0,
                 kappa=l * l, M=l * l, eta=eta, rho=rho, dt=dt)
+
+
+# Inertialess sheared series of Table I (sets DV1s .. DV6s): l = 0.00156,
+# rho = 0, box 2 x 1, 1024 x 512, dt = 0.016; the sets differ in eta and
+# the shear rate.  phi0 uniform in [-0.01, 0.01] (Section III initial
+# condition).
+DV_SHEARED = {
+    "DV1s": (1000.0, 0.01),
+    "DV2s": (100.0, 0.01),
+    "DV3s": (10.0, 0.01),
+    "DV4s": (1.0, 0.01),
+    "DV5s": (0.3, 0.01),
+    "DV6s": (0.1, 0.03),
+}
+DV_AMP = 0.01
+
+
+def dv_sheared(name):
+    eta, gdot = DV_SHEARED[name]
+    return paper_units(0.00156, eta, 0.0, gdot, 2.0, 1024, 512, 0.016)
