@@ -363,6 +363,18 @@ def main():
                  f"the 1024^2 FP64 plain run, t = {corrector.T_START:g}..{corrector.T_END:g}, "
                  f"gdot = 0.01, held-out seed; errors of L(t) against the fine run and "
                  f"against the fine field restricted to the coarse grid")
+        # the inertialess sheared set DV4s of Table I in paper units (1024 x 512,
+        # Stokes branch), 20000 steps with observables every 5000
+        print("bench: variant dv4s", file=sys.stderr, flush=True)
+        from paper_0710_5912_amd import inputs, series
+        pdv = configs.dv_sheared("DV4s")
+        rdv = series.run_series(pdv, inputs.noise_phi0(512, 1024, 500, amp=configs.DV_AMP),
+                                20000, 5000)
+        var["dv4s_1024x512_stokes_fp64"] = dict(
+            value=rdv["site_updates_per_s"], steps=20000, strain=float(rdv["strain"][-1]),
+            L_par=float(rdv["L_par"][-1]), L_perp=float(rdv["L_perp"][-1]),
+            note="Table I set DV4s (eta = 1, gdot = 0.01, l = 0.00156, rho = 0, box 2 x 1), "
+                 "wall time of stepping plus observables every 5000 steps")
         # the large single-GPU grid, FP64 and FP32 bulk
         for prec in ("fp64", "fp32"):
             p = configs.LARGE_4096["params"]
