@@ -50,3 +50,19 @@ DV_AMP = 0.01
 def dv_sheared(name):
     eta, gdot = DV_SHEARED[name]
     return paper_units(0.00156, eta, 0.0, gdot, 2.0, 1024, 512, 0.016)
+
+
+# Zero-shear diffusive-to-viscous series of Table I (sets DV1u .. DV6u):
+# l = 0.00156, rho = 0, box 1 x 1 on 512 x 512, dt = 0.016.
+DV_UNSHEARED = {
+    "DV1u": 1000.0,
+    "DV2u": 100.0,
+    "DV3u": 10.0,
+    "DV4u": 1.0,
+    "DV5u": 0.3,
+    "DV6u": 0.1,
+}
+
+
+def dv_unsheared(name):
+    return paper_units(0.00156, DV_UNSHEARED[name], 0.0, 0.0, 1.0, 512, 512, 0.016)

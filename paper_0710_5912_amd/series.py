@@ -39,3 +39,31 @@ def run_series(params, phi0, steps: int, every: int, precision: str = "fp64", st
     res["wall_s"] = wall
     res["site_updates_per_s"] = params["nx"] * params["ny"] * steps / wall
     return res
+
+
+def fit_power(t, L, t_min: float = 40.0, L_max: float = 0.02, n_int: int = 400):
+    """Growth exponent of a coarsening segment (Section V A protocol): samples
+    with t < t_min are discarded as the initial transient, the segment is cut
+    once L reaches L_max, and an offset t_int is subtracted from t.  t_int is
+    chosen (on a grid in [-4 t_first, t_first)) as the one whose straight-line
+    fit of log L against log(t - t_int) leaves the smallest residual; returns
+    (exponent, t_int, number of samples)."""
+    t = np.asarray(t, dtype=float)
+    L = np.asarray(L, dtype=float)
+    keep = t >= t_min
+    t, L = t[keep], L[keep]
+    if L.size and np.any(L >= L_max):
+        stop = int(np.argmax(L >= L_max))
+        t, L = t[:stop], L[:stop]
+    if t.size < 4:
+        raise ValueError("too few samples in the segment")
+    y = np.log(L)
+    best = None
+    for ti in np.linspace(-4.0 * t[0], t[0], n_int, endpoint=False):
+        x = np.log(t - ti)
+        a = np.vstack([x, np.ones_like(x)]).T
+        coef, res, _, _ = np.linalg.lstsq(a, y, rcond=None)
+        r = float(np.sum((a @ coef - y) ** 2))
+        if best is None or r < best[0]:
+            best = (r, float(coef[0]), float(ti))
+    return best[1], best[2], int(t.size)

@@ -46,3 +46,18 @@ def test_dv_series_runner():
     assert np.max(np.abs(r["mean_phi"] - phi0.mean())) <= 1e-13
     assert r["Ls"][-1] > r["Ls"][0] > 0.0
     assert r["site_updates_per_s"] > 0.0
+
+
+@pytest.mark.parametrize("name", ["DV2u", "DV5u"])
+def test_dv_unsheared_step_matches_oracle(name):
+    """Zero-shear sets on 512^2 (box 1): 20 steps against the oracle, FP64."""
+    p = configs.dv_unsheared(name)
+    phi0 = inputs.noise_phi0(512, 512, 43, amp=configs.DV_AMP)
+    print(f"case {name} 512x512 20 steps", flush=True)
+    with le.Context(p, phi0) as c:
+        c.step(20)
+        g = c.get_state()
+    op = mh.Params(**p)
+    st = mh.run(op, mh.initial_state(op, phi0, None), 20)
+    assert rel(g["phi"], st.phi) <= 1e-10
+    assert rel(g["psi"], st.psi) <= 1e-10
