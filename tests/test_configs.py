@@ -1,5 +1,8 @@
-"""Workload presets against the paper's parameter tables."""
-from paper_0710_5912_amd import configs
+"""Workload presets against the paper's parameter tables, and the growth-law
+fit of the coarsening series."""
+import numpy as np
+
+from paper_0710_5912_amd import configs, series
 
 
 def test_dv_sheared_presets_follow_table_one():
@@ -29,10 +32,7 @@ def test_dv_unsheared_presets_follow_table_one():
 def test_fit_power_recovers_a_known_law():
     """L = a (t - t0)^p sampled on a grid: the fit returns p and t0 (close to
     the grid of offsets), after dropping t < t_min and cutting at L_max."""
-    import numpy as np
-    pytest = __import__("pytest")
-    series = pytest.importorskip("paper_0710_5912_amd.series")
-    t = np.arange(10.0, 3000.0, 10.0)
+    t = np.arange(20.0, 3000.0, 10.0)
     for p, t0, a in ((1.0 / 3.0, 15.0, 1e-3), (2.0 / 3.0, -30.0, 1e-4)):
         L = a * (t - t0) ** p
         e, ti, n = series.fit_power(t, L, t_min=40.0, L_max=0.02)
