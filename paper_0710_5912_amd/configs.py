@@ -66,3 +66,22 @@ DV_UNSHEARED = {
 
 def dv_unsheared(name):
     return paper_units(0.00156, DV_UNSHEARED[name], 0.0, 0.0, 1.0, 512, 512, 0.016)
+
+
+# Inertial sheared sets of Table I used for the steady-state scaling plot
+# (R028bs, R022bs, R029bs, R020s, R030s, R019s, R032s): (eta, rho, gdot, dt);
+# l = 0.00156, box 2 x 1 on 1024 x 512.
+R_SHEARED = {
+    "R028bs": (0.444, 8704.0, 0.0765, 0.008),
+    "R022bs": (0.339, 22590.0, 0.0355, 0.008),
+    "R029bs": (0.0809, 8037.0, 0.0591, 0.008),
+    "R020s": (0.0785, 16180.0, 0.0256, 0.008),
+    "R030s": (0.0122, 6250.0, 0.0410, 0.004),
+    "R019s": (0.00876, 32814.0, 0.0251, 0.004),
+    "R032s": (0.00391, 20067.0, 0.051, 0.004),
+}
+
+
+def r_sheared(name):
+    eta, rho, gdot, dt = R_SHEARED[name]
+    return paper_units(0.00156, eta, rho, gdot, 2.0, 1024, 512, dt)

@@ -67,3 +67,42 @@ def fit_power(t, L, t_min: float = 40.0, L_max: float = 0.02, n_int: int = 400):
         if best is None or r < best[0]:
             best = (r, float(coef[0]), float(ti))
     return best[1], best[2], int(t.size)
+
+
+def interfacial_tension(params) -> float:
+    """sigma = sqrt(8 kappa A^3 / (9 B^2)) of the flat interface of the
+    phi^4 free energy; with A = B = G and kappa = l^2 G this is the paper's
+    2 sqrt(2) l G / 3 (Section II)."""
+    return float(np.sqrt(8.0 * params["kappa"] * params["A"] ** 3 / (9.0 * params["B"] ** 2)))
+
+
+def visco_inertial_scales(params):
+    """(L_VI, t_VI) = (eta^2 / (rho sigma), eta^3 / (rho sigma^2)), the
+    viscous-to-inertial crossover length and time (Section III)."""
+    s = interfacial_tension(params)
+    eta, rho = params["eta"], params["rho"]
+    return eta * eta / (rho * s), eta ** 3 / (rho * s * s)
+
+
+def steady_average(res, strain_min: float = 100.0):
+    """Mean and standard deviation of L_par and L_perp over the samples with
+    strain >= strain_min (the steady-state averages of the scaling plot)."""
+    keep = res["strain"] >= strain_min
+    if not np.any(keep):
+        raise ValueError("no samples past the strain cut")
+    lp, lq = res["L_par"][keep], res["L_perp"][keep]
+    return dict(L_par=float(lp.mean()), L_par_sd=float(lp.std()), L_perp=float(lq.mean()),
+                L_perp_sd=float(lq.std()), samples=int(keep.sum()))
+
+
+def power_fit(x, y):
+    """Least-squares slope of log y against log x and its standard error
+    (the power-law fits of the steady-state scaling plot, Section V B)."""
+    lx = np.log(np.asarray(x, dtype=float))
+    ly = np.log(np.asarray(y, dtype=float))
+    a = np.vstack([lx, np.ones_like(lx)]).T
+    coef, _, _, _ = np.linalg.lstsq(a, ly, rcond=None)
+    r = ly - a @ coef
+    s2 = float(r @ r) / max(1, lx.size - 2)
+    cov = s2 * np.linalg.inv(a.T @ a)
+    return float(coef[0]), float(np.sqrt(cov[0, 0]))

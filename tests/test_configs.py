@@ -39,3 +39,47 @@ def test_fit_power_recovers_a_known_law():
         assert abs(e - p) < 0.01, (p, e)
         assert abs(ti - t0) < 2.0, (t0, ti)
         assert n >= 4 and n < t.size
+
+
+def test_inertial_sheared_presets_and_crossover_scales():
+    """Table I inertial sheared sets: (eta, rho, gdot, dt) per set, and the
+    crossover length L_VI = eta^2 / (rho sigma) reproduces the table's column
+    (sigma = 2 sqrt(2) l / 3) to 1% (R022bs differs by 0.9%, the other sets
+    by at most 0.2%)."""
+    table = {"R028bs": (0.444, 8704.0, 0.0765, 0.008, 0.0154),
+             "R022bs": (0.339, 22590.0, 0.0355, 0.008, 0.00349),
+             "R029bs": (0.0809, 8037.0, 0.0591, 0.008, 0.000554),
+             "R020s": (0.0785, 16180.0, 0.0256, 0.008, 0.000259),
+             "R030s": (0.0122, 6250.0, 0.0410, 0.004, 0.0000162),
+             "R019s": (0.00876, 32814.0, 0.0251, 0.004, 0.00000159),
+             "R032s": (0.00391, 20067.0, 0.051, 0.004, 0.000000518)}
+    for name, (eta, rho, gdot, dt, lvi) in table.items():
+        p = configs.r_sheared(name)
+        assert (p["eta"], p["rho"], p["gdot"], p["dt"]) == (eta, rho, gdot, dt)
+        assert (p["nx"], p["ny"], p["lx"], p["ly"]) == (1024, 512, 2.0, 1.0)
+        L_VI, t_VI = series.visco_inertial_scales(p)
+        assert abs(L_VI - lvi) <= 0.01 * lvi, (name, L_VI, lvi)
+        assert abs(t_VI - L_VI * eta / series.interfacial_tension(p)) <= 1e-12 * t_VI
+    assert abs(series.interfacial_tension(configs.r_sheared("R020s"))
+               - 2.0 * np.sqrt(2.0) * 0.00156 / 3.0) <= 1e-15
+
+
+def test_power_fit_slope_and_error():
+    """An exact power law gives its exponent with zero error; scatter of known
+    size gives the textbook standard error of a regression slope."""
+    x = np.logspace(-7, -0.5, 7)
+    e, se = series.power_fit(x, 3.0 * x ** -0.62)
+    assert abs(e + 0.62) < 1e-12 and se < 1e-12
+    rng = np.random.default_rng(5)
+    noise = rng.normal(0.0, 0.05, x.size)
+    e, se = series.power_fit(x, 3.0 * x ** -0.62 * np.exp(noise))
+    lx = np.log(x)
+    ly = np.log(3.0 * x ** -0.62 * np.exp(noise))
+    # textbook simple regression: slope from centred sums, intercept from the
+    # means, standard error from the residual variance over n - 2
+    sxx = np.sum((lx - lx.mean()) ** 2)
+    slope = np.sum((lx - lx.mean()) * (ly - ly.mean())) / sxx
+    resid = ly - (ly.mean() + slope * (lx - lx.mean()))
+    expect = np.sqrt((resid @ resid) / (x.size - 2) / sxx)
+    assert abs(e - slope) <= 1e-12
+    assert abs(se - expect) <= 1e-10 * expect

@@ -61,3 +61,17 @@ def test_dv_unsheared_step_matches_oracle(name):
     st = mh.run(op, mh.initial_state(op, phi0, None), 20)
     assert rel(g["phi"], st.phi) <= 1e-10
     assert rel(g["psi"], st.psi) <= 1e-10
+
+
+def test_inertial_sheared_step_matches_oracle():
+    """Table I set R029bs (inertial, sheared, 1024 x 512): 20 steps, FP64."""
+    p = configs.r_sheared("R029bs")
+    phi0 = inputs.noise_phi0(512, 1024, 44, amp=configs.DV_AMP)
+    print("case R029bs 1024x512 20 steps", flush=True)
+    with le.Context(p, phi0) as c:
+        c.step(20)
+        g = c.get_state()
+    op = mh.Params(**p)
+    st = mh.run(op, mh.initial_state(op, phi0, None), 20)
+    for k in ("phi", "omega", "psi"):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k
