@@ -85,3 +85,21 @@ R_SHEARED = {
 def r_sheared(name):
     eta, rho, gdot, dt = R_SHEARED[name]
     return paper_units(0.00156, eta, rho, gdot, 2.0, 1024, 512, dt)
+
+
+# Zero-shear viscous-to-inertial series of Table I (sets R028u .. R032u):
+# (eta, rho); l = 0.00156, box 1 x 1 on 512 x 512, dt = 0.008.
+R_UNSHEARED = {
+    "R028u": (0.111, 136.0),
+    "R022u": (0.196, 2510.0),
+    "R029u": (0.0467, 893.0),
+    "R020u": (0.0785, 16180.0),
+    "R030u": (0.0122, 6250.0),
+    "R019u": (0.00876, 32814.0),
+    "R032u": (0.00391, 20067.0),
+}
+
+
+def r_unsheared(name):
+    eta, rho = R_UNSHEARED[name]
+    return paper_units(0.00156, eta, rho, 0.0, 1.0, 512, 512, 0.008)

@@ -83,3 +83,15 @@ def test_power_fit_slope_and_error():
     expect = np.sqrt((resid @ resid) / (x.size - 2) / sxx)
     assert abs(e - slope) <= 1e-12
     assert abs(se - expect) <= 1e-10 * expect
+
+
+def test_inertial_unsheared_presets_follow_table_one():
+    """Sets R028u .. R032u of Table I: (eta, rho), zero shear, 512^2, box 1,
+    dt = 0.008."""
+    table = {"R028u": (0.111, 136.0), "R022u": (0.196, 2510.0), "R029u": (0.0467, 893.0),
+             "R020u": (0.0785, 16180.0), "R030u": (0.0122, 6250.0),
+             "R019u": (0.00876, 32814.0), "R032u": (0.00391, 20067.0)}
+    for name, (eta, rho) in table.items():
+        p = configs.r_unsheared(name)
+        assert (p["eta"], p["rho"], p["gdot"], p["dt"]) == (eta, rho, 0.0, 0.008)
+        assert (p["nx"], p["ny"], p["lx"], p["ly"]) == (512, 512, 1.0, 1.0)
