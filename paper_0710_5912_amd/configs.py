@@ -34,8 +34,8 @@ def paper_units(l, eta, rho, gdot, lx, nx, ny, dt):
 
 # Inertialess sheared series of Table I (sets DV1s .. DV6s): l = 0.00156,
 # rho = 0, box 2 x 1, 1024 x 512, dt = 0.016; the sets differ in eta and
-# the shear rate.  phi0 uniform in [-0.01, 0.01] (Section III initial
-# condition).
+# the shear rate.  phi0 uniform in [-0.01, 0.01] (the initial condition of
+# Section VIII).
 DV_SHEARED = {
     "DV1s": (1000.0, 0.01),
     "DV2s": (100.0, 0.01),

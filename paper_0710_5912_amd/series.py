@@ -1,7 +1,7 @@
 """Time series of one run: the characteristic lengths against strain.
 
 Drives a Context through `steps` steps and samples the observables every
-`every` steps (Section IV: L_s from the structure factor, L_par and L_perp
+`every` steps (Section VI: L_s from the structure factor, L_par and L_perp
 from the principal axes of the second-moment tensor of S(q), the excess
 shear stress).  Every step and observable runs in the library; this module
 only loops and collects.
@@ -42,7 +42,7 @@ def run_series(params, phi0, steps: int, every: int, precision: str = "fp64", st
 
 
 def fit_power(t, L, t_min: float = 40.0, L_max: float = 0.02, n_int: int = 400):
-    """Growth exponent of a coarsening segment (Section V A protocol): samples
+    """Growth exponent of a coarsening segment (the protocol of Section VIII A): samples
     with t < t_min are discarded as the initial transient, the segment is cut
     once L reaches L_max, and an offset t_int is subtracted from t.  t_int is
     chosen (on a grid in [-4 t_first, t_first)) as the one whose straight-line
@@ -78,7 +78,7 @@ def interfacial_tension(params) -> float:
 
 def visco_inertial_scales(params):
     """(L_VI, t_VI) = (eta^2 / (rho sigma), eta^3 / (rho sigma^2)), the
-    viscous-to-inertial crossover length and time (Section III)."""
+    viscous-to-inertial crossover length and time (Section VI)."""
     s = interfacial_tension(params)
     eta, rho = params["eta"], params["rho"]
     return eta * eta / (rho * s), eta ** 3 / (rho * s * s)
@@ -97,7 +97,7 @@ def steady_average(res, strain_min: float = 100.0):
 
 def power_fit(x, y):
     """Least-squares slope of log y against log x and its standard error
-    (the power-law fits of the steady-state scaling plot, Section V B)."""
+    (the power-law fits of the steady-state scaling plot, Section VIII B)."""
     lx = np.log(np.asarray(x, dtype=float))
     ly = np.log(np.asarray(y, dtype=float))
     a = np.vstack([lx, np.ones_like(lx)]).T
