@@ -1,0 +1,118 @@
+"""The Table I campaigns as commands (one JSON line per set, then a summary).
+
+  python -m paper_0710_5912_amd.campaigns dv-sheared   [--steps 500000] [--every 5000]
+  python -m paper_0710_5912_amd.campaigns zero-shear   [--seeds 4]
+  python -m paper_0710_5912_amd.campaigns steady-states [--strain 150]
+
+dv-sheared: the inertialess sheared sets DV1s .. DV6s, L_par and L_perp
+against strain (Section VIII D).  zero-shear: the sets DV1u .. DV6u and
+R028u .. R032u to L_s = 0.025, growth exponents of L_s(t) by the protocol of
+Section VIII A with a fitted offset.  steady-states: the inertial sheared
+sets of the scaling plot to the given strain, averages over strain >= 100
+and the power-law fits of L_par, L_perp against gdot t_VI (Section VIII B).
+Every step and observable runs in the library (FP64).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import configs, inputs, le, series
+
+
+def dv_sheared(steps: int, every: int):
+    for k, name in enumerate(configs.DV_SHEARED):
+        p = configs.dv_sheared(name)
+        phi0 = inputs.noise_phi0(512, 1024, 500 + k, amp=configs.DV_AMP)
+        try:
+            r = series.run_series(p, phi0, steps, every)
+        except (le.LeError, FloatingPointError) as ex:
+            print(json.dumps({"set": name, "stopped": str(ex)}), flush=True)
+            continue
+        print(json.dumps({"set": name, "steps": steps, "wall_s": r["wall_s"],
+                          "site_updates_per_s": r["site_updates_per_s"],
+                          "strain": r["strain"].tolist(), "L_par": r["L_par"].tolist(),
+                          "L_perp": r["L_perp"].tolist()}), flush=True)
+
+
+def _to_length(p, phi0, L_stop=0.025, chunk=250, max_chunks=1600):
+    t, L = [], []
+    with le.Context(p, phi0) as c:
+        for _ in range(max_chunks):
+            c.step(chunk)
+            o, _ = c.observables(sk=False)
+            t.append(o["t"])
+            L.append(o["Ls"])
+            if o["Ls"] >= L_stop:
+                break
+    return np.asarray(t), np.asarray(L)
+
+
+def zero_shear(seeds: int):
+    sets = [(n, configs.dv_unsheared(n)) for n in configs.DV_UNSHEARED] + \
+           [(n, configs.r_unsheared(n)) for n in configs.R_UNSHEARED]
+    summary = {}
+    for k, (name, p) in enumerate(sets):
+        ex = []
+        for seed in range(seeds):
+            phi0 = inputs.noise_phi0(512, 512, 3000 + 100 * k + seed, amp=configs.DV_AMP)
+            try:
+                t, L = _to_length(p, phi0)
+                e, ti, n = series.fit_power(t, L)
+            except (le.LeError, ValueError) as err:
+                print(json.dumps({"set": name, "seed": seed, "stopped": str(err)}), flush=True)
+                continue
+            ex.append(e)
+            print(json.dumps({"set": name, "seed": seed, "t_end": float(t[-1]),
+                              "exponent": e, "t_int": ti, "samples": n}), flush=True)
+        if ex:
+            summary[name] = {"mean": float(np.mean(ex)), "sd": float(np.std(ex)), "runs": len(ex)}
+    print(json.dumps({"summary": summary}), flush=True)
+
+
+def steady_states(strain: float):
+    rows = []
+    for k, name in enumerate(configs.R_SHEARED):
+        p = configs.r_sheared(name)
+        steps = int(round(strain / (p["gdot"] * p["dt"])))
+        phi0 = inputs.noise_phi0(512, 1024, 800 + k, amp=configs.DV_AMP)
+        r = series.run_series(p, phi0, steps, max(1, steps // 300))
+        avg = series.steady_average(r, 100.0)
+        L_VI, t_VI = series.visco_inertial_scales(p)
+        row = {"set": name, "steps": steps, "wall_s": r["wall_s"], "gdot_t_VI": p["gdot"] * t_VI,
+               "L_VI": L_VI, **avg}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    x = [r["gdot_t_VI"] for r in rows]
+    ep = series.power_fit(x, [r["L_par"] / r["L_VI"] for r in rows])
+    eq = series.power_fit(x, [r["L_perp"] / r["L_VI"] for r in rows])
+    print(json.dumps({"summary": {"L_par_exponent": ep, "L_perp_exponent": eq}}), flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("dv-sheared")
+    a.add_argument("--steps", type=int, default=500000)
+    a.add_argument("--every", type=int, default=5000)
+    b = sub.add_parser("zero-shear")
+    b.add_argument("--seeds", type=int, default=4)
+    c = sub.add_parser("steady-states")
+    c.add_argument("--strain", type=float, default=150.0)
+    args = ap.parse_args(argv)
+    t0 = time.time()
+    if args.cmd == "dv-sheared":
+        dv_sheared(args.steps, args.every)
+    elif args.cmd == "zero-shear":
+        zero_shear(args.seeds)
+    else:
+        steady_states(args.strain)
+    print(json.dumps({"wall_s": time.time() - t0}), file=sys.stderr, flush=True)
+
+
+if __name__ == "__main__":
+    main()
