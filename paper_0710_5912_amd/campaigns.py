@@ -2,14 +2,15 @@
 
   python -m paper_0710_5912_amd.campaigns dv-sheared   [--steps 500000] [--every 5000]
   python -m paper_0710_5912_amd.campaigns zero-shear   [--seeds 4]
-  python -m paper_0710_5912_amd.campaigns steady-states [--strain 150]
+  python -m paper_0710_5912_amd.campaigns steady-states [--strain 150] [--lb-sets]
 
 dv-sheared: the inertialess sheared sets DV1s .. DV6s, L_par and L_perp
 against strain (Section VIII D).  zero-shear: the sets DV1u .. DV6u and
 R028u .. R032u to L_s = 0.025, growth exponents of L_s(t) by the protocol of
 Section VIII A with a fitted offset.  steady-states: the inertial sheared
 sets of the scaling plot to the given strain, averages over strain >= 100
-and the power-law fits of L_par, L_perp against gdot t_VI (Section VIII B).
+and the power-law fits of L_par, L_perp against gdot t_VI (Section VIII B);
+with --lb-sets the sets R028s, R022s, R029s of Table I, averages only.
 Every step and observable runs in the library (FP64).
 """
 from __future__ import annotations
@@ -74,12 +75,13 @@ def zero_shear(seeds: int):
     print(json.dumps({"summary": summary}), flush=True)
 
 
-def steady_states(strain: float):
+def steady_states(strain: float, lb_sets: bool = False):
     rows = []
-    for k, name in enumerate(configs.R_SHEARED):
+    names = configs.R_SHEARED_LB if lb_sets else configs.R_SHEARED
+    for k, name in enumerate(names):
         p = configs.r_sheared(name)
         steps = int(round(strain / (p["gdot"] * p["dt"])))
-        phi0 = inputs.noise_phi0(512, 1024, 800 + k, amp=configs.DV_AMP)
+        phi0 = inputs.noise_phi0(512, 1024, (900 if lb_sets else 800) + k, amp=configs.DV_AMP)
         r = series.run_series(p, phi0, steps, max(1, steps // 300))
         avg = series.steady_average(r, 100.0)
         L_VI, t_VI = series.visco_inertial_scales(p)
@@ -87,6 +89,8 @@ def steady_states(strain: float):
                "L_VI": L_VI, **avg}
         rows.append(row)
         print(json.dumps(row), flush=True)
+    if lb_sets:
+        return
     x = [r["gdot_t_VI"] for r in rows]
     ep = series.power_fit(x, [r["L_par"] / r["L_VI"] for r in rows])
     eq = series.power_fit(x, [r["L_perp"] / r["L_VI"] for r in rows])
@@ -103,6 +107,8 @@ def main(argv=None):
     b.add_argument("--seeds", type=int, default=4)
     c = sub.add_parser("steady-states")
     c.add_argument("--strain", type=float, default=150.0)
+    c.add_argument("--lb-sets", action="store_true",
+                   help="the sets R028s, R022s, R029s instead of the scaling-plot sets")
     args = ap.parse_args(argv)
     t0 = time.time()
     if args.cmd == "dv-sheared":
@@ -110,7 +116,7 @@ def main(argv=None):
     elif args.cmd == "zero-shear":
         zero_shear(args.seeds)
     else:
-        steady_states(args.strain)
+        steady_states(args.strain, args.lb_sets)
     print(json.dumps({"wall_s": time.time() - t0}), file=sys.stderr, flush=True)
 
 

@@ -52,7 +52,11 @@ def test_inertial_sheared_presets_and_crossover_scales():
              "R020s": (0.0785, 16180.0, 0.0256, 0.008, 0.000259),
              "R030s": (0.0122, 6250.0, 0.0410, 0.004, 0.0000162),
              "R019s": (0.00876, 32814.0, 0.0251, 0.004, 0.00000159),
-             "R032s": (0.00391, 20067.0, 0.051, 0.004, 0.000000518)}
+             "R032s": (0.00391, 20067.0, 0.051, 0.004, 0.000000518),
+             "R028s": (0.111, 136.0, 0.0765, 0.008, 0.0616),
+             "R022s": (0.196, 2510.0, 0.0205, 0.008, 0.0104),
+             "R029s": (0.0467, 893.0, 0.0341, 0.008, 0.00166)}
+    assert set(table) == set(configs.R_SHEARED) | set(configs.R_SHEARED_LB)
     for name, (eta, rho, gdot, dt, lvi) in table.items():
         p = configs.r_sheared(name)
         assert (p["eta"], p["rho"], p["gdot"], p["dt"]) == (eta, rho, gdot, dt)

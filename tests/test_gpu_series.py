@@ -63,11 +63,13 @@ def test_dv_unsheared_step_matches_oracle(name):
     assert rel(g["psi"], st.psi) <= 1e-10
 
 
-def test_inertial_sheared_step_matches_oracle():
-    """Table I set R029bs (inertial, sheared, 1024 x 512): 20 steps, FP64."""
-    p = configs.r_sheared("R029bs")
+@pytest.mark.parametrize("name", ["R029bs", "R028s"])
+def test_inertial_sheared_step_matches_oracle(name):
+    """Table I sets R029bs and R028s (inertial, sheared, 1024 x 512; R028s has
+    the lowest density of the table): 20 steps, FP64."""
+    p = configs.r_sheared(name)
     phi0 = inputs.noise_phi0(512, 1024, 44, amp=configs.DV_AMP)
-    print("case R029bs 1024x512 20 steps", flush=True)
+    print(f"case {name} 1024x512 20 steps", flush=True)
     with le.Context(p, phi0) as c:
         c.step(20)
         g = c.get_state()
