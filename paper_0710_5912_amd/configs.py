@@ -32,6 +32,12 @@ def paper_units(l, eta, rho, gdot, lx, nx, ny, dt):
                 kappa=l * l, M=l * l, eta=eta, rho=rho, dt=dt)
 
 
+def _refine(refine):
+    if refine not in (1, 2):
+        raise ValueError("refine must be 1 (the grid of Table I) or 2 (half its mesh interval)")
+    return refine
+
+
 # Inertialess sheared series of Table I (sets DV1s .. DV6s): l = 0.00156,
 # rho = 0, box 2 x 1, 1024 x 512, dt = 0.016; the sets differ in eta and
 # the shear rate.  phi0 uniform in [-0.01, 0.01] (the initial condition of
@@ -47,9 +53,13 @@ DV_SHEARED = {
 DV_AMP = 0.01
 
 
-def dv_sheared(name):
+def dv_sheared(name, refine=1):
+    """refine = 2: half the mesh interval at the same l (2048 x 1024).  The
+    explicit Cahn-Hilliard terms then need dt = 0.004: with |s| up to 1 the
+    lab wavenumber reaches |q|^2 = 5 (pi / delta)^2 (series.explicit_ch_number)."""
     eta, gdot = DV_SHEARED[name]
-    return paper_units(0.00156, eta, 0.0, gdot, 2.0, 1024, 512, 0.016)
+    r = _refine(refine)
+    return paper_units(0.00156, eta, 0.0, gdot, 2.0, 1024 * r, 512 * r, 0.016 / (r * r))
 
 
 # Zero-shear diffusive-to-viscous series of Table I (sets DV1u .. DV6u):
@@ -64,8 +74,10 @@ DV_UNSHEARED = {
 }
 
 
-def dv_unsheared(name):
-    return paper_units(0.00156, DV_UNSHEARED[name], 0.0, 0.0, 1.0, 512, 512, 0.016)
+def dv_unsheared(name, refine=1):
+    """refine = 2: 1024^2 at the same l and dt (still within the explicit bound)."""
+    r = _refine(refine)
+    return paper_units(0.00156, DV_UNSHEARED[name], 0.0, 0.0, 1.0, 512 * r, 512 * r, 0.016)
 
 
 # Inertial sheared sets of Table I used for the steady-state scaling plot

@@ -15,10 +15,12 @@ import numpy as np
 from . import le
 
 
-def run_series(params, phi0, steps: int, every: int, precision: str = "fp64", stream=None):
+def run_series(params, phi0, steps: int, every: int, precision: str = "fp64", stream=None,
+               on_sample=None):
     """Advance a run from phi0 (omega0 = 0) and return the sampled series:
     dict of arrays t, strain, Ls, L_par, L_perp, sigma_xy, mean_phi, plus the
-    GPU-side wall time of the stepping (seconds) and the site-updates/s."""
+    GPU-side wall time of the stepping (seconds) and the site-updates/s.
+    on_sample(steps_done, observables) is called after each sample."""
     keys = ("t", "strain", "Ls", "L_par", "L_perp", "sigma_xy", "mean_phi")
     out = {k: [] for k in keys}
     wall = 0.0
@@ -35,10 +37,25 @@ def run_series(params, phi0, steps: int, every: int, precision: str = "fp64", st
                 raise FloatingPointError(f"state not finite at step {done}")
             for k in keys:
                 out[k].append(o[k])
+            if on_sample is not None:
+                on_sample(done, o)
     res = {k: np.asarray(v) for k, v in out.items()}
     res["wall_s"] = wall
     res["site_updates_per_s"] = params["nx"] * params["ny"] * steps / wall
     return res
+
+
+def explicit_ch_number(params):
+    """dt M max|q_lab|^2 (3B - A) / 2 for a run: the Cahn-Hilliard terms taken
+    explicitly (the A and f terms of Appendix B) stay stable while it is <= 1
+    (linearised about phi = +-1).  In the cosheared frame the lab wave vector
+    is (q_x, q_y - s q_x) with |s| <= Lx / (2 Ly) under shear, so the largest
+    |q_lab|^2 is reached at the corner mode with the largest |s|."""
+    qx = np.pi * params["nx"] / params["lx"]
+    qy = np.pi * params["ny"] / params["ly"]
+    smax = params["lx"] / (2.0 * params["ly"]) if params["gdot"] != 0.0 else 0.0
+    q2 = qx * qx + (qy + smax * qx) ** 2
+    return params["dt"] * params["M"] * q2 * (3.0 * params["B"] - params["A"]) / 2.0
 
 
 def fit_power(t, L, t_min: float = 40.0, L_max: float = 0.02, n_int: int = 400):

@@ -1,6 +1,9 @@
 """Workload presets against the paper's parameter tables, and the growth-law
 fit of the coarsening series."""
 import numpy as np
+import pytest
+
+from oracle import model_h as mh
 
 from paper_0710_5912_amd import configs, series
 
@@ -99,3 +102,49 @@ def test_inertial_unsheared_presets_follow_table_one():
         p = configs.r_unsheared(name)
         assert (p["eta"], p["rho"], p["gdot"], p["dt"]) == (eta, rho, 0.0, 0.008)
         assert (p["nx"], p["ny"], p["lx"], p["ly"]) == (512, 512, 1.0, 1.0)
+
+
+def test_explicit_ch_number_is_the_oracle_stability_edge():
+    """A Nyquist-corner perturbation of phi = 1 under the oracle's Cahn-Hilliard
+    stage (Appendix B, stage 1b; no flow) decays at explicit_ch_number 0.98 and
+    grows at 1.02: the number is the edge of the linearised scheme (the nabla^4
+    Crank-Nicolson part cancels from the edge; kappa is small here so that it
+    does not also pull the growth factor towards -1 on both sides).  Under shear the bound's lab
+    wavenumber 5 (pi/delta)^2 caps the oracle's |lambda| at s = -1 and is
+    reached to within the grid's last modes."""
+    base = dict(nx=32, ny=32, lx=1.0, ly=1.0, gdot=0.0, A=1.0, B=1.0, kappa=1e-6,
+                M=0.7e-3, eta=1.0, rho=0.0, dt=1.0)
+    unit = series.explicit_ch_number(base)
+    j, i = np.mgrid[0:32, 0:32]
+    mode = np.where((i + j) % 2 == 0, 1.0, -1.0)
+    growth = {}
+    for target in (0.98, 1.02):
+        p = dict(base, dt=target / unit)
+        assert abs(series.explicit_ch_number(p) - target) < 1e-12
+        op = mh.Params(**p)
+        phi = 1.0 + 1e-8 * mode
+        for _ in range(200):
+            phi = mh.stage_cahn_hilliard(op, phi, phi ** 3, 0.0)
+        growth[target] = float(np.max(np.abs(phi - 1.0)) / 1e-8)
+    assert growth[0.98] < 1e-2 and growth[1.02] > 1e2, growth
+    sh = mh.Params(nx=128, ny=64, lx=2.0, ly=1.0, gdot=0.01)
+    lam_max = float(np.max(-mh.symbol_laplacian(sh, -1.0)))
+    bound = 5.0 * (np.pi * 64) ** 2
+    assert 0.9 * bound < lam_max <= bound
+
+
+def test_presets_within_the_explicit_bound():
+    """Every Table I preset (and the refined DV grids) keeps the explicit
+    Cahn-Hilliard terms stable; the refined sheared grid at the table's dt
+    would not (2.0), hence its dt = 0.004."""
+    ps = [configs.dv_sheared(n, r) for n in configs.DV_SHEARED for r in (1, 2)]
+    ps += [configs.dv_unsheared(n, r) for n in configs.DV_UNSHEARED for r in (1, 2)]
+    ps += [configs.r_sheared(n) for n in list(configs.R_SHEARED) + list(configs.R_SHEARED_LB)]
+    ps += [configs.r_unsheared(n) for n in configs.R_UNSHEARED]
+    assert all(series.explicit_ch_number(p) <= 0.81 for p in ps)
+    p = configs.dv_sheared("DV6s", 2)
+    assert (p["nx"], p["ny"], p["dt"]) == (2048, 1024, 0.004)
+    assert configs.dv_unsheared("DV6u", 2)["nx"] == 1024
+    assert abs(series.explicit_ch_number(dict(p, dt=0.016)) - 2.0148) < 1e-3
+    with pytest.raises(ValueError):
+        configs.dv_sheared("DV1s", 3)

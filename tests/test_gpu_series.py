@@ -34,6 +34,21 @@ def test_dv_step_matches_oracle(name):
     assert rel(g["psi"], st.psi) <= 1e-10
 
 
+def test_dv_refined_step_matches_oracle():
+    """DV6s on the refined grid (2048 x 1024, half the mesh interval at the same
+    l, dt = 0.004): 10 steps, FP64."""
+    p = configs.dv_sheared("DV6s", 2)
+    phi0 = inputs.noise_phi0(1024, 2048, 45, amp=configs.DV_AMP)
+    print("case DV6s 2048x1024 10 steps", flush=True)
+    with le.Context(p, phi0) as c:
+        c.step(10)
+        g = c.get_state()
+    op = mh.Params(**p)
+    st = mh.run(op, mh.initial_state(op, phi0, None), 10)
+    assert rel(g["phi"], st.phi) <= 1e-10
+    assert rel(g["psi"], st.psi) <= 1e-10
+
+
 def test_dv_series_runner():
     """DV4s for 3000 steps sampled every 500: strain = gdot t, mean phi kept,
     every sample finite, the domains coarsen."""
