@@ -148,11 +148,13 @@ constexpr int fft_passes(int L, int E) {
 
 // v[r] *= w^r (r = 1 .. E-1; conj(w)^r for DIR > 0).  The powers come from
 // a product tree of depth <= 3 in FP64 (error ~1e-15), each rounded once to T.
-template <typename T, int DIR, int E>
-__device__ __forceinline__ void twiddle_powers(c2<T>* v, c2<double> w1) {
+// With v1 != nullptr (TWO) the same powers also multiply v1.
+template <typename T, int DIR, int E, bool TWO = false>
+__device__ __forceinline__ void twiddle_powers(c2<T>* v, c2<double> w1, c2<T>* v1 = nullptr) {
   auto app = [&](int r, c2<double> wd) {
     const c2<T> w = {static_cast<T>(wd.x), static_cast<T>(wd.y)};
     v[r] = DIR < 0 ? cmul(v[r], w) : cmulc(v[r], w);
+    if constexpr (TWO) v1[r] = DIR < 0 ? cmul(v1[r], w) : cmulc(v1[r], w);
   };
   if constexpr (E >= 2) app(1, w1);
   if constexpr (E >= 4) {
@@ -235,6 +237,74 @@ __device__ __forceinline__ void fft_group(c2<T>* v, c2<T>* lds, int LS,
       const int idxD = (t / Ns) * Ns * E + k;
 #pragma unroll
       for (int r = 0; r < E; ++r) lds[(idxD + r * Ns) * LS] = v[r];
+      Ns *= E;
+    }
+  }
+}
+
+// Two independent length-L transforms (v0 in lds0, v1 in lds1) by the same
+// group, pass by pass: each pass of both shares one pair of barriers, and
+// each result equals fft_group's for that array alone (same operations).
+template <typename T, int L, int E, int DIR>
+__device__ __forceinline__ void fft_group2(c2<T>* v0, c2<T>* v1, c2<T>* lds0, c2<T>* lds1,
+                                           int LS, gp<const c2<double>> __restrict__ tw,
+                                           int t) {
+  constexpr int P = L / E;
+  constexpr int R0 = first_radix(L, E);
+  constexpr int Q = E / R0;
+  static_assert(L % E == 0 && E % R0 == 0, "bad FFT factorisation");
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    c2<T> b0[R0], b1[R0];
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      b0[r] = v0[q + r * Q];
+      b1[r] = v1[q + r * Q];
+    }
+    dft_reg<T, DIR, R0>(b0);
+    dft_reg<T, DIR, R0>(b1);
+    if constexpr (L == R0) {
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        v0[r] = b0[r];
+        v1[r] = b1[r];
+      }
+    } else {
+      const int j = t + q * P;
+#pragma unroll
+      for (int r = 0; r < R0; ++r) {
+        lds0[(j * R0 + r) * LS] = b0[r];
+        lds1[(j * R0 + r) * LS] = b1[r];
+      }
+    }
+  }
+  if constexpr (L > R0) {
+    constexpr int NP = fft_passes(L, E);
+    auto tw_of = [&](int Ns) { return ldg<double>(tw + (2 * L / E) / Ns * (t & (Ns - 1))); };
+    c2<double> wn = tw_of(R0);
+    int Ns = R0;
+#pragma unroll
+    for (int pass = 0; pass < NP; ++pass) {
+      const c2<double> w = wn;
+      if (pass + 1 < NP) wn = tw_of(Ns * E);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        v0[r] = lds0[(t + r * P) * LS];
+        v1[r] = lds1[(t + r * P) * LS];
+      }
+      twiddle_powers<T, DIR, E, true>(v0, w, v1);
+      dft_reg<T, DIR, E>(v0);
+      dft_reg<T, DIR, E>(v1);
+      if (pass + 1 == NP) break;
+      __syncthreads();
+      const int k = t & (Ns - 1);
+      const int idxD = (t / Ns) * Ns * E + k;
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        lds0[(idxD + r * Ns) * LS] = v0[r];
+        lds1[(idxD + r * Ns) * LS] = v1[r];
+      }
       Ns *= E;
     }
   }

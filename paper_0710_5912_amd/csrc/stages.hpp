@@ -25,6 +25,9 @@ constexpr int col_elems(int L) { return L >= 8 ? 8 : L; }
 
 // Occupancy hint for the stage kernels (waves per SIMD the register
 // allocation must allow).
+#ifndef LE_COL_DUAL
+#define LE_COL_DUAL 1
+#endif
 #ifndef LE_WAVES
 #define LE_WAVES 2
 #endif
@@ -1051,7 +1054,14 @@ __global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void
   auto tw = to_global<const c2<double>>(R.twy);
   constexpr int NIN = (MODE == COL_CH || MODE == COL_FLOW) ? 2 : 1;
   constexpr int NOUT = (MODE == COL_FLOW) ? 2 : 1;
-  __shared__ c2<T> lds[C::CW * L];
+  // Both fields' transforms side by side (one barrier per pass for the two)
+  // where LDS holds two areas: in FP32 and for columns up to 512 values (in
+  // FP64 at 2048 and 4096 the doubled LDS halves the blocks per CU and the
+  // pass runs slower).
+  constexpr bool DUAL = LE_COL_DUAL && NIN == 2 && (sizeof(T) == 4 || L <= 512) &&
+                        2L * C::CW * L * (long)sizeof(c2<T>) <= 160L * 1024;
+  __shared__ c2<T> lds[(DUAL ? 2 : 1) * C::CW * L];
+  c2<T>* const lds1 = lds + (DUAL ? C::CW * L : 0);
   const int S = geo.nx / 2 + 1;
   const int c = threadIdx.x % C::CW, t = threadIdx.x / C::CW;
   const int m0 = bp.x * C::CW + c;
@@ -1060,8 +1070,14 @@ __global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void
   c2<T> v0[C::E], v1[C::E];
 #pragma unroll
   for (int q = 0; q < C::E; ++q) v0[q] = ldg<T>(in0 + (size_t)(t + q * C::P) * S + m);
-  fft_group<T, L, C::E, -1>(v0, lds + c, C::CW, tw, t);
-  if constexpr (NIN == 2) {
+  if constexpr (DUAL) {
+#pragma unroll
+    for (int q = 0; q < C::E; ++q) v1[q] = ldg<T>(in1 + (size_t)(t + q * C::P) * S + m);
+    fft_group2<T, L, C::E, -1>(v0, v1, lds + c, lds1 + c, C::CW, tw, t);
+  } else {
+    fft_group<T, L, C::E, -1>(v0, lds + c, C::CW, tw, t);
+  }
+  if constexpr (NIN == 2 && !DUAL) {
 #pragma unroll
     for (int q = 0; q < C::E; ++q) v1[q] = ldg<T>(in1 + (size_t)(t + q * C::P) * S + m);
     __syncthreads();
@@ -1111,6 +1127,17 @@ __global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void
     LE_SCHED_FENCE();
   }
   __syncthreads();
+  if constexpr (DUAL && NOUT == 2) {
+    fft_group2<T, L, C::E, +1>(v0, v1, lds + c, lds1 + c, C::CW, tw, t);
+    if (ok) {
+#pragma unroll
+      for (int q = 0; q < C::E; ++q) {
+        stg<T>(out0 + (size_t)(t + q * C::P) * S + m, v0[q]);
+        stg<T>(out1 + (size_t)(t + q * C::P) * S + m, v1[q]);
+      }
+    }
+    return;
+  }
   fft_group<T, L, C::E, +1>(v0, lds + c, C::CW, tw, t);
   if (ok) {
 #pragma unroll

@@ -152,6 +152,29 @@ def test_nonfinite_state_is_reported():
     ctx.close()
 
 
+def test_zero_steps_is_a_no_op_and_negative_steps_are_rejected():
+    """le_step(c, 0) leaves the state, step counter and clock alone; a negative
+    count is LE_EINVAL and changes nothing either."""
+    p = params(32, 32, gdot=0.4)
+    phi0 = inputs.noise_phi0(32, 32, 9, amp=0.3)
+    with le.Context(p, phi0) as ctx:
+        ctx.step(3)
+        before = ctx.get_state()
+        ctx.step(0)
+        with pytest.raises(le.LeError) as ei:
+            ctx.step(-1)
+        assert ei.value.code == le.LE_EINVAL
+        after = ctx.get_state()
+        assert after["step"] == before["step"] == 3
+        for k in ("phi", "omega", "psi"):
+            assert np.array_equal(before[k], after[k]), k
+        ctx.step(2)
+        g = ctx.get_state()
+    op = mh.Params(**p)
+    st = mh.run(op, mh.initial_state(op, phi0), 5)
+    assert rel(g["phi"], st.phi) <= 1e-10
+
+
 @pytest.mark.parametrize("rho", [1.0, 0.0])
 def test_fp32_error_bound(rho):
     """FP32 bulk: error after 100 steps stays within the stated 2e-5 bound."""
