@@ -242,6 +242,29 @@ void le_batch_destroy(le_batch* b);  /* NULL-safe */
  */
 int le_corrector_load(le_ctx* c, const float* params, int32_t nparams, const float* scales);
 int le_step_corrected(le_ctx* c, int64_t ncoarse);
+
+/*
+ * Corrector audit (failure detection; the paper has no corrector, so this
+ * is a safeguard of the learned step, not part of the method).  With
+ * every > 0, le_step_corrected runs, after each `every` corrected steps, an
+ * audit window of `window` steps (fewer if the call ends first) twice from
+ * the same state: corrected, then plain.  The audit passes when the
+ * corrected state is finite, its L_s is within relative `tol` of the plain
+ * run's and its mean phi equals the plain run's (to 1e-9; FP32 runs 1e-5);
+ * then the corrected state continues.  On a failed audit the plain state is
+ * kept and every later corrected step of the context runs as a plain step
+ * (the fallback), until the next le_corrector_load or le_corrector_audit.
+ * every = 0 switches audits off (the default).  The context allocates two
+ * state snapshots (phi and the omega, psi row spectra) on the first call
+ * with every > 0.
+ * Errors: LE_EINVAL (no corrector loaded, every < 0, or every > 0 with
+ * window < 1 or tol < 0 or NaN), LE_ENOMEM.
+ * le_corrector_status: fallback (1 once an audit failed), the number of
+ * audits run and the last audit's relative L_s deviation (INFINITY when the
+ * corrected state was not finite); NULL outputs are skipped.
+ */
+int le_corrector_audit(le_ctx* c, int64_t every, int64_t window, double tol);
+int le_corrector_status(le_ctx* c, int32_t* fallback, int64_t* audits, double* last_dev);
 int le_restrict(le_ctx* c, int32_t factor, double* phi_out, double* omega_out);
 int le_set_fields(le_ctx* c, const double* phi, const double* omega, int64_t step);
 

@@ -157,6 +157,15 @@ struct le_ctx {
   int64_t stage_n[LE_NSTAGES] = {0};
   Net* net = nullptr;              // learned corrector (single inertial run)
   double* d_restrict = nullptr;    // restriction output
+  // corrector audit: every `audit_every` corrected steps a window of
+  // `audit_window` steps is run both corrected and plain from the same state
+  // (two snapshots of phi, omega_h, psi_h); a failed audit keeps the plain
+  // result and every later corrected step runs plain (until the next
+  // le_corrector_load or le_corrector_audit)
+  int64_t audit_every = 0, audit_window = 0, since_audit = 0, audits = 0;
+  double audit_tol = 0.0, audit_dev = 0.0;
+  bool corr_fallback = false;
+  void* snap[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
   // engines of several grid classes: one stream per class (default priority)
   // so that the classes' independent kernels overlap, forked from and joined
   // back into `stream` around every chunk of steps
@@ -208,6 +217,12 @@ void release(Engine* e) {
     e->net = nullptr;
   }
   if (e->d_restrict) (void)hipFree(e->d_restrict);
+  for (auto& sn : e->snap)
+    for (void*& b : sn)
+      if (b) {
+        (void)hipFree(b);
+        b = nullptr;
+      }
   for (hipStream_t cs : e->cls_streams)
     if (cs) (void)hipStreamDestroy(cs);
   e->cls_streams.clear();
@@ -915,8 +930,7 @@ int stage_times_of(Engine* e, double* ms, int64_t* launches, int32_t cap) {
 // Coarse steps each followed by the learned correction: omega to real
 // space, phi += r_phi - mean(r_phi), omega += r_omega, then psi from the
 // corrected omega by the Poisson solve at the step's strain offset.
-int step_corrected(Engine* e, int64_t ncoarse) {
-  if (!e || ncoarse < 0 || !e->net || e->nruns != 1) return LE_EINVAL;
+int corrected_steps(Engine* e, int64_t ncoarse) {
   RunHost& r = e->runs[0];
   const Ops& o = e->classes[r.cls].ops;
   const Run* d = desc(e, r);
@@ -963,10 +977,112 @@ int step_corrected(Engine* e, int64_t ncoarse) {
     LE_TRY(hipStreamSynchronize(e->stream));
     remaining -= count;
   }
+  return LE_OK;
+}
+
+// The state between steps: real phi and the row spectra of omega and psi.
+int copy_state(Engine* e, const RunHost& r, bool to_snap, int k) {
+  const int bufs[3] = {B_PHI, B_OM_S, B_PS_S};
+  const size_t bytes[3] = {r.n_real * r.tsize, r.n_spec * 2 * r.tsize, r.n_spec * 2 * r.tsize};
+  for (int i = 0; i < 3; ++i) {
+    void* live = r.buf[bufs[i]];
+    void* snap = e->snap[k][i];
+    LE_TRY(hipMemcpyAsync(to_snap ? snap : live, to_snap ? live : snap, bytes[i],
+                          hipMemcpyDeviceToDevice, e->stream));
+  }
+  return LE_OK;
+}
+
+// Mean phi and L_s of the current state.
+int audit_measure(Engine* e, const RunHost& r, double* mean, double* Ls, bool* finite) {
+  LE_RC(reduce_observables(e, r, true));
+  const double* h = e->h_out;
+  *mean = h[OBS_SUM_PHI] / (double)r.n_real;
+  *Ls = h[OBS_SUM_S_NZ] > 0.0 ? h[OBS_SUM_S_OVER_Q] / h[OBS_SUM_S_NZ] : 0.0;
+  *finite = h[OBS_NONFINITE] == 0.0;
+  return LE_OK;
+}
+
+// One audit window of n steps: corrected from the saved state, then plain
+// from the same state.  Passed (finite, L_s within the tolerance of the
+// plain run's, mean phi equal to 1e-9, FP32 runs 1e-5): the corrected state
+// is restored.
+// Failed: the plain state stays and the context falls back to plain steps.
+int audit_window(Engine* e, int64_t n) {
+  RunHost& r = e->runs[0];
+  const int64_t step0 = e->step, wraps0 = r.wraps;
+  LE_RC(copy_state(e, r, true, 0));
+  LE_RC(corrected_steps(e, n));
+  double mc, lc, mp, lp;
+  bool fc, fp;
+  LE_RC(audit_measure(e, r, &mc, &lc, &fc));
+  LE_RC(copy_state(e, r, true, 1));
+  const int64_t step1 = e->step, wraps1 = r.wraps;
+  LE_RC(copy_state(e, r, false, 0));
+  e->step = step0;
+  r.wraps = wraps0;
+  LE_RC(step_engine(e, n));
+  LE_RC(audit_measure(e, r, &mp, &lp, &fp));
+  if (!fp) return LE_ENONFINITE;
+  const double dev = lp > 0.0 ? std::fabs(lc - lp) / lp : (lc == lp ? 0.0 : INFINITY);
+  e->audits += 1;
+  e->audit_dev = fc ? dev : INFINITY;
+  const double mean_tol = r.tsize == sizeof(double) ? 1e-9 : 1e-5;
+  if (fc && dev <= e->audit_tol && std::fabs(mc - mp) <= mean_tol) {
+    LE_RC(copy_state(e, r, false, 1));
+    e->step = step1;
+    r.wraps = wraps1;
+  } else {
+    e->corr_fallback = true;
+  }
+  LE_TRY(hipStreamSynchronize(e->stream));
+  return LE_OK;
+}
+
+int step_corrected(Engine* e, int64_t ncoarse) {
+  if (!e || ncoarse < 0 || !e->net || e->nruns != 1) return LE_EINVAL;
+  RunHost& r = e->runs[0];
+  int64_t remaining = ncoarse;
+  while (remaining > 0 && !e->corr_fallback) {
+    int64_t n = remaining;
+    if (e->audit_every > 0) {
+      if (e->since_audit >= e->audit_every) {
+        n = std::min(remaining, e->audit_window);
+        LE_RC(audit_window(e, n));
+        e->since_audit = 0;
+        remaining -= n;
+        continue;
+      }
+      n = std::min(remaining, e->audit_every - e->since_audit);
+    }
+    LE_RC(corrected_steps(e, n));
+    e->since_audit += n;
+    remaining -= n;
+  }
+  if (remaining > 0) return step_engine(e, remaining);
   if (ncoarse > 0) {
     LE_RC(reduce_observables(e, r, false));
     if (e->h_out[OBS_NONFINITE] != 0.0) return LE_ENONFINITE;
   }
+  return LE_OK;
+}
+
+int corrector_audit(Engine* e, int64_t every, int64_t window, double tol) {
+  if (!e || !e->net || every < 0 || (every > 0 && (window < 1 || !(tol >= 0.0))))
+    return LE_EINVAL;
+  RunHost& r = e->runs[0];
+  if (every > 0 && !e->snap[0][0]) {
+    const size_t bytes[3] = {r.n_real * r.tsize, r.n_spec * 2 * r.tsize, r.n_spec * 2 * r.tsize};
+    for (auto& sn : e->snap)
+      for (int i = 0; i < 3; ++i) LE_RC(alloc(&sn[i], bytes[i]));
+  }
+  e->audit_every = every;
+  e->audit_window = window;
+  e->audit_tol = tol;
+  e->since_audit = 0;
+  e->audits = 0;
+  e->audit_dev = 0.0;
+  e->corr_fallback = false;
   return LE_OK;
 }
 
@@ -1180,6 +1296,10 @@ int le_corrector_load(le_ctx* c, const float* params, int32_t nparams, const flo
   }
   for (int k = 0; k < 4; ++k) c->net->scales[k] = scales[k];
   if (net_set_params(c->net, params, c->stream)) return LE_EDEVICE;
+  c->corr_fallback = false;
+  c->since_audit = 0;
+  c->audits = 0;
+  c->audit_dev = 0.0;
   // captured corrected chunks hold the old scales as launch arguments
   for (auto it = c->graphs.begin(); it != c->graphs.end();) {
     if (it->first < 0) {
@@ -1195,6 +1315,18 @@ int le_corrector_load(le_ctx* c, const float* params, int32_t nparams, const flo
 }
 
 int le_step_corrected(le_ctx* c, int64_t ncoarse) { return step_corrected(c, ncoarse); }
+
+int le_corrector_audit(le_ctx* c, int64_t every, int64_t window, double tol) {
+  return corrector_audit(c, every, window, tol);
+}
+
+int le_corrector_status(le_ctx* c, int32_t* fallback, int64_t* audits, double* last_dev) {
+  if (!c) return LE_EINVAL;
+  if (fallback) *fallback = c->corr_fallback ? 1 : 0;
+  if (audits) *audits = c->audits;
+  if (last_dev) *last_dev = c->audit_dev;
+  return LE_OK;
+}
 
 int le_restrict(le_ctx* c, int32_t factor, double* phi_out, double* omega_out) {
   if (!c || factor < 1) return LE_EINVAL;

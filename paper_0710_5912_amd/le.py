@@ -140,6 +140,11 @@ def lib():
         L.le_corrector_load.restype = C.c_int
         L.le_step_corrected.argtypes = [C.c_void_p, C.c_int64]
         L.le_step_corrected.restype = C.c_int
+        L.le_corrector_audit.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_double]
+        L.le_corrector_audit.restype = C.c_int
+        L.le_corrector_status.argtypes = [C.c_void_p, C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.le_corrector_status.restype = C.c_int
         L.le_restrict.argtypes = [C.c_void_p, C.c_int32, _DP, _DP]
         L.le_restrict.restype = C.c_int
         L.le_set_fields.argtypes = [C.c_void_p, _DP, _DP, C.c_int64]
@@ -314,6 +319,22 @@ class Context:
         rc = lib().le_step_corrected(self._h, int(ncoarse))
         if rc != LE_OK:
             raise LeError(rc, "le_step_corrected")
+
+    def corrector_audit(self, every: int, window: int, tol: float) -> None:
+        """Audit the corrected run against the plain step (le_corrector_audit)."""
+        self._check()
+        rc = lib().le_corrector_audit(self._h, int(every), int(window), float(tol))
+        if rc != LE_OK:
+            raise LeError(rc, "le_corrector_audit")
+
+    def corrector_status(self):
+        """(fallback, audits, last relative L_s deviation)."""
+        self._check()
+        fb, n, dev = C.c_int32(), C.c_int64(), C.c_double()
+        rc = lib().le_corrector_status(self._h, C.byref(fb), C.byref(n), C.byref(dev))
+        if rc != LE_OK:
+            raise LeError(rc, "le_corrector_status")
+        return bool(fb.value), n.value, dev.value
 
     def restrict(self, factor: int):
         """(phi, omega) block means over factor x factor cells."""

@@ -80,6 +80,8 @@ def test_null_arguments_rejected():
     assert lib.le_observables(None, None, None, 0) == le.LE_EINVAL
     assert lib.le_tuning(None, None, 0) == le.LE_EINVAL
     assert lib.le_batch_tuning(None, None, 0) == le.LE_EINVAL
+    assert lib.le_corrector_audit(None, 10, 2, 0.02) == le.LE_EINVAL
+    assert lib.le_corrector_status(None, None, None, None) == le.LE_EINVAL
     lib.le_destroy(None)   # NULL-safe
 
 

@@ -147,3 +147,60 @@ def test_corrected_graph_replays_match_eager(fixed_variants):
     finally:
         a.close()
         b.close()
+
+
+def test_audit_that_passes_leaves_the_corrected_run(fixed_variants):
+    """Audits every 10 corrected steps (windows of 4) with a tolerance no run
+    exceeds: the state equals the unaudited corrected run bit for bit."""
+    p = configs.model_h(64, 64, gdot=0.1, rho=1.0)
+    phi0 = inputs.noise_phi0(64, 64, 8, amp=0.6)
+    params = inputs.cnn_init_params(3) * 2.0
+    scales = [1.0, 10.0, 0.02, 0.005]
+    with le.Context(p, phi0) as a, le.Context(p, phi0) as b:
+        a.corrector_load(params, scales)
+        b.corrector_load(params, scales)
+        a.corrector_audit(10, 4, 1e9)
+        a.step_corrected(30)
+        b.step_corrected(30)
+        ga, gb = a.get_state(), b.get_state()
+        fallback, audits, dev = a.corrector_status()
+    assert ga["step"] == gb["step"] == 30
+    for k in ("phi", "omega", "psi"):
+        assert np.array_equal(ga[k], gb[k]), k
+    assert not fallback and audits == 2 and 0.0 < dev < 1e9
+
+
+def test_failed_audit_falls_back_to_plain_steps(fixed_variants):
+    """With tolerance 0 the first audit (steps 6..8) fails: the context keeps
+    the plain result of that window and steps plainly from then on, so the run
+    equals 6 corrected steps followed by 14 plain ones, bit for bit."""
+    p = configs.model_h(64, 64, gdot=0.1, rho=1.0)
+    phi0 = inputs.noise_phi0(64, 64, 9, amp=0.6)
+    params = inputs.cnn_init_params(4) * 2.0
+    scales = [1.0, 10.0, 0.02, 0.005]
+    with le.Context(p, phi0) as a, le.Context(p, phi0) as b:
+        a.corrector_load(params, scales)
+        b.corrector_load(params, scales)
+        a.corrector_audit(6, 3, 0.0)
+        a.step_corrected(20)
+        fallback, audits, dev = a.corrector_status()
+        b.step_corrected(6)
+        b.step(14)
+        ga, gb = a.get_state(), b.get_state()
+        assert fallback and audits == 1 and dev > 0.0
+        a.corrector_audit(0, 0, 0.0)
+        assert a.corrector_status() == (False, 0, 0.0)
+        with pytest.raises(le.LeError) as ei:
+            a.corrector_audit(5, 0, 0.02)
+        assert ei.value.code == le.LE_EINVAL
+    assert ga["step"] == gb["step"] == 20
+    for k in ("phi", "omega", "psi"):
+        assert np.array_equal(ga[k], gb[k]), k
+
+
+def test_audit_needs_a_corrector():
+    p = configs.model_h(32, 32, rho=1.0)
+    with le.Context(p, inputs.noise_phi0(32, 32, 0)) as c:
+        with pytest.raises(le.LeError) as ei:
+            c.corrector_audit(10, 2, 0.02)
+        assert ei.value.code == le.LE_EINVAL
