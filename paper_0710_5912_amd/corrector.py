@@ -138,10 +138,12 @@ def train(xs, ts, epochs=20, batch=16, lr=1e-3, seed=0, log=print):
 
 
 def evaluate(params, scales, gdot=0.01, seed=99, t0=T_START, t_end=T_END, every=5.0, n=FINE_N,
-             factor=FACTOR, log=print):
+             factor=FACTOR, log=print, audit=None):
     """L(t) of the plain fine run, of its restriction to the coarse grid, of the
     corrected coarse run and of the plain coarse run, all from the same
-    restricted state at t0, with wall times."""
+    restricted state at t0, with wall times.  audit = (every, window, tol)
+    adds a corrected run under le_corrector_audit ("audited": its L(t), wall
+    time and the audit status)."""
     import torch
 
     fp, cp = fine_params(gdot, n), coarse_params(gdot, n, factor)
@@ -169,21 +171,29 @@ def evaluate(params, scales, gdot=0.01, seed=99, t0=T_START, t_end=T_END, every=
         out["restricted"].append(op["Ls"])
     fine.close()
     probe.close()
-    for name in ("corrected", "coarse"):
+    runs = ("corrected", "coarse") + (("audited",) if audit else ())
+    out["audited"] = []
+    for name in runs:
         c = le.Context(cp, np.zeros((nc, nc)))
         c.set_fields(phi_c, om_c, k0 // factor)
-        if name == "corrected":
+        if name != "coarse":
             c.corrector_load(params, scales)
+        if name == "audited":
+            c.corrector_audit(*audit)
         torch.cuda.synchronize()
         t_a = time.perf_counter()
         for i in range(nsamp):
-            if name == "corrected":
-                c.step_corrected(kc)
-            else:
+            if name == "coarse":
                 c.step(kc)
+            else:
+                c.step_corrected(kc)
             o, _ = c.observables(sk=False)
             out[name].append(o["Ls"])
         out["wall_" + name] = time.perf_counter() - t_a
+        if name == "audited":
+            fb, na, dev = c.corrector_status()
+            out["audit"] = dict(every=audit[0], window=audit[1], tol=audit[2], fallback=fb,
+                                audits=na, last_dev=dev)
         c.close()
     out["wall_fine"] = wall_fine
     f = np.array(out["fine"])
@@ -200,6 +210,9 @@ def evaluate(params, scales, gdot=0.01, seed=99, t0=T_START, t_end=T_END, every=
     out["fine_rate"] = sites_fine / wall_fine
     out["corrected_fine_equiv_rate"] = sites_fine / out["wall_corrected"]
     out["gain"] = wall_fine / out["wall_corrected"]
+    if audit:
+        out["audited_fine_equiv_rate"] = sites_fine / out["wall_audited"]
+        out["audited_equals_corrected"] = bool(np.array_equal(out["audited"], out["corrected"]))
     log(f"corrector eval gdot={gdot}: L err mean corrected {out['err_mean_corrected']:.3f} "
         f"(vs restricted {out['err_mean_corrected_vs_restricted']:.3f}), plain coarse "
         f"{out['err_mean_coarse']:.3f} ({out['err_mean_coarse_vs_restricted']:.3f}), "

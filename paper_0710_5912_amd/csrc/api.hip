@@ -33,7 +33,7 @@ constexpr int64_t kProfChunk = 256;  // steps per chunk while stage timing is on
 constexpr int kRealBlocks = 256;     // blocks of the real-space reduction
 constexpr int64_t kGraphMin = 8;     // shortest chunk worth capturing
 constexpr int64_t kGraphChunk = 128; // longest captured chunk (longer graphs replay slower)
-constexpr size_t kGraphCacheMax = 4;
+constexpr size_t kGraphCacheMax = 16;  // holds every power-of-two piece of both step kinds
 
 thread_local char g_last_error[256] = "";
 
@@ -343,6 +343,34 @@ void enqueue_step(Engine* e, const StepArgs* sa, hipEvent_t* ev) {
 // Enqueue `count` steps through enqueue_one(k, events): replayed from the
 // graph cached under `key` when there is one, else captured (chunks of at
 // least kGraphMin steps, when not timing stages) or launched directly.
+template <typename F>
+int enqueue_chunk(Engine* e, int64_t key, int64_t count, F&& enqueue_one);
+
+// Copy the chunk's StepArgs rows h_args[0 .. count) to the device and
+// enqueue the chunk through launch(n) (n steps, rows at d_args[0 .. n)).
+// With graphs on, the chunk runs as power-of-two pieces, largest first, each
+// piece's rows copied to the start of d_args (stream order keeps a piece's
+// copy behind the previous piece's kernels): chunks of any length then
+// replay the same few captured graphs instead of capturing one per length.
+template <typename F>
+int enqueue_pieces(Engine* e, int64_t count, size_t row, F&& launch) {
+  const bool split = e->use_graphs && !e->profiling;
+  int64_t k0 = 0;
+  while (k0 < count) {
+    int64_t n = count - k0;
+    if (split) {
+      int64_t b = 1;
+      while (2 * b <= n) b *= 2;
+      n = b;
+    }
+    LE_TRY(hipMemcpyAsync(e->d_args, e->h_args + (size_t)k0 * row,
+                          (size_t)n * row * sizeof(StepArgs), hipMemcpyHostToDevice, e->stream));
+    LE_RC(launch(n));
+    k0 += n;
+  }
+  return LE_OK;
+}
+
 template <typename F>
 int enqueue_chunk(Engine* e, int64_t key, int64_t count, F&& enqueue_one) {
   const bool graph_ok = e->use_graphs && count >= kGraphMin && !e->profiling;
@@ -851,9 +879,7 @@ int step_engine(Engine* e, int64_t nsteps) {
         break;
       }
     }
-    LE_TRY(hipMemcpyAsync(e->d_args, e->h_args, (size_t)count * row * sizeof(StepArgs),
-                          hipMemcpyHostToDevice, e->stream));
-    LE_RC(enqueue_steps(e, count));
+    LE_RC(enqueue_pieces(e, count, row, [&](int64_t n) { return enqueue_steps(e, n); }));
     e->step = n0 + count;
     for (RunHost& r : e->runs) {
       const int64_t k_new = wrap_count(r.p, e->step);
@@ -947,25 +973,26 @@ int corrected_steps(Engine* e, int64_t ncoarse) {
         break;
       }
     }
-    LE_TRY(hipMemcpyAsync(e->d_args, e->h_args, (size_t)count * sizeof(StepArgs),
-                          hipMemcpyHostToDevice, e->stream));
     // corrected chunks share the graph cache under negative keys
-    LE_RC(enqueue_chunk(e, -count, count, [&](int64_t k, hipEvent_t* ev) {
-      const StepArgs* sa = e->d_args + k;
-      enqueue_step(e, sa, ev);
-      o.row_c2r(d, 1, r.p.ny, B_OM_S, B_OM_R, B_OM_S, B_OM_R, 1, e->classes[r.cls].row_variant,
-                e->stream);
-      int rc = r.tsize == sizeof(double)
-                   ? net_residual<double>(e->net, static_cast<const double*>(r.buf[B_PHI]),
-                                          static_cast<const double*>(r.buf[B_OM_R]), e->stream)
-                   : net_residual<float>(e->net, static_cast<const float*>(r.buf[B_PHI]),
-                                         static_cast<const float*>(r.buf[B_OM_R]), e->stream);
-      if (rc) return (int)LE_EDEVICE;
-      const CorrArgs ca{net_z_out(e->net), net_partials(e->net), net_tiles(e->net),
-                        e->net->scales[2], e->net->scales[3]};
-      o.row_r2c_corr(d, r.p.ny, ca, e->classes[r.cls].row_variant, e->stream);
-      o.column(COL_POISSON, d, 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0, e->stream);
-      return (int)LE_OK;
+    LE_RC(enqueue_pieces(e, count, 1, [&](int64_t n) {
+      return enqueue_chunk(e, -n, n, [&](int64_t k, hipEvent_t* ev) {
+        const StepArgs* sa = e->d_args + k;
+        enqueue_step(e, sa, ev);
+        o.row_c2r(d, 1, r.p.ny, B_OM_S, B_OM_R, B_OM_S, B_OM_R, 1,
+                  e->classes[r.cls].row_variant, e->stream);
+        int rc = r.tsize == sizeof(double)
+                     ? net_residual<double>(e->net, static_cast<const double*>(r.buf[B_PHI]),
+                                            static_cast<const double*>(r.buf[B_OM_R]),
+                                            e->stream)
+                     : net_residual<float>(e->net, static_cast<const float*>(r.buf[B_PHI]),
+                                           static_cast<const float*>(r.buf[B_OM_R]), e->stream);
+        if (rc) return (int)LE_EDEVICE;
+        const CorrArgs ca{net_z_out(e->net), net_partials(e->net), net_tiles(e->net),
+                          e->net->scales[2], e->net->scales[3]};
+        o.row_r2c_corr(d, r.p.ny, ca, e->classes[r.cls].row_variant, e->stream);
+        o.column(COL_POISSON, d, 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0, e->stream);
+        return (int)LE_OK;
+      });
     }));
     e->step = n0 + count;
     const int64_t k_new = wrap_count(r.p, e->step);
