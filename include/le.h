@@ -113,6 +113,20 @@ int le_create(const le_params* p, const double* phi0, const double* omega0,
 int le_step(le_ctx* c, int64_t nsteps);
 
 /*
+ * Scheme variants either side of the default reading of Appendix B (for
+ * convergence studies; the default, flags = 0, is the scheme as read):
+ *   LE_SCHEME_F_HALF      f = (phi^{n+1/2})^3, the cube of the advected phi
+ *                         (the stage 1b update formula writes f^n, the
+ *                         default takes that as (phi^n)^3);
+ *   LE_SCHEME_MIDPOINT_S  every operator of step n at the sawtooth of the
+ *                         step's midpoint, s(t_n + dt/2) in the frame of step
+ *                         n, instead of s(t_n) (observables stay at s(t_n)).
+ * Takes effect from the next step; flags outside these bits: LE_EINVAL.
+ */
+enum { LE_SCHEME_F_HALF = 1, LE_SCHEME_MIDPOINT_S = 2 };
+int le_set_scheme(le_ctx* c, int32_t flags);
+
+/*
  * Compute the observables of the current state into *o.  If Sk is non-NULL,
  * the shell-averaged structure factor S(k_b) = mean over the modes of shell
  * b of |F[phi](q)|^2 / N is written for b = 1 .. min(sk_cap, ny/2) into

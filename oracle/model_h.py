@@ -28,7 +28,9 @@ Readings taken where the paper is silent (each is listed in the design notes):
   q_x q_y is set to zero on the Nyquist row and column so every multiplier is
   Hermitian;
 * every operator of step n uses s_n; f = (phi^n)^3; the omega Crank-Nicolson
-  update starts from the advected omega^{n+1/2};
+  update starts from the advected omega^{n+1/2} (Params.f_half and
+  Params.midpoint_s switch to the other readings of the first two: f of the
+  advected phi, and s at the step's midpoint);
 * the q = 0 mode: phi untouched, omega and psi set to zero;
 * at a strain wrap s -> s - c (c = Lx/Ly) the fields are remapped row by row,
   new[j][i] = old[j][(i - r j) mod Nx] with r = Nx/Ny, so the lab-frame field
@@ -68,6 +70,10 @@ class Params:
     eta: float = 1.0
     rho: float = 1.0
     dt: float = 0.005
+    # scheme variants either side of the default reading (both off: the scheme
+    # as read): f from the advected phi; the sawtooth at the step's midpoint
+    f_half: bool = False
+    midpoint_s: bool = False
 
     @property
     def dx(self) -> float:
@@ -115,6 +121,11 @@ def wrap_count(p: Params, n: int) -> int:
 def strain_offset(p: Params, n: int) -> float:
     """The sawtooth s(t_n) of the cosheared gradient operator."""
     return strain_total(p, n) - p.c * wrap_count(p, n)
+
+
+def strain_offset_mid(p: Params, n: int) -> float:
+    """The sawtooth at t_n + dt/2, in the frame of step n (wrap count k_n)."""
+    return p.gdot * ((float(n) + 0.5) * p.dt) - p.c * wrap_count(p, n)
 
 
 def remap(p: Params, a: np.ndarray, dk: int) -> np.ndarray:
@@ -239,7 +250,7 @@ def stage_advect(p: Params, st: State, s: float):
         omega_h = st.omega - p.dt * advection(p, st.psi, st.omega, s)
     else:
         omega_h = st.omega
-    f = st.phi ** 3
+    f = (phi_h if p.f_half else st.phi) ** 3
     return phi_h, omega_h, f
 
 
@@ -317,7 +328,7 @@ def initial_state(p: Params, phi0: np.ndarray, omega0: np.ndarray | None = None)
 def step(p: Params, st: State) -> State:
     """One full time step n -> n+1, then the sawtooth shift and remap if due."""
     n = st.step
-    s = strain_offset(p, n)
+    s = strain_offset_mid(p, n) if p.midpoint_s else strain_offset(p, n)
     phi_h, omega_h, f = stage_advect(p, st, s)
     phi_new = stage_cahn_hilliard(p, phi_h, f, s)
     g = vorticity_source(p, phi_new, s)

@@ -68,6 +68,12 @@ double strain_offset(const le_params& p, int64_t n) {
   const double c = p.lx / p.ly;
   return strain_total(p, n) - c * (double)wrap_count(p, n);
 }
+// The sawtooth at the midpoint of step n, t = (n + 1/2) dt, in the frame of
+// step n (wrap count k_n): the LE_SCHEME_MIDPOINT_S variant.
+double strain_offset_mid(const le_params& p, int64_t n) {
+  const double c = p.lx / p.ly;
+  return p.gdot * (((double)n + 0.5) * p.dt) - c * (double)wrap_count(p, n);
+}
 #pragma clang fp contract(on)
 
 bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
@@ -165,6 +171,7 @@ struct le_ctx {
   int64_t audit_every = 0, audit_window = 0, since_audit = 0, audits = 0;
   double audit_tol = 0.0, audit_dev = 0.0;
   bool corr_fallback = false;
+  bool midpoint_s = false;  // LE_SCHEME_MIDPOINT_S
   void* snap[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
   // engines of several grid classes: one stream per class (default priority)
   // so that the classes' independent kernels overlap, forked from and joined
@@ -692,7 +699,7 @@ int create_engine(int32_t n, const le_params* ps, const double* const* phi0s,
     g.nx = p.nx;
     g.ny = p.ny;
     g.r = p.nx >= p.ny ? p.nx / p.ny : 0;
-    g.pad0 = 0;
+    g.f_half = 0;
     g.lx = p.lx;
     g.ly = p.ly;
     g.dx = p.lx / p.nx;
@@ -870,7 +877,7 @@ int step_engine(Engine* e, int64_t nsteps) {
       bool wrap = false;
       for (const RunHost& r : e->runs) {
         StepArgs& a = e->h_args[(size_t)k * row + r.internal];
-        a.s = strain_offset(r.p, n0 + k);
+        a.s = e->midpoint_s ? strain_offset_mid(r.p, n0 + k) : strain_offset(r.p, n0 + k);
         a.pad = 0.0;
         wrap = wrap || wrap_count(r.p, n0 + k + 1) != wrap_count(r.p, n0 + k);
       }
@@ -966,7 +973,8 @@ int corrected_steps(Engine* e, int64_t ncoarse) {
     const int64_t cap = e->use_graphs ? kGraphChunk : kChunkCap;
     int64_t count = remaining < cap ? remaining : cap;
     for (int64_t k = 0; k < count; ++k) {
-      e->h_args[k].s = strain_offset(r.p, n0 + k);
+      e->h_args[k].s =
+          e->midpoint_s ? strain_offset_mid(r.p, n0 + k) : strain_offset(r.p, n0 + k);
       e->h_args[k].pad = 0.0;
       if (wrap_count(r.p, n0 + k + 1) != wrap_count(r.p, n0 + k)) {
         count = k + 1;
@@ -1146,6 +1154,20 @@ int le_create(const le_params* p, const double* phi0, const double* omega0, le_c
 }
 
 int le_step(le_ctx* c, int64_t nsteps) { return step_engine(c, nsteps); }
+
+int le_set_scheme(le_ctx* c, int32_t flags) {
+  if (!c || (flags & ~(LE_SCHEME_F_HALF | LE_SCHEME_MIDPOINT_S)) != 0) return LE_EINVAL;
+  c->midpoint_s = (flags & LE_SCHEME_MIDPOINT_S) != 0;
+  std::vector<Run> h((size_t)c->nruns);
+  LE_TRY(hipMemcpy(h.data(), c->d_desc, sizeof(Run) * h.size(), hipMemcpyDeviceToHost));
+  for (RunHost& r : c->runs) {
+    r.g.f_half = (flags & LE_SCHEME_F_HALF) ? 1 : 0;
+    h[r.internal].g = r.g;
+  }
+  LE_TRY(hipStreamSynchronize(c->stream));
+  LE_TRY(hipMemcpy(c->d_desc, h.data(), sizeof(Run) * h.size(), hipMemcpyHostToDevice));
+  return LE_OK;
+}
 
 int le_observables(le_ctx* c, le_obs* o, double* Sk, int32_t sk_cap) {
   if (!c || !o) return LE_EINVAL;

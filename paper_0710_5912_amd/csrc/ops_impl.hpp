@@ -106,7 +106,7 @@ struct RowLaunch {
                      int variant, int row_variant, hipStream_t st) {
     if (variant <= 0) {
       Jobs jobs{{{JOB_ADVECT, B_PHI, B_PS_R, B_PHIH},
-                 {JOB_CUBE, B_PHI, B_PHI, B_FH},
+                 {JOB_CUBE, B_PHI, B_PS_R, B_FH},
                  {JOB_ADVECT, B_OM_R, B_PS_R, B_OMH}}};
       bracket(runs, nruns, ny, sa, jobs, inertial ? 3 : 2, st);
       return;

@@ -439,7 +439,8 @@ __device__ __forceinline__ void quad_dys(const Quad<T>& up, const Quad<T>& dn,
 
 // One output field of a bracket row kernel.
 //   JOB_ADVECT: out = a - dt [Dx a Dys b - Dys a Dx b]   (stage 1a, b = psi)
-//   JOB_CUBE:   out = a^3                                  (stage 1a, f)
+//   JOB_CUBE:   out = a^3                                  (stage 1a, f; with
+//               geo.f_half the JOB_ADVECT value of a with b = psi, cubed)
 //   JOB_SOURCE: out = -[Dx a Dys b - Dys a Dx b] / c       (stage 2a, a = phi,
 //               b = mu, c = rho, or eta on the Stokes branch)
 enum JobKind { JOB_ADVECT = 0, JOB_CUBE = 1, JOB_SOURCE = 2 };
@@ -473,7 +474,9 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_bracket(
   auto fa = bufp<const T>(R, job.a);
   auto a_c = fa + (size_t)j * NX;
   c2<T> v[C::E];
-  if (job.kind == JOB_CUBE) {
+  // f of the advected phi (job.b = psi): the advection job's value, cubed
+  const bool cube_half = job.kind == JOB_CUBE && geo.f_half;
+  if (job.kind == JOB_CUBE && !cube_half) {
 #pragma unroll
     for (int q = 0; q < C::E; ++q) {
       const c2<T> p = load_pair<T, NX>(a_c, 2 * (t + q * C::P));
@@ -487,7 +490,7 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_bracket(
     auto b_c = fb + (size_t)j * NX;
     auto b_p = fb + (size_t)jp * NX;
     auto b_m = fb + (size_t)jm * NX;
-    const bool adv = job.kind == JOB_ADVECT;
+    const bool adv = job.kind != JOB_SOURCE;
     const T alpha = adv ? T(1) : T(0);
     const T beta = adv ? T(-geo.dt) : T(-1.0 / (geo.rho > 0.0 ? geo.rho : geo.eta));
 #pragma unroll
@@ -506,6 +509,7 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_bracket(
       quad_dys<T, NX, R1>(Bp, Bm, b_p, b_m, x, st, by0, by1);
       v[q] = {alpha * A.a0 + beta * (by0 * ax0 - bx0 * ay0),
               alpha * A.a1 + beta * (by1 * ax1 - bx1 * ay1)};
+      if (cube_half) v[q] = {v[q].x * v[q].x * v[q].x, v[q].y * v[q].y * v[q].y};
       LE_SCHED_FENCE();
     }
   }
@@ -582,6 +586,7 @@ __global__ __launch_bounds__(strip_threads(NX)) void k_adv_strip(
   auto o_om = bufp<T>(R, B_OMH);
   const Stencil<T> st = make_stencil<T>(geo, sa[bp.z].s);
   const T dt = T(geo.dt);
+  const bool fh = geo.f_half != 0;
   const bool inr = inertial != 0;
   auto row = [&](gp<const T> f, int j) { return f + (size_t)(j < 0 ? j + ny : (j >= ny ? j - ny : j)) * NX; };
   Quad<T> Fm = to_quad(load_raw(row(phi, j0 - 1), sl), sl);
@@ -611,10 +616,10 @@ __global__ __launch_bounds__(strip_threads(NX)) void k_adv_strip(
     quad_dx(Fc, st.inv2dx, ax0, ax1);
     quad_dys<T, NX, R1>(Fp, Fm, row(phi, j + 1), row(phi, j - 1), sl.x, st, ay0, ay1);
     const size_t o = (size_t)j * (NX + 2) + sl.x;
-    stg<T>(reinterpret_cast<gp<c2<T>>>(o_phi + o),
-           {Fc.a0 - dt * (ax0 * sy0 - ay0 * sx0), Fc.a1 - dt * (ax1 * sy1 - ay1 * sx1)});
-    stg<T>(reinterpret_cast<gp<c2<T>>>(o_f + o),
-           {Fc.a0 * Fc.a0 * Fc.a0, Fc.a1 * Fc.a1 * Fc.a1});
+    const T h0 = Fc.a0 - dt * (ax0 * sy0 - ay0 * sx0), h1 = Fc.a1 - dt * (ax1 * sy1 - ay1 * sx1);
+    const T c0 = fh ? h0 : Fc.a0, c1 = fh ? h1 : Fc.a1;
+    stg<T>(reinterpret_cast<gp<c2<T>>>(o_phi + o), {h0, h1});
+    stg<T>(reinterpret_cast<gp<c2<T>>>(o_f + o), {c0 * c0 * c0, c1 * c1 * c1});
     if (inr) {
       quad_dx(Wc, st.inv2dx, ax0, ax1);
       quad_dys<T, NX, R1>(Wp, Wm, row(om, j + 1), row(om, j - 1), sl.x, st, ay0, ay1);
@@ -661,6 +666,7 @@ __global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __res
   auto tw = to_global<const c2<double>>(R.twx);
   const Stencil<T> st = make_stencil<T>(geo, sa[bp.z].s);
   const T dt = T(geo.dt);
+  const bool fh = geo.f_half != 0;
   const bool inr = inertial != 0;
   const int grp = threadIdx.x / PF, tt = threadIdx.x % PF;
   const int nf = inr ? 3 : 2;
@@ -709,8 +715,11 @@ __global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __res
       quad_dx(Fc[g], st.inv2dx, ax0, ax1);
       quad_dys<T, NX, R1>(Fp, Fm[g], row(phi, j + 1), row(phi, j - 1), sl.x, st, ay0, ay1);
       const int pr = slot * L + sl.x / 2;
-      buf[pr] = {Fc[g].a0 - dt * (ax0 * sy0 - ay0 * sx0), Fc[g].a1 - dt * (ax1 * sy1 - ay1 * sx1)};
-      buf[4 * L + pr] = {Fc[g].a0 * Fc[g].a0 * Fc[g].a0, Fc[g].a1 * Fc[g].a1 * Fc[g].a1};
+      const T h0 = Fc[g].a0 - dt * (ax0 * sy0 - ay0 * sx0);
+      const T h1 = Fc[g].a1 - dt * (ax1 * sy1 - ay1 * sx1);
+      const T c0 = fh ? h0 : Fc[g].a0, c1 = fh ? h1 : Fc[g].a1;
+      buf[pr] = {h0, h1};
+      buf[4 * L + pr] = {c0 * c0 * c0, c1 * c1 * c1};
       if (inr) {
         quad_dx(Wc[g], st.inv2dx, ax0, ax1);
         quad_dys<T, NX, R1>(Wp, Wm[g], row(om, j + 1), row(om, j - 1), sl.x, st, ay0, ay1);

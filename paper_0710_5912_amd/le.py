@@ -15,6 +15,7 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmodelh.so")
 
 LE_OK, LE_EINVAL, LE_ENOMEM, LE_EDEVICE, LE_ENONFINITE, LE_ESTATE = 0, -1, -2, -3, -4, -5
+LE_SCHEME_F_HALF, LE_SCHEME_MIDPOINT_S = 1, 2
 LE_FP64, LE_FP32 = 0, 1
 
 SYMBOLS = ("le_create", "le_step", "le_observables", "le_destroy", "le_get_state",
@@ -23,6 +24,7 @@ SYMBOLS = ("le_create", "le_step", "le_observables", "le_destroy", "le_get_state
            "le_batch_profile", "le_batch_stage_times", "le_batch_destroy",
            "le_tuning", "le_batch_tuning", "le_time_stage",
            "le_corrector_load", "le_step_corrected", "le_restrict", "le_set_fields",
+           "le_corrector_audit", "le_corrector_status", "le_set_scheme",
            "le_cnn_nparams", "le_cnn_create", "le_cnn_destroy", "le_cnn_set_params",
            "le_cnn_get_params", "le_cnn_forward", "le_cnn_grad", "le_cnn_adam",
            "le_cnn_layer_fwd", "le_cnn_layer_bwd", "le_cnn_mfma_probe")
@@ -98,6 +100,8 @@ def lib():
         L.le_create.restype = C.c_int
         L.le_step.argtypes = [C.c_void_p, C.c_int64]
         L.le_step.restype = C.c_int
+        L.le_set_scheme.argtypes = [C.c_void_p, C.c_int32]
+        L.le_set_scheme.restype = C.c_int
         L.le_observables.argtypes = [C.c_void_p, C.POINTER(LeObs), _DP, C.c_int32]
         L.le_observables.restype = C.c_int
         L.le_destroy.argtypes = [C.c_void_p]
@@ -237,6 +241,15 @@ class Context:
         rc = lib().le_step(self._h, int(nsteps))
         if rc != LE_OK:
             raise LeError(rc, "le_step")
+
+    def set_scheme(self, f_half: bool = False, midpoint_s: bool = False) -> None:
+        """Scheme variants (le_set_scheme): f of the advected phi, and/or the
+        sawtooth at the step's midpoint."""
+        self._check()
+        flags = (LE_SCHEME_F_HALF if f_half else 0) | (LE_SCHEME_MIDPOINT_S if midpoint_s else 0)
+        rc = lib().le_set_scheme(self._h, flags)
+        if rc != LE_OK:
+            raise LeError(rc, "le_set_scheme")
 
     def observables(self, sk: bool = True):
         """Return (dict of le_obs fields, S(k) array or None)."""

@@ -466,3 +466,44 @@ def test_flow_lowers_free_energy(rho):
         dF = _free_energy(p, phi_h) - _free_energy(p, st.phi)
         assert np.max(np.abs(st.psi)) > 1e-4
         assert dF < 0.0, dF
+
+
+# ------------- scheme variants either side of the default reading (f4)
+
+def test_scheme_variants_reduce_to_the_default_where_they_coincide():
+    """f of the advected phi equals f^n where advection vanishes (a y-only
+    profile: Dx = 0, so adv = 0 and phi_h = phi^n), and the midpoint sawtooth
+    equals s_n without shear: both variants then give the default bit for bit."""
+    import dataclasses
+    p = P(nx=16, ny=32, lx=16.0, ly=32.0, gdot=0.2, kappa=2.0, M=0.5)
+    y = np.arange(p.ny) * p.dy
+    phi = np.repeat((0.8 * np.tanh((y - 8.0) / 2.0) * np.tanh((y - 24.0) / 2.0))[:, None],
+                    p.nx, axis=1)
+    a = mh.run(p, mh.initial_state(p, phi), 40)
+    b = mh.run(dataclasses.replace(p, f_half=True), mh.initial_state(p, phi), 40)
+    assert np.array_equal(a.phi, b.phi)
+    q = P(nx=32, ny=32, lx=8.0, ly=8.0, gdot=0.0, kappa=0.05, M=0.5, dt=0.01)
+    phi, om = smooth_init(q)
+    a = mh.run(q, mh.initial_state(q, phi, om), 20)
+    b = mh.run(dataclasses.replace(q, midpoint_s=True), mh.initial_state(q, phi, om), 20)
+    assert np.array_equal(a.phi, b.phi) and np.array_equal(a.omega, b.omega)
+
+
+@pytest.mark.parametrize("flag", ["f_half", "midpoint_s"])
+def test_scheme_variants_are_first_order_close_to_the_default(flag):
+    """Both readings are first-order schemes for the same equations: at fixed
+    T their difference from the default halves with dt (order 1 within 0.2),
+    and it is not zero (the switch acts)."""
+    import dataclasses
+    T = 0.32
+    d = []
+    for dt in (0.02, 0.01, 0.005):
+        p = P(nx=32, ny=32, lx=8.0, ly=8.0, gdot=0.3, kappa=0.05, M=0.5, dt=dt)
+        q = dataclasses.replace(p, **{flag: True})
+        phi, om = smooth_init(p)
+        a = mh.run(p, mh.initial_state(p, phi, om), int(round(T / dt)))
+        b = mh.run(q, mh.initial_state(q, phi, om), int(round(T / dt)))
+        d.append(np.max(np.abs(a.phi - b.phi)) + np.max(np.abs(a.omega - b.omega)))
+    assert d[2] > 1e-5
+    for e1, e2 in ((d[0], d[1]), (d[1], d[2])):
+        assert abs(math.log2(e1 / e2) - 1.0) < 0.2, d
