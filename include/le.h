@@ -113,6 +113,19 @@ int le_create(const le_params* p, const double* phi0, const double* omega0,
 int le_step(le_ctx* c, int64_t nsteps);
 
 /*
+ * Recovery from a non-finite state (failure handling; not part of the
+ * method).  With enable != 0, le_step keeps a copy of the state at the start
+ * of each call (two state snapshots are allocated here: LE_ENOMEM); when the
+ * call ends with a non-finite phi it replays the call's steps one at a time
+ * from that copy and leaves the context at the last step whose phi is finite
+ * (step counter and wrap count included), still returning LE_ENONFINITE.  A
+ * call that starts from a non-finite state is left at its start.  enable = 0
+ * (the default): le_step returns LE_ENONFINITE with the non-finite state.
+ * Single contexts only (LE_EINVAL for NULL).
+ */
+int le_set_recovery(le_ctx* c, int enable);
+
+/*
  * Scheme variants either side of the default reading of Appendix B (for
  * convergence studies; the default, flags = 0, is the scheme as read):
  *   LE_SCHEME_F_HALF      f = (phi^{n+1/2})^3, the cube of the advected phi

@@ -172,6 +172,7 @@ struct le_ctx {
   double audit_tol = 0.0, audit_dev = 0.0;
   bool corr_fallback = false;
   bool midpoint_s = false;  // LE_SCHEME_MIDPOINT_S
+  bool recovery = false;    // le_set_recovery
   void* snap[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
   // engines of several grid classes: one stream per class (default priority)
   // so that the classes' independent kernels overlap, forked from and joined
@@ -1015,6 +1016,15 @@ int corrected_steps(Engine* e, int64_t ncoarse) {
   return LE_OK;
 }
 
+// Two state snapshots of run 0 (phi, omega_h, psi_h), allocated on first use.
+int alloc_snapshots(Engine* e, const RunHost& r) {
+  const size_t bytes[3] = {r.n_real * r.tsize, r.n_spec * 2 * r.tsize, r.n_spec * 2 * r.tsize};
+  for (auto& sn : e->snap)
+    for (int i = 0; i < 3; ++i)
+      if (!sn[i]) LE_RC(alloc(&sn[i], bytes[i]));
+  return LE_OK;
+}
+
 // The state between steps: real phi and the row spectra of omega and psi.
 int copy_state(Engine* e, const RunHost& r, bool to_snap, int k) {
   const int bufs[3] = {B_PHI, B_OM_S, B_PS_S};
@@ -1102,15 +1112,41 @@ int step_corrected(Engine* e, int64_t ncoarse) {
   return LE_OK;
 }
 
+// le_step with recovery: the state at the call's start is kept; if the call
+// ends non-finite, its steps are replayed one by one from that state (the
+// step is deterministic) and the context stops at the last step whose phi is
+// finite.
+int step_recover(Engine* e, int64_t nsteps) {
+  if (nsteps < 0) return LE_EINVAL;
+  RunHost& r = e->runs[0];
+  const int64_t step0 = e->step, wraps0 = r.wraps;
+  LE_RC(copy_state(e, r, true, 0));
+  int rc = step_engine(e, nsteps);
+  if (rc != LE_ENONFINITE) return rc;
+  LE_RC(copy_state(e, r, false, 0));
+  e->step = step0;
+  r.wraps = wraps0;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    const int64_t sk = e->step, wk = r.wraps;
+    LE_RC(copy_state(e, r, true, 1));
+    rc = step_engine(e, 1);
+    if (rc == LE_ENONFINITE) {
+      LE_RC(copy_state(e, r, false, 1));
+      e->step = sk;
+      r.wraps = wk;
+      LE_TRY(hipStreamSynchronize(e->stream));
+      return LE_ENONFINITE;
+    }
+    LE_RC(rc);
+  }
+  return LE_OK;
+}
+
 int corrector_audit(Engine* e, int64_t every, int64_t window, double tol) {
   if (!e || !e->net || every < 0 || (every > 0 && (window < 1 || !(tol >= 0.0))))
     return LE_EINVAL;
   RunHost& r = e->runs[0];
-  if (every > 0 && !e->snap[0][0]) {
-    const size_t bytes[3] = {r.n_real * r.tsize, r.n_spec * 2 * r.tsize, r.n_spec * 2 * r.tsize};
-    for (auto& sn : e->snap)
-      for (int i = 0; i < 3; ++i) LE_RC(alloc(&sn[i], bytes[i]));
-  }
+  if (every > 0) LE_RC(alloc_snapshots(e, r));
   e->audit_every = every;
   e->audit_window = window;
   e->audit_tol = tol;
@@ -1153,7 +1189,17 @@ int le_create(const le_params* p, const double* phi0, const double* omega0, le_c
   return create_engine(1, p, phis, oms, out);
 }
 
-int le_step(le_ctx* c, int64_t nsteps) { return step_engine(c, nsteps); }
+int le_step(le_ctx* c, int64_t nsteps) {
+  if (c && c->recovery) return step_recover(c, nsteps);
+  return step_engine(c, nsteps);
+}
+
+int le_set_recovery(le_ctx* c, int enable) {
+  if (!c || c->nruns != 1) return LE_EINVAL;
+  if (enable) LE_RC(alloc_snapshots(c, c->runs[0]));
+  c->recovery = enable != 0;
+  return LE_OK;
+}
 
 int le_set_scheme(le_ctx* c, int32_t flags) {
   if (!c || (flags & ~(LE_SCHEME_F_HALF | LE_SCHEME_MIDPOINT_S)) != 0) return LE_EINVAL;

@@ -24,7 +24,7 @@ SYMBOLS = ("le_create", "le_step", "le_observables", "le_destroy", "le_get_state
            "le_batch_profile", "le_batch_stage_times", "le_batch_destroy",
            "le_tuning", "le_batch_tuning", "le_time_stage",
            "le_corrector_load", "le_step_corrected", "le_restrict", "le_set_fields",
-           "le_corrector_audit", "le_corrector_status", "le_set_scheme",
+           "le_corrector_audit", "le_corrector_status", "le_set_scheme", "le_set_recovery",
            "le_cnn_nparams", "le_cnn_create", "le_cnn_destroy", "le_cnn_set_params",
            "le_cnn_get_params", "le_cnn_forward", "le_cnn_grad", "le_cnn_adam",
            "le_cnn_layer_fwd", "le_cnn_layer_bwd", "le_cnn_mfma_probe")
@@ -102,6 +102,8 @@ def lib():
         L.le_step.restype = C.c_int
         L.le_set_scheme.argtypes = [C.c_void_p, C.c_int32]
         L.le_set_scheme.restype = C.c_int
+        L.le_set_recovery.argtypes = [C.c_void_p, C.c_int]
+        L.le_set_recovery.restype = C.c_int
         L.le_observables.argtypes = [C.c_void_p, C.POINTER(LeObs), _DP, C.c_int32]
         L.le_observables.restype = C.c_int
         L.le_destroy.argtypes = [C.c_void_p]
@@ -241,6 +243,13 @@ class Context:
         rc = lib().le_step(self._h, int(nsteps))
         if rc != LE_OK:
             raise LeError(rc, "le_step")
+
+    def set_recovery(self, enable: bool = True) -> None:
+        """Stop at the last finite step when a step call goes non-finite."""
+        self._check()
+        rc = lib().le_set_recovery(self._h, 1 if enable else 0)
+        if rc != LE_OK:
+            raise LeError(rc, "le_set_recovery")
 
     def set_scheme(self, f_half: bool = False, midpoint_s: bool = False) -> None:
         """Scheme variants (le_set_scheme): f of the advected phi, and/or the

@@ -82,6 +82,8 @@ def test_null_arguments_rejected():
     assert lib.le_batch_tuning(None, None, 0) == le.LE_EINVAL
     assert lib.le_corrector_audit(None, 10, 2, 0.02) == le.LE_EINVAL
     assert lib.le_corrector_status(None, None, None, None) == le.LE_EINVAL
+    assert lib.le_set_recovery(None, 1) == le.LE_EINVAL
+    assert lib.le_set_scheme(None, 0) == le.LE_EINVAL
     lib.le_destroy(None)   # NULL-safe
 
 

@@ -152,6 +152,30 @@ def test_nonfinite_state_is_reported():
     ctx.close()
 
 
+def test_recovery_stops_at_the_last_finite_step():
+    """An explicit Cahn-Hilliard number of ~20 (dt = 1, kappa = 0.01) blows the
+    run up.  With recovery on, the failing call leaves the context at the last
+    step whose phi is finite: it equals a fresh run of that many steps bit for
+    bit, and one more step from there goes non-finite."""
+    p = params(32, 32, gdot=0.0, kappa=0.01, dt=1.0)
+    phi0 = inputs.noise_phi0(32, 32, 7, amp=0.05)
+    with le.Context(p, phi0) as a, le.Context(p, phi0) as b:
+        a.set_recovery(True)
+        with pytest.raises(le.LeError) as ei:
+            a.step(500)
+        assert ei.value.code == le.LE_ENONFINITE
+        g = a.get_state()
+        m = g["step"]
+        assert 0 < m < 500 and np.all(np.isfinite(g["phi"]))
+        b.step(m)
+        gb = b.get_state()
+        for k in ("phi", "omega", "psi"):
+            assert np.array_equal(g[k], gb[k], equal_nan=True), k
+        with pytest.raises(le.LeError) as ei:
+            b.step(1)
+        assert ei.value.code == le.LE_ENONFINITE
+
+
 def test_zero_steps_is_a_no_op_and_negative_steps_are_rejected():
     """le_step(c, 0) leaves the state, step counter and clock alone; a negative
     count is LE_EINVAL and changes nothing either."""
