@@ -109,7 +109,8 @@ int le_create(const le_params* p, const double* phi0, const double* omega0,
 
 /* Advance nsteps >= 0 full time steps (the sawtooth clock advances with
  * them).  Returns LE_ENONFINITE if phi became non-finite, checked at the end
- * of the call. */
+ * of the call; the context then holds the non-finite state, or with
+ * le_set_recovery on, the last finite one.  nsteps < 0: LE_EINVAL. */
 int le_step(le_ctx* c, int64_t nsteps);
 
 /*
