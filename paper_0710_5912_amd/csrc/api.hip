@@ -1117,7 +1117,7 @@ int step_corrected(Engine* e, int64_t ncoarse) {
 // step is deterministic) and the context stops at the last step whose phi is
 // finite.
 int step_recover(Engine* e, int64_t nsteps) {
-  if (nsteps < 0) return LE_EINVAL;
+  if (nsteps <= 0) return step_engine(e, nsteps);
   RunHost& r = e->runs[0];
   const int64_t step0 = e->step, wraps0 = r.wraps;
   LE_RC(copy_state(e, r, true, 0));

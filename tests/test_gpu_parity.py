@@ -152,11 +152,11 @@ def test_nonfinite_state_is_reported():
     ctx.close()
 
 
-def test_recovery_stops_at_the_last_finite_step():
+def test_recovery_stops_at_the_last_finite_step(fixed_variants):
     """An explicit Cahn-Hilliard number of ~20 (dt = 1, kappa = 0.01) blows the
     run up.  With recovery on, the failing call leaves the context at the last
     step whose phi is finite: it equals a fresh run of that many steps bit for
-    bit, and one more step from there goes non-finite."""
+    bit (same kernel variants), and one more step from there goes non-finite."""
     p = params(32, 32, gdot=0.0, kappa=0.01, dt=1.0)
     phi0 = inputs.noise_phi0(32, 32, 7, amp=0.05)
     with le.Context(p, phi0) as a, le.Context(p, phi0) as b:
