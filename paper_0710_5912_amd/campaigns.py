@@ -2,7 +2,7 @@
 
   python -m paper_0710_5912_amd.campaigns dv-sheared   [--strain 80] [--samples 100] [--refine 2] [--sets DV5s,DV6s]
   python -m paper_0710_5912_amd.campaigns zero-shear   [--seeds 4] [--refine 2] [--sets DV6u]
-  python -m paper_0710_5912_amd.campaigns steady-states [--strain 150] [--lb-sets]
+  python -m paper_0710_5912_amd.campaigns steady-states [--strain 150] [--lb-sets] [--refine 2] [--sets R030s]
 
 dv-sheared: the inertialess sheared sets DV1s .. DV6s, L_par and L_perp
 against strain (Section VIII D).  zero-shear: the sets DV1u .. DV6u and
@@ -97,21 +97,32 @@ def zero_shear(seeds: int, refine: int = 1, sets: str = ""):
     print(json.dumps({"summary": summary}), flush=True)
 
 
-def steady_states(strain: float, lb_sets: bool = False):
+def steady_states(strain: float, lb_sets: bool = False, refine: int = 1, sets: str = ""):
     rows = []
-    names = configs.R_SHEARED_LB if lb_sets else configs.R_SHEARED
-    for k, name in enumerate(names):
-        p = configs.r_sheared(name)
+    table = configs.R_SHEARED_LB if lb_sets else configs.R_SHEARED
+    for k, name in _pick(table, sets):
+        p = configs.r_sheared(name, refine)
         steps = int(round(strain / (p["gdot"] * p["dt"])))
-        phi0 = inputs.noise_phi0(512, 1024, (900 if lb_sets else 800) + k, amp=configs.DV_AMP)
-        r = series.run_series(p, phi0, steps, max(1, steps // 300))
+        phi0 = inputs.noise_phi0(p["ny"], p["nx"], (900 if lb_sets else 800) + k,
+                                 amp=configs.DV_AMP)
+        every = max(1, steps // 300)
+
+        def progress(done, o, name=name, every=every):
+            if (done // every) % 30 == 0:
+                print(f"{name}: strain {o['strain']:.1f}", file=sys.stderr, flush=True)
+
+        try:
+            r = series.run_series(p, phi0, steps, every, on_sample=progress)
+        except (le.LeError, FloatingPointError) as ex:
+            print(json.dumps({"set": name, "stopped": str(ex)}), flush=True)
+            continue
         avg = series.steady_average(r, 100.0)
         L_VI, t_VI = series.visco_inertial_scales(p)
-        row = {"set": name, "steps": steps, "wall_s": r["wall_s"], "gdot_t_VI": p["gdot"] * t_VI,
-               "L_VI": L_VI, **avg}
+        row = {"set": name, "grid": [p["nx"], p["ny"]], "dt": p["dt"], "steps": steps,
+               "wall_s": r["wall_s"], "gdot_t_VI": p["gdot"] * t_VI, "L_VI": L_VI, **avg}
         rows.append(row)
         print(json.dumps(row), flush=True)
-    if lb_sets:
+    if lb_sets or len(rows) < 3:
         return
     x = [r["gdot_t_VI"] for r in rows]
     ep = series.power_fit(x, [r["L_par"] / r["L_VI"] for r in rows])
@@ -135,6 +146,9 @@ def main(argv=None):
     c.add_argument("--strain", type=float, default=150.0)
     c.add_argument("--lb-sets", action="store_true",
                    help="the sets R028s, R022s, R029s instead of the scaling-plot sets")
+    c.add_argument("--refine", type=int, default=1, choices=(1, 2),
+                   help="2: half the mesh interval of Table I at the same l")
+    c.add_argument("--sets", default="", help="comma-separated subset of the sets")
     args = ap.parse_args(argv)
     t0 = time.time()
     if args.cmd == "dv-sheared":
@@ -142,7 +156,7 @@ def main(argv=None):
     elif args.cmd == "zero-shear":
         zero_shear(args.seeds, args.refine, args.sets)
     else:
-        steady_states(args.strain, args.lb_sets)
+        steady_states(args.strain, args.lb_sets, args.refine, args.sets)
     print(json.dumps({"wall_s": time.time() - t0}), file=sys.stderr, flush=True)
 
 

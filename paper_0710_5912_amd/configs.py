@@ -104,9 +104,13 @@ R_SHEARED_LB = {
 }
 
 
-def r_sheared(name):
+def r_sheared(name, refine=1):
+    """refine = 2: half the mesh interval at the same l (2048 x 1024), with dt
+    capped at 0.004 for the explicit Cahn-Hilliard terms."""
     eta, rho, gdot, dt = R_SHEARED[name] if name in R_SHEARED else R_SHEARED_LB[name]
-    return paper_units(0.00156, eta, rho, gdot, 2.0, 1024, 512, dt)
+    r = _refine(refine)
+    return paper_units(0.00156, eta, rho, gdot, 2.0, 1024 * r, 512 * r,
+                       min(dt, 0.016 / (r * r)))
 
 
 # Zero-shear viscous-to-inertial series of Table I (sets R028u .. R032u):

@@ -139,7 +139,8 @@ def test_presets_within_the_explicit_bound():
     would not (2.0), hence its dt = 0.004."""
     ps = [configs.dv_sheared(n, r) for n in configs.DV_SHEARED for r in (1, 2)]
     ps += [configs.dv_unsheared(n, r) for n in configs.DV_UNSHEARED for r in (1, 2)]
-    ps += [configs.r_sheared(n) for n in list(configs.R_SHEARED) + list(configs.R_SHEARED_LB)]
+    ps += [configs.r_sheared(n, r) for n in list(configs.R_SHEARED) + list(configs.R_SHEARED_LB)
+           for r in (1, 2)]
     ps += [configs.r_unsheared(n) for n in configs.R_UNSHEARED]
     assert all(series.explicit_ch_number(p) <= 0.81 for p in ps)
     p = configs.dv_sheared("DV6s", 2)
