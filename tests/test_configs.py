@@ -149,3 +149,16 @@ def test_presets_within_the_explicit_bound():
     assert abs(series.explicit_ch_number(dict(p, dt=0.016)) - 2.0148) < 1e-3
     with pytest.raises(ValueError):
         configs.dv_sheared("DV1s", 3)
+
+
+def test_campaign_set_selection():
+    """The campaigns' --sets subset keeps the table's index (the seed offset)
+    and rejects unknown names."""
+    from paper_0710_5912_amd import campaigns
+    assert campaigns._pick(configs.DV_SHEARED, "DV5s,DV6s") == [(4, "DV5s"), (5, "DV6s")]
+    assert [n for _, n in campaigns._pick(configs.R_SHEARED, "")] == list(configs.R_SHEARED)
+    with pytest.raises(SystemExit):
+        campaigns._pick(configs.DV_SHEARED, "DV7s")
+    p = configs.r_sheared("R028bs", 2)
+    assert (p["nx"], p["ny"], p["dt"]) == (2048, 1024, 0.004)
+    assert configs.r_sheared("R032s", 2)["dt"] == 0.004
