@@ -7,8 +7,8 @@
 dv-sheared: the inertialess sheared sets DV1s .. DV6s, L_par and L_perp
 against strain (Section VIII D).  zero-shear: the sets DV1u .. DV6u and
 R028u .. R032u to L_s = 0.025, growth exponents of L_s(t) by the protocol of
-Section VIII A with a fitted offset.  --refine 2 runs the DV sets on a grid of
-half the mesh interval at the same interfacial width (the low-viscosity sets
+Section VIII A with a fitted offset.  --refine 2 runs the sets on a grid of
+half the mesh interval at the same interfacial width (the low-viscosity DV sets
 need it: on the Table I grid, l = 0.8 mesh intervals, they become non-finite).  steady-states: the inertial sheared
 sets of the scaling plot to the given strain, averages over strain >= 100
 and the power-law fits of L_par, L_perp against gdot t_VI (Section VIII B);
@@ -74,9 +74,7 @@ def _to_length(p, phi0, L_stop=0.025, chunk=250, max_chunks=1600):
 
 def zero_shear(seeds: int, refine: int = 1, sets: str = ""):
     table = {**{n: configs.dv_unsheared(n, refine) for n in configs.DV_UNSHEARED},
-             **{n: configs.r_unsheared(n) for n in configs.R_UNSHEARED}}
-    if refine != 1:
-        table = {n: p for n, p in table.items() if n in configs.DV_UNSHEARED}
+             **{n: configs.r_unsheared(n, refine) for n in configs.R_UNSHEARED}}
     summary = {}
     for k, name in _pick(table, sets):
         p = table[name]
@@ -140,7 +138,7 @@ def main(argv=None):
     b.add_argument("--seeds", type=int, default=4)
     for x in (a, b):
         x.add_argument("--refine", type=int, default=1, choices=(1, 2),
-                       help="2: half the mesh interval of Table I at the same l (DV sets)")
+                       help="2: half the mesh interval of Table I at the same l")
         x.add_argument("--sets", default="", help="comma-separated subset of the sets")
     c = sub.add_parser("steady-states")
     c.add_argument("--strain", type=float, default=150.0)

@@ -126,6 +126,8 @@ R_UNSHEARED = {
 }
 
 
-def r_unsheared(name):
+def r_unsheared(name, refine=1):
+    """refine = 2: 1024^2 at the same l and dt (within the explicit bound)."""
     eta, rho = R_UNSHEARED[name]
-    return paper_units(0.00156, eta, rho, 0.0, 1.0, 512, 512, 0.008)
+    r = _refine(refine)
+    return paper_units(0.00156, eta, rho, 0.0, 1.0, 512 * r, 512 * r, 0.008)

@@ -141,7 +141,7 @@ def test_presets_within_the_explicit_bound():
     ps += [configs.dv_unsheared(n, r) for n in configs.DV_UNSHEARED for r in (1, 2)]
     ps += [configs.r_sheared(n, r) for n in list(configs.R_SHEARED) + list(configs.R_SHEARED_LB)
            for r in (1, 2)]
-    ps += [configs.r_unsheared(n) for n in configs.R_UNSHEARED]
+    ps += [configs.r_unsheared(n, r) for n in configs.R_UNSHEARED for r in (1, 2)]
     assert all(series.explicit_ch_number(p) <= 0.81 for p in ps)
     p = configs.dv_sheared("DV6s", 2)
     assert (p["nx"], p["ny"], p["dt"]) == (2048, 1024, 0.004)
