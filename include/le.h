@@ -271,6 +271,9 @@ void le_batch_destroy(le_batch* b);  /* NULL-safe */
 int le_corrector_load(le_ctx* c, const float* params, int32_t nparams, const float* scales);
 int le_step_corrected(le_ctx* c, int64_t ncoarse);
 
+int le_restrict(le_ctx* c, int32_t factor, double* phi_out, double* omega_out);
+int le_set_fields(le_ctx* c, const double* phi, const double* omega, int64_t step);
+
 /*
  * Corrector audit (failure detection; the paper has no corrector, so this
  * is a safeguard of the learned step, not part of the method).  With
@@ -293,8 +296,6 @@ int le_step_corrected(le_ctx* c, int64_t ncoarse);
  */
 int le_corrector_audit(le_ctx* c, int64_t every, int64_t window, double tol);
 int le_corrector_status(le_ctx* c, int32_t* fallback, int64_t* audits, double* last_dev);
-int le_restrict(le_ctx* c, int32_t factor, double* phi_out, double* omega_out);
-int le_set_fields(le_ctx* c, const double* phi, const double* omega, int64_t step);
 
 /*
  * Training the corrector network on the GPU (BF16 matrix-core kernels, FP32
