@@ -249,6 +249,7 @@ int le_batch_get_state(le_batch* b, int32_t run, double* phi, double* omega, dou
 int le_batch_profile(le_batch* b, int enable);
 int le_batch_stage_times(le_batch* b, double* ms, int64_t* launches, int32_t cap);
 int le_batch_tuning(le_batch* b, int32_t* out, int32_t cap);
+int le_batch_set_scheme(le_batch* b, int32_t flags);  /* le_set_scheme for every run */
 void le_batch_destroy(le_batch* b);  /* NULL-safe */
 
 /*

@@ -1203,6 +1203,7 @@ int le_set_recovery(le_ctx* c, int enable) {
 
 int le_set_scheme(le_ctx* c, int32_t flags) {
   if (!c || (flags & ~(LE_SCHEME_F_HALF | LE_SCHEME_MIDPOINT_S)) != 0) return LE_EINVAL;
+  // every run of the engine (one for a context, all of a batch)
   c->midpoint_s = (flags & LE_SCHEME_MIDPOINT_S) != 0;
   std::vector<Run> h((size_t)c->nruns);
   LE_TRY(hipMemcpy(h.data(), c->d_desc, sizeof(Run) * h.size(), hipMemcpyDeviceToHost));
@@ -1367,6 +1368,10 @@ int le_batch_profile(le_batch* b, int enable) {
 }
 
 int le_tuning(le_ctx* c, int32_t* out, int32_t cap) { return tuning_of(c, out, cap); }
+
+int le_batch_set_scheme(le_batch* b, int32_t flags) {
+  return b ? le_set_scheme(b->e, flags) : LE_EINVAL;
+}
 
 int le_batch_tuning(le_batch* b, int32_t* out, int32_t cap) {
   return b ? tuning_of(b->e, out, cap) : LE_EINVAL;

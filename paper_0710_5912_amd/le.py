@@ -25,6 +25,7 @@ SYMBOLS = ("le_create", "le_step", "le_observables", "le_destroy", "le_get_state
            "le_tuning", "le_batch_tuning", "le_time_stage",
            "le_corrector_load", "le_step_corrected", "le_restrict", "le_set_fields",
            "le_corrector_audit", "le_corrector_status", "le_set_scheme", "le_set_recovery",
+           "le_batch_set_scheme",
            "le_cnn_nparams", "le_cnn_create", "le_cnn_destroy", "le_cnn_set_params",
            "le_cnn_get_params", "le_cnn_forward", "le_cnn_grad", "le_cnn_adam",
            "le_cnn_layer_fwd", "le_cnn_layer_bwd", "le_cnn_mfma_probe")
@@ -104,6 +105,8 @@ def lib():
         L.le_set_scheme.restype = C.c_int
         L.le_set_recovery.argtypes = [C.c_void_p, C.c_int]
         L.le_set_recovery.restype = C.c_int
+        L.le_batch_set_scheme.argtypes = [C.c_void_p, C.c_int32]
+        L.le_batch_set_scheme.restype = C.c_int
         L.le_observables.argtypes = [C.c_void_p, C.POINTER(LeObs), _DP, C.c_int32]
         L.le_observables.restype = C.c_int
         L.le_destroy.argtypes = [C.c_void_p]
@@ -422,6 +425,13 @@ class Batch:
         self.n = n
         self._keep = None
         self._keep_om = None
+
+    def set_scheme(self, f_half: bool = False, midpoint_s: bool = False) -> None:
+        """Scheme variants for every run (le_batch_set_scheme)."""
+        flags = (LE_SCHEME_F_HALF if f_half else 0) | (LE_SCHEME_MIDPOINT_S if midpoint_s else 0)
+        rc = lib().le_batch_set_scheme(self._h, flags)
+        if rc != LE_OK:
+            raise LeError(rc, "le_batch_set_scheme")
 
     def step(self, nsteps: int) -> None:
         rc = lib().le_batch_step(self._h, int(nsteps))

@@ -86,3 +86,25 @@ def test_scheme_switches_back_and_rejects_unknown_flags():
     b = dataclasses.replace(a, f_half=True, midpoint_s=True)
     st = mh.run(a, mh.run(b, mh.initial_state(b, phi0), 10), 10)
     assert rel(g["phi"], st.phi) <= 1e-10
+
+
+def test_batch_scheme_equals_single_runs(fixed_variants):
+    """le_batch_set_scheme: a batch of two grid classes with both variants on
+    equals each run stepped alone with the same switches, bit for bit."""
+    runs = [(params(64, 64, gdot=0.5), inputs.noise_phi0(64, 64, 35, amp=0.5)),
+            (params(128, 64, lx=128.0, ly=64.0, gdot=0.2, rho=0.0),
+             inputs.noise_phi0(64, 128, 36, amp=0.5))]
+    b = le.Batch([r[0] for r in runs], [r[1] for r in runs])
+    try:
+        b.set_scheme(f_half=True, midpoint_s=True)
+        b.step(30)
+        for i, (p, phi0) in enumerate(runs):
+            gb = b.get_state(i)
+            with le.Context(p, phi0) as c:
+                c.set_scheme(f_half=True, midpoint_s=True)
+                c.step(30)
+                gc = c.get_state()
+            for k in ("phi", "psi"):
+                assert np.array_equal(gb[k], gc[k]), (i, k)
+    finally:
+        b.close()
