@@ -152,12 +152,15 @@ def test_nonfinite_state_is_reported():
     ctx.close()
 
 
-def test_recovery_stops_at_the_last_finite_step(fixed_variants):
+@pytest.mark.parametrize("gdot", [0.0, 0.4])
+def test_recovery_stops_at_the_last_finite_step(fixed_variants, gdot):
     """An explicit Cahn-Hilliard number of ~20 (dt = 1, kappa = 0.01) blows the
-    run up.  With recovery on, the failing call leaves the context at the last
-    step whose phi is finite: it equals a fresh run of that many steps bit for
-    bit (same kernel variants), and one more step from there goes non-finite."""
-    p = params(32, 32, gdot=0.0, kappa=0.01, dt=1.0)
+    run up (with gdot = 0.4 the strain wraps at step 2, inside the replay).
+    With recovery on, the failing call leaves the context at the last step
+    whose phi is finite: it equals a fresh run of that many steps bit for bit
+    (same kernel variants, same wrap count), and one more step from there goes
+    non-finite."""
+    p = params(32, 32, gdot=gdot, kappa=0.01, dt=1.0)
     phi0 = inputs.noise_phi0(32, 32, 7, amp=0.05)
     with le.Context(p, phi0) as a, le.Context(p, phi0) as b:
         a.set_recovery(True)
@@ -169,6 +172,7 @@ def test_recovery_stops_at_the_last_finite_step(fixed_variants):
         assert 0 < m < 500 and np.all(np.isfinite(g["phi"]))
         b.step(m)
         gb = b.get_state()
+        assert g["wraps"] == gb["wraps"]
         for k in ("phi", "omega", "psi"):
             assert np.array_equal(g[k], gb[k], equal_nan=True), k
         with pytest.raises(le.LeError) as ei:
