@@ -40,13 +40,19 @@ def test_set_fields_resolves_psi():
     assert np.max(np.abs(g["psi"] - psi)) <= 1e-12 * np.max(np.abs(psi))
 
 
-def test_zero_network_leaves_the_plain_step():
-    """With the last layer zeroed the residual vanishes: corrected = plain."""
+@pytest.mark.parametrize("scheme", [False, True])
+def test_zero_network_leaves_the_plain_step(scheme):
+    """With the last layer zeroed the residual vanishes: corrected = plain,
+    also with the scheme switches on (they act on the corrected step's plain
+    part as on the plain step)."""
     p = configs.model_h(64, 64, gdot=0.5, rho=1.0)
     phi0 = inputs.noise_phi0(64, 64, 5, amp=0.5)
     params = inputs.cnn_init_params(1)
     params[19104:] = 0.0
     with le.Context(p, phi0) as a, le.Context(p, phi0) as b:
+        if scheme:
+            a.set_scheme(f_half=True, midpoint_s=True)
+            b.set_scheme(f_half=True, midpoint_s=True)
         a.corrector_load(params, [1.0, 10.0, 1.0, 1.0])
         a.step_corrected(220)          # crosses the wrap at strain 0.5 (step 200)
         b.step(220)
