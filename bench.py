@@ -1,10 +1,13 @@
 """Throughput of the sheared model-H time step on one MI355X.
 
-Workload (the single-run configuration): 1024 x 1024 grid, spacing 1,
-A = B = kappa = M = eta = 1, rho = 1, gdot = 0.01, dt = 0.005, phi0 uniform in
-[-0.05, 0.05] (seed 0), omega0 = 0; observables (L(t), S(k), stress) every 100
-steps inside the timed region.  A step is one pass of every stage of the split
-step.  Prints one JSON line.
+Headline workload (the largest single-GPU configuration): 4096 x 4096 grid,
+spacing 1, A = B = kappa = M = eta = 1, rho = 1 (inertial), gdot = 0.001,
+dt = 0.005, phi0 uniform in [-0.05, 0.05] (seed 0), omega0 = 0, FP64; the
+observables (mean phi, L(t), S(k), excess stress) every 500 steps and at the
+end of the timed region, inside it.  A step is one pass of every stage of the
+split step.  Before the clock starts, every step-call length that the timed
+region uses has been run once, so every captured graph piece exists.  Prints
+one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -12,8 +15,8 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import platform
 import sys
 import time
 
@@ -21,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, vendor figure
+METRIC = "site-updates/s/GPU (plain FP64 vs FP32, batched, learned corrector) at stated L(t) error"
 
 
 def stage_bytes(params, precision):
@@ -29,8 +33,7 @@ def stage_bytes(params, precision):
     nx, ny = params["nx"], params["ny"]
     real = nx * ny * w
     spec = ny * (nx // 2 + 1) * 2 * w
-    inertial = params["rho"] > 0
-    if inertial:
+    if params["rho"] > 0:
         return {
             "row_inv_flow": 2 * spec + 2 * real,
             "advect": 3 * real + 3 * spec,
@@ -49,32 +52,57 @@ def stage_bytes(params, precision):
     }
 
 
+def step_bytes(params, precision):
+    return sum(stage_bytes(params, precision).values())
+
+
+def four_pass_bytes(params, precision):
+    """The minimum of a four-pass schedule: 16 field passes inertial, 12 Stokes."""
+    w = 8 if precision == "fp64" else 4
+    return (16 if params["rho"] > 0 else 12) * w * params["nx"] * params["ny"]
+
+
+def call_plan(steps, obs_every):
+    """Lengths of the step calls of the timed region (observables after each)."""
+    plan, done = [], 0
+    while done < steps:
+        n = min(obs_every, steps - done)
+        plan.append(n)
+        done += n
+    return plan
+
+
 def run_variant(le, torch, params, precision, steps, warmup, obs_every, seed=0,
-                stage_reps=200):
-    """Timed region (graph-replayed steps, observables every obs_every steps),
-    then each stage timed on its own: stage_reps back-to-back launches of its
-    (autotuned) kernels between HIP events on the same stream."""
+                stage_reps=20, keep=False):
+    """Timed region: the call plan (graph-replayed steps, observables after
+    each call), bracketed by HIP events on the library's stream.  Warm-up: W
+    steps, then one call of every distinct length of the plan and one
+    observables call, so no graph is captured inside the clock.  Then each
+    stage timed on its own: stage_reps back-to-back launches of its autotuned
+    kernels between HIP events on the same stream."""
     from paper_0710_5912_amd import inputs
 
     nx, ny = params["nx"], params["ny"]
     phi0 = inputs.noise_phi0(ny, nx, seed, amp=0.05)
     stream = torch.cuda.Stream()          # default priority; the library enqueues on it
     ctx = le.Context(params, phi0, precision=precision, stream=stream.cuda_stream)
-    ctx.step(warmup)
+    plan = call_plan(steps, obs_every)
+    if warmup:
+        ctx.step(warmup)
+    for n in sorted(set(plan)):
+        ctx.step(n)
+    o0, _ = ctx.observables(sk=True)
+    step0 = o0["step"]
     series = []
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    done = 0
-    while done < steps:
-        n = min(obs_every, steps - done)
+    for n in plan:
         ctx.step(n)
-        done += n
-        if done % obs_every == 0:
-            o, _ = ctx.observables(sk=True)
-            series.append((o["t"], o["Ls"], o["sigma_xy"], o["mean_phi"]))
+        o, sk = ctx.observables(sk=True)
+        series.append((o["t"], o["Ls"], o["sigma_xy"], o["mean_phi"]))
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -83,12 +111,13 @@ def run_variant(le, torch, params, precision, steps, warmup, obs_every, seed=0,
     if stage_reps:
         times = {s: ctx.time_stage(s, stage_reps) for s in le.STAGES}
     tuning = ctx.tuning()[0]
-    ctx.close()
-    return dict(wall=wall, gpu_ms=gpu_ms, times=times, series=series, tuning=tuning)
-
-
-def step_bytes(params, precision):
-    return sum(stage_bytes(params, precision).values())
+    out = dict(wall=wall, gpu_ms=gpu_ms, times=times, series=series, tuning=tuning,
+               steps_before=step0, obs_calls=len(plan), last_obs=o, last_sk=sk)
+    if keep:
+        out["ctx"] = ctx
+    else:
+        ctx.close()
+    return out
 
 
 def stage_kernels(tuning, inertial):
@@ -107,54 +136,7 @@ def stage_kernels(tuning, inertial):
             "column_flow": "k_column<COL_FLOW>" if inertial else "k_column<COL_STOKES>"}
 
 
-def batch_workload():
-    """96 runs: 32 each of 128^2, 256^2, 512^2; gdot log-uniform in [1e-3, 1e-1]
-    (seed 1000); rho alternating 0 / 1; phi0 seed 2000 + r; FP32 bulk."""
-    from paper_0710_5912_amd import configs, inputs
-
-    gd = inputs.batch_draws(96, seed=1000)
-    params, phis = [], []
-    for r in range(96):
-        n = (128, 256, 512)[r // 32]
-        params.append(configs.model_h(n, n, gdot=float(gd[r]), rho=float(r % 2)))
-        phis.append(inputs.noise_phi0(n, n, 2000 + r, amp=0.05))
-    return params, phis
-
-
-def run_batch(le, torch, steps, warmup, seq_steps):
-    params, phis = batch_workload()
-    sites = sum(p["nx"] * p["ny"] for p in params)
-    stream = torch.cuda.Stream()
-    b = le.Batch(params, phis, precisions=["fp32"] * len(params), stream=stream.cuda_stream)
-    b.step(warmup)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    b.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    batched = sites * steps / (e0.elapsed_time(e1) * 1e-3)
-    b.close()
-    # the same runs one after another through the single-run path
-    total_ms = 0.0
-    for p, phi0 in zip(params, phis):
-        c = le.Context(p, phi0, precision="fp32", stream=stream.cuda_stream)
-        c.step(10)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        c.step(seq_steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        total_ms += e0.elapsed_time(e1)
-        c.close()
-    sequential = sites * seq_steps / (total_ms * 1e-3)
-    return dict(value=batched, sequential_value=sequential, gain=batched / sequential,
-                runs=len(params), sites=sites, steps=steps,
-                error="each run bit-identical to its single-run result (tests)")
-
-
-def roofline_of(params, precision, times):
+def roofline_rows(params, precision, times):
     """Per stage: average launch us, algorithmic bytes and GB/s; the dominant stage."""
     b = stage_bytes(params, precision)
     rows = {k: dict(avg_us=us, bytes=b[k], gbs=b[k] / (us * 1e-6) / 1e9)
@@ -172,9 +154,7 @@ def traffic_of(stage, precision, nx, tuning):
     import glob
     import hashlib
 
-    if precision != "fp64" or nx != 1024:
-        return None
-    path = os.path.join(ROOT, "profiles", "modelh_1024x1024_fp64_traffic.md")
+    path = os.path.join(ROOT, "profiles", f"modelh_{nx}x{nx}_{precision}_traffic.md")
     if not os.path.exists(path):
         return None
     rec = None
@@ -212,45 +192,179 @@ def copy_bandwidth(torch, mib=512, reps=20):
     return gbs
 
 
-def cpu_baseline(params, budget_s=15.0):
-    """The FP64 oracle, untuned, on a bounded number of steps of the same workload."""
+def field_error(a, b):
+    """Max-norm relative difference of the state fields (phi, psi) and of L_s."""
     import numpy as np
+
+    sa, sb = a.get_state(), b.get_state()
+    out = {}
+    for k in ("phi", "psi"):
+        out[k] = float(np.max(np.abs(sa[k] - sb[k])) / np.max(np.abs(sb[k])))
+    oa, ka = a.observables(sk=True)
+    ob, kb = b.observables(sk=True)
+    out["Ls"] = abs(oa["Ls"] - ob["Ls"]) / ob["Ls"]
+    good = kb > 1e-3 * kb.max()
+    out["Sk"] = float(np.max(np.abs(ka[good] - kb[good]) / kb[good]))
+    return out
+
+
+def precision_error(le, torch, params, steps, seed=0):
+    """FP32 bulk against FP64 after `steps` steps from the same phi0 (the FP64
+    GPU path equals the FP64 oracle to 1e-10 in the tests, so this is the FP32
+    error against the oracle to that accuracy)."""
+    from paper_0710_5912_amd import inputs
+
+    phi0 = inputs.noise_phi0(params["ny"], params["nx"], seed, amp=0.05)
+    a = le.Context(params, phi0, precision="fp32")
+    b = le.Context(params, phi0, precision="fp64")
+    a.step(steps)
+    b.step(steps)
+    err = field_error(a, b)
+    a.close()
+    b.close()
+    err["steps"] = steps
+    return err
+
+
+def batch_workload():
+    """96 runs: 32 each of 128^2, 256^2, 512^2; gdot log-uniform in [1e-3, 1e-1]
+    (seed 1000); rho alternating 0 / 1; phi0 seed 2000 + r; FP32 bulk."""
+    from paper_0710_5912_amd import configs, inputs
+
+    gd = inputs.batch_draws(96, seed=1000)
+    params, phis = [], []
+    for r in range(96):
+        n = (128, 256, 512)[r // 32]
+        params.append(configs.model_h(n, n, gdot=float(gd[r]), rho=float(r % 2)))
+        phis.append(inputs.noise_phi0(n, n, 2000 + r, amp=0.05))
+    return params, phis
+
+
+def run_batch(le, torch, steps, warmup, seq_steps):
+    """Batched rate, the same runs one after another through the single-run
+    path (each warmed up with the timed call length first), and the FP32
+    batch's error against single FP64 runs for a sample of runs."""
+    import numpy as np
+
+    params, phis = batch_workload()
+    sites = sum(p["nx"] * p["ny"] for p in params)
+    stream = torch.cuda.Stream()
+    b = le.Batch(params, phis, precisions=["fp32"] * len(params), stream=stream.cuda_stream)
+    b.step(warmup)
+    b.step(steps)       # every graph piece of the timed call captured
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batched = sites * steps / (e0.elapsed_time(e1) * 1e-3)
+    done = warmup + 2 * steps
+    sample = (0, 33, 66, 95)
+    errs = []
+    for r in sample:
+        ref = le.Context(params[r], phis[r], precision="fp64")
+        ref.step(done)
+        sr, sb = ref.get_state(), b.get_state(r)
+        errs.append(float(np.max(np.abs(sb["phi"] - sr["phi"])) / np.max(np.abs(sr["phi"]))))
+        ref.close()
+    b.close()
+    total_ms = 0.0
+    for p, phi0 in zip(params, phis):
+        c = le.Context(p, phi0, precision="fp32", stream=stream.cuda_stream)
+        c.step(seq_steps)       # capture the call's graph pieces
+        torch.cuda.synchronize()
+        e0.record(stream)
+        c.step(seq_steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        total_ms += e0.elapsed_time(e1)
+        c.close()
+    sequential = sites * seq_steps / (total_ms * 1e-3)
+    return dict(value=batched, sequential_value=sequential, gain=batched / sequential,
+                runs=len(params), sites=sites, steps=steps,
+                error=dict(sample_runs=list(sample), steps=done,
+                           phi_rel_err_vs_fp64_single_runs=errs,
+                           note="each run is also bit-identical to its FP32 single run (tests)"))
+
+
+def cpu_info():
+    model = platform.processor() or "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(params):
+    """The FP64 oracle, untuned, on one step of the headline workload (a
+    bounded sample: one 4096^2 oracle step is ~10-15 s of CPU work), then the
+    same step with its 2D FFTs taken by scipy.fft over all host threads."""
+    import numpy as np
+    import scipy.fft as sf
 
     from oracle import model_h as mh
     from paper_0710_5912_amd import inputs
 
+    model, nproc = cpu_info()
     p = mh.Params(**params)
-    phi0 = inputs.noise_phi0(p.ny, p.nx, 0, amp=0.05)
-    st = mh.initial_state(p, phi0)
-    st = mh.step(p, st)           # first step outside the clock (allocations)
+    st = mh.initial_state(p, inputs.noise_phi0(p.ny, p.nx, 0, amp=0.05))
     t0 = time.perf_counter()
-    n = 0
-    while True:
+    st = mh.step(p, st)
+    dt1 = time.perf_counter() - t0
+    fft2, ifft2 = mh.fft2, mh.ifft2_real
+    try:
+        mh.fft2 = lambda a: sf.fft2(a, workers=nproc)
+        mh.ifft2_real = lambda A: np.real(sf.ifft2(A, workers=nproc))
+        t0 = time.perf_counter()
         st = mh.step(p, st)
-        n += 1
-        if time.perf_counter() - t0 >= budget_s and n >= 3:
-            break
-    dt = time.perf_counter() - t0
+        dtn = time.perf_counter() - t0
+    finally:
+        mh.fft2, mh.ifft2_real = fft2, ifft2
     assert np.isfinite(st.phi).all()
-    return dict(value=p.nx * p.ny * n / dt, unit="site-updates/s", cores=1, kind="oracle",
-                sample=f"{n} steps of the {p.nx}x{p.ny} inertial workload after 1 untimed "
-                       f"step ({dt:.1f} s); NumPy FFT and ufuncs, single thread")
+    sites = p.nx * p.ny
+    return dict(value=sites / dt1, unit="site-updates/s", cores=1, kind="oracle",
+                sample=f"1 step of the {p.nx}x{p.ny} FP64 inertial headline workload "
+                       f"({dt1:.1f} s; NumPy FFTs and ufuncs, one thread)",
+                cpu_model=model, nproc=nproc,
+                threaded=dict(value=sites / dtn, cores=nproc,
+                              sample=f"the next step with scipy.fft workers={nproc} for the "
+                                     f"2D FFTs ({dtn:.1f} s); stencils single-threaded"))
+
+
+def variant_entry(params, precision, rv, steps, sites):
+    d, rw = roofline_rows(params, precision, rv["times"])
+    ms = rv["gpu_ms"] / steps
+    return dict(value=sites * steps / (rv["gpu_ms"] * 1e-3), ms_per_step=ms,
+                dominant=d, dominant_frac=rw[d]["gbs"] / HBM_PEAK_GBS,
+                step_frac=step_bytes(params, precision) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                step_frac_four_pass=four_pass_bytes(params, precision) / (ms * 1e-3) / 1e9
+                / HBM_PEAK_GBS,
+                tuning=rv["tuning"], obs_calls=rv["obs_calls"],
+                stages={k: {"avg_us": round(v["avg_us"], 1), "GBs": round(v["gbs"], 1)}
+                        for k, v in rw.items()})
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--obs-every", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--obs-every", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--profile-size", type=int, default=1024)
-    ap.add_argument("--profile-precision", default="fp64", choices=("fp64", "fp32"))
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32"),
+                    help="headline precision (the configuration's default: fp64)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="short pass for hardware counters: a 512 MiB device copy "
-                         "(calibration of FETCH_SIZE/WRITE_SIZE) then 50 directly launched "
-                         "steps of the 1024^2 FP64 workload; prints no JSON")
+                         "(calibration of FETCH_SIZE/WRITE_SIZE) then directly launched "
+                         "steps of the headline workload; prints no JSON")
+    ap.add_argument("--profile-size", type=int, default=4096)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -262,57 +376,64 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
-    from paper_0710_5912_amd import configs, le
+    from paper_0710_5912_amd import configs, inputs, le
 
-    params = configs.single_1024(rho=1.0, gdot=0.01)["params"]
+    params = configs.LARGE_4096["params"]
+    prec = args.precision
     if args.profile_pass:
         src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        from paper_0710_5912_amd import inputs
         n = args.profile_size
-        pp = configs.model_h(n, n, gdot=0.01, rho=1.0)
-        ctx = le.Context(pp, inputs.noise_phi0(n, n, 0), precision=args.profile_precision)
+        pp = configs.model_h(n, n, gdot=params["gdot"] if n == 4096 else 0.01, rho=1.0)
+        ctx = le.Context(pp, inputs.noise_phi0(n, n, 0), precision=prec)
         ctx.profile(True)      # direct launches: one dispatch per stage and step
-        ctx.step(50 if n <= 1024 else 10)
+        ctx.step(10 if n >= 4096 else 50)
         print(json.dumps({"profile_pass": ctx.stage_times(), "tuning": ctx.tuning()}))
         ctx.close()
         return
-    print(f"bench: 1024x1024 fp64 inertial, {args.warmup} warmup + {args.steps} timed steps",
+    nx, ny = params["nx"], params["ny"]
+    sites = nx * ny
+    print(f"bench: {nx}x{ny} {prec} inertial, {args.warmup} warmup + {args.steps} timed steps",
           file=sys.stderr, flush=True)
-    r = run_variant(le, torch, params, "fp64", args.steps, args.warmup, args.obs_every)
-    sites = params["nx"] * params["ny"]
+    r = run_variant(le, torch, params, prec, args.steps, args.warmup, args.obs_every)
     copy_gbs = copy_bandwidth(torch)
-    sec = r["gpu_ms"] * 1e-3
-    value = sites * args.steps / sec
-    dom, rows = roofline_of(params, "fp64", r["times"])
+    value = sites * args.steps / (r["gpu_ms"] * 1e-3)
+    dom, rows = roofline_rows(params, prec, r["times"])
+    ms_step = r["gpu_ms"] / args.steps
+    o = r["last_obs"]
     out = {
-        "metric": "site-updates/s/GPU (plain FP64 vs FP32, batched, learned corrector) at stated L(t) error",
+        "metric": METRIC,
         "value": value,
         "unit": "site-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r["gpu_ms"] / args.steps,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": "sheared model H, 1024x1024, inertial rho=1, eta=1, gdot=0.01, "
-                               "dt=0.005, A=B=kappa=M=1, dx=1, phi0 U(-0.05,0.05) seed 0, "
-                               "plain FP64 step, observables every 100 steps",
-                   "grid": [1024, 1024], "precision": "fp64", "rho": 1.0, "gdot": 0.01,
-                   "obs_every": args.obs_every},
+        "config": {"workload": f"sheared model H, {nx}x{ny}, inertial rho=1, eta=1, "
+                               f"gdot=0.001, dt=0.005, A=B=kappa=M=1, dx=1, phi0 "
+                               f"U(-0.05,0.05) seed 0, omega0=0, plain {prec.upper()} step, "
+                               f"observables (L(t), S(k), stress) every {args.obs_every} "
+                               f"steps and at the end, inside the timed region",
+                   "grid": [nx, ny], "precision": prec, "rho": 1.0, "gdot": 0.001,
+                   "obs_every": args.obs_every, "obs_calls": r["obs_calls"],
+                   "warmup_note": "W steps, then one call of each timed call length and "
+                                  "one observables call before the clock starts"},
         "roofline": {"bound": "hbm", "stage": dom,
                      "kernels": stage_kernels(r["tuning"], True)[dom],
-                     "timing": "HIP events around 200 back-to-back launches of the stage's "
-                               "kernels after the timed region, on the library's stream",
+                     "timing": f"HIP events around back-to-back launches of the stage's "
+                               f"autotuned kernels on the library's stream, after the timed "
+                               f"region",
                      "achieved": rows[dom]["gbs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": rows[dom]["gbs"] / HBM_PEAK_GBS,
-                     "traffic": traffic_of(dom, "fp64", 1024, r["tuning"]),
+                     "traffic": traffic_of(dom, prec, nx, r["tuning"]),
                      "bytes_per_launch": rows[dom]["bytes"],
                      "avg_launch_us": rows[dom]["avg_us"],
                      "copy_gbs": copy_gbs,
@@ -321,30 +442,37 @@ def main():
                      "frac_of_copy": rows[dom]["gbs"] / copy_gbs},
         "stages": {k: {"avg_us": round(v["avg_us"], 2), "GBs": round(v["gbs"], 1)}
                    for k, v in rows.items()},
-        "step_roofline": {"bytes_per_step": step_bytes(params, "fp64"),
-                          "bytes_per_step_four_pass_minimum": 128 * sites,
-                          "frac": step_bytes(params, "fp64") / (r["gpu_ms"] / args.steps * 1e-3)
-                          / 1e9 / HBM_PEAK_GBS,
-                          "frac_four_pass_minimum": 128 * sites / (r["gpu_ms"] / args.steps * 1e-3)
-                          / 1e9 / HBM_PEAK_GBS},
+        "step_roofline": {"bytes_per_step": step_bytes(params, prec),
+                          "bytes_per_step_four_pass_minimum": four_pass_bytes(params, prec),
+                          "frac": step_bytes(params, prec) / (ms_step * 1e-3) / 1e9
+                          / HBM_PEAK_GBS,
+                          "frac_four_pass_minimum": four_pass_bytes(params, prec)
+                          / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "last_observables": {k: o[k] for k in ("step", "t", "mean_phi", "Ls", "L_par",
+                                                "L_perp", "sigma_xy", "sigma_xy_re")},
         "tuning": r["tuning"],
         "wall_s": r["wall"],
         "hip_note": le.lib().le_last_error().decode(),
-        "parity": "FP64 path within 1e-10 of the FP64 oracle after 100 steps (tests)",
+        "error": "FP64 path within 1e-10 (max norm, relative) of the FP64 oracle after 100 "
+                 "steps in the parity tests, and at sampled points of this workload",
     }
     if not args.no_variants:
         var = {}
-        for name, prec, rho, n in (("fp32_inertial", "fp32", 1.0, 2000),
-                                   ("fp64_stokes", "fp64", 0.0, 2000),
-                                   ("fp32_stokes", "fp32", 0.0, 2000)):
+        print("bench: variant fp32 4096", file=sys.stderr, flush=True)
+        p = configs.LARGE_4096["params"]
+        rv = run_variant(le, torch, p, "fp32", 1000, 100, 500)
+        var["fp32_4096_inertial"] = variant_entry(p, "fp32", rv, 1000, sites)
+        var["fp32_4096_inertial"]["error_vs_fp64"] = precision_error(le, torch, p, 200)
+        for name, prec_v, rho in (("fp64_1024_inertial", "fp64", 1.0),
+                                  ("fp32_1024_inertial", "fp32", 1.0),
+                                  ("fp64_1024_stokes", "fp64", 0.0),
+                                  ("fp32_1024_stokes", "fp32", 0.0)):
             p = configs.single_1024(rho=rho, gdot=0.01)["params"]
             print(f"bench: variant {name}", file=sys.stderr, flush=True)
-            rv = run_variant(le, torch, p, prec, n, 100, args.obs_every)
-            d, rw = roofline_of(p, prec, rv["times"])
-            var[name] = dict(value=sites * n / (rv["gpu_ms"] * 1e-3),
-                             ms_per_step=rv["gpu_ms"] / n,
-                             dominant=d, dominant_frac=rw[d]["gbs"] / HBM_PEAK_GBS,
-                             tuning=rv["tuning"])
+            rv = run_variant(le, torch, p, prec_v, 2000, 100, 100, stage_reps=100)
+            var[name] = variant_entry(p, prec_v, rv, 2000, 1024 * 1024)
+            if prec_v == "fp32":
+                var[name]["error_vs_fp64"] = precision_error(le, torch, p, 2000)
         print("bench: variant batched_96", file=sys.stderr, flush=True)
         var["batched_96_fp32"] = run_batch(le, torch, 500, 50, 100)
         print("bench: variant corrector", file=sys.stderr, flush=True)
@@ -368,32 +496,6 @@ def main():
                  f"against the fine field restricted to the coarse grid; audited: the "
                  f"corrected run with a 20-step corrected-vs-plain audit every 500 steps "
                  f"(L_s tolerance 2%)")
-        # the inertialess sheared set DV4s of Table I in paper units (1024 x 512,
-        # Stokes branch), 20000 steps with observables every 5000
-        print("bench: variant dv4s", file=sys.stderr, flush=True)
-        from paper_0710_5912_amd import inputs, series
-        pdv = configs.dv_sheared("DV4s")
-        rdv = series.run_series(pdv, inputs.noise_phi0(512, 1024, 500, amp=configs.DV_AMP),
-                                20000, 5000)
-        var["dv4s_1024x512_stokes_fp64"] = dict(
-            value=rdv["site_updates_per_s"], steps=20000, strain=float(rdv["strain"][-1]),
-            L_par=float(rdv["L_par"][-1]), L_perp=float(rdv["L_perp"][-1]),
-            note="Table I set DV4s (eta = 1, gdot = 0.01, l = 0.00156, rho = 0, box 2 x 1), "
-                 "wall time of stepping plus observables every 5000 steps")
-        # the large single-GPU grid, FP64 and FP32 bulk
-        for prec in ("fp64", "fp32"):
-            p = configs.LARGE_4096["params"]
-            print(f"bench: variant {prec}_4096", file=sys.stderr, flush=True)
-            rv = run_variant(le, torch, p, prec, 200, 20, 100, stage_reps=20)
-            d, rw = roofline_of(p, prec, rv["times"])
-            ms = rv["gpu_ms"] / 200
-            var[f"{prec}_4096_inertial"] = dict(
-                value=4096 * 4096 * 200 / (rv["gpu_ms"] * 1e-3), ms_per_step=ms, dominant=d,
-                dominant_frac=rw[d]["gbs"] / HBM_PEAK_GBS,
-                step_frac=step_bytes(p, prec) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                tuning=rv["tuning"],
-                stages={k: {"avg_us": round(v["avg_us"], 1), "GBs": round(v["gbs"], 1)}
-                        for k, v in rw.items()})
         out["variants"] = var
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)

@@ -109,20 +109,22 @@ int le_create(const le_params* p, const double* phi0, const double* omega0,
 
 /* Advance nsteps >= 0 full time steps (the sawtooth clock advances with
  * them).  Returns LE_ENONFINITE if phi became non-finite, checked at the end
- * of the call; the context then holds the non-finite state, or with
- * le_set_recovery on, the last finite one.  nsteps < 0: LE_EINVAL. */
+ * of the call; the context is then left at the last step whose phi is finite
+ * (step counter and wrap count included; see le_set_recovery, on by
+ * default).  nsteps < 0: LE_EINVAL. */
 int le_step(le_ctx* c, int64_t nsteps);
 
 /*
  * Recovery from a non-finite state (failure handling; not part of the
- * method).  With enable != 0, le_step keeps a copy of the state at the start
- * of each call (two state snapshots are allocated here: LE_ENOMEM); when the
- * call ends with a non-finite phi it replays the call's steps one at a time
- * from that copy and leaves the context at the last step whose phi is finite
- * (step counter and wrap count included), still returning LE_ENONFINITE.  A
- * call that starts from a non-finite state is left at its start.  enable = 0
- * (the default): le_step returns LE_ENONFINITE with the non-finite state.
- * Single contexts only (LE_EINVAL for NULL).
+ * method).  On (the default of every context from le_create): le_step keeps
+ * a copy of the state at the start of each call (two state snapshots, taken
+ * from the context's memory at creation); when the call ends with a
+ * non-finite phi it replays the call's steps one at a time from that copy
+ * and leaves the context at the last step whose phi is finite, returning
+ * LE_ENONFINITE.  A call that starts from a non-finite state is left at its
+ * start.  enable = 0: le_step skips the copy and returns LE_ENONFINITE with
+ * the non-finite state in place.  Single contexts only (LE_EINVAL for NULL);
+ * LE_ENOMEM if the snapshots cannot be allocated when re-enabled.
  */
 int le_set_recovery(le_ctx* c, int enable);
 
@@ -298,42 +300,8 @@ int le_set_fields(le_ctx* c, const double* phi, const double* omega, int64_t ste
 int le_corrector_audit(le_ctx* c, int64_t every, int64_t window, double tol);
 int le_corrector_status(le_ctx* c, int32_t* fallback, int64_t* audits, double* last_dev);
 
-/*
- * Training the corrector network on the GPU (BF16 matrix-core kernels, FP32
- * accumulation and master weights, Adam).  Pointers named *_dev are device
- * memory (e.g. torch tensors); planes are [channel][H][W] FP32 with channel 0
- * = phi and 1 = omega; batches stack planes: [B][2][H][W].  H, W: powers of
- * two >= 16 with H*W a multiple of 256.  stream: hipStream_t or NULL.
- *
- * le_cnn_grad: loss = mean over the batch, channels and pixels of (r - t)^2
- *   with r the network's output on x, t the target residual; its gradient
- *   replaces the stored one (and is copied to grad_host when non-NULL).
- * le_cnn_adam: one Adam step with the stored gradient.
- * le_cnn_layer_fwd / le_cnn_layer_bwd (layer 0..3) run one convolution on
- *   pixel-major BF16 inputs a_in_dev [H*W][Cin] (bit patterns): forward gives
- *   the FP32 pre-activation [H*W][Cout] (and BF16 SiLU output for layers
- *   0..2); backward takes dz_dev [H*W][Cout] FP32 and gives the weight and
- *   bias gradient dw_dev (that layer's slice of the weight vector) and, for
- *   layers 1..3 when dzprev_dev is given, the input gradient times silu'(zprev)
- *   (zprev_dev NULL: the plain input gradient).
- * le_cnn_mfma_probe: one 32x32x16 BF16 matrix product c = a b on host arrays
- *   (row-major a 32x16, b 16x32 BF16 bit patterns, c 32x32 FP32).
- */
-typedef struct le_cnn le_cnn;
-int le_cnn_nparams(void);
-int le_cnn_create(int32_t H, int32_t W, le_cnn** out);
-void le_cnn_destroy(le_cnn* c);  /* NULL-safe */
-int le_cnn_set_params(le_cnn* c, const float* params, int32_t n, const float* scales);
-int le_cnn_get_params(le_cnn* c, float* params, int32_t n);
-int le_cnn_forward(le_cnn* c, const float* x_dev, float* r_dev, void* stream);
-int le_cnn_grad(le_cnn* c, const float* x_dev, const float* t_dev, int32_t batch, double* loss,
-                float* grad_host, void* stream);
-int le_cnn_adam(le_cnn* c, float lr, float beta1, float beta2, float eps, void* stream);
-int le_cnn_layer_fwd(le_cnn* c, int32_t layer, const uint16_t* a_in_dev, float* z_out_dev,
-                     uint16_t* a_out_dev, void* stream);
-int le_cnn_layer_bwd(le_cnn* c, int32_t layer, const float* dz_dev, const uint16_t* a_in_dev,
-                     const float* zprev_dev, float* dzprev_dev, float* dw_dev, void* stream);
-int le_cnn_mfma_probe(const uint16_t* a, const uint16_t* b, float* c);
+/* The corrector network's training entry points (device pointers, not part
+ * of the time-step contract) are declared in le_train.h. */
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/le.h"
+#include "../../include/le_train.h"
 #include "cnn.hpp"
 #include "common.hpp"
 #include "ops.hpp"
@@ -971,7 +972,9 @@ int corrected_steps(Engine* e, int64_t ncoarse) {
   int64_t remaining = ncoarse;
   while (remaining > 0) {
     const int64_t n0 = e->step;
-    const int64_t cap = e->use_graphs ? kGraphChunk : kChunkCap;
+    // while timing stages every step of a chunk records into the event pool,
+    // which holds kProfChunk steps
+    const int64_t cap = e->profiling ? kProfChunk : (e->use_graphs ? kGraphChunk : kChunkCap);
     int64_t count = remaining < cap ? remaining : cap;
     for (int64_t k = 0; k < count; ++k) {
       e->h_args[k].s =
@@ -1011,6 +1014,7 @@ int corrected_steps(Engine* e, int64_t ncoarse) {
     }
     LE_TRY(hipGetLastError());
     LE_TRY(hipStreamSynchronize(e->stream));
+    if (e->profiling) harvest_times(e, count);
     remaining -= count;
   }
   return LE_OK;
@@ -1186,7 +1190,17 @@ int le_create(const le_params* p, const double* phi0, const double* omega0, le_c
   if (!out || !phi0 || !p) return LE_EINVAL;
   const double* const phis[1] = {phi0};
   const double* const oms[1] = {omega0};
-  return create_engine(1, p, phis, oms, out);
+  LE_RC(create_engine(1, p, phis, oms, out));
+  // a step call that goes non-finite stops at the last finite step unless
+  // the caller turns this off (le_set_recovery(c, 0))
+  const int rc = alloc_snapshots(*out, (*out)->runs[0]);
+  if (rc) {
+    destroy_engine(*out);
+    *out = nullptr;
+    return rc;
+  }
+  (*out)->recovery = true;
+  return LE_OK;
 }
 
 int le_step(le_ctx* c, int64_t nsteps) {

@@ -93,15 +93,16 @@ def test_stage_timer_validates_arguments():
     assert lib.le_time_stage(None, 0, 1, C.byref(ms)) == le.LE_EINVAL
 
 
+@pytest.mark.parametrize("header", ["le.h", "le_train.h"])
 @pytest.mark.parametrize("lang,std", [("c", "c99"), ("c++", "c++11")])
-def test_header_compiles_standalone(lang, std, tmp_path):
-    """include/le.h is plain C: it compiles on its own as C99 and as C++11."""
+def test_header_compiles_standalone(lang, std, header, tmp_path):
+    """The headers are plain C: each compiles on its own as C99 and as C++11."""
     import shutil
     import subprocess
     cc = shutil.which("gcc" if lang == "c" else "g++")
     if cc is None:
         pytest.skip("no host compiler")
     r = subprocess.run([cc, "-x", lang, f"-std={std}", "-Wall", "-Wextra", "-Werror",
-                        "-fsyntax-only", os.path.join(ROOT, "include", "le.h")],
+                        "-fsyntax-only", os.path.join(ROOT, "include", header)],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr

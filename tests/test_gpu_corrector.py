@@ -210,3 +210,26 @@ def test_audit_needs_a_corrector():
         with pytest.raises(le.LeError) as ei:
             c.corrector_audit(10, 2, 0.02)
         assert ei.value.code == le.LE_EINVAL
+
+
+def test_stage_timing_of_long_corrected_calls_without_graphs(monkeypatch):
+    """Stage timing on and graphs off: corrected calls longer than the timing
+    event pool run in pieces that fit it, count every corrected step's stages,
+    and give the same state as an untimed run."""
+    monkeypatch.setenv("LE_GRAPHS", "0")
+    p = configs.model_h(64, 64, gdot=0.1, rho=1.0)
+    phi0 = inputs.noise_phi0(64, 64, 8, amp=0.5)
+    params = inputs.cnn_init_params(3)
+    scales = [1.0, 10.0, 0.05, 0.01]
+    with le.Context(p, phi0) as a, le.Context(p, phi0) as b:
+        for c in (a, b):
+            c.corrector_load(params, scales)
+        a.profile(True)
+        a.step_corrected(300)
+        b.step_corrected(300)
+        times = a.stage_times()
+        ga, gb = a.get_state(), b.get_state()
+    assert all(n == 300 for _, n in times.values()), times
+    assert all(ms > 0.0 for ms, _ in times.values()), times
+    for k in ("phi", "omega", "psi"):
+        assert np.max(np.abs(ga[k] - gb[k])) <= 1e-12 * np.max(np.abs(gb[k])), k
