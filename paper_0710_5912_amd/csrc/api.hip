@@ -1025,7 +1025,7 @@ int alloc_snapshots(Engine* e, const RunHost& r) {
   const size_t bytes[3] = {r.n_real * r.tsize, r.n_spec * 2 * r.tsize, r.n_spec * 2 * r.tsize};
   for (auto& sn : e->snap)
     for (int i = 0; i < 3; ++i)
-      if (!sn[i]) LE_RC(alloc(&sn[i], bytes[i]));
+      if (!sn[i] && (i != 1 || r.inertial)) LE_RC(alloc(&sn[i], bytes[i]));
   return LE_OK;
 }
 
@@ -1036,6 +1036,7 @@ int copy_state(Engine* e, const RunHost& r, bool to_snap, int k) {
   for (int i = 0; i < 3; ++i) {
     void* live = r.buf[bufs[i]];
     void* snap = e->snap[k][i];
+    if (!live) continue;  // omega's spectrum of a Stokes run
     LE_TRY(hipMemcpyAsync(to_snap ? snap : live, to_snap ? live : snap, bytes[i],
                           hipMemcpyDeviceToDevice, e->stream));
   }
