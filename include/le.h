@@ -204,21 +204,25 @@ int le_time_stage(le_ctx* c, int32_t stage, int32_t reps, double* ms_per_launch)
  * rounding; runs are bit-identical only between equal variants).  le_tuning
  * writes, per group, LE_TUNING_FIELDS int32 values
  *   nx, ny, precision, inertial, advect, mu_source, column_ch, column_flow,
- *   row
+ *   row, row_fwd
  * (advect / mu_source: 0 = one fused stencil-and-row-transform kernel,
  * 0 < k < 64 = a stencil kernel over k-row strips then in-place row
  * transforms; advect 64 + k and 96 + k (two or one x pairs per thread, nx
  * 256 .. 1024) and mu_source 64 + k (nx 256 .. 2048) = the k-row strip
  * stencil and the row transforms in one kernel (other nx: as k);
- * column_*: block shape 0 .. 3; row: row-transform shape 0 .. 3, 8 or 4
- * values per thread, all or a quarter of the rows per block), at most cap
+ * column_*: block shape 0 .. 4 (8 or 16 values per thread, columns per
+ * block); row / row_fwd: shape 0 .. 5 of the inverse / forward row
+ * transforms (8 or 4 values per thread; all or a quarter of the rows per
+ * block, or 4 and 5: groups of four consecutive rows stored or loaded
+ * together)), at most cap
  * values in all, and returns the number of
  * groups (LE_EINVAL for NULL c, cap < 0 or out NULL with cap > 0).  The
  * environment variables LE_TUNE_ADV, LE_TUNE_MU, LE_TUNE_COL_CH,
- * LE_TUNE_COL_FLOW and LE_TUNE_ROW, when set, fix the corresponding variant
- * at creation.
+ * LE_TUNE_COL_FLOW, LE_TUNE_ROW and LE_TUNE_ROW_FWD, when set, fix the
+ * corresponding variant at creation (LE_TUNE_LOG=1 prints every candidate's
+ * time to stderr).
  */
-enum { LE_TUNING_FIELDS = 9 };
+enum { LE_TUNING_FIELDS = 10 };
 int le_tuning(le_ctx* c, int32_t* out, int32_t cap);
 
 /*

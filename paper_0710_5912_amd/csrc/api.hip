@@ -129,7 +129,9 @@ struct Class {
   int mu_variant = 0;        // Ops::mu_source
   int col_ch_variant = 0;    // Ops::column, Cahn-Hilliard pass
   int col_flow_variant = 0;  // Ops::column, flow (or Stokes) pass
-  int row_variant = 0;       // Ops::row_r2c / row_c2r (and the strip variants' transforms)
+  int row_variant = 0;       // Ops::row_c2r (inverse row transforms)
+  int row_fwd_variant = 0;   // Ops::row_r2c (forward row transforms, also of the
+                             // two-kernel stencil stages)
   std::vector<int> members;  // run ids
   int first = 0;             // internal index of members[0]
 };
@@ -292,7 +294,7 @@ int solve_psi(Engine* e, const RunHost& r) {
     k.ops.column(COL_POISSON, desc(e, r), 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0,
                  e->stream);
   } else {
-    k.ops.mu_source(desc(e, r), 1, r.p.ny, sa, k.mu_variant, k.row_variant, e->stream);
+    k.ops.mu_source(desc(e, r), 1, r.p.ny, sa, k.mu_variant, k.row_fwd_variant, e->stream);
     k.ops.column(COL_STOKES, desc(e, r), 1, r.p.nx, sa, B_GH, B_GH, B_PS_S, B_PS_S,
                  k.col_flow_variant, e->stream);
   }
@@ -319,7 +321,7 @@ void enqueue_step(Engine* e, const StepArgs* sa, hipEvent_t* ev) {
   mark(1);
   for (const Class& k : e->classes)
     k.ops.advect(e->d_desc + k.first, (int)k.members.size(), k.ny, sa + k.first, k.inertial,
-                 k.adv_variant, k.row_variant, st);
+                 k.adv_variant, k.row_fwd_variant, st);
   mark(2);
   for (const Class& k : e->classes)
     k.ops.column(COL_CH, e->d_desc + k.first, (int)k.members.size(), k.nx, sa + k.first,
@@ -331,7 +333,7 @@ void enqueue_step(Engine* e, const StepArgs* sa, hipEvent_t* ev) {
   mark(4);
   for (const Class& k : e->classes)
     k.ops.mu_source(e->d_desc + k.first, (int)k.members.size(), k.ny, sa + k.first,
-                    k.mu_variant, k.row_variant, st);
+                    k.mu_variant, k.row_fwd_variant, st);
   mark(5);
   for (const Class& k : e->classes) {
     if (k.inertial)
@@ -436,10 +438,10 @@ void enqueue_class_step(const Engine* e, const Class& k, const StepArgs* sa, hip
     k.ops.row_c2r(d, n, k.ny, B_OM_S, B_OM_R, B_PS_S, B_PS_R, 2, k.row_variant, st);
   else
     k.ops.row_c2r(d, n, k.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1, k.row_variant, st);
-  k.ops.advect(d, n, k.ny, a, k.inertial, k.adv_variant, k.row_variant, st);
+  k.ops.advect(d, n, k.ny, a, k.inertial, k.adv_variant, k.row_fwd_variant, st);
   k.ops.column(COL_CH, d, n, k.nx, a, B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant, st);
   k.ops.row_c2r(d, n, k.ny, B_PHIN, B_PHI, B_PHIN, B_PHI, 1, k.row_variant, st);
-  k.ops.mu_source(d, n, k.ny, a, k.mu_variant, k.row_variant, st);
+  k.ops.mu_source(d, n, k.ny, a, k.mu_variant, k.row_fwd_variant, st);
   if (k.inertial)
     k.ops.column(COL_FLOW, d, n, k.nx, a, B_OMH, B_GH, B_OM_S, B_PS_S, k.col_flow_variant, st);
   else
@@ -512,7 +514,8 @@ int reduce_observables(Engine* e, const RunHost& r, bool spectral) {
   int nsblk = 0;
   if (spectral) {
     LE_RC(set_args_one(e, r, e->step));
-    o.row_r2c(desc(e, r), 1, r.p.ny, B_PHI, B_PHIH, e->classes[r.cls].row_variant, e->stream);
+    o.row_r2c(desc(e, r), 1, r.p.ny, B_PHI, B_PHIH, e->classes[r.cls].row_fwd_variant,
+              e->stream);
     o.obs_spectral(desc(e, r), r.p.nx, e->d_args + r.internal, B_PHIH,
                    r.inertial ? B_PS_S : -1, e->d_spart, e->d_bins, e->d_counts, e->stream);
     nsblk = o.obs_blocks(r.p.nx);
@@ -582,11 +585,11 @@ int observables_of(Engine* e, const RunHost& r, le_obs* o, double* Sk, int32_t s
 // tests that exercise every path.
 namespace {
 
-constexpr int kRowCand[] = {0, 1, 2, 3};
+constexpr int kRowCand[] = {0, 1, 2, 3, 4, 5};
 constexpr int kAdvCand[] = {0,  2,  4,  8,  16, 32, kStripFft + 2, kStripFft + 4,
                              kStripFft + 8, kStripFft1 + 2, kStripFft1 + 4, kStripFft1 + 8};
 constexpr int kMuCand[] = {0, 2, 4, 8, 16, 32, kStripFft + 2, kStripFft + 4, kStripFft + 8};
-constexpr int kColCand[] = {0, 1, 2, 3};
+constexpr int kColCand[] = {0, 1, 2, 3, 4};
 
 int env_variant(const char* name) {
   const char* v = std::getenv(name);
@@ -630,6 +633,12 @@ int pick(Engine* e, hipEvent_t a, hipEvent_t b, const int (&cand)[N], const char
   for (size_t i = 1; i < N; ++i)
     if (best[i] < best[w]) w = i;
   *out = cand[w];
+  const char* log = std::getenv("LE_TUNE_LOG");
+  if (log && log[0] == '1') {
+    std::fprintf(stderr, "le tune %s:", env);
+    for (size_t i = 0; i < N; ++i) std::fprintf(stderr, " %d=%.1fus", cand[i], best[i] * 1e3f / 3);
+    std::fprintf(stderr, " -> %d\n", cand[w]);
+  }
   return LE_OK;
 }
 
@@ -651,11 +660,18 @@ int autotune(Engine* e) {
       k.ops.row_c2r(d, n, k.ny, B_PS_S, B_TMP, B_PS_S, B_TMP, 2, v, st);
       k.ops.row_c2r(d, n, k.ny, B_PHIN, B_TMP, B_PHIN, B_TMP, 1, v, st);
     });
+    // forward row transforms: timed as the two-kernel advection stage runs
+    // them, three real scratch fields into three spectral ones (a working set
+    // beyond the last-level cache on large grids, as in a step)
+    rc = rc ? rc : pick(e, a, b, kRowCand, "LE_TUNE_ROW_FWD", &k.row_fwd_variant, [&](int v) {
+      const int bins[3] = {B_TMP, B_R1, B_R2}, bouts[3] = {B_PHIH, B_FH, B_PHIN};
+      k.ops.row_r2c_n(d, n, k.ny, bins, bouts, 3, v, st);
+    });
     rc = rc ? rc : pick(e, a, b, kAdvCand, "LE_TUNE_ADV", &k.adv_variant, [&](int v) {
-      k.ops.advect(d, n, k.ny, sa, k.inertial, v, k.row_variant, st);
+      k.ops.advect(d, n, k.ny, sa, k.inertial, v, k.row_fwd_variant, st);
     });
     rc = rc ? rc : pick(e, a, b, kMuCand, "LE_TUNE_MU", &k.mu_variant, [&](int v) {
-      k.ops.mu_source(d, n, k.ny, sa, v, k.row_variant, st);
+      k.ops.mu_source(d, n, k.ny, sa, v, k.row_fwd_variant, st);
     });
     rc = rc ? rc : pick(e, a, b, kColCand, "LE_TUNE_COL_CH", &k.col_ch_variant, [&](int v) {
       k.ops.column(COL_CH, d, n, k.nx, sa, B_PHIH, B_FH, B_PHIN, B_PHIN, v, st);
@@ -719,7 +735,7 @@ int create_engine(int32_t n, const le_params* ps, const double* const* phi0s,
     r.inertial = p.rho > 0.0;
     r.tsize = p.precision == LE_FP64 ? sizeof(double) : sizeof(float);
     r.n_real = (size_t)p.nx * p.ny;
-    r.n_spec = (size_t)p.ny * (p.nx / 2 + 1);
+    r.n_spec = spec_elems(p.nx, p.ny);   // tiled, with the pad column
     r.wraps = wrap_count(r.p, 0);
     int cls = -1;
     for (size_t k = 0; k < e->classes.size(); ++k) {
@@ -768,7 +784,7 @@ int create_engine(int32_t n, const le_params* ps, const double* const* phi0s,
     const size_t rb = r.n_real * r.tsize, sb = r.n_spec * 2 * r.tsize;
     max_real = std::max(max_real, r.n_real);
     const int specs[] = {B_PS_S, B_PHIH, B_FH, B_GH, B_PHIN};
-    const int reals[] = {B_PHI, B_OM_R, B_PS_R, B_TMP};
+    const int reals[] = {B_PHI, B_OM_R, B_PS_R, B_TMP, B_R1, B_R2};
     for (int b : specs) rc = rc ? rc : alloc(&r.buf[b], sb);
     for (int b : reals) rc = rc ? rc : alloc(&r.buf[b], rb);
     if (r.inertial) {
@@ -832,7 +848,7 @@ int create_engine(int32_t n, const le_params* ps, const double* const* phi0s,
       }
       if (!rc)
         e->classes[r.cls].ops.row_r2c(desc(e, r), 1, r.p.ny, B_OM_R, B_OM_S,
-                                      e->classes[r.cls].row_variant, e->stream);
+                                      e->classes[r.cls].row_fwd_variant, e->stream);
     }
     if (!rc) rc = solve_psi(e, r);
   }
@@ -1001,7 +1017,7 @@ int corrected_steps(Engine* e, int64_t ncoarse) {
         if (rc) return (int)LE_EDEVICE;
         const CorrArgs ca{net_z_out(e->net), net_partials(e->net), net_tiles(e->net),
                           e->net->scales[2], e->net->scales[3]};
-        o.row_r2c_corr(d, r.p.ny, ca, e->classes[r.cls].row_variant, e->stream);
+        o.row_r2c_corr(d, r.p.ny, ca, e->classes[r.cls].row_fwd_variant, e->stream);
         o.column(COL_POISSON, d, 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0, e->stream);
         return (int)LE_OK;
       });
@@ -1253,11 +1269,11 @@ int le_set_state(le_ctx* c, const double* phi, const double* omega, const double
   LE_RC(upload_real(c, r, phi, B_PHI));
   if (r.inertial) {
     LE_RC(upload_real(c, r, omega, B_OM_R));
-    o.row_r2c(desc(c, r), 1, r.p.ny, B_OM_R, B_OM_S, c->classes[r.cls].row_variant,
+    o.row_r2c(desc(c, r), 1, r.p.ny, B_OM_R, B_OM_S, c->classes[r.cls].row_fwd_variant,
               c->stream);
   }
   LE_RC(upload_real(c, r, psi, B_PS_R));
-  o.row_r2c(desc(c, r), 1, r.p.ny, B_PS_R, B_PS_S, c->classes[r.cls].row_variant,
+  o.row_r2c(desc(c, r), 1, r.p.ny, B_PS_R, B_PS_S, c->classes[r.cls].row_fwd_variant,
             c->stream);
   LE_TRY(hipGetLastError());
   LE_TRY(hipStreamSynchronize(c->stream));
@@ -1290,7 +1306,7 @@ int time_stage_of(Engine* e, int32_t stage, int32_t reps, double* ms_per_launch)
             k.ops.row_c2r(d, n, k.ny, B_PS_S, B_TMP, B_PS_S, B_TMP, 1, k.row_variant, st);
           break;
         case 1:
-          k.ops.advect(d, n, k.ny, sa, k.inertial, k.adv_variant, k.row_variant, st);
+          k.ops.advect(d, n, k.ny, sa, k.inertial, k.adv_variant, k.row_fwd_variant, st);
           break;
         case 2:
           k.ops.column(COL_CH, d, n, k.nx, sa, B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant,
@@ -1300,7 +1316,7 @@ int time_stage_of(Engine* e, int32_t stage, int32_t reps, double* ms_per_launch)
           k.ops.row_c2r(d, n, k.ny, B_PHIN, B_TMP, B_PHIN, B_TMP, 1, k.row_variant, st);
           break;
         case 4:
-          k.ops.mu_source(d, n, k.ny, sa, k.mu_variant, k.row_variant, st);
+          k.ops.mu_source(d, n, k.ny, sa, k.mu_variant, k.row_fwd_variant, st);
           break;
         default:  // outputs into the spectral scratch, the state untouched
           if (k.inertial)
@@ -1339,7 +1355,8 @@ int tuning_of(le_ctx* c, int32_t* out, int32_t cap) {
   for (const Class& k : c->classes) {
     const int32_t rec[LE_TUNING_FIELDS] = {k.nx, k.ny, k.prec, k.inertial ? 1 : 0,
                                            k.adv_variant, k.mu_variant, k.col_ch_variant,
-                                           k.col_flow_variant, k.row_variant};
+                                           k.col_flow_variant, k.row_variant,
+                                           k.row_fwd_variant};
     for (int i = 0; i < LE_TUNING_FIELDS && w < cap; ++i) out[w++] = rec[i];
   }
   return (int)c->classes.size();
@@ -1484,7 +1501,7 @@ int le_set_fields(le_ctx* c, const double* phi, const double* omega, int64_t ste
     } else {
       LE_TRY(hipMemsetAsync(r.buf[B_OM_R], 0, r.n_real * r.tsize, c->stream));
     }
-    o.row_r2c(desc(c, r), 1, r.p.ny, B_OM_R, B_OM_S, c->classes[r.cls].row_variant,
+    o.row_r2c(desc(c, r), 1, r.p.ny, B_OM_R, B_OM_S, c->classes[r.cls].row_fwd_variant,
               c->stream);
   }
   LE_RC(solve_psi(c, r));

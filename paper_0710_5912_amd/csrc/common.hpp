@@ -34,9 +34,28 @@ enum Buf {
   B_OMH,
   B_GH,
   B_PHIN,
-  B_TMP,      // real scratch (remap, downloads)
+  B_TMP,      // real scratch (remap, downloads, stencil outputs)
+  B_R1,       // real scratch (stencil outputs of the two-kernel stage forms)
+  B_R2,
   NBUF
 };
+
+// Row spectra (modes m = 0 .. nx/2 of every row) are stored column-tiled:
+// tiles of kTW adjacent modes, each tile holding its ny rows one after the
+// other, so element (row j, mode m) sits at
+//   ((m / kTW) * ny + j) * kTW + m % kTW.
+// A column pass then reads and writes each tile as one contiguous run, and a
+// row pass writes kTW adjacent modes of a row per tile.  The last tile is
+// padded (nx/2 + 1 is odd); the pad column is never read as data.
+constexpr int kTW = 2;
+__host__ __device__ constexpr int spec_tiles(int nx) { return (nx / 2 + 1 + kTW - 1) / kTW; }
+// Complex elements of one row-spectrum buffer.
+__host__ __device__ constexpr size_t spec_elems(int nx, int ny) {
+  return (size_t)spec_tiles(nx) * (size_t)ny * kTW;
+}
+__host__ __device__ __forceinline__ size_t spec_index(int ny, int j, int m) {
+  return ((size_t)(m / kTW) * (size_t)ny + (size_t)j) * kTW + (size_t)(m % kTW);
+}
 
 // Descriptor of one run, read by the kernels (blockIdx.z picks the run).
 struct Run {

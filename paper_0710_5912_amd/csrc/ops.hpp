@@ -29,6 +29,9 @@ struct Ops {
   // row transforms; variant (a tuning choice): 0 = 8 values per thread, 1 = 4
   void (*row_r2c)(const Run* runs, int nruns, int ny, int bin, int bout, int variant,
                   hipStream_t st);
+  // njobs (<= 3) forward row transforms in one launch: real bins[k] -> spectra bouts[k]
+  void (*row_r2c_n)(const Run* runs, int nruns, int ny, const int* bins, const int* bouts,
+                    int njobs, int variant, hipStream_t st);
   // one run: the corrected step's update of phi and omega from the network
   // output and the forward row transform of omega (B_OM_R -> B_OM_S)
   void (*row_r2c_corr)(const Run* runs, int ny, const CorrArgs& ca, int variant, hipStream_t st);

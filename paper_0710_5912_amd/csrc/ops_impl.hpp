@@ -11,7 +11,9 @@ namespace le {
 // Row transform shapes (variant, a tuning choice): 0 = 8 values per thread,
 // 1 = 4 (twice the threads per row: shorter chains for latency-bound grids),
 // 2 and 3 = the same with a quarter of the rows per block (more blocks for
-// small grids).
+// small grids), 4 and 5 = 8 values per thread, at least four or two rows
+// per block, the spectra staged through LDS and stored (loaded) tile by
+// tile.
 template <typename T, int L>
 struct RowLaunch {
   using C = RowCfg<L>;
@@ -34,12 +36,35 @@ struct RowLaunch {
                        runs, bin0, bout0, bin1, bout1);
   }
   static constexpr int E4 = L >= 16 ? 4 : row_elems(L);
+  // the LDS-staged shapes: 8 values per thread, at least RB0 rows per block
+  template <int RB0>
+  static void r2c_t(const Run* runs, int nruns, int ny, const R2cJobs& jobs, int njobs,
+                    hipStream_t st) {
+    constexpr int E = row_elems(L);
+    using CE = RowT<L, E, RB0>;
+    static_assert(CE::OK, "staged row shape does not fit");
+    hipLaunchKernelGGL((k_row_r2c_t<T, L, E, RB0>),
+                       dim3((ny + CE::RB - 1) / CE::RB, njobs, nruns), dim3(CE::THREADS), 0, st,
+                       runs, jobs);
+  }
+  template <int RB0>
+  static void c2r_t(const Run* runs, int nruns, int ny, int bin0, int bout0, int bin1,
+                    int bout1, int nfields, hipStream_t st) {
+    constexpr int E = row_elems(L);
+    using CE = RowT<L, E, RB0>;
+    static_assert(CE::OK, "staged row shape does not fit");
+    hipLaunchKernelGGL((k_row_c2r_t<T, L, E, RB0>),
+                       dim3((ny + CE::RB - 1) / CE::RB, nfields, nruns), dim3(CE::THREADS), 0,
+                       st, runs, bin0, bout0, bin1, bout1);
+  }
   static void r2c_jobs(const Run* runs, int nruns, int ny, const R2cJobs& jobs, int njobs,
                        int variant, hipStream_t st) {
     switch (variant) {
       case 1: r2c_shape<E4, 1>(runs, nruns, ny, jobs, njobs, st); break;
       case 2: r2c_shape<row_elems(L), 4>(runs, nruns, ny, jobs, njobs, st); break;
       case 3: r2c_shape<E4, 4>(runs, nruns, ny, jobs, njobs, st); break;
+      case 4: r2c_t<4>(runs, nruns, ny, jobs, njobs, st); break;
+      case 5: r2c_t<2>(runs, nruns, ny, jobs, njobs, st); break;
       default: r2c_shape<row_elems(L), 1>(runs, nruns, ny, jobs, njobs, st); break;
     }
   }
@@ -47,6 +72,12 @@ struct RowLaunch {
                   hipStream_t st) {
     R2cJobs jobs{{{bin, bout, 2 * L}, {}, {}}};
     r2c_jobs(runs, nruns, ny, jobs, 1, variant, st);
+  }
+  static void r2c_n(const Run* runs, int nruns, int ny, const int* bins, const int* bouts,
+                    int njobs, int variant, hipStream_t st) {
+    R2cJobs jobs{};
+    for (int k = 0; k < njobs && k < 3; ++k) jobs.j[k] = {bins[k], bouts[k], 2 * L};
+    r2c_jobs(runs, nruns, ny, jobs, njobs < 3 ? njobs : 3, variant, st);
   }
   template <int E, int GD>
   static void r2c_corr_shape(const Run* runs, int ny, const CorrArgs& ca, hipStream_t st) {
@@ -70,6 +101,8 @@ struct RowLaunch {
         c2r_shape<row_elems(L), 4>(runs, nruns, ny, bin0, bout0, bin1, bout1, nfields, st);
         break;
       case 3: c2r_shape<E4, 4>(runs, nruns, ny, bin0, bout0, bin1, bout1, nfields, st); break;
+      case 4: c2r_t<4>(runs, nruns, ny, bin0, bout0, bin1, bout1, nfields, st); break;
+      case 5: c2r_t<2>(runs, nruns, ny, bin0, bout0, bin1, bout1, nfields, st); break;
       default:
         c2r_shape<row_elems(L), 1>(runs, nruns, ny, bin0, bout0, bin1, bout1, nfields, st);
         break;
@@ -132,7 +165,7 @@ struct RowLaunch {
     else
       hipLaunchKernelGGL((k_adv_strip<T, NX, false>), gs, dim3(TPB), 0, st, runs, sa, variant,
                          inertial ? 1 : 0);
-    R2cJobs jobs{{{B_PHIH, B_PHIH, NX + 2}, {B_FH, B_FH, NX + 2}, {B_OMH, B_OMH, NX + 2}}};
+    R2cJobs jobs{{{B_TMP, B_PHIH, NX}, {B_R1, B_FH, NX}, {B_R2, B_OMH, NX}}};
     r2c_jobs(runs, nruns, ny, jobs, inertial ? 3 : 2, row_variant, st);
   }
   // variant 0: mu into the real scratch field, then the source bracket and
@@ -161,7 +194,7 @@ struct RowLaunch {
     }
     const dim3 gs(NX / 2 / TPB, (ny + variant - 1) / variant, nruns);
     hipLaunchKernelGGL((k_mug_strip<T, NX>), gs, dim3(TPB), 0, st, runs, sa, variant);
-    R2cJobs jobs{{{B_GH, B_GH, NX + 2}, {}, {}}};
+    R2cJobs jobs{{{B_TMP, B_GH, NX}, {}, {}}};
     r2c_jobs(runs, nruns, ny, jobs, 1, row_variant, st);
   }
 };
@@ -183,6 +216,7 @@ struct ColLaunch {
       case 1: launch<MODE, 1>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
       case 2: launch<MODE, 2>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
       case 3: launch<MODE, 3>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
+      case 4: launch<MODE, 4>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
       default: launch<MODE, 0>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
     }
   }
@@ -235,6 +269,7 @@ struct Misc {
 template <typename T, int L>
 void set_row(Ops* o) {
   o->row_r2c = &RowLaunch<T, L>::r2c;
+  o->row_r2c_n = &RowLaunch<T, L>::r2c_n;
   o->row_r2c_corr = &RowLaunch<T, L>::r2c_corr;
   o->row_c2r = &RowLaunch<T, L>::c2r;
   o->advect = &RowLaunch<T, L>::advect;

@@ -1,10 +1,13 @@
 // stages.hpp -- the stage kernels of the split step (Appendix B), templated
 // on the storage type T (float or double) and the transform lengths.
 //
-// Field layouts in HBM (all row-major, x fastest):
-//   real field       T[ny][nx]
-//   row spectrum     c2<T>[ny][nx/2 + 1]: the unnormalised DFT of each real
-//                    row along x, modes m = 0 .. nx/2 (DC and Nyquist real).
+// Field layouts in HBM:
+//   real field       T[ny][nx], x fastest
+//   row spectrum     the unnormalised DFT of each real row along x, modes
+//                    m = 0 .. nx/2 (DC and Nyquist real), column-tiled:
+//                    (row j, mode m) at spec_index(ny, j, m) (common.hpp),
+//                    so that each tile of kTW modes is one contiguous run
+//                    down the column.
 // A 2D transform is a row transform (fused into the row kernels) followed by
 // a column transform over each of the nx/2+1 columns (fused into the column
 // kernels, which also apply the per-mode update and the inverse column
@@ -50,26 +53,24 @@ struct RowCfg {
   static constexpr int THREADS = G * P;
 };
 
-// Column kernel shapes, VAR (a tuning choice, 0 .. 3): 8 values per thread
-// and CW0 = 256/P columns per block (VAR 0), twice the columns per block
-// where threads <= 1024 and LDS <= 160 KB allow (VAR 1), a quarter (VAR 2:
-// more, smaller blocks for grids whose column pass has few blocks), and
-// other values per thread (VAR 3): 16 in FP32 (fewer LDS passes), 4 in FP64
-// (where 16 would not fit the registers).
+// Column kernel shapes, VAR (a tuning choice, 0 .. 4): E values per thread
+// (8, or 16 for VAR 3 and 4: two register passes fewer LDS exchanges) and
+// CW adjacent columns per block: CW0 = 256/P (VAR 0, 3), twice that (VAR 1,
+// 4) where threads <= 1024 and LDS <= 160 KB allow, or a quarter (VAR 2:
+// more, smaller blocks for grids whose column pass has few blocks).
 template <typename T, int L, int VAR>
 struct ColCfg {
-  static constexpr bool F32 = sizeof(T) == 4;
-  static constexpr bool ALT_E = L >= 16 && VAR == 3;
-  static constexpr int E = !ALT_E ? col_elems(L) : (F32 ? 16 : 4);
+  static constexpr int E = (VAR >= 3 && L >= 16) ? 16 : col_elems(L);
   static constexpr int P = L / E;
   static constexpr int CW0 = clampi(256 / P, 1, 64);
-  static constexpr int CWD = VAR == 1 ? 2 * CW0 : (VAR == 2 ? (CW0 / 4 > 1 ? CW0 / 4 : 1) : CW0);
+  static constexpr int CWD = (VAR == 1 || VAR == 4) ? 2 * CW0
+                             : (VAR == 2 ? (CW0 / 4 > 1 ? CW0 / 4 : 1) : CW0);
   static constexpr bool FITS =
       CWD <= 64 && CWD * P <= 1024 && (long)CWD * L * (long)sizeof(c2<T>) <= 160L * 1024;
   static constexpr int CW = FITS ? CWD : CW0;
   static constexpr int THREADS = CW * P;
 };
-constexpr int kColVariants = 4;
+constexpr int kColVariants = 5;
 
 // Observables' column kernel (its LDS also holds the shell partials).
 template <int L>
@@ -110,29 +111,34 @@ __device__ __forceinline__ gp<T> bufp(const Run& R, int b) {
 
 // ---------------------------------------------------------------- helpers
 
+// Row j of a (column-tiled) row spectrum X with ny rows: the packed half
+// spectrum of row_r2c (v[q] = X[m], m = t + q P, with (X[0], X[L]) at m = 0)
+// stored as modes 0 .. L.
 template <typename T, int L, int E>
-__device__ __forceinline__ void store_row_spec(gp<c2<T>> __restrict__ X, const c2<T>* v, int t) {
+__device__ __forceinline__ void store_row_spec(gp<c2<T>> __restrict__ X, int ny, int j,
+                                               const c2<T>* v, int t) {
   constexpr int P = L / E;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int m = t + q * P;
     if (m == 0) {
-      stg<T>(X, {v[q].x, T(0)});
-      stg<T>(X + L, {v[q].y, T(0)});
+      stg<T>(X + spec_index(ny, j, 0), {v[q].x, T(0)});
+      stg<T>(X + spec_index(ny, j, L), {v[q].y, T(0)});
     } else {
-      stg<T>(X + m, v[q]);
+      stg<T>(X + spec_index(ny, j, m), v[q]);
     }
   }
 }
 
 template <typename T, int L, int E>
-__device__ __forceinline__ void load_row_spec(gp<const c2<T>> __restrict__ X, c2<T>* v, int t) {
+__device__ __forceinline__ void load_row_spec(gp<const c2<T>> __restrict__ X, int ny, int j,
+                                              c2<T>* v, int t) {
   constexpr int P = L / E;
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int m = t + q * P;
-    const c2<T> xm = ldg<T>(X + m);
-    v[q] = (m == 0) ? c2<T>{xm.x, X[L].x} : xm;
+    const c2<T> xm = ldg<T>(X + spec_index(ny, j, m));
+    v[q] = (m == 0) ? c2<T>{xm.x, X[spec_index(ny, j, L)].x} : xm;
   }
 }
 
@@ -216,7 +222,7 @@ __global__ __launch_bounds__((RowCfg<L, E, GDIV>::THREADS)) LE_OCCUPANCY void k_
 #pragma unroll
   for (int q = 0; q < C::E; ++q) v[q] = ldg<T>(xr + t + q * C::P);
   row_r2c<T, L, C::E>(v, lds + g * L, tw, t);
-  if (ok) store_row_spec<T, L, C::E>(X + (size_t)j * (L + 1), v, t);
+  if (ok) store_row_spec<T, L, C::E>(X, ny, j, v, t);
 }
 
 // The corrected step's update and the vorticity's forward row transform in
@@ -282,7 +288,7 @@ __global__ __launch_bounds__((RowCfg<L, E, GDIV>::THREADS)) LE_OCCUPANCY void k_
     }
   }
   row_r2c<T, L, C::E>(v, lds + g * L, tw, t);
-  if (ok) store_row_spec<T, L, C::E>(X + (size_t)j * (L + 1), v, t);
+  if (ok) store_row_spec<T, L, C::E>(X, ny, j, v, t);
 }
 
 // Inverse row transform; the block's y picks the field (bin0 -> bout0, or
@@ -303,12 +309,115 @@ __global__ __launch_bounds__((RowCfg<L, E, GDIV>::THREADS)) LE_OCCUPANCY void k_
   const bool ok = j < ny;
   const int jj = ok ? j : 0;
   c2<T> v[C::E];
-  load_row_spec<T, L, C::E>(X + (size_t)jj * (L + 1), v, t);
+  load_row_spec<T, L, C::E>(X, ny, jj, v, t);
   row_c2r<T, L, C::E>(v, lds + g * L, tw, t);
   if (ok) {
     auto xr = reinterpret_cast<gp<c2<T>>>(x + (size_t)j * 2 * L);
 #pragma unroll
     for (int q = 0; q < C::E; ++q) stg<T>(xr + t + q * C::P, v[q]);
+  }
+}
+
+// Row transforms with the row spectra staged through LDS.  A block owns RB
+// consecutive rows (RB >= RB0, a power of two): after the row transforms the
+// RB spectra go to LDS and the block stores them tile by tile, consecutive
+// threads writing consecutive elements of a tile (the RB rows' kTW modes),
+// so every store instruction writes whole runs of RB kTW values instead of
+// one row's kTW values per tile; the inverse loads the same runs into LDS
+// and hands each row to its transform group.  Rows in LDS have stride L + 1
+// (the packed DC/Nyquist slot plus the Nyquist mode).
+template <int L, int E, int RB0>
+struct RowT {
+  static constexpr int P = L / E;
+  static constexpr int G0 = clampi(128 / P, 1, 16);
+  static constexpr int RB = G0 > RB0 ? G0 : RB0;  // rows per block
+  static constexpr int THREADS = RB * P;
+  static constexpr bool OK = THREADS <= 1024 && (long)RB * (L + 1) * 16 <= 160L * 1024;
+};
+// Blocks of the staged row kernels are taken in launch order (consecutive
+// blocks go to different XCDs and run at the same time), so the blocks in
+// flight cover consecutive rows: their tile runs lie next to each other.
+__device__ __forceinline__ BPos block_pos_linear() {
+  return {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z};
+}
+
+template <typename T, int L, int E, int RB0>
+__global__ __launch_bounds__((RowT<L, E, RB0>::THREADS)) LE_OCCUPANCY void k_row_r2c_t(
+    const Run* __restrict__ runs, R2cJobs jobs) {
+  using C = RowT<L, E, RB0>;
+  constexpr int LS = L + 1;
+  __shared__ c2<T> lds[C::RB * LS];
+  const BPos bp = block_pos_linear();
+  const Run& R = runs[bp.z];
+  const R2cJob job = jobs.j[bp.y];
+  const int ny = R.g.ny;
+  auto x = bufp<T>(R, job.bin);
+  auto X = bufp<c2<T>>(R, job.bout);
+  auto tw = to_global<const c2<double>>(R.twx);
+  const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
+  const int j0 = bp.x * C::RB;  // ny is a power of two >= 8: whole blocks when RB <= ny
+  const int rows = C::RB < ny ? C::RB : ny;
+  const bool ok = g < rows;
+  auto xr = reinterpret_cast<gp<const c2<T>>>(x + (size_t)(j0 + (ok ? g : 0)) * job.rs);
+  c2<T> v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) v[q] = ldg<T>(xr + t + q * C::P);
+  row_r2c<T, L, E>(v, lds + g * L, tw, t);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < E; ++q) lds[g * LS + t + q * C::P] = v[q];
+  __syncthreads();
+  // tile k holds modes 2k, 2k + 1 (k = L/2: the Nyquist mode and the pad)
+  const int run = kTW * rows;
+  const int total = (L / kTW + 1) * run;
+  for (int e = threadIdx.x; e < total; e += C::THREADS) {
+    const int k = e / run, w = e % run;
+    const int r = w / kTW, m = k * kTW + w % kTW;
+    if (m > L) continue;
+    const c2<T> a = lds[r * LS + (m == L ? 0 : m)];
+    const c2<T> val = m == 0 ? c2<T>{a.x, T(0)} : (m == L ? c2<T>{a.y, T(0)} : a);
+    stg<T>(X + spec_index(ny, j0 + r, m), val);
+  }
+}
+
+template <typename T, int L, int E, int RB0>
+__global__ __launch_bounds__((RowT<L, E, RB0>::THREADS)) LE_OCCUPANCY void k_row_c2r_t(
+    const Run* __restrict__ runs, int bin0, int bout0, int bin1, int bout1) {
+  using C = RowT<L, E, RB0>;
+  constexpr int LS = L + 1;
+  __shared__ c2<T> lds[C::RB * LS];
+  const BPos bp = block_pos_linear();
+  const Run& R = runs[bp.z];
+  const int ny = R.g.ny;
+  auto X = bufp<const c2<T>>(R, bp.y == 0 ? bin0 : bin1);
+  auto x = bufp<T>(R, bp.y == 0 ? bout0 : bout1);
+  auto tw = to_global<const c2<double>>(R.twx);
+  const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
+  const int j0 = bp.x * C::RB;
+  const int rows = C::RB < ny ? C::RB : ny;
+  const int run = kTW * rows;
+  const int total = (L / kTW + 1) * run;
+  for (int e = threadIdx.x; e < total; e += C::THREADS) {
+    const int k = e / run, w = e % run;
+    const int r = w / kTW, m = k * kTW + w % kTW;
+    if (m <= L) lds[r * LS + m] = ldg<T>(X + spec_index(ny, j0 + r, m));
+  }
+  __syncthreads();
+  const bool ok = g < rows;
+  const int gr = ok ? g : 0;
+  c2<T> v[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int m = t + q * C::P;
+    v[q] = lds[gr * LS + m];
+    if (m == 0) v[q].y = lds[gr * LS + L].x;
+  }
+  __syncthreads();
+  row_c2r<T, L, E>(v, lds + g * L, tw, t);
+  if (ok) {
+    auto xr = reinterpret_cast<gp<c2<T>>>(x + (size_t)(j0 + g) * 2 * L);
+#pragma unroll
+    for (int q = 0; q < E; ++q) stg<T>(xr + t + q * C::P, v[q]);
   }
 }
 
@@ -515,14 +624,14 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_bracket(
   }
   row_r2c<T, L, C::E>(v, lds + g * L, tw, t);
   auto out = bufp<c2<T>>(R, job.out);
-  if (ok) store_row_spec<T, L, C::E>(out + (size_t)j * (L + 1), v, t);
+  if (ok) store_row_spec<T, L, C::E>(out, geo.ny, j, v, t);
 }
 
 // Stage 1a (Eq. advective) as a stencil over row strips, no transform:
 //   phi_h = phi - dt [Dx phi Dys psi - Dys phi Dx psi],  f = phi^3,
 //   omega_h = omega - dt [Dx omega Dys psi - Dys omega Dx psi]  (inertial)
-// into B_PHIH, B_FH, B_OMH as real rows at the spectral row offsets (row
-// stride nx + 2), for the in-place forward row transforms that follow.
+// into the real scratch fields B_TMP, B_R1, B_R2, for the forward row
+// transforms that follow.
 // Thread: one x pair of a row, walking `rows` consecutive rows; it keeps the
 // quads of rows j-1, j, j+1 in registers and reads one new row per field and
 // step (row j+2, requested a step ahead).
@@ -581,9 +690,9 @@ __global__ __launch_bounds__(strip_threads(NX)) void k_adv_strip(
   auto phi = bufp<const T>(R, B_PHI);
   auto psi = bufp<const T>(R, B_PS_R);
   auto om = bufp<const T>(R, B_OM_R);
-  auto o_phi = bufp<T>(R, B_PHIH);
-  auto o_f = bufp<T>(R, B_FH);
-  auto o_om = bufp<T>(R, B_OMH);
+  auto o_phi = bufp<T>(R, B_TMP);
+  auto o_f = bufp<T>(R, B_R1);
+  auto o_om = bufp<T>(R, B_R2);
   const Stencil<T> st = make_stencil<T>(geo, sa[bp.z].s);
   const T dt = T(geo.dt);
   const bool fh = geo.f_half != 0;
@@ -615,7 +724,7 @@ __global__ __launch_bounds__(strip_threads(NX)) void k_adv_strip(
     quad_dys<T, NX, R1>(Sp, Sm, row(psi, j + 1), row(psi, j - 1), sl.x, st, sy0, sy1);
     quad_dx(Fc, st.inv2dx, ax0, ax1);
     quad_dys<T, NX, R1>(Fp, Fm, row(phi, j + 1), row(phi, j - 1), sl.x, st, ay0, ay1);
-    const size_t o = (size_t)j * (NX + 2) + sl.x;
+    const size_t o = (size_t)j * NX + sl.x;
     const T h0 = Fc.a0 - dt * (ax0 * sy0 - ay0 * sx0), h1 = Fc.a1 - dt * (ax1 * sy1 - ay1 * sx1);
     const T c0 = fh ? h0 : Fc.a0, c1 = fh ? h1 : Fc.a1;
     stg<T>(reinterpret_cast<gp<c2<T>>>(o_phi + o), {h0, h1});
@@ -740,7 +849,7 @@ __global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __res
       row_r2c<T, L, EF>(v, area, tw, tt);
       if (grp < nf) {
         auto out = bufp<c2<T>>(R, grp == 0 ? B_PHIH : (grp == 1 ? B_FH : B_OMH));
-        store_row_spec<T, L, EF>(out + (size_t)j * (L + 1), v, tt);
+        store_row_spec<T, L, EF>(out, ny, j, v, tt);
       }
       __syncthreads();
     } else if (slot == 3 || j + 1 == j1) {  // a batch of up to four rows is complete
@@ -754,7 +863,7 @@ __global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __res
         row_r2c<T, L, EF>(v, area, tw, tt);
         if (grp <= slot) {
           auto out = bufp<c2<T>>(R, f == 0 ? B_PHIH : (f == 1 ? B_FH : B_OMH));
-          store_row_spec<T, L, EF>(out + (size_t)(j - slot + grp) * (L + 1), v, tt);
+          store_row_spec<T, L, EF>(out, ny, j - slot + grp, v, tt);
         }
       }
       __syncthreads();
@@ -765,7 +874,7 @@ __global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __res
 // Stage 2a as a stencil over row strips (square cells, r = 1), no transform:
 //   mu = B phi^3 - A phi - kappa [(1+s^2) Dxx + Dyy - 2 s Dxy] phi,
 //   g = -[Dx phi Dys mu - Dys phi Dx mu] / c   (c = rho, or eta for Stokes)
-// into B_GH as real rows at the spectral row offsets (row stride nx + 2).
+// into the real scratch field B_TMP.
 // mu never leaves the registers: a thread walks its strip keeping the phi
 // quads of rows j-1 .. j+2 and the mu quads of rows j-1 .. j+1; mu at x-1 /
 // x+2 for the first / last lane of a run is computed by that lane from one
@@ -836,7 +945,7 @@ __global__ __launch_bounds__(strip_threads(NX)) void k_mug_strip(
   const int j0 = bp.y * rows;
   const int j1 = min(j0 + rows, ny);
   auto phi = bufp<const T>(R, B_PHI);
-  auto o_g = bufp<T>(R, B_GH);
+  auto o_g = bufp<T>(R, B_TMP);
   const double s = sa[bp.z].s;
   const MuCoef<T> k = {T((1.0 + s * s) / (geo.dx * geo.dx)), T(1.0 / (geo.dy * geo.dy)),
                        T(-2.0 * s / (4.0 * geo.dx * geo.dy)), T(geo.A), T(geo.B), T(geo.kappa)};
@@ -863,7 +972,7 @@ __global__ __launch_bounds__(strip_threads(NX)) void k_mug_strip(
     quad_dys<T, NX, true>(F3.q, F1.q, row(j + 1), row(j - 1), sl.x, st, py0, py1);
     quad_dx(Mc, st.inv2dx, mx0, mx1);
     quad_dys<T, NX, true>(Mp, Mm, row(j + 1), row(j - 1), sl.x, st, my0, my1);
-    const size_t o = (size_t)j * (NX + 2) + sl.x;
+    const size_t o = (size_t)j * NX + sl.x;
     stg<T>(reinterpret_cast<gp<c2<T>>>(o_g + o),
            {neg_inv * (px0 * my0 - py0 * mx0), neg_inv * (px1 * my1 - py1 * mx1)});
     F1 = F2; F2 = F3; F3 = F4;
@@ -932,7 +1041,7 @@ __global__ __launch_bounds__(NX / 2) void k_mug_strip_fft(const Run* __restrict_
       for (int q = 0; q < EF; ++q) v[q] = buf[grp * L + tt + q * PF];
       __syncthreads();
       row_r2c<T, L, EF>(v, buf + grp * L, tw, tt);
-      if (grp <= slot) store_row_spec<T, L, EF>(out + (size_t)(j - slot + grp) * (L + 1), v, tt);
+      if (grp <= slot) store_row_spec<T, L, EF>(out, ny, j - slot + grp, v, tt);
       __syncthreads();
     }
   }
@@ -982,17 +1091,19 @@ __global__ __launch_bounds__(RowCfg<L>::THREADS) LE_OCCUPANCY void k_mu(
 }
 
 // Strain-wrap remap of a row spectrum: row j shifted by sh_j = (dkr * j) mod nx,
-// X[j][m] *= exp(-2 pi i m sh_j / nx).
+// X[j][m] *= exp(-2 pi i m sh_j / nx).  e runs over the tiled storage.
 template <typename T>
 __global__ void k_remap_spec(const Run* __restrict__ run, int b, int dkr) {
   const int nx = run->g.nx, ny = run->g.ny;
   auto X = bufp<c2<T>>(*run, b);
   auto twx = to_global<const c2<double>>(run->twx);
   const int S = nx / 2 + 1;
-  const size_t total = (size_t)ny * S;
+  const size_t total = spec_elems(nx, ny);
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
        e += (size_t)gridDim.x * blockDim.x) {
-    const int j = (int)(e / S), m = (int)(e % S);
+    const size_t tile = e / ((size_t)ny * kTW), rem = e % ((size_t)ny * kTW);
+    const int j = (int)(rem / kTW), m = (int)(tile * kTW + rem % kTW);
+    if (m >= S) continue;  // pad column
     const long long sh = (((long long)dkr * j) % nx + nx) % nx;
     const int idx = (int)(((long long)m * sh) % nx);
     const c2<double> w = ldg<double>(twx + idx);
@@ -1076,19 +1187,21 @@ __global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void
   const int m0 = bp.x * C::CW + c;
   const bool ok = m0 < S;
   const int m = ok ? m0 : 0;
+  // column m of the tiled spectra: element n at col + n kTW
+  const size_t col = spec_index(L, 0, m);
   c2<T> v0[C::E], v1[C::E];
 #pragma unroll
-  for (int q = 0; q < C::E; ++q) v0[q] = ldg<T>(in0 + (size_t)(t + q * C::P) * S + m);
+  for (int q = 0; q < C::E; ++q) v0[q] = ldg<T>(in0 + col + (size_t)(t + q * C::P) * kTW);
   if constexpr (DUAL) {
 #pragma unroll
-    for (int q = 0; q < C::E; ++q) v1[q] = ldg<T>(in1 + (size_t)(t + q * C::P) * S + m);
+    for (int q = 0; q < C::E; ++q) v1[q] = ldg<T>(in1 + col + (size_t)(t + q * C::P) * kTW);
     fft_group2<T, L, C::E, -1>(v0, v1, lds + c, lds1 + c, C::CW, tw, t);
   } else {
     fft_group<T, L, C::E, -1>(v0, lds + c, C::CW, tw, t);
   }
   if constexpr (NIN == 2 && !DUAL) {
 #pragma unroll
-    for (int q = 0; q < C::E; ++q) v1[q] = ldg<T>(in1 + (size_t)(t + q * C::P) * S + m);
+    for (int q = 0; q < C::E; ++q) v1[q] = ldg<T>(in1 + col + (size_t)(t + q * C::P) * kTW);
     __syncthreads();
     fft_group<T, L, C::E, -1>(v1, lds + c, C::CW, tw, t);
   }
@@ -1141,8 +1254,8 @@ __global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void
     if (ok) {
 #pragma unroll
       for (int q = 0; q < C::E; ++q) {
-        stg<T>(out0 + (size_t)(t + q * C::P) * S + m, v0[q]);
-        stg<T>(out1 + (size_t)(t + q * C::P) * S + m, v1[q]);
+        stg<T>(out0 + col + (size_t)(t + q * C::P) * kTW, v0[q]);
+        stg<T>(out1 + col + (size_t)(t + q * C::P) * kTW, v1[q]);
       }
     }
     return;
@@ -1150,14 +1263,14 @@ __global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void
   fft_group<T, L, C::E, +1>(v0, lds + c, C::CW, tw, t);
   if (ok) {
 #pragma unroll
-    for (int q = 0; q < C::E; ++q) stg<T>(out0 + (size_t)(t + q * C::P) * S + m, v0[q]);
+    for (int q = 0; q < C::E; ++q) stg<T>(out0 + col + (size_t)(t + q * C::P) * kTW, v0[q]);
   }
   if constexpr (NOUT == 2) {
     __syncthreads();
     fft_group<T, L, C::E, +1>(v1, lds + c, C::CW, tw, t);
     if (ok) {
 #pragma unroll
-      for (int q = 0; q < C::E; ++q) stg<T>(out1 + (size_t)(t + q * C::P) * S + m, v1[q]);
+      for (int q = 0; q < C::E; ++q) stg<T>(out1 + col + (size_t)(t + q * C::P) * kTW, v1[q]);
     }
   }
 }
@@ -1207,14 +1320,15 @@ __global__ __launch_bounds__(ObsCfg<L>::THREADS) LE_OCCUPANCY void k_obs_spectra
   const int m0 = xcd_block(blockIdx.x, gridDim.x) * C::CW + c;
   const bool ok = m0 < S;
   const int m = ok ? m0 : 0;
+  const size_t col = spec_index(L, 0, m);
   c2<T> v0[C::E], v1[C::E];
 #pragma unroll
-  for (int q = 0; q < C::E; ++q) v0[q] = ldg<T>(phih + (size_t)(t + q * C::P) * S + m);
+  for (int q = 0; q < C::E; ++q) v0[q] = ldg<T>(phih + col + (size_t)(t + q * C::P) * kTW);
   fft_group<T, L, C::E, -1>(v0, lds + c, C::CW, tw, t);
   const bool has_psi = psih != nullptr;
   if (has_psi) {
 #pragma unroll
-    for (int q = 0; q < C::E; ++q) v1[q] = ldg<T>(psih + (size_t)(t + q * C::P) * S + m);
+    for (int q = 0; q < C::E; ++q) v1[q] = ldg<T>(psih + col + (size_t)(t + q * C::P) * kTW);
     __syncthreads();
     fft_group<T, L, C::E, -1>(v1, lds + c, C::CW, tw, t);
   }

@@ -31,9 +31,9 @@ SYMBOLS = ("le_create", "le_step", "le_observables", "le_destroy", "le_get_state
            "le_cnn_layer_fwd", "le_cnn_layer_bwd", "le_cnn_mfma_probe")
 LE_NSTAGES = 6
 STAGES = ("row_inv_flow", "advect", "column_ch", "row_inv_phi", "mu_source", "column_flow")
-LE_TUNING_FIELDS = 9
+LE_TUNING_FIELDS = 10
 TUNING_KEYS = ("nx", "ny", "precision", "inertial", "advect", "mu_source", "column_ch",
-               "column_flow", "row")
+               "column_flow", "row", "row_fwd")
 
 
 class LeParams(C.Structure):

@@ -13,7 +13,8 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: longer CPU test")
 
 
-TUNE_KEYS = ("LE_TUNE_ROW", "LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH", "LE_TUNE_COL_FLOW")
+TUNE_KEYS = ("LE_TUNE_ROW", "LE_TUNE_ROW_FWD", "LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH",
+             "LE_TUNE_COL_FLOW")
 
 
 @pytest.fixture

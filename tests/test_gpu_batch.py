@@ -63,7 +63,8 @@ def test_batch_one_kernel_strips_equal_single_runs(monkeypatch, adv, mu):
     batch of 256^2 and 512^2 runs (two runs per class, inertial and Stokes)
     reproduce each run alone with the same variants bit for bit."""
     for k, v in (("LE_TUNE_ADV", adv), ("LE_TUNE_MU", mu), ("LE_TUNE_COL_CH", 0),
-                 ("LE_TUNE_COL_FLOW", 0), ("LE_TUNE_ROW", 0)):
+                 ("LE_TUNE_COL_FLOW", 0), ("LE_TUNE_ROW", 0),
+                 ("LE_TUNE_ROW_FWD", 0)):
         monkeypatch.setenv(k, str(v))
     runs = []
     for k, (n, rho, gdot) in enumerate([(256, 1.0, 0.3), (256, 1.0, -0.2), (512, 0.0, 0.1),

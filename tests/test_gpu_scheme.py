@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 le = pytest.importorskip("paper_0710_5912_amd.le")
 
-KEYS = ("LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH", "LE_TUNE_COL_FLOW", "LE_TUNE_ROW")
+KEYS = ("LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH", "LE_TUNE_COL_FLOW", "LE_TUNE_ROW",
+        "LE_TUNE_ROW_FWD")
 
 
 def params(nx, ny, **kw):
@@ -31,7 +32,7 @@ def rel(a, b):
 
 def run_both(monkeypatch, p, steps, seed, f_half, midpoint_s, adv=None):
     if adv is not None:
-        for k, v in zip(KEYS, (adv, 0, 0, 0, 0)):
+        for k, v in zip(KEYS, (adv, 0, 0, 0, 0, 0)):
             monkeypatch.setenv(k, str(v))
     phi0 = inputs.noise_phi0(p["ny"], p["nx"], seed, amp=0.5)
     om0 = inputs.noise_omega0(p["ny"], p["nx"], seed) if p["rho"] > 0 else None

@@ -19,12 +19,15 @@ pytestmark = pytest.mark.gpu
 le = pytest.importorskip("paper_0710_5912_amd.le")
 
 KEYS = ("LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH", "LE_TUNE_COL_FLOW", "LE_TUNE_ROW")
+# the row shape of a combination is forced for the forward and the inverse row
+# transforms alike
 # (advect, mu_source, column_ch, column_flow, row)
 # advect 64 + k / 96 + k, mu_source 64 + k: strip stencil and row transforms
 # in one kernel (k-row strips; advect with two / one x pairs per thread)
 COMBOS = [(0, 0, 0, 0, 0), (4, 4, 1, 1, 1), (32, 32, 2, 2, 2), (8, 16, 3, 3, 3),
           (2, 2, 0, 0, 1), (66, 4, 0, 1, 2), (72, 8, 2, 0, 0), (100, 2, 1, 3, 0),
-          (98, 66, 0, 0, 3), (4, 68, 1, 1, 0), (100, 72, 3, 2, 1)]
+          (98, 66, 0, 0, 3), (4, 68, 1, 1, 0), (100, 72, 3, 2, 1), (8, 8, 4, 4, 4),
+          (68, 68, 4, 3, 5), (4, 4, 2, 4, 5)]
 
 
 def params(nx, ny, **kw):
@@ -55,6 +58,7 @@ def oracle(p, steps, seed):
 def run_forced(monkeypatch, p, steps, seed, combo, precision="fp64"):
     for k, v in zip(KEYS, combo):
         monkeypatch.setenv(k, str(v))
+    monkeypatch.setenv("LE_TUNE_ROW_FWD", str(combo[4]))
     phi0, om0, st = oracle(p, steps, seed)
     print(f"case nx={p['nx']} ny={p['ny']} rho={p['rho']} steps={steps} combo={combo} "
           f"{precision}", flush=True)
@@ -63,6 +67,7 @@ def run_forced(monkeypatch, p, steps, seed, combo, precision="fp64"):
         c.step(steps)
         g = c.get_state()
     assert (t["advect"], t["mu_source"], t["column_ch"], t["column_flow"], t["row"]) == combo
+    assert t["row_fwd"] == combo[4]
     return g, st
 
 
@@ -76,7 +81,7 @@ def test_variants_512_fp64(monkeypatch, combo, rho):
 
 
 @pytest.mark.parametrize("combo", [(4, 4, 1, 3, 1), (32, 8, 3, 2, 3), (68, 4, 0, 0, 1),
-                                   (98, 8, 2, 1, 2), (66, 68, 1, 1, 2)])
+                                   (98, 8, 2, 1, 2), (66, 68, 1, 1, 2), (8, 4, 4, 4, 4), (16, 8, 3, 4, 5)])
 def test_variants_512_fp32(monkeypatch, combo):
     """FP32 shapes (16 values per thread in shapes 2 and 3) within the FP32 bound."""
     p = params(512, 512)
@@ -125,7 +130,8 @@ def test_autotuner_reports_valid_choices():
     assert (t["nx"], t["ny"], t["precision"], t["inertial"]) == (256, 256, 0, 1)
     assert t["advect"] in (0, 2, 4, 8, 16, 32, 66, 68, 72, 98, 100, 104)
     assert t["mu_source"] in (0, 2, 4, 8, 16, 32, 66, 68, 72)
-    assert t["column_ch"] in range(4) and t["column_flow"] in range(4) and t["row"] in range(4)
+    assert t["column_ch"] in range(5) and t["column_flow"] in range(5) and t["row"] in range(6)
+    assert t["row_fwd"] in range(6)
 
 
 @pytest.mark.parametrize("rho", [1.0, 0.0])
@@ -135,6 +141,7 @@ def test_stage_timer_leaves_the_state(monkeypatch, rho):
     same variants, fixed here)."""
     for k, v in zip(KEYS, (4, 4, 0, 0, 1)):
         monkeypatch.setenv(k, str(v))
+    monkeypatch.setenv("LE_TUNE_ROW_FWD", "1")
     p = params(128, 128, rho=rho)
     phi0 = inputs.noise_phi0(128, 128, 31, amp=0.5)
     with le.Context(p, phi0) as a, le.Context(p, phi0) as b:
@@ -151,3 +158,24 @@ def test_stage_timer_leaves_the_state(monkeypatch, rho):
         ga, gb = a.get_state(), b.get_state()
         for k in ("phi", "omega", "psi"):
             assert np.array_equal(ga[k], gb[k]), k
+
+
+@pytest.mark.parametrize("col", range(5))
+@pytest.mark.parametrize("rho", [1.0, 0.0])
+def test_column_shapes_at_4096_point_columns(monkeypatch, col, rho):
+    """16 x 4096 (gdot = 0): the column passes transform 4096-point columns,
+    the length of the largest grid, in every block shape."""
+    p = params(16, 4096, gdot=0.0, rho=rho)
+    g, st = run_forced(monkeypatch, p, 3, 27, (0, 0, col, col, 0))
+    for k in ("phi", "psi") + (("omega",) if rho > 0 else ()):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k
+
+
+@pytest.mark.parametrize("row", range(6))
+def test_row_shapes_at_4096_point_rows(monkeypatch, row):
+    """4096 x 16 (gdot = 0.05, r = 256): 4096-point rows in every row shape,
+    with the two-kernel strip stages (real rows through the real scratch)."""
+    p = params(4096, 16, gdot=0.05)
+    g, st = run_forced(monkeypatch, p, 3, 28, (4, 8, 0, 0, row))
+    for k in ("phi", "omega", "psi"):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k
