@@ -115,6 +115,31 @@ int le_create(const le_params* p, const double* phi0, const double* omega0,
 int le_step(le_ctx* c, int64_t nsteps);
 
 /*
+ * le_step without a context, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  phi_dev, omega_dev, psi_dev: the caller's device arrays of
+ * nx*ny doubles, row-major [j][i] (x fastest), the real fields phi, omega,
+ * psi of step step0 >= 0 (the state le_get_state returns; omega_dev is
+ * ignored and may be NULL when rho == 0); on return they hold the state of
+ * step step0 + nsteps, remapped at every strain wrap as le_step does.  Every
+ * other buffer (row spectra, stencil outputs, twiddles, the descriptor, the
+ * strain offsets and the reduction) lives in one static device array of
+ * 8 MiB that the library holds on each device it runs on until the process
+ * ends; the call allocates nothing.  Limits: p->precision == LE_FP64 and a
+ * grid whose buffers fit that array (up to 256 x 256, or equivalently small
+ * non-square grids), else LE_EINVAL (le_last_error names the size).  The
+ * kernel shapes are the defaults (no autotuning), so results equal a
+ * context's to rounding, not bit for bit.  Runs on p->stream (NULL: the null
+ * stream) and returns after draining it.  No recovery: LE_ENONFINITE leaves
+ * the non-finite state in the caller's arrays.  Calls on one device share
+ * the static array: calls that overlap in time on one device race (run them
+ * on one stream, one after another); the array keeps the last call's
+ * contents, none of which a later call reads before writing it.
+ */
+int le_step_noalloc(const le_params* p, double* phi_dev, double* omega_dev, double* psi_dev,
+                    int64_t step0, int64_t nsteps);
+
+/*
  * Recovery from a non-finite state (failure handling; not part of the
  * method).  On (the default of every context from le_create): le_step keeps
  * a copy of the state at the start of each call (two state snapshots, taken

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -94,17 +95,46 @@ int validate(const le_params* p) {
   return LE_OK;
 }
 
-// Twiddle table exp(-2 pi i k / n), k < n, rounded from long double.
+// Twiddle table exp(-2 pi i k / n), k < n, rounded from long double, into
+// tw[0 .. 2n).
 template <typename T>
-std::vector<T> twiddles(int n) {
-  std::vector<T> tw(2 * (size_t)n);
+void fill_twiddles(T* tw, int n) {
   const long double pi = 3.141592653589793238462643383279502884L;
   for (int k = 0; k < n; ++k) {
     const long double a = -2.0L * pi * (long double)k / (long double)n;
     tw[2 * k] = (T)std::cos(a);
     tw[2 * k + 1] = (T)std::sin(a);
   }
+}
+template <typename T>
+std::vector<T> twiddles(int n) {
+  std::vector<T> tw(2 * (size_t)n);
+  fill_twiddles(tw.data(), n);
   return tw;
+}
+
+// The Geo of a validated parameter set.
+Geo make_geo(const le_params& p) {
+  Geo g;
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.r = p.nx >= p.ny ? p.nx / p.ny : 0;
+  g.f_half = 0;
+  g.lx = p.lx;
+  g.ly = p.ly;
+  g.dx = p.lx / p.nx;
+  g.dy = p.ly / p.ny;
+  g.c = p.lx / p.ly;
+  g.A = p.A;
+  g.B = p.B;
+  g.kappa = p.kappa;
+  g.M = p.M;
+  g.eta = p.eta;
+  g.rho = p.rho;
+  g.dt = p.dt;
+  g.kx0 = 6.283185307179586476925286766559 / p.lx;
+  g.ky0 = 6.283185307179586476925286766559 / p.ly;
+  return g;
 }
 
 struct RunHost {
@@ -430,14 +460,17 @@ int enqueue_chunk(Engine* e, int64_t key, int64_t count, F&& enqueue_one) {
 }
 
 // One step of one class on stream st (the stages of enqueue_step).
-void enqueue_class_step(const Engine* e, const Class& k, const StepArgs* sa, hipStream_t st) {
-  const Run* d = e->d_desc + k.first;
-  const int n = (int)k.members.size();
-  const StepArgs* a = sa + k.first;
-  if (k.inertial)
-    k.ops.row_c2r(d, n, k.ny, B_OM_S, B_OM_R, B_PS_S, B_PS_R, 2, k.row_variant, st);
-  else
-    k.ops.row_c2r(d, n, k.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1, k.row_variant, st);
+// The stages of one step of n runs of class k (descriptors d, StepArgs a);
+// with inverse == false the real omega and psi are taken as they are (the
+// inverse row transforms of stage 0 are skipped).
+void enqueue_runs_step(const Class& k, const Run* d, int n, const StepArgs* a, hipStream_t st,
+                       bool inverse = true) {
+  if (inverse) {
+    if (k.inertial)
+      k.ops.row_c2r(d, n, k.ny, B_OM_S, B_OM_R, B_PS_S, B_PS_R, 2, k.row_variant, st);
+    else
+      k.ops.row_c2r(d, n, k.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1, k.row_variant, st);
+  }
   k.ops.advect(d, n, k.ny, a, k.inertial, k.adv_variant, k.row_fwd_variant, st);
   k.ops.column(COL_CH, d, n, k.nx, a, B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant, st);
   k.ops.row_c2r(d, n, k.ny, B_PHIN, B_PHI, B_PHIN, B_PHI, 1, k.row_variant, st);
@@ -447,6 +480,10 @@ void enqueue_class_step(const Engine* e, const Class& k, const StepArgs* sa, hip
   else
     k.ops.column(COL_STOKES, d, n, k.nx, a, B_GH, B_GH, B_PS_S, B_PS_S, k.col_flow_variant,
                  st);
+}
+
+void enqueue_class_step(const Engine* e, const Class& k, const StepArgs* sa, hipStream_t st) {
+  enqueue_runs_step(k, e->d_desc + k.first, (int)k.members.size(), sa + k.first, st);
 }
 
 // Enqueue `count` plain steps whose StepArgs rows are d_args[0 .. count)
@@ -713,25 +750,7 @@ int create_engine(int32_t n, const le_params* ps, const double* const* phi0s,
     r.p = p;
     r.p.stream = nullptr;
     for (void*& b : r.buf) b = nullptr;
-    Geo& g = r.g;
-    g.nx = p.nx;
-    g.ny = p.ny;
-    g.r = p.nx >= p.ny ? p.nx / p.ny : 0;
-    g.f_half = 0;
-    g.lx = p.lx;
-    g.ly = p.ly;
-    g.dx = p.lx / p.nx;
-    g.dy = p.ly / p.ny;
-    g.c = p.lx / p.ly;
-    g.A = p.A;
-    g.B = p.B;
-    g.kappa = p.kappa;
-    g.M = p.M;
-    g.eta = p.eta;
-    g.rho = p.rho;
-    g.dt = p.dt;
-    g.kx0 = 6.283185307179586476925286766559 / p.lx;
-    g.ky0 = 6.283185307179586476925286766559 / p.ly;
+    r.g = make_geo(p);
     r.inertial = p.rho > 0.0;
     r.tsize = p.precision == LE_FP64 ? sizeof(double) : sizeof(float);
     r.n_real = (size_t)p.nx * p.ny;
@@ -1187,6 +1206,179 @@ void destroy_engine(Engine* e) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- no-allocation step
+//
+// le_step_noalloc takes every device buffer beyond the caller's three fields
+// from one file-scope device array, `scratch`.  In host code the array's
+// name is only a handle: its device address is looked up once per device
+// with hipGetSymbolAddress (each device holds its own copy) and only that
+// address reaches kernels and copies.
+constexpr size_t kNoAllocBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+std::atomic<void*> g_scratch_dev[kNoAllocDevices];
+
+// Set-up of one call: the run descriptor (a kernel argument) into d, and the
+// twiddle tables exp(-2 pi i k / nx), k < nx, and exp(-2 pi i k / (2 ny)),
+// k < 2 ny (sincospi of the exact fraction -2k/n).
+__global__ void k_noalloc_setup(Run h, Run* __restrict__ d, double* __restrict__ twx,
+                                double* __restrict__ twy, int nx, int ny) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *d = h;
+  if (i < nx) sincospi(-2.0 * (double)i / (double)nx, &twx[2 * i + 1], &twx[2 * i]);
+  if (i < 2 * ny) sincospi(-2.0 * (double)i / (double)(2 * ny), &twy[2 * i + 1], &twy[2 * i]);
+}
+
+// StepArgs of steps n0 .. n0 + count - 1: the sawtooth s_n formed exactly as
+// the host clock forms it (same operations, no contraction).
+__global__ void k_step_args(StepArgs* __restrict__ out, int count, long long n0, double gdot,
+                            double dt, double c) {
+#pragma clang fp contract(off)
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  const double X = gdot * ((double)(n0 + k) * dt);
+  const double w = floor((X + 0.5 * c) / c);
+  out[k].s = X - c * w;
+  out[k].pad = 0.0;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Device address of this device's scratch array (looked up on first use).
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  LE_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocDevices) {
+    std::snprintf(g_last_error, sizeof(g_last_error),
+                  "le_step_noalloc: device %d beyond the %d supported", dev, kNoAllocDevices);
+    return LE_EDEVICE;
+  }
+  void* p = g_scratch_dev[dev].load();
+  if (!p) {
+    LE_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_dev[dev].store(p);
+  }
+  *out = p;
+  return LE_OK;
+}
+
+int step_noalloc(const le_params* pp, double* phi, double* omega, double* psi, int64_t step0,
+                 int64_t nsteps) {
+  LE_RC(validate(pp));
+  const le_params& p = *pp;
+  const bool inertial = p.rho > 0.0;
+  if (!phi || !psi || (inertial && !omega) || step0 < 0 || nsteps < 0) return LE_EINVAL;
+  if (p.precision != LE_FP64) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "le_step_noalloc: LE_FP64 only");
+    return LE_EINVAL;
+  }
+  if (nsteps == 0) return LE_OK;
+  // layout of the scratch array
+  const size_t n_real = (size_t)p.nx * p.ny;
+  const size_t spec_b = spec_elems(p.nx, p.ny) * 2 * sizeof(double);
+  size_t off = 0;
+  const size_t o_run = off;   off = align256(off + sizeof(Run));
+  const size_t o_args = off;  off = align256(off + (size_t)kChunkCap * sizeof(StepArgs));
+  const size_t o_twx = off;   off = align256(off + (size_t)p.nx * 2 * sizeof(double));
+  const size_t o_twy = off;   off = align256(off + (size_t)p.ny * 4 * sizeof(double));
+  const size_t o_rpart = off; off = align256(off + (size_t)kRealBlocks * 3 * sizeof(double));
+  const size_t o_out = off;   off = align256(off + (size_t)OBS_NTOTAL * sizeof(double));
+  const int specs[] = {B_OM_S, B_PS_S, B_PHIH, B_FH, B_OMH, B_GH, B_PHIN};
+  const int reals[] = {B_TMP, B_R1, B_R2};
+  size_t o_buf[NBUF] = {0};
+  for (int b : specs) {
+    if (!inertial && (b == B_OM_S || b == B_OMH)) continue;
+    o_buf[b] = off;
+    off = align256(off + spec_b);
+  }
+  for (int b : reals) {
+    o_buf[b] = off;
+    off = align256(off + n_real * sizeof(double));
+  }
+  if (off > kNoAllocBytes) {
+    std::snprintf(g_last_error, sizeof(g_last_error),
+                  "le_step_noalloc: a %dx%d grid needs %zu bytes of scratch, the maximum is %zu",
+                  p.nx, p.ny, off, kNoAllocBytes);
+    return LE_EINVAL;
+  }
+  void* base = nullptr;
+  LE_RC(noalloc_scratch(&base));
+  unsigned char* sc = static_cast<unsigned char*>(base);
+  hipStream_t st = static_cast<hipStream_t>(p.stream);
+  Class k;
+  k.nx = p.nx;
+  k.ny = p.ny;
+  k.prec = LE_FP64;
+  k.inertial = inertial;
+  if (!get_ops(LE_FP64, p.nx, p.ny, &k.ops)) return LE_EINVAL;
+  Run h;
+  h.g = make_geo(p);
+  for (int b = 0; b < NBUF; ++b) h.buf[b] = o_buf[b] ? sc + o_buf[b] : nullptr;
+  h.buf[B_PHI] = phi;
+  h.buf[B_OM_R] = inertial ? omega : nullptr;
+  h.buf[B_PS_R] = psi;
+  h.twx = sc + o_twx;
+  h.twy = sc + o_twy;
+  Run* d = reinterpret_cast<Run*>(sc + o_run);
+  StepArgs* args = reinterpret_cast<StepArgs*>(sc + o_args);
+  double* rpart = reinterpret_cast<double*>(sc + o_rpart);
+  double* out = reinterpret_cast<double*>(sc + o_out);
+  {
+    const int nt = p.nx > 2 * p.ny ? p.nx : 2 * p.ny;
+    hipLaunchKernelGGL(k_noalloc_setup, dim3((nt + 255) / 256), dim3(256), 0, st, h, d,
+                       reinterpret_cast<double*>(sc + o_twx),
+                       reinterpret_cast<double*>(sc + o_twy), p.nx, p.ny);
+  }
+  // the caller's omega and psi are the real fields of step step0: the first
+  // step takes them as they are
+  bool inverse = false;
+  int64_t n0 = step0, remaining = nsteps;
+  int64_t wraps = wrap_count(p, n0);
+  while (remaining > 0) {
+    int64_t count = remaining < kChunkCap ? remaining : kChunkCap;
+    for (int64_t q = 0; q < count; ++q)
+      if (wrap_count(p, n0 + q + 1) != wrap_count(p, n0 + q)) {
+        count = q + 1;
+        break;
+      }
+    hipLaunchKernelGGL(k_step_args, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, args,
+                       (int)count, (long long)n0, p.gdot, p.dt, p.lx / p.ly);
+    for (int64_t q = 0; q < count; ++q) {
+      enqueue_runs_step(k, d, 1, args + q, st, inverse);
+      inverse = true;
+    }
+    n0 += count;
+    const int64_t k_new = wrap_count(p, n0);
+    if (k_new != wraps) {
+      const int dkr = (int)(((k_new - wraps) * (int64_t)h.g.r) % p.nx);
+      k.ops.remap_real(d, B_PHI, B_TMP, dkr, st);
+      k.ops.copy_real(d, B_TMP, B_PHI, st);
+      k.ops.remap_spec(d, B_PS_S, dkr, st);
+      if (inertial) k.ops.remap_spec(d, B_OM_S, dkr, st);
+      wraps = k_new;
+    }
+    LE_TRY(hipGetLastError());
+    remaining -= count;
+  }
+  // the state's real omega and psi into the caller's fields
+  if (inertial)
+    k.ops.row_c2r(d, 1, p.ny, B_OM_S, B_OM_R, B_PS_S, B_PS_R, 2, k.row_variant, st);
+  else
+    k.ops.row_c2r(d, 1, p.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1, k.row_variant, st);
+  k.ops.obs_real(d, B_PHI, rpart, kRealBlocks, st);
+  launch_obs_final(nullptr, 0, rpart, kRealBlocks, nullptr, nullptr, 0, out, st);
+  LE_TRY(hipGetLastError());
+  double bad = 0.0;
+  LE_TRY(hipMemcpyAsync(&bad, out + OBS_NONFINITE, sizeof(double), hipMemcpyDeviceToHost, st));
+  LE_TRY(hipStreamSynchronize(st));
+  return bad == 0.0 ? LE_OK : LE_ENONFINITE;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* le_last_error(void) { return g_last_error; }
@@ -1218,6 +1410,11 @@ int le_create(const le_params* p, const double* phi0, const double* omega0, le_c
   }
   (*out)->recovery = true;
   return LE_OK;
+}
+
+int le_step_noalloc(const le_params* p, double* phi_dev, double* omega_dev, double* psi_dev,
+                    int64_t step0, int64_t nsteps) {
+  return step_noalloc(p, phi_dev, omega_dev, psi_dev, step0, nsteps);
 }
 
 int le_step(le_ctx* c, int64_t nsteps) {

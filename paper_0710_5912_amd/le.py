@@ -18,7 +18,7 @@ LE_OK, LE_EINVAL, LE_ENOMEM, LE_EDEVICE, LE_ENONFINITE, LE_ESTATE = 0, -1, -2, -
 LE_SCHEME_F_HALF, LE_SCHEME_MIDPOINT_S = 1, 2
 LE_FP64, LE_FP32 = 0, 1
 
-SYMBOLS = ("le_create", "le_step", "le_observables", "le_destroy", "le_get_state",
+SYMBOLS = ("le_create", "le_step", "le_step_noalloc", "le_observables", "le_destroy", "le_get_state",
            "le_set_state", "le_strerror", "le_profile", "le_stage_times", "le_last_error",
            "le_batch_create", "le_batch_step", "le_batch_observables", "le_batch_get_state",
            "le_batch_profile", "le_batch_stage_times", "le_batch_destroy",
@@ -101,6 +101,9 @@ def lib():
         L.le_create.restype = C.c_int
         L.le_step.argtypes = [C.c_void_p, C.c_int64]
         L.le_step.restype = C.c_int
+        L.le_step_noalloc.argtypes = [C.POINTER(LeParams), C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_int64, C.c_int64]
+        L.le_step_noalloc.restype = C.c_int
         L.le_set_scheme.argtypes = [C.c_void_p, C.c_int32]
         L.le_set_scheme.restype = C.c_int
         L.le_set_recovery.argtypes = [C.c_void_p, C.c_int]
@@ -501,6 +504,25 @@ class Batch:
 def _ptr(t):
     """Device pointer of a torch tensor (or None)."""
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def step_noalloc(params: dict, phi, omega, psi, step0: int, nsteps: int, stream=None) -> None:
+    """le_step_noalloc on caller device buffers (torch float64 CUDA tensors of
+    shape (ny, nx), C-contiguous; omega may be None when rho == 0), advanced in
+    place from step step0 by nsteps steps."""
+    p = make_params(params, "fp64", stream)
+    shape = (int(params["ny"]), int(params["nx"]))
+    for t in (phi, omega, psi):
+        if t is None:
+            continue
+        if (tuple(t.shape) != shape or not t.is_cuda or not t.is_contiguous()
+                or str(t.dtype) != "torch.float64"):
+            raise ValueError("step_noalloc: fields must be contiguous float64 CUDA tensors "
+                             f"of shape {shape}")
+    rc = lib().le_step_noalloc(C.byref(p), _ptr(phi), _ptr(omega), _ptr(psi), int(step0),
+                               int(nsteps))
+    if rc != LE_OK:
+        raise LeError(rc, "le_step_noalloc")
 
 
 class Net:
