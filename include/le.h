@@ -188,6 +188,23 @@ int le_get_state(le_ctx* c, double* phi, double* omega, double* psi,
 int le_set_state(le_ctx* c, const double* phi, const double* omega,
                  const double* psi, int64_t step, int64_t wraps);
 
+/*
+ * Checkpoint of the exact stored state, for a bitwise resume (le_get_state /
+ * le_set_state pass omega and psi through real space, which rounds).
+ * le_checkpoint_size: the blob's byte count.  le_checkpoint_save writes into
+ * buf (cap >= that size, else LE_EINVAL) a header (format tag, nx, ny,
+ * precision, inertia, step, wraps) and the stored fields as they are on the
+ * device: phi (real), the row spectra of omega (rho > 0) and psi, in storage
+ * precision and the library's layout.  le_checkpoint_load restores such a
+ * blob into a context of the same nx, ny, precision and inertia (LE_EINVAL
+ * otherwise, or for a damaged or short blob); the continued run equals the
+ * saved one bit for bit when both contexts use the same kernel variants
+ * (le_tuning).  Single contexts only.
+ */
+int le_checkpoint_size(le_ctx* c, int64_t* bytes);
+int le_checkpoint_save(le_ctx* c, void* buf, int64_t cap);
+int le_checkpoint_load(le_ctx* c, const void* buf, int64_t bytes);
+
 /* Static description of an error code. */
 const char* le_strerror(int code);
 

@@ -1540,6 +1540,83 @@ int time_stage_of(Engine* e, int32_t stage, int32_t reps, double* ms_per_launch)
   return rc;
 }
 
+// Checkpoint blob: a header, then phi (real), the omega row spectrum
+// (inertial runs) and the psi row spectrum, as stored (storage precision,
+// the library's layout).
+struct CkptHeader {
+  uint64_t magic;
+  int32_t version, nx, ny, precision, inertial, pad;
+  int64_t step, wraps;
+  uint64_t bytes;
+};
+constexpr uint64_t kCkptMagic = 0x31504b43484d454cull;  // "LEMHCKP1"
+
+int64_t ckpt_bytes(const RunHost& r) {
+  const size_t spec = r.n_spec * 2 * r.tsize;
+  return (int64_t)(sizeof(CkptHeader) + r.n_real * r.tsize + (r.inertial ? spec : 0) + spec);
+}
+
+int le_checkpoint_size(le_ctx* c, int64_t* bytes) {
+  if (!c || !bytes || c->nruns != 1) return LE_EINVAL;
+  *bytes = ckpt_bytes(c->runs[0]);
+  return LE_OK;
+}
+
+int le_checkpoint_save(le_ctx* c, void* buf, int64_t cap) {
+  if (!c || !buf || c->nruns != 1) return LE_EINVAL;
+  const RunHost& r = c->runs[0];
+  const int64_t need = ckpt_bytes(r);
+  if (cap < need) return LE_EINVAL;
+  CkptHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.magic = kCkptMagic;
+  h.version = 1;
+  h.nx = r.p.nx;
+  h.ny = r.p.ny;
+  h.precision = r.p.precision;
+  h.inertial = r.inertial ? 1 : 0;
+  h.step = c->step;
+  h.wraps = r.wraps;
+  h.bytes = (uint64_t)need;
+  unsigned char* o = static_cast<unsigned char*>(buf);
+  std::memcpy(o, &h, sizeof(h));
+  size_t off = sizeof(h);
+  const int bufs[3] = {B_PHI, B_OM_S, B_PS_S};
+  const size_t sizes[3] = {r.n_real * r.tsize, r.n_spec * 2 * r.tsize, r.n_spec * 2 * r.tsize};
+  for (int i = 0; i < 3; ++i) {
+    if (i == 1 && !r.inertial) continue;
+    LE_TRY(hipMemcpyAsync(o + off, r.buf[bufs[i]], sizes[i], hipMemcpyDeviceToHost, c->stream));
+    off += sizes[i];
+  }
+  LE_TRY(hipStreamSynchronize(c->stream));
+  return LE_OK;
+}
+
+int le_checkpoint_load(le_ctx* c, const void* buf, int64_t bytes) {
+  if (!c || !buf || c->nruns != 1 || bytes < (int64_t)sizeof(CkptHeader)) return LE_EINVAL;
+  RunHost& r = c->runs[0];
+  CkptHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (h.magic != kCkptMagic || h.version != 1 || h.nx != r.p.nx || h.ny != r.p.ny ||
+      h.precision != r.p.precision || h.inertial != (r.inertial ? 1 : 0) ||
+      (int64_t)h.bytes != ckpt_bytes(r) || bytes < ckpt_bytes(r) || h.step < 0 ||
+      h.wraps != wrap_count(r.p, h.step))
+    return LE_EINVAL;
+  const unsigned char* in = static_cast<const unsigned char*>(buf);
+  size_t off = sizeof(h);
+  const int bufs[3] = {B_PHI, B_OM_S, B_PS_S};
+  const size_t sizes[3] = {r.n_real * r.tsize, r.n_spec * 2 * r.tsize, r.n_spec * 2 * r.tsize};
+  for (int i = 0; i < 3; ++i) {
+    if (i == 1 && !r.inertial) continue;
+    LE_TRY(hipMemcpyAsync(r.buf[bufs[i]], in + off, sizes[i], hipMemcpyHostToDevice, c->stream));
+    off += sizes[i];
+  }
+  LE_TRY(hipStreamSynchronize(c->stream));
+  c->step = h.step;
+  r.wraps = h.wraps;
+  return LE_OK;
+}
+
 int le_time_stage(le_ctx* c, int32_t stage, int32_t reps, double* ms_per_launch) {
   return time_stage_of(c, stage, reps, ms_per_launch);
 }

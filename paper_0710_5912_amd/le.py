@@ -18,7 +18,8 @@ LE_OK, LE_EINVAL, LE_ENOMEM, LE_EDEVICE, LE_ENONFINITE, LE_ESTATE = 0, -1, -2, -
 LE_SCHEME_F_HALF, LE_SCHEME_MIDPOINT_S = 1, 2
 LE_FP64, LE_FP32 = 0, 1
 
-SYMBOLS = ("le_create", "le_step", "le_step_noalloc", "le_observables", "le_destroy", "le_get_state",
+SYMBOLS = ("le_create", "le_step", "le_step_noalloc", "le_checkpoint_size",
+           "le_checkpoint_save", "le_checkpoint_load", "le_observables", "le_destroy", "le_get_state",
            "le_set_state", "le_strerror", "le_profile", "le_stage_times", "le_last_error",
            "le_batch_create", "le_batch_step", "le_batch_observables", "le_batch_get_state",
            "le_batch_profile", "le_batch_stage_times", "le_batch_destroy",
@@ -101,6 +102,12 @@ def lib():
         L.le_create.restype = C.c_int
         L.le_step.argtypes = [C.c_void_p, C.c_int64]
         L.le_step.restype = C.c_int
+        L.le_checkpoint_size.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.le_checkpoint_size.restype = C.c_int
+        L.le_checkpoint_save.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
+        L.le_checkpoint_save.restype = C.c_int
+        L.le_checkpoint_load.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
+        L.le_checkpoint_load.restype = C.c_int
         L.le_step_noalloc.argtypes = [C.POINTER(LeParams), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_int64, C.c_int64]
         L.le_step_noalloc.restype = C.c_int
@@ -290,6 +297,26 @@ class Context:
         if rc != LE_OK:
             raise LeError(rc, "le_get_state")
         return dict(phi=phi, omega=om, psi=psi, step=step.value, wraps=wraps.value)
+
+    def checkpoint(self) -> bytes:
+        """The exact stored state as a blob (le_checkpoint_save)."""
+        self._check()
+        n = C.c_int64()
+        rc = lib().le_checkpoint_size(self._h, C.byref(n))
+        if rc != LE_OK:
+            raise LeError(rc, "le_checkpoint_size")
+        buf = C.create_string_buffer(n.value)
+        rc = lib().le_checkpoint_save(self._h, buf, n.value)
+        if rc != LE_OK:
+            raise LeError(rc, "le_checkpoint_save")
+        return buf.raw
+
+    def restore(self, blob: bytes) -> None:
+        """Load a blob from checkpoint() (le_checkpoint_load)."""
+        self._check()
+        rc = lib().le_checkpoint_load(self._h, blob, len(blob))
+        if rc != LE_OK:
+            raise LeError(rc, "le_checkpoint_load")
 
     def set_state(self, phi, omega, psi, step: int, wraps: int) -> None:
         self._check()

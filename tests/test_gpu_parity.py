@@ -121,7 +121,30 @@ def test_mean_phi_conserved_and_deterministic(fixed_variants):
     assert np.array_equal(runs[0]["psi"], runs[1]["psi"])
 
 
-def test_checkpoint_resume_is_bitwise(fixed_variants):
+@pytest.mark.parametrize("rho,prec", [(1.0, "fp64"), (0.0, "fp64"), (1.0, "fp32")])
+def test_checkpoint_resume_is_bitwise(fixed_variants, rho, prec):
+    """A blob saved at step 150 and loaded into a fresh context continues
+    bit for bit as the run it came from (a wrap at step 200 in between)."""
+    p = params(64, 64, gdot=1.0, rho=rho)
+    phi0 = inputs.noise_phi0(64, 64, 2, amp=0.5)
+    with le.Context(p, phi0, precision=prec) as a, \
+            le.Context(p, np.zeros((64, 64)), precision=prec) as b:
+        a.step(150)
+        blob = a.checkpoint()
+        a.step(150)
+        ref = a.get_state()
+        b.restore(blob)
+        b.step(150)
+        got = b.get_state()
+        assert got["step"] == ref["step"] == 300 and got["wraps"] == ref["wraps"]
+        for k in ("phi", "omega", "psi"):
+            assert np.array_equal(got[k], ref[k]), k
+        with pytest.raises(le.LeError) as ei:
+            b.restore(blob[:-8])
+        assert ei.value.code == le.LE_EINVAL
+
+
+def test_set_state_resume_to_rounding(fixed_variants):
     p = params(64, 64, gdot=1.0, rho=1.0)    # a wrap at strain 0.5 (step 100)
     phi0 = inputs.noise_phi0(64, 64, 2, amp=0.5)
     a = le.Context(p, phi0)
