@@ -155,6 +155,7 @@ def evaluate(params, scales, gdot=0.01, seed=99, t0=T_START, t_end=T_END, every=
     nsamp = int(round((t_end - t0) / every))
     kf, kc = int(round(every / DT)), int(round(every / (DT * factor)))
     out = {"t": [], "fine": [], "restricted": [], "corrected": [], "coarse": []}
+    sks = {"restricted": [], "corrected": [], "coarse": []}
     torch.cuda.synchronize()
     wall_fine = 0.0
     probe = le.Context(cp, np.zeros((nc, nc)))
@@ -167,8 +168,9 @@ def evaluate(params, scales, gdot=0.01, seed=99, t0=T_START, t_end=T_END, every=
         out["fine"].append(o["Ls"])
         pr, orr = fine.restrict(factor)
         probe.set_fields(pr, orr, (k0 + kf * (i + 1)) // factor)
-        op, _ = probe.observables(sk=False)
+        op, skp = probe.observables(sk=True)
         out["restricted"].append(op["Ls"])
+        sks["restricted"].append(skp)
     fine.close()
     probe.close()
     runs = ("corrected", "coarse") + (("audited",) if audit else ())
@@ -187,8 +189,10 @@ def evaluate(params, scales, gdot=0.01, seed=99, t0=T_START, t_end=T_END, every=
                 c.step(kc)
             else:
                 c.step_corrected(kc)
-            o, _ = c.observables(sk=False)
+            o, skc = c.observables(sk=True)
             out[name].append(o["Ls"])
+            if name in sks:
+                sks[name].append(skc)
         out["wall_" + name] = time.perf_counter() - t_a
         if name == "audited":
             fb, na, dev = c.corrector_status()
@@ -206,6 +210,21 @@ def evaluate(params, scales, gdot=0.01, seed=99, t0=T_START, t_end=T_END, every=
         out["err_max_" + name] = float(e.max())
         out["err_mean_" + name + "_vs_restricted"] = float(er.mean())
         out["err_max_" + name + "_vs_restricted"] = float(er.max())
+    # S(k) of the coarse runs against S(k) of the restricted fine field (the
+    # same field seen on the coarse grid): relative L2 error per sample,
+    # averaged over the samples, over the shells 1 .. nc/4 (|k| up to half the
+    # coarse Nyquist), and apart over the domain band 1 .. nc/8 (the S(k) peak
+    # and below) and the interface band nc/8 .. nc/2
+    for name, v in sks.items():
+        out["Sk_" + name] = [list(map(float, a)) for a in v]
+    bands = {"": (0, nc // 4), "_low": (0, nc // 8), "_high": (nc // 8, nc // 2)}
+    for suffix, (lo, hi) in bands.items():
+        sr = np.array(sks["restricted"])[:, lo:hi]
+        for name in ("corrected", "coarse"):
+            sc = np.array(sks[name])[:, lo:hi]
+            e = np.linalg.norm(sc - sr, axis=1) / np.linalg.norm(sr, axis=1)
+            out["Sk" + suffix + "_err_mean_" + name] = float(e.mean())
+            out["Sk" + suffix + "_err_max_" + name] = float(e.max())
     sites_fine = n * n * (t_end - t0) / DT
     out["fine_rate"] = sites_fine / wall_fine
     out["corrected_fine_equiv_rate"] = sites_fine / out["wall_corrected"]
@@ -215,8 +234,11 @@ def evaluate(params, scales, gdot=0.01, seed=99, t0=T_START, t_end=T_END, every=
         out["audited_equals_corrected"] = bool(np.array_equal(out["audited"], out["corrected"]))
     log(f"corrector eval gdot={gdot}: L err mean corrected {out['err_mean_corrected']:.3f} "
         f"(vs restricted {out['err_mean_corrected_vs_restricted']:.3f}), plain coarse "
-        f"{out['err_mean_coarse']:.3f} ({out['err_mean_coarse_vs_restricted']:.3f}), "
-        f"gain {out['gain']:.1f}x")
+        f"{out['err_mean_coarse']:.3f} ({out['err_mean_coarse_vs_restricted']:.3f}); S(k) err "
+        f"corrected {out['Sk_err_mean_corrected']:.3f} (low {out['Sk_low_err_mean_corrected']:.3f}, "
+        f"high {out['Sk_high_err_mean_corrected']:.3f}), plain coarse "
+        f"{out['Sk_err_mean_coarse']:.3f} (low {out['Sk_low_err_mean_coarse']:.3f}, high "
+        f"{out['Sk_high_err_mean_coarse']:.3f}); gain {out['gain']:.1f}x")
     return out
 
 
