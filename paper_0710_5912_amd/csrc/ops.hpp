@@ -24,6 +24,10 @@ struct CorrArgs {
 // k-row strips with the row transforms in the same kernel, two x pairs per
 // thread; kStripFft1 + k the same with one pair per thread.
 constexpr int kStripFft = 64, kStripFft1 = 96;
+// Advect variants kAdvBatch + k and kAdvBatch2 + k: the batched one-kernel
+// form over k-row strips in batches of four or two rows (nx 512 .. 4096;
+// elsewhere the two-kernel strip over k rows).
+constexpr int kAdvBatch = 128, kAdvBatch2 = 192;
 
 struct Ops {
   // row transforms; variant (a tuning choice): 0 = 8 values per thread, 1 = 4

@@ -129,6 +129,22 @@ struct RowLaunch {
       hipLaunchKernelGGL((k_adv_strip_fft<T, NX, false, SEG>), gf, dim3(L / SEG), 0, st, runs,
                          sa, rows, inertial ? 1 : 0);
   }
+  // NR rows per batch; 16 values per thread in the four-row transforms
+  // (fewer threads, more registers each), 8 in the two-row ones
+  template <int NR>
+  static void adv_batch(const Run* runs, const StepArgs* sa, int ny, dim3 gb, int rows,
+                        bool inertial, hipStream_t st) {
+    constexpr int NX = 2 * L, EF = NR == 4 ? 16 : 8;
+    if constexpr (adv_batch_ok(NX)) {
+      using CB = AdvBatch<T, NX, NR, EF>;
+      if (ny == NX)
+        hipLaunchKernelGGL((k_adv_batch<T, NX, true, NR, EF>), gb, dim3(CB::TPB), 0, st, runs,
+                           sa, rows, inertial ? 1 : 0);
+      else
+        hipLaunchKernelGGL((k_adv_batch<T, NX, false, NR, EF>), gb, dim3(CB::TPB), 0, st,
+                           runs, sa, rows, inertial ? 1 : 0);
+    }
+  }
   // variant 0: the fused bracket kernel (stencil and row transform per
   // block); variant 0 < k < kStripFft: the strip stencil over k-row strips
   // into the spectral buffers, then in-place row transforms; variant
@@ -145,6 +161,19 @@ struct RowLaunch {
       return;
     }
     constexpr int NX = 2 * L, TPB = strip_threads(NX);
+    if (variant >= kAdvBatch) {
+      const bool four = variant < kAdvBatch2;
+      const int rows = variant - (four ? kAdvBatch : kAdvBatch2);
+      if constexpr (adv_batch_ok(NX)) {
+        const dim3 gb(1, (ny + rows - 1) / rows, nruns);
+        if (four)
+          adv_batch<4>(runs, sa, ny, gb, rows, inertial, st);
+        else
+          adv_batch<2>(runs, sa, ny, gb, rows, inertial, st);
+        return;
+      }
+      variant = rows;  // grids outside the batched kernel's range: the two-kernel form
+    }
     if (variant >= kStripFft) {
       const bool two = variant < kStripFft1;
       const int rows = variant - (two ? kStripFft : kStripFft1);

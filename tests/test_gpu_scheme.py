@@ -109,3 +109,13 @@ def test_batch_scheme_equals_single_runs(fixed_variants):
                 assert np.array_equal(gb[k], gc[k]), (i, k)
     finally:
         b.close()
+
+
+@pytest.mark.parametrize("adv", [136, 196])
+@pytest.mark.parametrize("rho", [1.0, 0.0])
+def test_f_half_batched_advection(monkeypatch, rho, adv):
+    """f of the advected phi through the batched one-kernel advection (512^2)."""
+    p = params(512, 512, rho=rho)
+    g, st = run_both(monkeypatch, p, 3, 32, True, False, adv)
+    for k in ("phi", "psi") + (("omega",) if rho > 0 else ()):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k

@@ -27,7 +27,8 @@ KEYS = ("LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH", "LE_TUNE_COL_FLOW", "LE_T
 COMBOS = [(0, 0, 0, 0, 0), (4, 4, 1, 1, 1), (32, 32, 2, 2, 2), (8, 16, 3, 3, 3),
           (2, 2, 0, 0, 1), (66, 4, 0, 1, 2), (72, 8, 2, 0, 0), (100, 2, 1, 3, 0),
           (98, 66, 0, 0, 3), (4, 68, 1, 1, 0), (100, 72, 3, 2, 1), (8, 8, 4, 4, 4),
-          (68, 68, 4, 3, 5), (4, 4, 2, 4, 5)]
+          (68, 68, 4, 3, 5), (4, 4, 2, 4, 5), (132, 4, 0, 3, 5), (136, 68, 4, 4, 4),
+          (160, 8, 3, 0, 0), (194, 4, 4, 3, 5), (200, 68, 0, 1, 2)]
 
 
 def params(nx, ny, **kw):
@@ -81,7 +82,8 @@ def test_variants_512_fp64(monkeypatch, combo, rho):
 
 
 @pytest.mark.parametrize("combo", [(4, 4, 1, 3, 1), (32, 8, 3, 2, 3), (68, 4, 0, 0, 1),
-                                   (98, 8, 2, 1, 2), (66, 68, 1, 1, 2), (8, 4, 4, 4, 4), (16, 8, 3, 4, 5)])
+                                   (98, 8, 2, 1, 2), (66, 68, 1, 1, 2), (8, 4, 4, 4, 4), (16, 8, 3, 4, 5),
+                                   (144, 8, 0, 2, 4)])
 def test_variants_512_fp32(monkeypatch, combo):
     """FP32 shapes (16 values per thread in shapes 2 and 3) within the FP32 bound."""
     p = params(512, 512)
@@ -171,11 +173,23 @@ def test_column_shapes_at_4096_point_columns(monkeypatch, col, rho):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
 
 
+@pytest.mark.parametrize("adv", [4, 136, 196])
 @pytest.mark.parametrize("row", range(6))
-def test_row_shapes_at_4096_point_rows(monkeypatch, row):
+def test_row_shapes_at_4096_point_rows(monkeypatch, row, adv):
     """4096 x 16 (gdot = 0.05, r = 256): 4096-point rows in every row shape,
-    with the two-kernel strip stages (real rows through the real scratch)."""
+    with the two-kernel strip stages (real rows through the real scratch) and
+    the batched one-kernel advection."""
     p = params(4096, 16, gdot=0.05)
-    g, st = run_forced(monkeypatch, p, 3, 28, (4, 8, 0, 0, row))
+    g, st = run_forced(monkeypatch, p, 3, 28, (adv, 8, 0, 0, row))
+    for k in ("phi", "omega", "psi"):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k
+
+
+@pytest.mark.parametrize("combo", [(132, 4, 0, 0, 0), (144, 8, 1, 1, 1), (194, 2, 3, 3, 3)])
+def test_batched_advection_non_square_cells(monkeypatch, combo):
+    """512 x 128 (r = 4, gdot = 0.2, strain wrap inside): the batched
+    one-kernel advection reads the diagonal pairs r = 4 columns away."""
+    p = params(512, 128, gdot=0.2, lx=512.0, ly=128.0)
+    g, st = run_forced(monkeypatch, p, 20, 29, combo)
     for k in ("phi", "omega", "psi"):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
