@@ -30,7 +30,9 @@ Readings taken where the paper is silent (each is listed in the design notes):
 * every operator of step n uses s_n; f = (phi^n)^3; the omega Crank-Nicolson
   update starts from the advected omega^{n+1/2} (Params.f_half and
   Params.midpoint_s switch to the other readings of the first two: f of the
-  advected phi, and s at the step's midpoint);
+  advected phi, and s at the step's midpoint; Params.upwind3 takes the
+  advected field's derivatives by the third-order upwind differences that
+  Appendix B keeps as a commented-out alternative, sheared like Eq. p1y);
 * the q = 0 mode: phi untouched, omega and psi set to zero;
 * at a strain wrap s -> s - c (c = Lx/Ly) the fields are remapped row by row,
   new[j][i] = old[j][(i - r j) mod Nx] with r = Nx/Ny, so the lab-frame field
@@ -70,10 +72,12 @@ class Params:
     eta: float = 1.0
     rho: float = 1.0
     dt: float = 0.005
-    # scheme variants either side of the default reading (both off: the scheme
-    # as read): f from the advected phi; the sawtooth at the step's midpoint
+    # scheme variants either side of the default reading (all off: the scheme
+    # as read): f from the advected phi; the sawtooth at the step's midpoint;
+    # third-order upwinding of the advected field's derivatives
     f_half: bool = False
     midpoint_s: bool = False
+    upwind3: bool = False
 
     @property
     def dx(self) -> float:
@@ -183,8 +187,52 @@ def d_xy(p: Params, a: np.ndarray) -> np.ndarray:
 
 
 def advection(p: Params, psi: np.ndarray, a: np.ndarray, s: float) -> np.ndarray:
-    """The bracket d_y psi d_x a - d_x psi d_y a of Eq. advective."""
+    """The bracket d_y psi d_x a - d_x psi d_y a of Eq. advective.
+
+    With p.upwind3 the derivatives of the advected field a are the
+    third-order upwind ones (the alternative Appendix B keeps in a comment),
+    upwind with respect to the velocity v = (d_y psi, -d_x psi) at each point;
+    the derivatives of psi stay central.
+    """
+    if p.upwind3:
+        vx = d_y_sheared(p, psi, s)
+        vy = -d_x(p, psi)
+        return vx * d_x_upwind(p, a, vx) + vy * d_y_sheared_upwind(p, a, vy, s)
     return d_y_sheared(p, psi, s) * d_x(p, a) - d_x(p, psi) * d_y_sheared(p, a, s)
+
+
+# Third-order upwind first difference: offsets -2 .. 1 with weights
+# (1, -6, 3, 2)/6 where the velocity is positive, the mirror image
+# (offsets 2 .. -1, weights (-1, 6, -3, -2)/6) where it is not.
+_UPWIND_POS = ((-2, 1.0), (-1, -6.0), (0, 3.0), (1, 2.0))
+_UPWIND_NEG = ((2, -1.0), (1, 6.0), (0, -3.0), (-1, -2.0))
+
+
+def d_x_upwind(p: Params, a: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """Third-order upwind x difference, upwind for the velocity field v."""
+    pos = sum(c * at(a, 0, k) for k, c in _UPWIND_POS) / (6.0 * p.dx)
+    neg = sum(c * at(a, 0, k) for k, c in _UPWIND_NEG) / (6.0 * p.dx)
+    return np.where(v > 0.0, pos, neg)
+
+
+def d_y_sheared_upwind(p: Params, a: np.ndarray, v: np.ndarray, s: float) -> np.ndarray:
+    """Third-order upwind y difference in the sheared frame.
+
+    The sample of row j + k is taken, as in Eq. p1y, between the column
+    straight above (weight 1 - |s|/c) and the column k r cells along the
+    grid diagonal (weight |s|/c, offset -sign(s) r k), i.e. on the line of
+    constant lab x; the upwind weights then act on these samples.  It
+    approximates the lab derivative d_y - s d_x to third order.
+    """
+    w = abs(s) / p.c
+    sg = 1 if s >= 0 else -1
+
+    def sample(k):
+        return (1.0 - w) * at(a, k, 0) + w * at(a, k, -sg * p.r * k)
+
+    pos = sum(c * sample(k) for k, c in _UPWIND_POS) / (6.0 * p.dy)
+    neg = sum(c * sample(k) for k, c in _UPWIND_NEG) / (6.0 * p.dy)
+    return np.where(v > 0.0, pos, neg)
 
 
 def chemical_potential(p: Params, phi: np.ndarray, s: float) -> np.ndarray:

@@ -507,3 +507,94 @@ def test_scheme_variants_are_first_order_close_to_the_default(flag):
     assert d[2] > 1e-5
     for e1, e2 in ((d[0], d[1]), (d[1], d[2])):
         assert abs(math.log2(e1 / e2) - 1.0) < 0.2, d
+
+
+# --------------- third-order upwind advection (the scheme switch upwind3)
+
+def _smooth_field(p):
+    j, i = np.meshgrid(np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    x, y = 2 * math.pi * i / p.nx, 2 * math.pi * j / p.ny
+    a = np.sin(x + 2 * y) + 0.5 * np.cos(3 * x - y)
+    ax = np.cos(x + 2 * y) - 1.5 * np.sin(3 * x - y)           # d/dx in units of 2 pi / lx
+    ay = 2 * np.cos(x + 2 * y) + 0.5 * np.sin(3 * x - y)       # d/dy in units of 2 pi / ly
+    return a, ax * 2 * math.pi / p.lx, ay * 2 * math.pi / p.ly
+
+
+@pytest.mark.parametrize("s", [0.0, 0.3, -0.45])
+@pytest.mark.parametrize("vsign", ["pos", "neg", "mixed"])
+def test_upwind_differences_are_third_order(s, vsign):
+    """The upwind x difference -> d_x and the sheared upwind y difference ->
+    d_y - s d_x (the lab y derivative) with errors O(delta^3), on grids with
+    r = 2 (the paper's geometry), for positive, negative and mixed-sign
+    velocity fields."""
+    ex, ey = [], []
+    for n in (32, 64, 128):
+        p = P(nx=2 * n, ny=n, lx=2.0, ly=1.0)
+        a, ax, ay = _smooth_field(p)
+        if vsign == "pos":
+            v = np.ones_like(a)
+        elif vsign == "neg":
+            v = -np.ones_like(a)
+        else:
+            v = np.sin(2 * math.pi * np.arange(p.nx) / p.nx)[None, :] * np.ones_like(a)
+        ex.append(np.max(np.abs(mh.d_x_upwind(p, a, v) - ax)))
+        ey.append(np.max(np.abs(mh.d_y_sheared_upwind(p, a, v, s) - (ay - s * ax))))
+    for e in (ex, ey):
+        orders = [math.log2(e[k] / e[k + 1]) for k in range(2)]
+        assert all(abs(o - 3.0) < 0.25 for o in orders), (orders, e)
+
+
+def test_upwind_pin_catches_a_mirrored_shear_offset(monkeypatch):
+    """Taking each row's sheared sample on the wrong diagonal (offset +sign(s) r k)
+    leaves an O(1) error in the lab derivative, which the order pin sees."""
+    def wrong(p, a, v, s):
+        w = abs(s) / p.c
+        sg = 1 if s >= 0 else -1
+
+        def sample(k):
+            return (1.0 - w) * mh.at(a, k, 0) + w * mh.at(a, k, sg * p.r * k)
+
+        pos = sum(c * sample(k) for k, c in mh._UPWIND_POS) / (6.0 * p.dy)
+        neg = sum(c * sample(k) for k, c in mh._UPWIND_NEG) / (6.0 * p.dy)
+        return np.where(v > 0.0, pos, neg)
+
+    p = P(nx=256, ny=128, lx=2.0, ly=1.0)
+    a, ax, ay = _smooth_field(p)
+    v = np.ones_like(a)
+    good = np.max(np.abs(mh.d_y_sheared_upwind(p, a, v, 0.3) - (ay - 0.3 * ax)))
+    monkeypatch.setattr(mh, "d_y_sheared_upwind", wrong)
+    bad = np.max(np.abs(mh.d_y_sheared_upwind(p, a, v, 0.3) - (ay - 0.3 * ax)))
+    assert bad > 100 * good
+
+
+def test_upwind_scheme_converges_to_the_central_one_in_space():
+    """Both advection forms are consistent with the same equations: at fixed T
+    the upwind variant's difference from the default shrinks as delta^2 (the
+    central form's truncation error), and it is not zero."""
+    import dataclasses
+    T = 0.4
+    d = []
+    for nn in (16, 32, 64):
+        p = P(nx=nn, ny=nn, lx=8.0, ly=8.0, gdot=0.3, kappa=0.5, M=0.5,
+              dt=0.4 * (8.0 / nn) ** 2 / 4)
+        q = dataclasses.replace(p, upwind3=True)
+        phi, om = smooth_init(p)
+        a = mh.run(p, mh.initial_state(p, phi, om), int(round(T / p.dt)))
+        b = mh.run(q, mh.initial_state(q, phi, om), int(round(T / q.dt)))
+        d.append(np.max(np.abs(a.phi - b.phi)) + np.max(np.abs(a.omega - b.omega)))
+    assert d[-1] > 1e-8
+    orders = [math.log2(d[k] / d[k + 1]) for k in range(2)]
+    assert all(abs(o - 2.0) < 0.3 for o in orders), (orders, d)
+
+
+def test_upwind_reduces_to_the_default_without_flow():
+    """With psi = 0 the advection vanishes in both forms: runs agree bit for bit
+    (a y-only profile keeps psi at zero)."""
+    import dataclasses
+    p = P(nx=16, ny=32, lx=16.0, ly=32.0, gdot=0.2, kappa=2.0, M=0.5)
+    y = np.arange(p.ny) * p.dy
+    phi = np.repeat((0.8 * np.tanh((y - 8.0) / 2.0) * np.tanh((y - 24.0) / 2.0))[:, None],
+                    p.nx, axis=1)
+    a = mh.run(p, mh.initial_state(p, phi), 40)
+    b = mh.run(dataclasses.replace(p, upwind3=True), mh.initial_state(p, phi), 40)
+    assert np.array_equal(a.phi, b.phi)
