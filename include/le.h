@@ -161,10 +161,18 @@ int le_set_recovery(le_ctx* c, int enable);
  *                         default takes that as (phi^n)^3);
  *   LE_SCHEME_MIDPOINT_S  every operator of step n at the sawtooth of the
  *                         step's midpoint, s(t_n + dt/2) in the frame of step
- *                         n, instead of s(t_n) (observables stay at s(t_n)).
+ *                         n, instead of s(t_n) (observables stay at s(t_n));
+ *   LE_SCHEME_UPWIND3     the derivatives of the advected fields (phi and
+ *                         omega in stage 1a) by the third-order upwind
+ *                         differences that Appendix B keeps as a commented-out
+ *                         alternative to Eq. p1y, upwind with respect to the
+ *                         local velocity (d_y psi, -d_x psi); the y samples
+ *                         are sheared as in Eq. p1y (weight |s|/c on the
+ *                         column r k cells along the grid diagonal for row
+ *                         j + k).  The derivatives of psi stay central.
  * Takes effect from the next step; flags outside these bits: LE_EINVAL.
  */
-enum { LE_SCHEME_F_HALF = 1, LE_SCHEME_MIDPOINT_S = 2 };
+enum { LE_SCHEME_F_HALF = 1, LE_SCHEME_MIDPOINT_S = 2, LE_SCHEME_UPWIND3 = 4 };
 int le_set_scheme(le_ctx* c, int32_t flags);
 
 /*

@@ -120,6 +120,7 @@ Geo make_geo(const le_params& p) {
   g.ny = p.ny;
   g.r = p.nx >= p.ny ? p.nx / p.ny : 0;
   g.f_half = 0;
+  g.upwind3 = 0;
   g.lx = p.lx;
   g.ly = p.ly;
   g.dx = p.lx / p.nx;
@@ -162,6 +163,8 @@ struct Class {
   int row_variant = 0;       // Ops::row_c2r (inverse row transforms)
   int row_fwd_variant = 0;   // Ops::row_r2c (forward row transforms, also of the
                              // two-kernel stencil stages)
+  bool upwind3 = false;      // LE_SCHEME_UPWIND3: the upwind advection kernel
+  int advect() const { return upwind3 ? kAdvUpwind : adv_variant; }
   std::vector<int> members;  // run ids
   int first = 0;             // internal index of members[0]
 };
@@ -351,7 +354,7 @@ void enqueue_step(Engine* e, const StepArgs* sa, hipEvent_t* ev) {
   mark(1);
   for (const Class& k : e->classes)
     k.ops.advect(e->d_desc + k.first, (int)k.members.size(), k.ny, sa + k.first, k.inertial,
-                 k.adv_variant, k.row_fwd_variant, st);
+                 k.advect(), k.row_fwd_variant, st);
   mark(2);
   for (const Class& k : e->classes)
     k.ops.column(COL_CH, e->d_desc + k.first, (int)k.members.size(), k.nx, sa + k.first,
@@ -471,7 +474,7 @@ void enqueue_runs_step(const Class& k, const Run* d, int n, const StepArgs* a, h
     else
       k.ops.row_c2r(d, n, k.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1, k.row_variant, st);
   }
-  k.ops.advect(d, n, k.ny, a, k.inertial, k.adv_variant, k.row_fwd_variant, st);
+  k.ops.advect(d, n, k.ny, a, k.inertial, k.advect(), k.row_fwd_variant, st);
   k.ops.column(COL_CH, d, n, k.nx, a, B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant, st);
   k.ops.row_c2r(d, n, k.ny, B_PHIN, B_PHI, B_PHIN, B_PHI, 1, k.row_variant, st);
   k.ops.mu_source(d, n, k.ny, a, k.mu_variant, k.row_fwd_variant, st);
@@ -1432,13 +1435,29 @@ int le_set_recovery(le_ctx* c, int enable) {
 }
 
 int le_set_scheme(le_ctx* c, int32_t flags) {
-  if (!c || (flags & ~(LE_SCHEME_F_HALF | LE_SCHEME_MIDPOINT_S)) != 0) return LE_EINVAL;
+  if (!c || (flags & ~(LE_SCHEME_F_HALF | LE_SCHEME_MIDPOINT_S | LE_SCHEME_UPWIND3)) != 0)
+    return LE_EINVAL;
   // every run of the engine (one for a context, all of a batch)
   c->midpoint_s = (flags & LE_SCHEME_MIDPOINT_S) != 0;
+  const bool up = (flags & LE_SCHEME_UPWIND3) != 0;
+  bool relaunch = false;
+  for (Class& k : c->classes) {
+    relaunch = relaunch || k.upwind3 != up;
+    k.upwind3 = up;
+  }
+  if (relaunch) {
+    // captured graphs hold the other advection kernel
+    for (auto& kv : c->graphs) {
+      (void)hipGraphExecDestroy(kv.second.second);
+      (void)hipGraphDestroy(kv.second.first);
+    }
+    c->graphs.clear();
+  }
   std::vector<Run> h((size_t)c->nruns);
   LE_TRY(hipMemcpy(h.data(), c->d_desc, sizeof(Run) * h.size(), hipMemcpyDeviceToHost));
   for (RunHost& r : c->runs) {
     r.g.f_half = (flags & LE_SCHEME_F_HALF) ? 1 : 0;
+    r.g.upwind3 = up ? 1 : 0;
     h[r.internal].g = r.g;
   }
   LE_TRY(hipStreamSynchronize(c->stream));
@@ -1505,7 +1524,7 @@ int time_stage_of(Engine* e, int32_t stage, int32_t reps, double* ms_per_launch)
             k.ops.row_c2r(d, n, k.ny, B_PS_S, B_TMP, B_PS_S, B_TMP, 1, k.row_variant, st);
           break;
         case 1:
-          k.ops.advect(d, n, k.ny, sa, k.inertial, k.adv_variant, k.row_fwd_variant, st);
+          k.ops.advect(d, n, k.ny, sa, k.inertial, k.advect(), k.row_fwd_variant, st);
           break;
         case 2:
           k.ops.column(COL_CH, d, n, k.nx, sa, B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant,

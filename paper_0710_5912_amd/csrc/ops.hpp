@@ -28,6 +28,9 @@ constexpr int kStripFft = 64, kStripFft1 = 96;
 // form over k-row strips in batches of four or two rows (nx 512 .. 4096;
 // elsewhere the two-kernel strip over k rows).
 constexpr int kAdvBatch = 128, kAdvBatch2 = 192;
+// Advect variant kAdvUpwind: the third-order upwind differences of the scheme
+// switch LE_SCHEME_UPWIND3 (stencil kernel, then the forward row transforms).
+constexpr int kAdvUpwind = 1024;
 
 struct Ops {
   // row transforms; variant (a tuning choice): 0 = 8 values per thread, 1 = 4

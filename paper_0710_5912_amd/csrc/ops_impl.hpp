@@ -161,6 +161,14 @@ struct RowLaunch {
       return;
     }
     constexpr int NX = 2 * L, TPB = strip_threads(NX);
+    if (variant == kAdvUpwind) {
+      const dim3 gu((NX / 2 + 255) / 256, ny, nruns);
+      hipLaunchKernelGGL((k_adv_upwind<T, NX>), gu, dim3(NX / 2 < 256 ? NX / 2 : 256), 0, st,
+                         runs, sa, inertial ? 1 : 0);
+      R2cJobs jobs{{{B_TMP, B_PHIH, NX}, {B_R1, B_FH, NX}, {B_R2, B_OMH, NX}}};
+      r2c_jobs(runs, nruns, ny, jobs, inertial ? 3 : 2, row_variant, st);
+      return;
+    }
     if (variant >= kAdvBatch) {
       const bool four = variant < kAdvBatch2;
       const int rows = variant - (four ? kAdvBatch : kAdvBatch2);

@@ -741,6 +741,78 @@ __global__ __launch_bounds__(strip_threads(NX)) void k_adv_strip(
   }
 }
 
+// Stage 1a with third-order upwind differences of the advected fields (the
+// alternative Appendix B keeps in a comment):
+//   out = a - dt (vx Dx^up a + vy Dys^up a),  vx = Dys psi, vy = -Dx psi,
+// with the central Eq. p1y differences of psi, and the upwind differences
+// taken over offsets -2 .. 1 with weights (1, -6, 3, 2)/6 where the velocity
+// component is positive, the mirror image where it is not.  The y samples of
+// row j + k lie on the sheared line: (1 - |s|/c) a[j+k][i] + |s|/c
+// a[j+k][i - sign(s) r k].  One thread per x pair of a row, every value read
+// from memory (a switch for studies of the scheme, not a tuned path); real
+// outputs phi_h, f, omega_h into B_TMP, B_R1, B_R2 for the forward row
+// transforms that follow.
+template <typename T, int NX>
+__global__ __launch_bounds__(256) void k_adv_upwind(const Run* __restrict__ runs,
+                                                    const StepArgs* __restrict__ sa,
+                                                    int inertial) {
+  const Run& R = runs[blockIdx.z];
+  const Geo& geo = R.g;
+  const int ny = geo.ny;
+  const int j = blockIdx.y;
+  const int x = 2 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (x >= NX) return;
+  auto phi = bufp<const T>(R, B_PHI);
+  auto psi = bufp<const T>(R, B_PS_R);
+  auto om = bufp<const T>(R, B_OM_R);
+  const double s = sa[blockIdx.z].s;
+  const T w = T(fabs(s) / geo.c), wm = T(1.0 - fabs(s) / geo.c);
+  const int sg = s >= 0.0 ? 1 : -1;
+  const int r = geo.r;
+  const T i2dx = T(1.0 / (2.0 * geo.dx)), i2dy = T(1.0 / (2.0 * geo.dy));
+  const T i6dx = T(1.0 / (6.0 * geo.dx)), i6dy = T(1.0 / (6.0 * geo.dy));
+  const T dt = T(geo.dt);
+  auto at = [&](gp<const T> f, int dj, int ii) {
+    int jj = j + dj;
+    jj = jj < 0 ? jj + ny : (jj >= ny ? jj - ny : jj);
+    return f[(size_t)jj * NX + (size_t)(ii & (NX - 1))];
+  };
+  // the sheared sample of row j + k at column i
+  auto samp = [&](gp<const T> f, int k, int i) {
+    return wm * at(f, k, i) + w * at(f, k, i - sg * r * k);
+  };
+  auto up = [&](T a_m2, T a_m1, T a_0, T a_p1, T a_p2, T v, T inv6) {
+    return v > T(0) ? (a_m2 - T(6) * a_m1 + T(3) * a_0 + T(2) * a_p1) * inv6
+                    : (-a_p2 + T(6) * a_p1 - T(3) * a_0 - T(2) * a_m1) * inv6;
+  };
+  const bool fh = geo.f_half != 0;
+  T out_phi[2], out_f[2], out_om[2];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int i = x + e;
+    const T vx = (wm * (at(psi, 1, i) - at(psi, -1, i)) +
+                  w * (at(psi, 1, i - sg * r) - at(psi, -1, i + sg * r))) * i2dy;
+    const T vy = -(at(psi, 0, i + 1) - at(psi, 0, i - 1)) * i2dx;
+    auto adv = [&](gp<const T> f) {
+      const T dx = up(at(f, 0, i - 2), at(f, 0, i - 1), at(f, 0, i), at(f, 0, i + 1),
+                      at(f, 0, i + 2), vx, i6dx);
+      const T dy = up(samp(f, -2, i), samp(f, -1, i), at(f, 0, i), samp(f, 1, i),
+                      samp(f, 2, i), vy, i6dy);
+      return at(f, 0, i) - dt * (vx * dx + vy * dy);
+    };
+    const T h = adv(phi);
+    const T c = fh ? h : at(phi, 0, i);
+    out_phi[e] = h;
+    out_f[e] = c * c * c;
+    out_om[e] = inertial ? adv(om) : T(0);
+  }
+  const size_t o = (size_t)j * NX + x;
+  stg<T>(reinterpret_cast<gp<c2<T>>>(bufp<T>(R, B_TMP) + o), {out_phi[0], out_phi[1]});
+  stg<T>(reinterpret_cast<gp<c2<T>>>(bufp<T>(R, B_R1) + o), {out_f[0], out_f[1]});
+  if (inertial)
+    stg<T>(reinterpret_cast<gp<c2<T>>>(bufp<T>(R, B_R2) + o), {out_om[0], out_om[1]});
+}
+
 // Stage 1a over row strips with the forward row transforms in the same
 // kernel (no real rows written and read back).  The block owns whole rows:
 // NX/(2 SEG) threads, thread t the SEG x pairs t + g NX/(2 SEG), each walked

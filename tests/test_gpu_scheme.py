@@ -30,19 +30,20 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-def run_both(monkeypatch, p, steps, seed, f_half, midpoint_s, adv=None):
+def run_both(monkeypatch, p, steps, seed, f_half, midpoint_s, adv=None, upwind3=False):
     if adv is not None:
         for k, v in zip(KEYS, (adv, 0, 0, 0, 0, 0)):
             monkeypatch.setenv(k, str(v))
     phi0 = inputs.noise_phi0(p["ny"], p["nx"], seed, amp=0.5)
     om0 = inputs.noise_omega0(p["ny"], p["nx"], seed) if p["rho"] > 0 else None
     print(f"case {p['nx']}x{p['ny']} rho={p['rho']} adv={adv} f_half={f_half} "
-          f"midpoint_s={midpoint_s} steps={steps}", flush=True)
+          f"midpoint_s={midpoint_s} upwind3={upwind3} steps={steps}", flush=True)
     with le.Context(p, phi0, om0) as c:
-        c.set_scheme(f_half=f_half, midpoint_s=midpoint_s)
+        c.set_scheme(f_half=f_half, midpoint_s=midpoint_s, upwind3=upwind3)
         c.step(steps)
         g = c.get_state()
-    op = dataclasses.replace(mh.Params(**p), f_half=f_half, midpoint_s=midpoint_s)
+    op = dataclasses.replace(mh.Params(**p), f_half=f_half, midpoint_s=midpoint_s,
+                             upwind3=upwind3)
     st = mh.run(op, mh.initial_state(op, phi0, om0), steps)
     return g, st
 
@@ -81,7 +82,7 @@ def test_scheme_switches_back_and_rejects_unknown_flags():
         c.set_scheme()
         c.step(10)
         g = c.get_state()
-        rc = le.lib().le_set_scheme(c._h, 4)
+        rc = le.lib().le_set_scheme(c._h, 8)
         assert rc == le.LE_EINVAL
     a = mh.Params(**p)
     b = dataclasses.replace(a, f_half=True, midpoint_s=True)
@@ -118,4 +119,37 @@ def test_f_half_batched_advection(monkeypatch, rho, adv):
     p = params(512, 512, rho=rho)
     g, st = run_both(monkeypatch, p, 3, 32, True, False, adv)
     for k in ("phi", "psi") + (("omega",) if rho > 0 else ()):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k
+
+
+@pytest.mark.parametrize("geom", [dict(nx=128, ny=128), dict(nx=256, ny=64, lx=256.0, ly=64.0)])
+@pytest.mark.parametrize("rho", [1.0, 0.0])
+def test_upwind3_matches_the_oracle(monkeypatch, geom, rho):
+    """Third-order upwind advection (square cells, and r = 4 with the sheared
+    samples four columns per row apart), 100 steps across a strain wrap."""
+    p = params(gdot=0.5, rho=rho, **geom)
+    steps = 220 if geom["nx"] == geom["ny"] else 100
+    g, st = run_both(monkeypatch, p, steps, 33, False, False, upwind3=True)
+    if geom["nx"] == geom["ny"]:
+        assert g["wraps"] == st.wraps == 1
+    for k in ("phi", "psi") + (("omega",) if rho > 0 else ()):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k
+
+
+def test_upwind3_with_the_other_switches_and_back(monkeypatch):
+    """All three switches together, then back to the default scheme on the
+    same context (the captured graphs of the other advection are dropped)."""
+    p = params(128, 128, gdot=0.3)
+    phi0 = inputs.noise_phi0(128, 128, 34, amp=0.5)
+    om0 = inputs.noise_omega0(128, 128, 34)
+    with le.Context(p, phi0, om0) as c:
+        c.set_scheme(f_half=True, midpoint_s=True, upwind3=True)
+        c.step(40)
+        c.set_scheme()
+        c.step(40)
+        g = c.get_state()
+    op = dataclasses.replace(mh.Params(**p), f_half=True, midpoint_s=True, upwind3=True)
+    st = mh.run(op, mh.initial_state(op, phi0, om0), 40)
+    st = mh.run(mh.Params(**p), st, 40)
+    for k in ("phi", "omega", "psi"):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
