@@ -32,7 +32,10 @@ Readings taken where the paper is silent (each is listed in the design notes):
   Params.midpoint_s switch to the other readings of the first two: f of the
   advected phi, and s at the step's midpoint; Params.upwind3 takes the
   advected field's derivatives by the third-order upwind differences that
-  Appendix B keeps as a commented-out alternative, sheared like Eq. p1y);
+  Appendix B keeps as a commented-out alternative, sheared like Eq. p1y;
+  Params.banded replaces the y part of the per-mode operators by the central
+  differences of the stencils: Fourier in x only, a cyclic banded system in
+  y per x wavenumber, solved here as such);
 * the q = 0 mode: phi untouched, omega and psi set to zero;
 * at a strain wrap s -> s - c (c = Lx/Ly) the fields are remapped row by row,
   new[j][i] = old[j][(i - r j) mod Nx] with r = Nx/Ny, so the lab-frame field
@@ -78,6 +81,9 @@ class Params:
     f_half: bool = False
     midpoint_s: bool = False
     upwind3: bool = False
+    # x spectral, y by finite differences in the per-mode operators: cyclic
+    # banded (tri-/penta-diagonal) systems per x wavenumber
+    banded: bool = False
 
     @property
     def dx(self) -> float:
@@ -302,12 +308,96 @@ def stage_advect(p: Params, st: State, s: float):
     return phi_h, omega_h, f
 
 
+# ---------------------------------------------------------------------------
+# The banded variant: Fourier in x only, y derivatives of the per-mode
+# operators by the central differences of the stencils (periodic), so each x
+# wavenumber carries a cyclic banded system in y
+# ---------------------------------------------------------------------------
+
+def banded_laplacian(p: Params, m: int, s: float) -> np.ndarray:
+    """The cosheared Laplacian on column m of the x transform, (ny, ny) complex:
+
+        L = -(1 + s^2) qx^2 I + D2 - 2 s (i qx) D1,
+
+    D2 = [1, -2, 1] / dy^2 and D1 = [-1, 0, 1] / (2 dy), cyclic in y (a cyclic
+    tridiagonal matrix); the cross term is dropped on the x Nyquist column, as
+    in the spectral symbol.
+    """
+    qx_all, _, nyq_x, _ = wavenumbers(p)
+    qx = qx_all[m]
+    n = p.ny
+    I = np.eye(n)
+    up = np.roll(I, 1, axis=1)     # (up a)[j] = a[j + 1]
+    dn = np.roll(I, -1, axis=1)    # (dn a)[j] = a[j - 1]
+    D2 = (up - 2.0 * I + dn) / (p.dy * p.dy)
+    D1 = (up - dn) / (2.0 * p.dy)
+    cross = 0.0 if nyq_x[m] else 1.0
+    return -(1.0 + s * s) * qx * qx * I + D2 - cross * 2.0 * s * 1j * qx * D1
+
+
+def _gauged_solve(Lop: np.ndarray, rhs: np.ndarray, m: int) -> np.ndarray:
+    """Solve Lop x = rhs; on column 0 (Lop singular on the constants) the
+    constant part of rhs is dropped and the solution taken with zero mean."""
+    if m != 0:
+        return np.linalg.solve(Lop, rhs)
+    n = len(rhs)
+    J = np.ones((n, n)) / n
+    r = rhs - rhs.mean()
+    return np.linalg.solve(Lop + J, r)
+
+
+def stage_cahn_hilliard_banded(p, phi_h, f, s):
+    """Stage 1b with the banded operators: per column m,
+    (I + dt kM L^2/2) Phi' = (I - dt A M L - dt kM L^2/2) Phi_h + dt B M L F."""
+    Ph = np.fft.fft(phi_h, axis=1)
+    F = np.fft.fft(f, axis=1)
+    out = np.empty_like(Ph)
+    I = np.eye(p.ny)
+    for m in range(p.nx):
+        L = banded_laplacian(p, m, s)
+        L2 = L @ L
+        lhs = I + 0.5 * p.dt * p.kappa * p.M * L2
+        rhs = (I - p.dt * p.A * p.M * L - 0.5 * p.dt * p.kappa * p.M * L2) @ Ph[:, m] \
+            + p.dt * p.B * p.M * (L @ F[:, m])
+        out[:, m] = np.linalg.solve(lhs, rhs)
+    return np.real(np.fft.ifft(out, axis=1))
+
+
+def stage_flow_banded(p, omega_h, g, s):
+    """Stages 2b and 3 with the banded operators: per column m,
+    (I - dt nu L/2) Om' = (I + dt nu L/2) Om_h + dt G,  -L Psi' = Om';
+    rho == 0: L^2 Psi' = G.  The q = 0 mode (column 0's mean) of Om' and Psi'
+    is zero."""
+    G = np.fft.fft(g, axis=1)
+    I = np.eye(p.ny)
+    Psi = np.empty_like(G)
+    if p.rho > 0.0:
+        nu = p.eta / p.rho
+        Om = np.fft.fft(omega_h, axis=1)
+        Om_new = np.empty_like(Om)
+        for m in range(p.nx):
+            L = banded_laplacian(p, m, s)
+            rhs = (I + 0.5 * p.dt * nu * L) @ Om[:, m] + p.dt * G[:, m]
+            o = np.linalg.solve(I - 0.5 * p.dt * nu * L, rhs)
+            if m == 0:
+                o = o - o.mean()
+            Om_new[:, m] = o
+            Psi[:, m] = _gauged_solve(-L, o, m)
+        return np.real(np.fft.ifft(Om_new, axis=1)), np.real(np.fft.ifft(Psi, axis=1))
+    for m in range(p.nx):
+        L = banded_laplacian(p, m, s)
+        Psi[:, m] = _gauged_solve(L @ L, G[:, m], m)
+    return np.zeros_like(omega_h), np.real(np.fft.ifft(Psi, axis=1))
+
+
 def stage_cahn_hilliard(p: Params, phi_h: np.ndarray, f: np.ndarray, s: float) -> np.ndarray:
     """Stage 1b: per-mode update, explicit in nabla^2 and f, Crank-Nicolson in nabla^4.
 
     phi' = phi_h + (1 + dt kM lam^2/2)^-1 (-dt A M lam phi_h - dt kM lam^2 phi_h
                                            + dt B M lam F)
     """
+    if p.banded:
+        return stage_cahn_hilliard_banded(p, phi_h, f, s)
     lam = symbol_laplacian(p, s)
     Ph = fft2(phi_h)
     F = fft2(f)
@@ -331,6 +421,8 @@ def stage_flow(p: Params, omega_h: np.ndarray, g: np.ndarray, s: float):
               Psi' = -Om' / lam.
     rho == 0: Psi' = G / lam^2 (biharmonic solve).  q = 0: Om' = Psi' = 0.
     """
+    if p.banded:
+        return stage_flow_banded(p, omega_h, g, s)
     lam = symbol_laplacian(p, s)
     G = fft2(g)
     zero = np.zeros_like(lam, dtype=bool)

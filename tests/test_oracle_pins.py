@@ -598,3 +598,100 @@ def test_upwind_reduces_to_the_default_without_flow():
     a = mh.run(p, mh.initial_state(p, phi), 40)
     b = mh.run(dataclasses.replace(p, upwind3=True), mh.initial_state(p, phi), 40)
     assert np.array_equal(a.phi, b.phi)
+
+
+# --------- the banded variant (x spectral, y finite differences per mode)
+
+def _fd_symbol(p, m, n, s):
+    """Closed-form eigenvalue of the cyclic banded operator on the plane wave
+    (m, n): -(1+s^2) qx^2 - 4 sin^2(ty/2)/dy^2 + 2 s qx sin(ty)/dy, ty = 2 pi n/ny
+    (the cross term dropped on the x Nyquist column)."""
+    qx = 2 * math.pi * (m if m < p.nx // 2 else m - p.nx) / p.lx
+    ty = 2 * math.pi * n / p.ny
+    cross = 0.0 if m == p.nx // 2 else 2 * s * qx * math.sin(ty) / p.dy
+    return -(1 + s * s) * qx * qx - 4 * math.sin(ty / 2) ** 2 / p.dy ** 2 + cross
+
+
+@pytest.mark.parametrize("gdot", [0.0, 0.05])
+def test_banded_single_mode_growth_factor(gdot):
+    """A small Cahn-Hilliard mode grows by the factor of the closed-form FD
+    symbol each step (plane waves are eigenvectors of circulant operators)."""
+    import dataclasses
+    p = dataclasses.replace(P(nx=32, ny=32, lx=40.0, ly=40.0, gdot=gdot, dt=0.01, kappa=1.3,
+                              M=0.7, A=0.9), banded=True)
+    m, n = 3, 2
+    j, i = np.meshgrid(np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    eps = 1e-6
+    phi0 = eps * np.cos(2 * math.pi * (m * i / p.nx + n * j / p.ny))
+    st = mh.initial_state(p, phi0, np.zeros_like(phi0))
+    amp = eps
+    for k in range(40):
+        lam = _fd_symbol(p, m, n, mh.strain_offset(p, k))
+        amp *= (1 - p.dt * p.A * p.M * lam - 0.5 * p.dt * p.kappa * p.M * lam ** 2) / (
+            1 + 0.5 * p.dt * p.kappa * p.M * lam ** 2)
+        st = mh.step(p, st)
+    got = 2 * np.abs(mh.fft2(st.phi)[n, m]) / (p.nx * p.ny)
+    assert abs(got - abs(amp)) <= 1e-10 * abs(amp)
+
+
+@pytest.mark.parametrize("gdot", [0.0, 0.2])
+def test_banded_kelvin_mode_decay(gdot):
+    import dataclasses
+    p = dataclasses.replace(P(nx=32, ny=32, lx=32.0, ly=32.0, gdot=gdot, dt=0.02, eta=1.5,
+                              rho=2.0), banded=True)
+    m, n = 1, 2
+    j, i = np.meshgrid(np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    eps = 1e-3
+    w0 = eps * np.cos(2 * math.pi * (m * i / p.nx + n * j / p.ny))
+    st = mh.initial_state(p, np.zeros_like(w0), w0)
+    nu = p.eta / p.rho
+    amp = eps
+    for k in range(100):           # strain 0.4 at gdot = 0.2: no wrap
+        lam = _fd_symbol(p, m, n, mh.strain_offset(p, k))
+        amp *= (1 + 0.5 * p.dt * nu * lam) / (1 - 0.5 * p.dt * nu * lam)
+        st = mh.step(p, st)
+    got = 2 * abs(mh.fft2(st.omega)[n, m]) / (p.nx * p.ny)
+    assert abs(got - amp) <= 1e-12 * amp + 1e-15
+
+
+@pytest.mark.parametrize("s", [0.0, 0.5, -0.5, 0.3])
+def test_banded_poisson_solve_inverts_the_fd_laplacian(s):
+    """The banded solve's psi satisfies L psi = -omega with L applied
+    independently: spectral x derivatives, periodic y differences by np.roll."""
+    import dataclasses
+    p = dataclasses.replace(P(nx=32, ny=16, lx=32.0, ly=16.0, dt=0.0), banded=True)
+    w = inputs.noise_omega0(p.ny, p.nx, 5)
+    w -= w.mean()
+    om, psi = mh.stage_flow(p, w, np.zeros_like(w), s)
+    kx = 2 * math.pi * np.fft.fftfreq(p.nx, d=p.dx)
+    kx_odd = kx.copy()
+    kx_odd[p.nx // 2] = 0.0
+
+    def dx(a, k):
+        return np.real(np.fft.ifft(np.fft.fft(a, axis=1) * k[None, :], axis=1))
+    psi_xx = dx(psi, -(kx ** 2))
+    psi_yy = (np.roll(psi, -1, 0) - 2 * psi + np.roll(psi, 1, 0)) / p.dy ** 2
+    psi_y = (np.roll(psi, -1, 0) - np.roll(psi, 1, 0)) / (2 * p.dy)
+    psi_xy = np.real(np.fft.ifft(np.fft.fft(psi_y, axis=1) * (1j * kx_odd)[None, :], axis=1))
+    lap = (1 + s * s) * psi_xx + psi_yy - 2 * s * psi_xy
+    assert np.max(np.abs(om - w)) <= 1e-14
+    assert np.max(np.abs(lap + w)) <= 1e-12 * np.max(np.abs(w))
+
+
+def test_banded_scheme_converges_to_the_spectral_one():
+    """At fixed T the banded scheme's difference from the spectral one shrinks
+    as delta^2 (the order of the y differences), and the mean is kept."""
+    import dataclasses
+    T = 0.4
+    d = []
+    for nn in (16, 32, 64):
+        p = P(nx=nn, ny=nn, lx=8.0, ly=8.0, gdot=0.3, kappa=0.5, M=0.5,
+              dt=0.4 * (8.0 / nn) ** 2 / 4)
+        q = dataclasses.replace(p, banded=True)
+        phi, om = smooth_init(p)
+        a = mh.run(p, mh.initial_state(p, phi, om), int(round(T / p.dt)))
+        b = mh.run(q, mh.initial_state(q, phi, om), int(round(T / q.dt)))
+        assert abs(b.phi.mean() - phi.mean()) <= 1e-14
+        d.append(np.max(np.abs(a.phi - b.phi)) + np.max(np.abs(a.omega - b.omega)))
+    orders = [math.log2(d[k] / d[k + 1]) for k in range(2)]
+    assert all(abs(o - 2.0) < 0.3 for o in orders), (orders, d)
