@@ -169,10 +169,24 @@ int le_set_recovery(le_ctx* c, int enable);
  *                         local velocity (d_y psi, -d_x psi); the y samples
  *                         are sheared as in Eq. p1y (weight |s|/c on the
  *                         column r k cells along the grid diagonal for row
- *                         j + k).  The derivatives of psi stay central.
+ *                         j + k).  The derivatives of psi stay central;
+ *   LE_SCHEME_BANDED      the per-mode operators of stages 1b, 2b and 3 with
+ *                         their y part by the stencils' central differences
+ *                         (Fourier in x only): per x wavenumber a cyclic
+ *                         tridiagonal system (omega, Poisson) or
+ *                         pentadiagonal one (Cahn-Hilliard, Stokes) in y.
+ *                         Their coefficients do not depend on y, so the
+ *                         column transform diagonalizes them: the solves are
+ *                         per-mode divisions by the banded operators'
+ *                         eigenvalues (the observables stay spectral).
  * Takes effect from the next step; flags outside these bits: LE_EINVAL.
  */
-enum { LE_SCHEME_F_HALF = 1, LE_SCHEME_MIDPOINT_S = 2, LE_SCHEME_UPWIND3 = 4 };
+enum {
+  LE_SCHEME_F_HALF = 1,
+  LE_SCHEME_MIDPOINT_S = 2,
+  LE_SCHEME_UPWIND3 = 4,
+  LE_SCHEME_BANDED = 8
+};
 int le_set_scheme(le_ctx* c, int32_t flags);
 
 /*

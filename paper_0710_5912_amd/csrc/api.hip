@@ -121,6 +121,7 @@ Geo make_geo(const le_params& p) {
   g.r = p.nx >= p.ny ? p.nx / p.ny : 0;
   g.f_half = 0;
   g.upwind3 = 0;
+  g.banded = 0;
   g.lx = p.lx;
   g.ly = p.ly;
   g.dx = p.lx / p.nx;
@@ -1435,7 +1436,9 @@ int le_set_recovery(le_ctx* c, int enable) {
 }
 
 int le_set_scheme(le_ctx* c, int32_t flags) {
-  if (!c || (flags & ~(LE_SCHEME_F_HALF | LE_SCHEME_MIDPOINT_S | LE_SCHEME_UPWIND3)) != 0)
+  if (!c ||
+      (flags & ~(LE_SCHEME_F_HALF | LE_SCHEME_MIDPOINT_S | LE_SCHEME_UPWIND3 | LE_SCHEME_BANDED)) !=
+          0)
     return LE_EINVAL;
   // every run of the engine (one for a context, all of a batch)
   c->midpoint_s = (flags & LE_SCHEME_MIDPOINT_S) != 0;
@@ -1458,6 +1461,7 @@ int le_set_scheme(le_ctx* c, int32_t flags) {
   for (RunHost& r : c->runs) {
     r.g.f_half = (flags & LE_SCHEME_F_HALF) ? 1 : 0;
     r.g.upwind3 = up ? 1 : 0;
+    r.g.banded = (flags & LE_SCHEME_BANDED) ? 1 : 0;
     h[r.internal].g = r.g;
   }
   LE_TRY(hipStreamSynchronize(c->stream));

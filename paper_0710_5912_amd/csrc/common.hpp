@@ -12,6 +12,7 @@ struct Geo {
   int r;          // nx / ny: x offset in cells of the sheared y stencil
   int f_half;     // 1: f = (phi_h)^3 from the advected phi instead of (phi^n)^3
   int upwind3;    // 1: third-order upwind differences of the advected fields
+  int banded;     // 1: y part of the per-mode operators by central differences
   double lx, ly, dx, dy, c;   // c = lx / ly, the sawtooth jump
   double A, B, kappa, M, eta, rho, dt;
   double kx0, ky0;   // 2 pi / lx, 2 pi / ly (wavenumber quanta)

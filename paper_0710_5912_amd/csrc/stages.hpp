@@ -189,6 +189,24 @@ __device__ __forceinline__ double lambda_of(const Modes& q, double s) {
   return D + 2.0 * s * q.P;
 }
 
+// The banded scheme switch: the same operator with its y part by the central
+// differences of the stencils, i.e. the eigenvalue of the cyclic banded
+// operator of column m on the y wave n:
+//   -(1 + s^2) qx^2 - 4 sin^2(pi n / ny) / dy^2 + 2 s qx sin(2 pi n / ny) / dy,
+// the cross term dropped on the x Nyquist column (the y Nyquist row has
+// sin = 0).  Solving the cyclic tri-/penta-diagonal systems of each column
+// is the per-mode division by this value (the DFT along y diagonalizes
+// them: their coefficients do not depend on y).
+__device__ __forceinline__ double lambda_banded(const Geo& g, int m, int n, double s) {
+  const int ms = (m >= g.nx / 2) ? m - g.nx : m;
+  const double qx = g.kx0 * (double)ms;
+  double sh, ch, s2, c2;
+  sincospi((double)n / (double)g.ny, &sh, &ch);        // sin, cos(pi n / ny)
+  sincospi(2.0 * (double)n / (double)g.ny, &s2, &c2);  // sin, cos(2 pi n / ny)
+  const double cross = (m == g.nx / 2) ? 0.0 : 2.0 * s * qx * s2 / g.dy;
+  return -((1.0 + s * s) * qx * qx) - 4.0 * sh * sh / (g.dy * g.dy) + cross;
+}
+
 // ---------------------------------------------------------------- row kernels
 
 // Forward row transforms: blockIdx.y picks the job (real buffer bin, row
@@ -1401,7 +1419,7 @@ __global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void
   for (int q = 0; q < C::E; ++q) {
     const int n = t + q * C::P;
     const Modes md = modes(geo, m, n);
-    const double lam = lambda_of(md, s);
+    const double lam = geo.banded ? lambda_banded(geo, m, n, s) : lambda_of(md, s);
     const bool zero = (m == 0 && n == 0);
     const double a0x = (double)v0[q].x, a0y = (double)v0[q].y;
     if constexpr (MODE == COL_CH) {

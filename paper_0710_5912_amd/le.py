@@ -15,7 +15,7 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmodelh.so")
 
 LE_OK, LE_EINVAL, LE_ENOMEM, LE_EDEVICE, LE_ENONFINITE, LE_ESTATE = 0, -1, -2, -3, -4, -5
-LE_SCHEME_F_HALF, LE_SCHEME_MIDPOINT_S, LE_SCHEME_UPWIND3 = 1, 2, 4
+LE_SCHEME_F_HALF, LE_SCHEME_MIDPOINT_S, LE_SCHEME_UPWIND3, LE_SCHEME_BANDED = 1, 2, 4, 8
 LE_FP64, LE_FP32 = 0, 1
 
 SYMBOLS = ("le_create", "le_step", "le_step_noalloc", "le_checkpoint_size",
@@ -265,12 +265,12 @@ class Context:
             raise LeError(rc, "le_set_recovery")
 
     def set_scheme(self, f_half: bool = False, midpoint_s: bool = False,
-                   upwind3: bool = False) -> None:
+                   upwind3: bool = False, banded: bool = False) -> None:
         """Scheme variants (le_set_scheme): f of the advected phi, and/or the
         sawtooth at the step's midpoint."""
         self._check()
         flags = ((LE_SCHEME_F_HALF if f_half else 0) | (LE_SCHEME_MIDPOINT_S if midpoint_s else 0)
-                 | (LE_SCHEME_UPWIND3 if upwind3 else 0))
+                 | (LE_SCHEME_UPWIND3 if upwind3 else 0) | (LE_SCHEME_BANDED if banded else 0))
         rc = lib().le_set_scheme(self._h, flags)
         if rc != LE_OK:
             raise LeError(rc, "le_set_scheme")
@@ -459,10 +459,10 @@ class Batch:
         self._keep_om = None
 
     def set_scheme(self, f_half: bool = False, midpoint_s: bool = False,
-                   upwind3: bool = False) -> None:
+                   upwind3: bool = False, banded: bool = False) -> None:
         """Scheme variants for every run (le_batch_set_scheme)."""
         flags = ((LE_SCHEME_F_HALF if f_half else 0) | (LE_SCHEME_MIDPOINT_S if midpoint_s else 0)
-                 | (LE_SCHEME_UPWIND3 if upwind3 else 0))
+                 | (LE_SCHEME_UPWIND3 if upwind3 else 0) | (LE_SCHEME_BANDED if banded else 0))
         rc = lib().le_batch_set_scheme(self._h, flags)
         if rc != LE_OK:
             raise LeError(rc, "le_batch_set_scheme")

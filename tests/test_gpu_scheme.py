@@ -30,7 +30,8 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-def run_both(monkeypatch, p, steps, seed, f_half, midpoint_s, adv=None, upwind3=False):
+def run_both(monkeypatch, p, steps, seed, f_half, midpoint_s, adv=None, upwind3=False,
+             banded=False):
     if adv is not None:
         for k, v in zip(KEYS, (adv, 0, 0, 0, 0, 0)):
             monkeypatch.setenv(k, str(v))
@@ -39,11 +40,11 @@ def run_both(monkeypatch, p, steps, seed, f_half, midpoint_s, adv=None, upwind3=
     print(f"case {p['nx']}x{p['ny']} rho={p['rho']} adv={adv} f_half={f_half} "
           f"midpoint_s={midpoint_s} upwind3={upwind3} steps={steps}", flush=True)
     with le.Context(p, phi0, om0) as c:
-        c.set_scheme(f_half=f_half, midpoint_s=midpoint_s, upwind3=upwind3)
+        c.set_scheme(f_half=f_half, midpoint_s=midpoint_s, upwind3=upwind3, banded=banded)
         c.step(steps)
         g = c.get_state()
     op = dataclasses.replace(mh.Params(**p), f_half=f_half, midpoint_s=midpoint_s,
-                             upwind3=upwind3)
+                             upwind3=upwind3, banded=banded)
     st = mh.run(op, mh.initial_state(op, phi0, om0), steps)
     return g, st
 
@@ -82,7 +83,7 @@ def test_scheme_switches_back_and_rejects_unknown_flags():
         c.set_scheme()
         c.step(10)
         g = c.get_state()
-        rc = le.lib().le_set_scheme(c._h, 8)
+        rc = le.lib().le_set_scheme(c._h, 16)
         assert rc == le.LE_EINVAL
     a = mh.Params(**p)
     b = dataclasses.replace(a, f_half=True, midpoint_s=True)
@@ -151,5 +152,27 @@ def test_upwind3_with_the_other_switches_and_back(monkeypatch):
     op = dataclasses.replace(mh.Params(**p), f_half=True, midpoint_s=True, upwind3=True)
     st = mh.run(op, mh.initial_state(op, phi0, om0), 40)
     st = mh.run(mh.Params(**p), st, 40)
+    for k in ("phi", "omega", "psi"):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k
+
+
+@pytest.mark.parametrize("geom", [dict(nx=64, ny=64), dict(nx=128, ny=32, lx=128.0, ly=32.0)])
+@pytest.mark.parametrize("rho", [1.0, 0.0])
+def test_banded_matches_the_oracle(monkeypatch, geom, rho):
+    """The banded scheme (cyclic banded y systems per x wavenumber, solved
+    densely by the oracle) against the GPU's per-mode division by the banded
+    operators' eigenvalues, 100 steps; the square case crosses a wrap."""
+    p = params(gdot=0.5 if geom["nx"] == geom["ny"] else 0.2, rho=rho, **geom)
+    steps = 220 if geom["nx"] == geom["ny"] else 100
+    g, st = run_both(monkeypatch, p, steps, 35, False, False, banded=True)
+    if geom["nx"] == geom["ny"]:
+        assert g["wraps"] == st.wraps == 1
+    for k in ("phi", "psi") + (("omega",) if rho > 0 else ()):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k
+
+
+def test_all_four_switches_together(monkeypatch):
+    p = params(64, 64, gdot=0.3)
+    g, st = run_both(monkeypatch, p, 60, 36, True, True, upwind3=True, banded=True)
     for k in ("phi", "omega", "psi"):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
