@@ -32,7 +32,7 @@ namespace {
 
 constexpr int64_t kChunkCap = 1024;  // steps per host chunk
 constexpr int64_t kProfChunk = 256;  // steps per chunk while stage timing is on
-constexpr int kRealBlocks = 256;     // blocks of the real-space reduction
+constexpr int kRealBlocks = 1024;    // blocks of the real-space reduction
 constexpr int64_t kGraphMin = 8;     // shortest chunk worth capturing
 constexpr int64_t kGraphChunk = 128; // longest captured chunk (longer graphs replay slower)
 constexpr size_t kGraphCacheMax = 16;  // holds every power-of-two piece of both step kinds
@@ -187,6 +187,7 @@ struct le_ctx {
   double* d_rpart = nullptr;
   double* d_bins = nullptr;
   double* d_counts = nullptr;
+  double* d_gsum = nullptr;      // shell group sums, then group weights
   double* d_out = nullptr;
   double* h_out = nullptr;
   int nsblk_max = 0, nbins_max = 0;
@@ -250,7 +251,8 @@ void release(Engine* e) {
     if (r.twx) (void)hipFree(r.twx);
     if (r.twy) (void)hipFree(r.twy);
   }
-  void* dev[] = {e->d_desc, e->d_args, e->d_spart, e->d_rpart, e->d_bins, e->d_counts, e->d_out};
+  void* dev[] = {e->d_desc,   e->d_args,   e->d_spart, e->d_rpart,
+                 e->d_bins,   e->d_counts, e->d_gsum,  e->d_out};
   for (void* d : dev)
     if (d) (void)hipFree(d);
   if (e->h_args) (void)hipHostFree(e->h_args);
@@ -563,7 +565,7 @@ int reduce_observables(Engine* e, const RunHost& r, bool spectral) {
   }
   o.obs_real(desc(e, r), B_PHI, e->d_rpart, kRealBlocks, e->stream);
   launch_obs_final(e->d_spart, nsblk, e->d_rpart, kRealBlocks, e->d_bins, e->d_counts,
-                   spectral ? nbins : 0, e->d_out, e->stream);
+                   spectral ? nbins : 0, e->d_gsum, e->d_out, e->stream);
   LE_TRY(hipGetLastError());
   const size_t nout = OBS_NTOTAL + (spectral ? 2 * (size_t)nbins : 0);
   LE_TRY(hipMemcpyAsync(e->h_out, e->d_out, nout * sizeof(double), hipMemcpyDeviceToHost,
@@ -852,6 +854,8 @@ int create_engine(int32_t n, const le_params* ps, const double* const* phi0s,
   rc = rc ? rc : alloc((void**)&e->d_bins, (size_t)e->nsblk_max * e->nbins_max * sizeof(double));
   rc = rc ? rc : alloc((void**)&e->d_counts,
                        (size_t)e->nsblk_max * e->nbins_max * sizeof(double));
+  rc = rc ? rc : alloc((void**)&e->d_gsum, 2 * (size_t)obs_shell_groups(e->nsblk_max) *
+                                               e->nbins_max * sizeof(double));
   rc = rc ? rc : alloc((void**)&e->d_out, nout * sizeof(double));
   if (!rc && hipHostMalloc((void**)&e->h_args, sizeof(StepArgs) * kChunkCap * n) != hipSuccess)
     rc = LE_ENOMEM;
@@ -1375,7 +1379,7 @@ int step_noalloc(const le_params* pp, double* phi, double* omega, double* psi, i
   else
     k.ops.row_c2r(d, 1, p.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1, k.row_variant, st);
   k.ops.obs_real(d, B_PHI, rpart, kRealBlocks, st);
-  launch_obs_final(nullptr, 0, rpart, kRealBlocks, nullptr, nullptr, 0, out, st);
+  launch_obs_final(nullptr, 0, rpart, kRealBlocks, nullptr, nullptr, 0, nullptr, out, st);
   LE_TRY(hipGetLastError());
   double bad = 0.0;
   LE_TRY(hipMemcpyAsync(&bad, out + OBS_NONFINITE, sizeof(double), hipMemcpyDeviceToHost, st));

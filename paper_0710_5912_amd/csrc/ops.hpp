@@ -78,8 +78,12 @@ bool get_ops(int precision, int nx, int ny, Ops* ops);
 bool get_ops_f64(int nx, int ny, Ops* ops);
 bool get_ops_f32(int nx, int ny, Ops* ops);
 
+// Final reductions of the observables' partials into out (OBS_NTOTAL sums,
+// then nbins shell sums, then nbins shell weights); gsum: scratch of
+// 2 obs_shell_groups(nsblk) nbins doubles (unused when nbins == 0).
 void launch_obs_final(const double* spart, int nsblk, const double* rpart, int nrblk,
-                      const double* bins, const double* counts, int nbins, double* out,
-                      hipStream_t st);
+                      const double* bins, const double* counts, int nbins, double* gsum,
+                      double* out, hipStream_t st);
+int obs_shell_groups(int nsblk);
 
 }  // namespace le

@@ -1514,13 +1514,12 @@ __global__ __launch_bounds__(ObsCfg<L>::THREADS) LE_OCCUPANCY void k_obs_spectra
   constexpr int NBT = (NB + C::THREADS - 1) / C::THREADS;
   constexpr int NE = C::CW * L;
   constexpr size_t LDS_BYTES = (size_t)NE * sizeof(c2<T>);
-  constexpr size_t BIN_BYTES = (size_t)NE * (2 * sizeof(double) + sizeof(int));
+  constexpr size_t BIN_BYTES = (size_t)NE * (sizeof(double) + sizeof(int));
   __shared__ __attribute__((aligned(16))) unsigned char raw[LDS_BYTES > BIN_BYTES ? LDS_BYTES : BIN_BYTES];
   c2<T>* lds = reinterpret_cast<c2<T>*>(raw);
   double* bval = reinterpret_cast<double*>(raw);
-  double* bwgt = bval + NE;
-  int* bidx = reinterpret_cast<int*>(bwgt + NE);
-  __shared__ double red[C::THREADS];
+  int* bidx = reinterpret_cast<int*>(bval + NE);
+  __shared__ double red[OBS_NSPEC * ((C::THREADS + 63) / 64)];
 
   const int S = geo.nx / 2 + 1;
   const int c = threadIdx.x % C::CW, t = threadIdx.x / C::CW;
@@ -1572,19 +1571,25 @@ __global__ __launch_bounds__(ObsCfg<L>::THREADS) LE_OCCUPANCY void k_obs_spectra
     const bool inb = (bin >= 1 && bin <= NB && wgt > 0.0);
     bidx[e] = inb ? bin : 0;
     bval[e] = inb ? wS : 0.0;
-    bwgt[e] = inb ? wgt : 0.0;
     LE_SCHED_FENCE();
   }
-  // fixed-order block reduction of each sum
+  // fixed-order block reduction of each sum: a butterfly across each
+  // wavefront (DPP/permute shuffles, no barrier), then the wavefront sums in
+  // wavefront order
+  constexpr int NW = (C::THREADS + 63) / 64;
+  constexpr int WS = C::THREADS < 64 ? C::THREADS : 64;
+#pragma unroll
   for (int k = 0; k < OBS_NSPEC; ++k) {
-    red[threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int w = C::THREADS / 2; w >= 1; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) part[(size_t)blockIdx.x * OBS_NSPEC + k] = red[0];
-    __syncthreads();
+    double v = acc[k];
+#pragma unroll
+    for (int off = WS / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, WS);
+    if ((threadIdx.x & 63) == 0) red[k * NW + (threadIdx.x >> 6)] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < OBS_NSPEC) {
+    double v = 0.0;
+    for (int w = 0; w < NW; ++w) v += red[threadIdx.x * NW + w];
+    part[(size_t)blockIdx.x * OBS_NSPEC + threadIdx.x] = v;
   }
   // Shells: thread owns shells b = 1 + tid + k * THREADS.  For each column
   // the modes of shell b lie in at most two runs of n (|q_lab| is a parabola
@@ -1601,23 +1606,24 @@ __global__ __launch_bounds__(ObsCfg<L>::THREADS) LE_OCCUPANCY void k_obs_spectra
       for (int cc = 0; cc < C::CW; ++cc) {
         const int mc = xcd_block(blockIdx.x, gridDim.x) * C::CW + cc;
         if (mc >= S) break;
-        // the Nyquist row (and the whole Nyquist column) drop the cross
-        // term: they are checked outright
+        // the Nyquist row drops the cross term: it is checked outright; the
+        // Nyquist column (no cross term either) has |q_lab|^2 =
+        // (1 + s^2) qx^2 + qy^2, bracketed about qy = 0
+        // a mode's weight is its column's (1 on the DC and Nyquist columns, 2
+        // on the others: each stands for its conjugate too)
+        const double wcol = (mc == 0 || mc == geo.nx / 2) ? 1.0 : 2.0;
         auto take = [&](int n) {
           const int e = n * C::CW + cc;
-          if (bidx[e] == b) { sb += bval[e]; cb += bwgt[e]; }
+          if (bidx[e] == b) { sb += bval[e]; cb += wcol; }
         };
-        if (mc == geo.nx / 2) {
-          for (int n = 0; n < ny; ++n) take(n);
-          continue;
-        }
         take(ny / 2);
+        const bool nyq = mc == geo.nx / 2;
         const Modes md = modes(geo, mc, 0);
-        const double qx2 = md.qx * md.qx;
+        const double qx2 = md.qx * md.qx * (nyq ? 1.0 + s * s : 1.0);
         if (qhi * qhi <= qx2 * (1.0 - 1e-12)) continue;
         const double a = sqrt(fmax(0.0, qlo * qlo - qx2));
         const double c2v = sqrt(fmax(0.0, qhi * qhi - qx2));
-        const double sh = s * md.qx;
+        const double sh = nyq ? 0.0 : s * md.qx;
         int lo1 = (int)floor((-c2v + sh) * rad) - 2, hi1 = (int)ceil((-a + sh) * rad) + 2;
         int lo2 = (int)floor((a + sh) * rad) - 2, hi2 = (int)ceil((c2v + sh) * rad) + 2;
         if (lo2 <= hi1 + 1) { hi1 = hi2; lo2 = 1; hi2 = 0; }   // the runs touch: merge
@@ -1635,31 +1641,40 @@ __global__ __launch_bounds__(ObsCfg<L>::THREADS) LE_OCCUPANCY void k_obs_spectra
   }
 }
 
-// Real-space partial sums: sum phi, sum phi^2 (FP64) and the non-finite count.
+// Real-space partial sums: sum phi, sum phi^2 (FP64) and the non-finite
+// count.  Block b sums its contiguous slice (pairs of values per load), each
+// thread in a fixed order, then a butterfly within each wavefront and the four
+// wavefront sums in order: deterministic.
 template <typename T>
 __global__ __launch_bounds__(256) void k_obs_real(const Run* __restrict__ run, int bphi,
                                                   double* __restrict__ part) {
-  __shared__ double red[3][256];
-  auto phi = bufp<const T>(*run, bphi);
-  const size_t n = (size_t)run->g.nx * run->g.ny;
+  __shared__ double red[3][4];
+  auto phi = reinterpret_cast<gp<const c2<T>>>(bufp<const T>(*run, bphi));
+  const size_t n = (size_t)run->g.nx * run->g.ny / 2;  // pairs (nx is even)
   const size_t per = (n + gridDim.x - 1) / gridDim.x;
   const size_t lo = blockIdx.x * per, hi = lo + per < n ? lo + per : n;
   double a = 0.0, b = 0.0, bad = 0.0;
   for (size_t e = lo + threadIdx.x; e < hi; e += 256) {
-    const double x = (double)phi[e];
-    if (isfinite(x)) { a += x; b += x * x; } else { bad += 1.0; }
+    const c2<T> v = ldg<T>(phi + e);
+    const double x0 = (double)v.x, x1 = (double)v.y;
+    if (isfinite(x0)) { a += x0; b += x0 * x0; } else { bad += 1.0; }
+    if (isfinite(x1)) { a += x1; b += x1 * x1; } else { bad += 1.0; }
   }
-  red[0][threadIdx.x] = a;
-  red[1][threadIdx.x] = b;
-  red[2][threadIdx.x] = bad;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+    bad += __shfl_xor(bad, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+    red[2][threadIdx.x >> 6] = bad;
+  }
   __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x < 3) part[(size_t)blockIdx.x * 3 + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 3)
+    part[(size_t)blockIdx.x * 3 + threadIdx.x] =
+        ((red[threadIdx.x][0] + red[threadIdx.x][1]) + red[threadIdx.x][2]) + red[threadIdx.x][3];
 }
 
 }  // namespace le
