@@ -284,7 +284,12 @@ int le_time_stage(le_ctx* c, int32_t stage, int32_t reps, double* ms_per_launch)
  * environment variables LE_TUNE_ADV, LE_TUNE_MU, LE_TUNE_COL_CH,
  * LE_TUNE_COL_FLOW, LE_TUNE_ROW and LE_TUNE_ROW_FWD, when set, fix the
  * corresponding variant at creation (LE_TUNE_LOG=1 prints every candidate's
- * time to stderr).
+ * time to stderr).  The choices are cached per (device, nx, ny, precision,
+ * inertia, runs in the group) for the life of the process, so later
+ * contexts and batches of the same shape take the same kernels (and give the
+ * same results) without re-timing; LE_TUNE_CACHE=<file> also keeps them in
+ * that text file across processes, LE_TUNE_CACHE=off times every creation
+ * afresh.  Choices fixed through LE_TUNE_* are not cached.
  */
 enum { LE_TUNING_FIELDS = 10 };
 int le_tuning(le_ctx* c, int32_t* out, int32_t cap);

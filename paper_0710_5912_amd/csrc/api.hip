@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -687,14 +688,99 @@ int pick(Engine* e, hipEvent_t a, hipEvent_t b, const int (&cand)[N], const char
   return LE_OK;
 }
 
+// Tuning cache: the choices of every (device, nx, ny, precision, inertia,
+// runs in the class) tuned so far in this process, so later contexts of the
+// same shape take the same kernels (equal results, no re-timing); with
+// LE_TUNE_CACHE=<file> also kept on disk across processes (one line per
+// entry: the key's six integers, then the six variants).  LE_TUNE_CACHE=off
+// re-times every context.  Variants fixed by LE_TUNE_* still apply.
+struct TuneEntry {
+  int key[6];
+  int val[6];  // advect, mu_source, column_ch, column_flow, row, row_fwd
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+const char* tune_cache_path() {
+  const char* p = std::getenv("LE_TUNE_CACHE");
+  return (p && p[0] && std::strcmp(p, "off") != 0) ? p : nullptr;
+}
+bool tune_cache_off() {
+  const char* p = std::getenv("LE_TUNE_CACHE");
+  return p && std::strcmp(p, "off") == 0;
+}
+
+void tune_key(const Class& k, int dev, int* key) {
+  const int v[6] = {dev, k.nx, k.ny, k.prec, k.inertial ? 1 : 0, (int)k.members.size()};
+  std::memcpy(key, v, sizeof(v));
+}
+
+// Caller holds g_tune_mu.
+void tune_cache_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  TuneEntry t;
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d", &t.key[0], &t.key[1], &t.key[2],
+                     &t.key[3], &t.key[4], &t.key[5], &t.val[0], &t.val[1], &t.val[2],
+                     &t.val[3], &t.val[4], &t.val[5]) == 12)
+    g_tune.push_back(t);
+  std::fclose(f);
+}
+
+bool tune_cache_find(const int* key, int* val) {
+  for (const TuneEntry& t : g_tune)
+    if (std::memcmp(t.key, key, sizeof(t.key)) == 0) {
+      std::memcpy(val, t.val, sizeof(t.val));
+      return true;
+    }
+  return false;
+}
+
+void tune_cache_add(const int* key, const int* val) {
+  TuneEntry t;
+  std::memcpy(t.key, key, sizeof(t.key));
+  std::memcpy(t.val, val, sizeof(t.val));
+  g_tune.push_back(t);
+  const char* path = tune_cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d\n", key[0], key[1], key[2], key[3], key[4],
+               key[5], val[0], val[1], val[2], val[3], val[4], val[5]);
+  std::fclose(f);
+}
+
 int autotune(Engine* e) {
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
     if (a) (void)hipEventDestroy(a);
     return LE_EDEVICE;
   }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const bool cache = !tune_cache_off();
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  if (cache) tune_cache_load();
   int rc = LE_OK;
   for (Class& k : e->classes) {
+    int key[6], val[6];
+    tune_key(k, dev, key);
+    if (cache && tune_cache_find(key, val)) {
+      const char* envs[6] = {"LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH",
+                             "LE_TUNE_COL_FLOW", "LE_TUNE_ROW", "LE_TUNE_ROW_FWD"};
+      int* dst[6] = {&k.adv_variant, &k.mu_variant, &k.col_ch_variant,
+                     &k.col_flow_variant, &k.row_variant, &k.row_fwd_variant};
+      for (int i = 0; i < 6; ++i) {
+        const int forced = env_variant(envs[i]);
+        *dst[i] = forced >= 0 ? forced : val[i];
+      }
+      continue;
+    }
     const Run* d = e->d_desc + k.first;
     const int n = (int)k.members.size();
     const StepArgs* sa = e->d_args + k.first;
@@ -727,6 +813,16 @@ int autotune(Engine* e) {
       else
         k.ops.column(COL_STOKES, d, n, k.nx, sa, B_GH, B_GH, B_PHIN, B_PHIN, v, st);
     });
+    if (!rc && cache) {
+      // only choices the timing made are shared (not ones fixed by LE_TUNE_*)
+      const char* envs[6] = {"LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH",
+                             "LE_TUNE_COL_FLOW", "LE_TUNE_ROW", "LE_TUNE_ROW_FWD"};
+      bool forced = false;
+      for (const char* v : envs) forced = forced || env_variant(v) >= 0;
+      const int got[6] = {k.adv_variant, k.mu_variant, k.col_ch_variant, k.col_flow_variant,
+                          k.row_variant, k.row_fwd_variant};
+      if (!forced) tune_cache_add(key, got);
+    }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);

@@ -193,3 +193,27 @@ def test_batched_advection_non_square_cells(monkeypatch, combo):
     g, st = run_forced(monkeypatch, p, 20, 29, combo)
     for k in ("phi", "omega", "psi"):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
+
+
+def test_tuning_cache_gives_equal_kernels_and_results(tmp_path, monkeypatch):
+    """Contexts of one shape created in one process take the cached choices of
+    the first (equal results bit for bit); LE_TUNE_CACHE writes them to a file
+    that a later process would read."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("LE_TUNE_CACHE", str(cache))
+    p = params(128, 16, gdot=0.2, lx=128.0, ly=16.0)   # a shape no other test tunes (FP32)
+    phi0 = inputs.noise_phi0(16, 128, 41, amp=0.5)
+    with le.Context(p, phi0, precision="fp32") as a, le.Context(p, phi0, precision="fp32") as b:
+        assert a.tuning() == b.tuning()
+        a.step(30)
+        b.step(30)
+        ga, gb = a.get_state(), b.get_state()
+    for k in ("phi", "omega", "psi"):
+        assert np.array_equal(ga[k], gb[k]), k
+    lines = cache.read_text().split("\n")
+    rec = [list(map(int, l.split())) for l in lines if l.strip()]
+    with le.Context(p, phi0, precision="fp32") as c:
+        t = c.tuning()[0]
+    assert any(r[1:6] == [128, 16, 1, 1, 1] and
+               r[6:] == [t["advect"], t["mu_source"], t["column_ch"], t["column_flow"],
+                         t["row"], t["row_fwd"]] for r in rec), rec
