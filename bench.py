@@ -538,6 +538,29 @@ def main():
                  f"against the fine field restricted to the coarse grid; audited: the "
                  f"corrected run with a 20-step corrected-vs-plain audit every 500 steps "
                  f"(L_s tolerance 2%)")
+        evp = corrector.evaluate(cp, cs, gdot=0.01, seed=99, log=lambda m: None, projection=1)
+        var["corrector_256_from_1024"]["projection_1"] = dict(
+            value=evp["corrected_fine_equiv_rate"], gain=evp["gain"],
+            L_err_mean=evp["err_mean_corrected"], L_err_max=evp["err_max_corrected"],
+            Sk_low_err_mean=evp["Sk_low_err_mean_corrected"],
+            Sk_high_err_mean=evp["Sk_high_err_mean_corrected"],
+            note="the same run with the phi residual's interpolated 16 x 16 tile means "
+                 "subtracted instead of its mean")
+        print("bench: variant corrector at 4096^2 / 1024^2", file=sys.stderr, flush=True)
+        ev5 = corrector.evaluate(cp, cs, gdot=0.001, seed=99, t_end=100.0, n=4096,
+                                 log=lambda m: None)
+        var["corrector_1024_from_4096_extrapolation"] = dict(
+            value=ev5["corrected_fine_equiv_rate"], plain_fine_value=ev5["fine_rate"],
+            gain=ev5["gain"], L_err_mean=ev5["err_mean_corrected"],
+            L_err_mean_plain_coarse=ev5["err_mean_coarse"],
+            Sk_low_err_mean=ev5["Sk_low_err_mean_corrected"],
+            Sk_low_err_mean_plain_coarse=ev5["Sk_low_err_mean_coarse"],
+            Sk_high_err_mean=ev5["Sk_high_err_mean_corrected"],
+            Sk_high_err_mean_plain_coarse=ev5["Sk_high_err_mean_coarse"],
+            note="the network trained on 1024^2 -> 256^2 data (gdot 0.003 .. 0.03) applied to "
+                 "a 4096^2 FP64 run restricted to 1024^2 (4 dt coarse steps) at gdot = 0.001, "
+                 "t = 20 .. 100, seed 99: an extrapolation in system size and shear rate; "
+                 "fine-equivalent rate = 4096^2 sites x fine steps / corrected wall time")
         print("bench: variant corrector ensemble", file=sys.stderr, flush=True)
         var["corrector_ensemble_8_seeds"] = corrector_ensemble(corrector, cp, cs)
         out["variants"] = var

@@ -346,6 +346,12 @@ void le_batch_destroy(le_batch* b);  /* NULL-safe */
  */
 int le_corrector_load(le_ctx* c, const float* params, int32_t nparams, const float* scales);
 int le_step_corrected(le_ctx* c, int64_t ncoarse);
+/* le_corrector_projection: mode 0 (the default) subtracts the mean of the
+ * phi residual (above); mode 1 subtracts its 16 x 16 tile means, interpolated
+ * bilinearly between the tile centres (periodic), which keeps the mean exact
+ * and takes out the residual's content at scales beyond a tile.  LE_EINVAL
+ * for other modes, or mode 1 when nx or ny is not a multiple of 16. */
+int le_corrector_projection(le_ctx* c, int32_t mode);
 
 int le_restrict(le_ctx* c, int32_t factor, double* phi_out, double* omega_out);
 int le_set_fields(le_ctx* c, const double* phi, const double* omega, int64_t step);

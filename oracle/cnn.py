@@ -143,3 +143,30 @@ def restrict4(a):
     """4 x 4 block mean (fine grid -> coarse grid); conserves the mean."""
     H, W = a.shape
     return a.reshape(H // 4, 4, W // 4, 4).mean(axis=(1, 3))
+
+
+def tile_mean_field(a, ft=16):
+    """The tile-mean field of a periodic plane a (H x W, both multiples of ft):
+    the means of its ft x ft tiles, placed at the tile centres
+    (ft t + (ft - 1) / 2 in pixel units) and interpolated bilinearly between
+    neighbouring centres, periodically.  The corrector subtracts this field from
+    its phi residual in projection mode 1 (in mode 0 it subtracts the plain
+    mean): the field has the same total as a, so the corrected phi keeps its
+    mean, and it carries a's content at scales beyond a tile."""
+    H, W = a.shape
+    ty, tx = H // ft, W // ft
+    tm = a.reshape(ty, ft, tx, ft).mean(axis=(1, 3))
+    out = np.empty((H, W))
+    for y in range(H):
+        v = (y + 0.5) / ft - 0.5
+        j0 = int(np.floor(v))
+        fy = v - j0
+        ja, jb = j0 % ty, (j0 + 1) % ty
+        for x in range(W):
+            u = (x + 0.5) / ft - 0.5
+            i0 = int(np.floor(u))
+            fx = u - i0
+            ia, ib = i0 % tx, (i0 + 1) % tx
+            out[y, x] = ((1 - fy) * ((1 - fx) * tm[ja, ia] + fx * tm[ja, ib])
+                         + fy * ((1 - fx) * tm[jb, ia] + fx * tm[jb, ib]))
+    return out

@@ -138,7 +138,7 @@ def train(xs, ts, epochs=20, batch=16, lr=1e-3, seed=0, log=print):
 
 
 def evaluate(params, scales, gdot=0.01, seed=99, t0=T_START, t_end=T_END, every=5.0, n=FINE_N,
-             factor=FACTOR, log=print, audit=None):
+             factor=FACTOR, log=print, audit=None, projection=0):
     """L(t) of the plain fine run, of its restriction to the coarse grid, of the
     corrected coarse run and of the plain coarse run, all from the same
     restricted state at t0, with wall times.  audit = (every, window, tol)
@@ -180,6 +180,7 @@ def evaluate(params, scales, gdot=0.01, seed=99, t0=T_START, t_end=T_END, every=
         c.set_fields(phi_c, om_c, k0 // factor)
         if name != "coarse":
             c.corrector_load(params, scales)
+            c.corrector_projection(projection)
         if name == "audited":
             c.corrector_audit(*audit)
         torch.cuda.synchronize()

@@ -210,6 +210,7 @@ struct le_ctx {
   int64_t audit_every = 0, audit_window = 0, since_audit = 0, audits = 0;
   double audit_tol = 0.0, audit_dev = 0.0;
   bool corr_fallback = false;
+  int corr_proj = 0;        // le_corrector_projection
   bool midpoint_s = false;  // LE_SCHEME_MIDPOINT_S
   bool recovery = false;    // le_set_recovery
   void* snap[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
@@ -1141,7 +1142,7 @@ int corrected_steps(Engine* e, int64_t ncoarse) {
                                            static_cast<const float*>(r.buf[B_OM_R]), e->stream);
         if (rc) return (int)LE_EDEVICE;
         const CorrArgs ca{net_z_out(e->net), net_partials(e->net), net_tiles(e->net),
-                          e->net->scales[2], e->net->scales[3]};
+                          e->net->scales[2], e->net->scales[3], e->corr_proj};
         o.row_r2c_corr(d, r.p.ny, ca, e->classes[r.cls].row_fwd_variant, e->stream);
         o.column(COL_POISSON, d, 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0, e->stream);
         return (int)LE_OK;
@@ -1846,6 +1847,25 @@ int le_corrector_load(le_ctx* c, const float* params, int32_t nparams, const flo
 }
 
 int le_step_corrected(le_ctx* c, int64_t ncoarse) { return step_corrected(c, ncoarse); }
+
+int le_corrector_projection(le_ctx* c, int32_t mode) {
+  if (!c || (mode != 0 && mode != 1)) return LE_EINVAL;
+  if (mode == 1 && (c->runs[0].p.nx % 16 || c->runs[0].p.ny % 16)) return LE_EINVAL;
+  if (c->corr_proj != mode) {
+    // captured corrected chunks hold the projection as a launch argument
+    for (auto it = c->graphs.begin(); it != c->graphs.end();) {
+      if (it->first < 0) {
+        (void)hipGraphExecDestroy(it->second.second);
+        (void)hipGraphDestroy(it->second.first);
+        it = c->graphs.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  c->corr_proj = mode;
+  return LE_OK;
+}
 
 int le_corrector_audit(le_ctx* c, int64_t every, int64_t window, double tol) {
   return corrector_audit(c, every, window, tol);

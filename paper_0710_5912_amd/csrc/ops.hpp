@@ -18,6 +18,8 @@ struct CorrArgs {
   const double* part;
   int nblk;
   float s2, s3;
+  int proj;  // 0: subtract the mean of z_phi; 1: subtract its tile means,
+             // interpolated bilinearly between the 16 x 16 tile centres
 };
 
 // Advect variants from kStripFft on: kStripFft + k = the strip stencil over

@@ -292,12 +292,31 @@ __global__ __launch_bounds__((RowCfg<L, E, GDIV>::THREADS)) LE_OCCUPANCY void k_
 #pragma unroll
   for (int k = 0; k < NW; ++k) total += wred[k];
   const double mean = total / ((double)ny * (double)(2 * L));
+  // with ca.proj, the subtracted field is the tile means of z_phi
+  // interpolated bilinearly between the tile centres (periodic): it sums to
+  // the same total, and it removes the residual's content at scales beyond a
+  // tile
+  constexpr int FT = 16;
+  const int tx = 2 * L / FT, ty = ny / FT;
+  auto tile_mean = [&](int x) {
+    const double u = (x + 0.5) / FT - 0.5, w = (ok ? j : 0) + 0.5;
+    const double vv = w / FT - 0.5;
+    const int i0 = (int)floor(u), j0 = (int)floor(vv);
+    const double fx = u - i0, fy = vv - j0;
+    const int ia = (i0 + tx) % tx, ib = (i0 + 1) % tx;
+    const int ja = (j0 + ty) % ty, jb = (j0 + 1) % ty;
+    const double inv = 1.0 / (FT * FT);
+    return inv * ((1.0 - fy) * ((1.0 - fx) * ca.part[ja * tx + ia] + fx * ca.part[ja * tx + ib]) +
+                  fy * ((1.0 - fx) * ca.part[jb * tx + ia] + fx * ca.part[jb * tx + ib]));
+  };
   c2<T> v[C::E];
 #pragma unroll
   for (int q = 0; q < C::E; ++q) {
     const size_t m = row + t + q * C::P;
-    const c2<T> fn = {(T)((double)f[q].x + (double)ca.s2 * ((double)zq[q].x - mean)),
-                      (T)((double)f[q].y + (double)ca.s2 * ((double)zq[q].z - mean))};
+    const int x0 = 2 * (t + q * C::P);
+    const double m0 = ca.proj ? tile_mean(x0) : mean, m1 = ca.proj ? tile_mean(x0 + 1) : mean;
+    const c2<T> fn = {(T)((double)f[q].x + (double)ca.s2 * ((double)zq[q].x - m0)),
+                      (T)((double)f[q].y + (double)ca.s2 * ((double)zq[q].z - m1))};
     v[q] = {(T)((double)w[q].x + (double)ca.s3 * (double)zq[q].y),
             (T)((double)w[q].y + (double)ca.s3 * (double)zq[q].w)};
     if (ok) {

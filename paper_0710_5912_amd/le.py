@@ -18,7 +18,7 @@ LE_OK, LE_EINVAL, LE_ENOMEM, LE_EDEVICE, LE_ENONFINITE, LE_ESTATE = 0, -1, -2, -
 LE_SCHEME_F_HALF, LE_SCHEME_MIDPOINT_S, LE_SCHEME_UPWIND3, LE_SCHEME_BANDED = 1, 2, 4, 8
 LE_FP64, LE_FP32 = 0, 1
 
-SYMBOLS = ("le_create", "le_step", "le_step_noalloc", "le_checkpoint_size",
+SYMBOLS = ("le_create", "le_step", "le_corrector_projection", "le_step_noalloc", "le_checkpoint_size",
            "le_checkpoint_save", "le_checkpoint_load", "le_observables", "le_destroy", "le_get_state",
            "le_set_state", "le_strerror", "le_profile", "le_stage_times", "le_last_error",
            "le_batch_create", "le_batch_step", "le_batch_observables", "le_batch_get_state",
@@ -108,6 +108,8 @@ def lib():
         L.le_checkpoint_save.restype = C.c_int
         L.le_checkpoint_load.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
         L.le_checkpoint_load.restype = C.c_int
+        L.le_corrector_projection.argtypes = [C.c_void_p, C.c_int32]
+        L.le_corrector_projection.restype = C.c_int
         L.le_step_noalloc.argtypes = [C.POINTER(LeParams), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_int64, C.c_int64]
         L.le_step_noalloc.restype = C.c_int
@@ -370,6 +372,13 @@ class Context:
                                      sc.ctypes.data_as(C.POINTER(C.c_float)))
         if rc != LE_OK:
             raise LeError(rc, "le_corrector_load")
+
+    def corrector_projection(self, mode: int) -> None:
+        """0: subtract the phi residual's mean; 1: its interpolated tile means."""
+        self._check()
+        rc = lib().le_corrector_projection(self._h, int(mode))
+        if rc != LE_OK:
+            raise LeError(rc, "le_corrector_projection")
 
     def step_corrected(self, ncoarse: int) -> None:
         self._check()

@@ -97,3 +97,47 @@ def test_restriction_conserves_mean():
     assert c.shape == (8, 4)
     assert abs(c.mean() - a.mean()) <= 1e-15
     assert abs(c[1, 2] - a[4:8, 8:12].mean()) <= 1e-15
+
+
+def test_tile_mean_field_constant_total_and_subtile_content():
+    """A constant plane is reproduced; the total is kept (so the corrected phi
+    keeps its mean); content that averages to zero over every 16 x 16 tile
+    (a period-16 cosine along x, a period-8 one along y) gives zero."""
+    assert np.allclose(cnn.tile_mean_field(np.full((32, 48), 0.37)), 0.37, atol=1e-15, rtol=0)
+    a = np.random.default_rng(7).standard_normal((48, 32))
+    assert abs(cnn.tile_mean_field(a).sum() - a.sum()) <= 1e-11
+    y, x = np.mgrid[0:32, 0:64]
+    sub = np.cos(2 * np.pi * x / 16) + np.sin(2 * np.pi * y / 8 + 0.3)
+    assert np.max(np.abs(cnn.tile_mean_field(sub))) <= 1e-13
+
+
+def test_tile_mean_field_hat_is_centred_and_oriented():
+    """One tile at 1, the rest at 0 (48 x 32, so rows and columns differ): the
+    result is the product of two hats centred on the tile's centre 7.5 in
+    both axes, symmetric about it, reaching the neighbouring tiles' centres
+    (23.5) at zero, with the tile's own pixels 7 and 8 at (1 - 1/32)^2."""
+    a = np.zeros((48, 32))
+    a[16:32, 0:16] = 1.0                       # tile row 1, tile column 0
+    f = cnn.tile_mean_field(a)
+    assert abs(f[23, 7] - (1 - 1 / 32) ** 2) <= 1e-15
+    assert abs(f[24, 8] - (1 - 1 / 32) ** 2) <= 1e-15
+    for d in range(8):
+        assert abs(f[23 - d, 7] - f[24 + d, 7]) <= 1e-15
+        assert abs(f[23, 7 - d] - f[23, 8 + d]) <= 1e-15
+    assert np.all(f[40:48, :] == 0.0) and np.all(f[0:8, :] == 0.0)   # rows beyond the hat
+    # periodic in x (two tiles wide): column 31 lies 8.5 from the centre across
+    # the wrap, as column 16 does on the other side
+    assert abs(f[23, 31] - f[23, 16]) <= 1e-15 and f[23, 31] > 0.0
+
+
+def test_tile_mean_field_second_order_on_smooth_planes():
+    """On a smooth periodic plane the field converges to the plane itself at
+    second order in the tile size over the wavelength (a midpoint mean plus
+    linear interpolation)."""
+    errs = []
+    for n in (256, 512, 1024):
+        y, x = np.mgrid[0:n // 4, 0:n]
+        a = np.sin(2 * np.pi * x / n + 0.4) + 0.5 * np.cos(2 * np.pi * y / (n // 4))
+        errs.append(np.max(np.abs(cnn.tile_mean_field(a) - a)))
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 3.5 <= e0 / e1 <= 4.5, errs
