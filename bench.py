@@ -120,17 +120,44 @@ def run_variant(le, torch, params, precision, steps, warmup, obs_every, seed=0,
     return out
 
 
+def _batch_nr_ef(v):
+    return (2, 16) if v >= 256 else (2, 8) if v >= 192 else (4, 16)
+
+
+def batch_fits(v, nx):
+    """The batched form applies: at least one wavefront per transform group."""
+    nr, ef = _batch_nr_ef(v)
+    return nr * (nx // 2 // ef) >= 64
+
+
+def batch_shape(v):
+    nr, ef = _batch_nr_ef(v)
+    return "%d rows per batch, %d values per thread" % (nr, ef)
+
+
 def stage_kernels(tuning, inertial):
     """Kernels each stage launches under the autotuned variants."""
-    a = tuning["advect"]
-    fused_strip = a >= 64 and 256 <= tuning["nx"] <= 1024
-    adv = ("k_bracket" if a == 0 else
-           ("k_adv_strip_fft" if fused_strip else "k_adv_strip + k_row_r2c"))
+    a, nx = tuning["advect"], tuning["nx"]
+    if a == 0:
+        adv = "k_bracket"
+    elif a == 1024:
+        adv = "k_adv_upwind + k_row_r2c"
+    elif a >= 128 and 512 <= nx <= 4096 and batch_fits(a, nx):
+        adv = "k_adv_batch (%s)" % batch_shape(a)
+    elif 64 <= a < 128 and 256 <= nx <= 1024:
+        adv = "k_adv_strip_fft"
+    else:
+        adv = "k_adv_strip + k_row_r2c"
     sq = tuning["nx"] == tuning["ny"]
     m = tuning["mu_source"]
-    mu = ("k_mu + k_bracket" if m == 0 or not sq else
-          ("k_mug_strip_fft" if m >= 64 and 256 <= tuning["nx"] <= 2048
-           else "k_mug_strip + k_row_r2c"))
+    if m == 0 or not sq:
+        mu = "k_mu + k_bracket"
+    elif m >= 128 and 512 <= nx <= 4096 and batch_fits(m, nx):
+        mu = "k_mug_batch (%s)" % batch_shape(m)
+    elif 64 <= m < 128 and 256 <= nx <= 2048:
+        mu = "k_mug_strip_fft"
+    else:
+        mu = "k_mug_strip + k_row_r2c"
     return {"row_inv_flow": "k_row_c2r", "advect": adv, "column_ch": "k_column<COL_CH>",
             "row_inv_phi": "k_row_c2r", "mu_source": mu,
             "column_flow": "k_column<COL_FLOW>" if inertial else "k_column<COL_STOKES>"}

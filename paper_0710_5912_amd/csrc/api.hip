@@ -634,8 +634,12 @@ constexpr int kRowCand[] = {0, 1, 2, 3, 4, 5};
 constexpr int kAdvCand[] = {0,  2,  4,  8,  16, 32, kStripFft + 2, kStripFft + 4,
                              kStripFft + 8, kStripFft1 + 2, kStripFft1 + 4, kStripFft1 + 8,
                              kAdvBatch + 4, kAdvBatch + 8, kAdvBatch + 16,
-                             kAdvBatch2 + 2, kAdvBatch2 + 4, kAdvBatch2 + 8};
-constexpr int kMuCand[] = {0, 2, 4, 8, 16, 32, kStripFft + 2, kStripFft + 4, kStripFft + 8};
+                             kAdvBatch2 + 2, kAdvBatch2 + 4, kAdvBatch2 + 8,
+                             kAdvBatch3 + 2, kAdvBatch3 + 4, kAdvBatch3 + 8};
+constexpr int kMuCand[] = {0, 2, 4, 8, 16, 32, kStripFft + 2, kStripFft + 4, kStripFft + 8,
+                            kAdvBatch + 4, kAdvBatch + 8, kAdvBatch + 16,
+                            kAdvBatch2 + 2, kAdvBatch2 + 4, kAdvBatch2 + 8,
+                            kAdvBatch3 + 2, kAdvBatch3 + 4, kAdvBatch3 + 8};
 constexpr int kColCand[] = {0, 1, 2, 3, 4};
 
 int env_variant(const char* name) {

@@ -26,10 +26,12 @@ struct CorrArgs {
 // k-row strips with the row transforms in the same kernel, two x pairs per
 // thread; kStripFft1 + k the same with one pair per thread.
 constexpr int kStripFft = 64, kStripFft1 = 96;
-// Advect variants kAdvBatch + k and kAdvBatch2 + k: the batched one-kernel
-// form over k-row strips in batches of four or two rows (nx 512 .. 4096;
-// elsewhere the two-kernel strip over k rows).
-constexpr int kAdvBatch = 128, kAdvBatch2 = 192;
+// Advect and mu_source variants kAdvBatch + k, kAdvBatch2 + k and
+// kAdvBatch3 + k: the batched one-kernel form over k-row strips in batches of
+// four rows (16 values per thread in the row transforms), two rows (8) or two
+// rows (16) (nx 512 .. 4096 with at least one wavefront per transform group,
+// mu_source on square cells; elsewhere the two-kernel strip over k rows).
+constexpr int kAdvBatch = 128, kAdvBatch2 = 192, kAdvBatch3 = 256;
 // Advect variant kAdvUpwind: the third-order upwind differences of the scheme
 // switch LE_SCHEME_UPWIND3 (stencil kernel, then the forward row transforms).
 constexpr int kAdvUpwind = 1024;

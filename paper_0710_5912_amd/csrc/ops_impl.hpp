@@ -129,20 +129,44 @@ struct RowLaunch {
       hipLaunchKernelGGL((k_adv_strip_fft<T, NX, false, SEG>), gf, dim3(L / SEG), 0, st, runs,
                          sa, rows, inertial ? 1 : 0);
   }
-  // NR rows per batch; 16 values per thread in the four-row transforms
-  // (fewer threads, more registers each), 8 in the two-row ones
-  template <int NR>
-  static void adv_batch(const Run* runs, const StepArgs* sa, int ny, dim3 gb, int rows,
-                        bool inertial, hipStream_t st) {
-    constexpr int NX = 2 * L, EF = NR == 4 ? 16 : 8;
-    if constexpr (adv_batch_ok(NX)) {
+  // The batched one-kernel forms (advect, and mu_source on square cells):
+  // NR rows per batch, EF values per thread in the row transforms.  Returns
+  // false where the shape does not apply to this row length (fewer than one
+  // wavefront per transform group, or a row outside nx 512 .. 4096).
+  template <int NR, int EF>
+  static bool batch_shape(bool mu, const Run* runs, const StepArgs* sa, int ny, dim3 gb,
+                          int rows, bool inertial, hipStream_t st) {
+    constexpr int NX = 2 * L;
+    if constexpr (adv_batch_ok(NX) && NR * (NX / 2 / EF) >= 64) {
       using CB = AdvBatch<T, NX, NR, EF>;
-      if (ny == NX)
+      if (mu)
+        hipLaunchKernelGGL((k_mug_batch<T, NX, NR, EF>), gb, dim3(CB::TPB), 0, st, runs, sa,
+                           rows);
+      else if (ny == NX)
         hipLaunchKernelGGL((k_adv_batch<T, NX, true, NR, EF>), gb, dim3(CB::TPB), 0, st, runs,
                            sa, rows, inertial ? 1 : 0);
       else
         hipLaunchKernelGGL((k_adv_batch<T, NX, false, NR, EF>), gb, dim3(CB::TPB), 0, st,
                            runs, sa, rows, inertial ? 1 : 0);
+      return true;
+    }
+    return false;
+  }
+  // variant kAdvBatch + k (four rows per batch, 16 values per thread),
+  // kAdvBatch2 + k (two, 8), kAdvBatch3 + k (two, 16); k rows per block.
+  // False (and *rows set) where the shape does not apply: the caller falls
+  // back to the two-kernel strip over k rows.
+  static bool batch(bool mu, const Run* runs, int nruns, const StepArgs* sa, int ny,
+                    int variant, bool inertial, hipStream_t st, int* rows) {
+    const int base = variant >= kAdvBatch3   ? kAdvBatch3
+                     : variant >= kAdvBatch2 ? kAdvBatch2
+                                             : kAdvBatch;
+    *rows = variant - base > 0 ? variant - base : 1;
+    const dim3 gb(1, (ny + *rows - 1) / *rows, nruns);
+    switch (base) {
+      case kAdvBatch3: return batch_shape<2, 16>(mu, runs, sa, ny, gb, *rows, inertial, st);
+      case kAdvBatch2: return batch_shape<2, 8>(mu, runs, sa, ny, gb, *rows, inertial, st);
+      default: return batch_shape<4, 16>(mu, runs, sa, ny, gb, *rows, inertial, st);
     }
   }
   // variant 0: the fused bracket kernel (stencil and row transform per
@@ -170,17 +194,9 @@ struct RowLaunch {
       return;
     }
     if (variant >= kAdvBatch) {
-      const bool four = variant < kAdvBatch2;
-      const int rows = variant - (four ? kAdvBatch : kAdvBatch2);
-      if constexpr (adv_batch_ok(NX)) {
-        const dim3 gb(1, (ny + rows - 1) / rows, nruns);
-        if (four)
-          adv_batch<4>(runs, sa, ny, gb, rows, inertial, st);
-        else
-          adv_batch<2>(runs, sa, ny, gb, rows, inertial, st);
-        return;
-      }
-      variant = rows;  // grids outside the batched kernel's range: the two-kernel form
+      int rows = 0;
+      if (batch(false, runs, nruns, sa, ny, variant, inertial, st, &rows)) return;
+      variant = rows;  // shapes outside the batched kernel's range: the two-kernel form
     }
     if (variant >= kStripFft) {
       const bool two = variant < kStripFft1;
@@ -209,7 +225,9 @@ struct RowLaunch {
   // its row transform; variant 0 < k < kStripFft (square cells only): the
   // strip stencil (mu in registers) over k-row strips into B_GH, then its
   // in-place row transform; kStripFft + k: the same strips with the row
-  // transforms in one kernel (nx 256 .. 2048; elsewhere the two-kernel form)
+  // transforms in one kernel (nx 256 .. 2048; elsewhere the two-kernel form);
+  // kAdvBatch + k .. kAdvBatch1 + k: the batched one-kernel forms over k-row
+  // strips (as for advect; elsewhere the two-kernel form)
   static void mu_source(const Run* runs, int nruns, int ny, const StepArgs* sa, int variant,
                         int row_variant, hipStream_t st) {
     constexpr int NX = 2 * L, TPB = strip_threads(NX);
@@ -219,6 +237,11 @@ struct RowLaunch {
       Jobs jobs{{{JOB_SOURCE, B_PHI, B_TMP, B_GH}, {}, {}}};
       bracket(runs, nruns, ny, sa, jobs, 1, st);
       return;
+    }
+    if (variant >= kAdvBatch) {
+      int rows = 0;
+      if (batch(true, runs, nruns, sa, ny, variant, false, st, &rows)) return;
+      variant = rows;  // shapes outside the batched kernel's range: the two-kernel form
     }
     if (variant >= kStripFft) {
       const int rows = variant - kStripFft;

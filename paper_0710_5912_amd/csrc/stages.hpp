@@ -1273,6 +1273,93 @@ __global__ __launch_bounds__(NX / 2) void k_mug_strip_fft(const Run* __restrict_
   }
 }
 
+// Stage 2a for long rows (square cells) in batches of NR rows, with the
+// forward row transform of g in the same kernel: the batched layout of
+// k_adv_batch (NR transform groups of L/EF threads; the block walks its strip
+// NR rows at a time, each batch one x segment of pairs after another).  For
+// a segment a thread requests its x pair of the phi rows j0-2 .. j0+NR+1 at
+// once, forms mu on rows j0-1 .. j0+NR in registers (the k_mug_strip
+// neighbourhoods) and g on the NR rows into LDS; the NR rows are then
+// transformed (group g row g), staged in LDS and stored tile by tile as
+// k_adv_batch stores them (B_GH).  The phi halo rows are read again by the
+// neighbouring batch (from the L2); nothing goes through the real scratch.
+template <typename T, int NX, int NR, int EF_>
+__global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_mug_batch(
+    const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int rows) {
+  using C = AdvBatch<T, NX, NR, EF_>;
+  constexpr int L = C::L, EF = C::EF, PF = C::PF, TPB = C::TPB, LS = L + 1;
+  __shared__ c2<T> buf[NR * LS];
+  const BPos bp = block_pos();
+  const Run& R = runs[bp.z];
+  const Geo& geo = R.g;
+  const int ny = geo.ny;
+  const int jb0 = bp.y * rows;
+  const int jb1 = min(jb0 + rows, ny);
+  auto phi = bufp<const T>(R, B_PHI);
+  auto out = bufp<c2<T>>(R, B_GH);
+  auto tw = to_global<const c2<double>>(R.twx);
+  const double s = sa[bp.z].s;
+  const MuCoef<T> k = {T((1.0 + s * s) / (geo.dx * geo.dx)), T(1.0 / (geo.dy * geo.dy)),
+                       T(-2.0 * s / (4.0 * geo.dx * geo.dy)), T(geo.A), T(geo.B), T(geo.kappa)};
+  const Stencil<T> st = make_stencil<T>(geo, s);
+  const T neg_inv = T(-1.0 / (geo.rho > 0.0 ? geo.rho : geo.eta));
+  const int grp = threadIdx.x / PF, tt = threadIdx.x % PF;
+  auto row = [&](int j) {
+    j = j % ny;
+    return phi + (size_t)(j < 0 ? j + ny : j) * NX;
+  };
+  for (int j0 = jb0; j0 < jb1; j0 += NR) {
+    __syncthreads();  // the previous batch's LDS reads are done
+#pragma unroll 1
+    for (int g = 0; g < C::SEG; ++g) {
+      const StripLanes<T, NX, TPB> sl(g);
+      RawPhi<T> rp[NR + 4];  // rows j0-2 .. j0+NR+1, requested at once
+#pragma unroll
+      for (int kk = 0; kk < NR + 4; ++kk) rp[kk] = load_phi(row(j0 - 2 + kk), sl);
+      PhiRow<T> F1 = to_phirow(rp[1], sl), F2 = to_phirow(rp[2], sl), F3 = to_phirow(rp[3], sl);
+      Quad<T> Mm = mu_quad(k, to_phirow(rp[0], sl), F1, F2, sl);  // mu rows j0-1, j0
+      Quad<T> Mc = mu_quad(k, F1, F2, F3, sl);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        // window: F1 = phi(j-1), F2 = phi(j), F3 = phi(j+1), j = j0 + r
+        const int j = j0 + r;
+        const PhiRow<T> F4 = to_phirow(rp[r + 4], sl);
+        const Quad<T> Mp = mu_quad(k, F2, F3, F4, sl);  // mu(j+1)
+        T px0, px1, py0, py1, mx0, mx1, my0, my1;
+        quad_dx(F2.q, st.inv2dx, px0, px1);
+        quad_dys<T, NX, true>(F3.q, F1.q, row(j + 1), row(j - 1), sl.x, st, py0, py1);
+        quad_dx(Mc, st.inv2dx, mx0, mx1);
+        quad_dys<T, NX, true>(Mp, Mm, row(j + 1), row(j - 1), sl.x, st, my0, my1);
+        buf[r * L + sl.x / 2] = {neg_inv * (px0 * my0 - py0 * mx0),
+                                 neg_inv * (px1 * my1 - py1 * mx1)};
+        F1 = F2; F2 = F3; F3 = F4;
+        Mm = Mc; Mc = Mp;
+      }
+    }
+    __syncthreads();
+    c2<T> v[EF];
+#pragma unroll
+    for (int q = 0; q < EF; ++q) v[q] = buf[grp * L + tt + q * PF];
+    __syncthreads();
+    row_r2c<T, L, EF>(v, buf + grp * L, tw, tt);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < EF; ++q) buf[grp * LS + tt + q * PF] = v[q];
+    __syncthreads();
+    const int nr = min(NR, jb1 - j0);
+    const int run = kTW * nr;
+    const int total = (L / kTW + 1) * run;
+    for (int e = threadIdx.x; e < total; e += TPB) {
+      const int kk = e / run, w = e % run;
+      const int r = w / kTW, m = kk * kTW + w % kTW;
+      if (m > L) continue;
+      const c2<T> a = buf[r * LS + (m == L ? 0 : m)];
+      const c2<T> val = m == 0 ? c2<T>{a.x, T(0)} : (m == L ? c2<T>{a.y, T(0)} : a);
+      stg<T>(out + spec_index(ny, j0 + r, m), val);
+    }
+  }
+}
+
 // Chemical potential (Eq. mu, stage 2a) on x pairs into a real field:
 //   mu = B phi^3 - A phi - kappa [(1+s^2) Dxx + Dyy - 2 s Dxy] phi.
 template <typename T, int L>

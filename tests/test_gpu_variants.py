@@ -23,12 +23,17 @@ KEYS = ("LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH", "LE_TUNE_COL_FLOW", "LE_T
 # transforms alike
 # (advect, mu_source, column_ch, column_flow, row)
 # advect 64 + k / 96 + k, mu_source 64 + k: strip stencil and row transforms
-# in one kernel (k-row strips; advect with two / one x pairs per thread)
+# in one kernel (k-row strips; advect with two / one x pairs per thread);
+# advect and mu_source 128 + k / 192 + k / 256 + k: the batched one-kernel
+# forms (k-row strips in batches of four / two / two rows; at 512 the two-row
+# 16-value form falls back to the strips)
 COMBOS = [(0, 0, 0, 0, 0), (4, 4, 1, 1, 1), (32, 32, 2, 2, 2), (8, 16, 3, 3, 3),
           (2, 2, 0, 0, 1), (66, 4, 0, 1, 2), (72, 8, 2, 0, 0), (100, 2, 1, 3, 0),
           (98, 66, 0, 0, 3), (4, 68, 1, 1, 0), (100, 72, 3, 2, 1), (8, 8, 4, 4, 4),
           (68, 68, 4, 3, 5), (4, 4, 2, 4, 5), (132, 4, 0, 3, 5), (136, 68, 4, 4, 4),
-          (160, 8, 3, 0, 0), (194, 4, 4, 3, 5), (200, 68, 0, 1, 2)]
+          (160, 8, 3, 0, 0), (194, 4, 4, 3, 5), (200, 68, 0, 1, 2),
+          (132, 132, 0, 0, 0), (196, 196, 3, 3, 5), (136, 144, 1, 2, 4), (4, 194, 4, 4, 1),
+          (68, 200, 2, 1, 3), (258, 260, 0, 3, 5), (264, 258, 1, 1, 2)]
 
 
 def params(nx, ny, **kw):
@@ -83,7 +88,7 @@ def test_variants_512_fp64(monkeypatch, combo, rho):
 
 @pytest.mark.parametrize("combo", [(4, 4, 1, 3, 1), (32, 8, 3, 2, 3), (68, 4, 0, 0, 1),
                                    (98, 8, 2, 1, 2), (66, 68, 1, 1, 2), (8, 4, 4, 4, 4), (16, 8, 3, 4, 5),
-                                   (144, 8, 0, 2, 4)])
+                                   (144, 8, 0, 2, 4), (132, 136, 0, 2, 4), (194, 196, 3, 3, 3)])
 def test_variants_512_fp32(monkeypatch, combo):
     """FP32 shapes (16 values per thread in shapes 2 and 3) within the FP32 bound."""
     p = params(512, 512)
@@ -130,8 +135,9 @@ def test_autotuner_reports_valid_choices():
     assert len(t) == 1
     t = t[0]
     assert (t["nx"], t["ny"], t["precision"], t["inertial"]) == (256, 256, 0, 1)
-    assert t["advect"] in (0, 2, 4, 8, 16, 32, 66, 68, 72, 98, 100, 104)
-    assert t["mu_source"] in (0, 2, 4, 8, 16, 32, 66, 68, 72)
+    batched = (132, 136, 144, 194, 196, 200, 258, 260, 264)
+    assert t["advect"] in (0, 2, 4, 8, 16, 32, 66, 68, 72, 98, 100, 104) + batched
+    assert t["mu_source"] in (0, 2, 4, 8, 16, 32, 66, 68, 72) + batched
     assert t["column_ch"] in range(5) and t["column_flow"] in range(5) and t["row"] in range(6)
     assert t["row_fwd"] in range(6)
 
@@ -181,6 +187,18 @@ def test_row_shapes_at_4096_point_rows(monkeypatch, row, adv):
     the batched one-kernel advection."""
     p = params(4096, 16, gdot=0.05)
     g, st = run_forced(monkeypatch, p, 3, 28, (adv, 8, 0, 0, row))
+    for k in ("phi", "omega", "psi"):
+        assert rel(g[k], getattr(st, k)) <= 1e-10, k
+
+
+@pytest.mark.parametrize("n,combo", [(1024, (132, 132, 3, 3, 5)), (1024, (196, 200, 2, 2, 4)),
+                                     (1024, (258, 260, 0, 0, 0)), (2048, (136, 136, 3, 3, 5)),
+                                     (2048, (260, 258, 0, 3, 5))])
+def test_batched_mu_source_long_rows(monkeypatch, n, combo):
+    """The batched one-kernel advect and mu_source forms at 1024^2 and 2048^2
+    (FP64, two steps) against the oracle, every field."""
+    p = params(n, n, gdot=0.01)
+    g, st = run_forced(monkeypatch, p, 2, 30, combo)
     for k in ("phi", "omega", "psi"):
         assert rel(g[k], getattr(st, k)) <= 1e-10, k
 
