@@ -166,7 +166,14 @@ struct Class {
   int row_fwd_variant = 0;   // Ops::row_r2c (forward row transforms, also of the
                              // two-kernel stencil stages)
   bool upwind3 = false;      // LE_SCHEME_UPWIND3: the upwind advection kernel
+  bool banded = false;       // LE_SCHEME_BANDED: the banded column kernels
   int advect() const { return upwind3 ? kAdvUpwind : adv_variant; }
+  // Ops::column with the banded flag of the scheme
+  void column(int mode, const Run* runs, int nruns, int nx, const StepArgs* sa, int bin0,
+              int bin1, int bout0, int bout1, int variant, hipStream_t st) const {
+    ops.column(mode | (banded ? COL_BANDED : 0), runs, nruns, nx, sa, bin0, bin1, bout0, bout1,
+               variant, st);
+  }
   std::vector<int> members;  // run ids
   int first = 0;             // internal index of members[0]
 };
@@ -329,11 +336,11 @@ int solve_psi(Engine* e, const RunHost& r) {
   const Class& k = e->classes[r.cls];
   const StepArgs* sa = e->d_args + r.internal;
   if (r.inertial) {
-    k.ops.column(COL_POISSON, desc(e, r), 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0,
+    k.column(COL_POISSON, desc(e, r), 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0,
                  e->stream);
   } else {
     k.ops.mu_source(desc(e, r), 1, r.p.ny, sa, k.mu_variant, k.row_fwd_variant, e->stream);
-    k.ops.column(COL_STOKES, desc(e, r), 1, r.p.nx, sa, B_GH, B_GH, B_PS_S, B_PS_S,
+    k.column(COL_STOKES, desc(e, r), 1, r.p.nx, sa, B_GH, B_GH, B_PS_S, B_PS_S,
                  k.col_flow_variant, e->stream);
   }
   LE_TRY(hipGetLastError());
@@ -362,7 +369,7 @@ void enqueue_step(Engine* e, const StepArgs* sa, hipEvent_t* ev) {
                  k.advect(), k.row_fwd_variant, st);
   mark(2);
   for (const Class& k : e->classes)
-    k.ops.column(COL_CH, e->d_desc + k.first, (int)k.members.size(), k.nx, sa + k.first,
+    k.column(COL_CH, e->d_desc + k.first, (int)k.members.size(), k.nx, sa + k.first,
                  B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant, st);
   mark(3);
   for (const Class& k : e->classes)
@@ -375,10 +382,10 @@ void enqueue_step(Engine* e, const StepArgs* sa, hipEvent_t* ev) {
   mark(5);
   for (const Class& k : e->classes) {
     if (k.inertial)
-      k.ops.column(COL_FLOW, e->d_desc + k.first, (int)k.members.size(), k.nx, sa + k.first,
+      k.column(COL_FLOW, e->d_desc + k.first, (int)k.members.size(), k.nx, sa + k.first,
                    B_OMH, B_GH, B_OM_S, B_PS_S, k.col_flow_variant, st);
     else
-      k.ops.column(COL_STOKES, e->d_desc + k.first, (int)k.members.size(), k.nx,
+      k.column(COL_STOKES, e->d_desc + k.first, (int)k.members.size(), k.nx,
                    sa + k.first, B_GH, B_GH, B_PS_S, B_PS_S, k.col_flow_variant, st);
   }
   mark(6);
@@ -480,13 +487,13 @@ void enqueue_runs_step(const Class& k, const Run* d, int n, const StepArgs* a, h
       k.ops.row_c2r(d, n, k.ny, B_PS_S, B_PS_R, B_PS_S, B_PS_R, 1, k.row_variant, st);
   }
   k.ops.advect(d, n, k.ny, a, k.inertial, k.advect(), k.row_fwd_variant, st);
-  k.ops.column(COL_CH, d, n, k.nx, a, B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant, st);
+  k.column(COL_CH, d, n, k.nx, a, B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant, st);
   k.ops.row_c2r(d, n, k.ny, B_PHIN, B_PHI, B_PHIN, B_PHI, 1, k.row_variant, st);
   k.ops.mu_source(d, n, k.ny, a, k.mu_variant, k.row_fwd_variant, st);
   if (k.inertial)
-    k.ops.column(COL_FLOW, d, n, k.nx, a, B_OMH, B_GH, B_OM_S, B_PS_S, k.col_flow_variant, st);
+    k.column(COL_FLOW, d, n, k.nx, a, B_OMH, B_GH, B_OM_S, B_PS_S, k.col_flow_variant, st);
   else
-    k.ops.column(COL_STOKES, d, n, k.nx, a, B_GH, B_GH, B_PS_S, B_PS_S, k.col_flow_variant,
+    k.column(COL_STOKES, d, n, k.nx, a, B_GH, B_GH, B_PS_S, B_PS_S, k.col_flow_variant,
                  st);
 }
 
@@ -810,13 +817,13 @@ int autotune(Engine* e) {
       k.ops.mu_source(d, n, k.ny, sa, v, k.row_fwd_variant, st);
     });
     rc = rc ? rc : pick(e, a, b, kColCand, "LE_TUNE_COL_CH", &k.col_ch_variant, [&](int v) {
-      k.ops.column(COL_CH, d, n, k.nx, sa, B_PHIH, B_FH, B_PHIN, B_PHIN, v, st);
+      k.column(COL_CH, d, n, k.nx, sa, B_PHIH, B_FH, B_PHIN, B_PHIN, v, st);
     });
     rc = rc ? rc : pick(e, a, b, kColCand, "LE_TUNE_COL_FLOW", &k.col_flow_variant, [&](int v) {
       if (k.inertial)
-        k.ops.column(COL_FLOW, d, n, k.nx, sa, B_OMH, B_GH, B_PHIH, B_FH, v, st);
+        k.column(COL_FLOW, d, n, k.nx, sa, B_OMH, B_GH, B_PHIH, B_FH, v, st);
       else
-        k.ops.column(COL_STOKES, d, n, k.nx, sa, B_GH, B_GH, B_PHIN, B_PHIN, v, st);
+        k.column(COL_STOKES, d, n, k.nx, sa, B_GH, B_GH, B_PHIN, B_PHIN, v, st);
     });
     if (!rc && cache) {
       // only choices the timing made are shared (not ones fixed by LE_TUNE_*)
@@ -1148,7 +1155,8 @@ int corrected_steps(Engine* e, int64_t ncoarse) {
         const CorrArgs ca{net_z_out(e->net), net_partials(e->net), net_tiles(e->net),
                           e->net->scales[2], e->net->scales[3], e->corr_proj};
         o.row_r2c_corr(d, r.p.ny, ca, e->classes[r.cls].row_fwd_variant, e->stream);
-        o.column(COL_POISSON, d, 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S, 0, e->stream);
+        e->classes[r.cls].column(COL_POISSON, d, 1, r.p.nx, sa, B_OM_S, B_OM_S, B_PS_S, B_PS_S,
+                                 0, e->stream);
         return (int)LE_OK;
       });
     }));
@@ -1548,13 +1556,15 @@ int le_set_scheme(le_ctx* c, int32_t flags) {
   // every run of the engine (one for a context, all of a batch)
   c->midpoint_s = (flags & LE_SCHEME_MIDPOINT_S) != 0;
   const bool up = (flags & LE_SCHEME_UPWIND3) != 0;
+  const bool band = (flags & LE_SCHEME_BANDED) != 0;
   bool relaunch = false;
   for (Class& k : c->classes) {
-    relaunch = relaunch || k.upwind3 != up;
+    relaunch = relaunch || k.upwind3 != up || k.banded != band;
     k.upwind3 = up;
+    k.banded = band;
   }
   if (relaunch) {
-    // captured graphs hold the other advection kernel
+    // captured graphs hold the other advection or column kernels
     for (auto& kv : c->graphs) {
       (void)hipGraphExecDestroy(kv.second.second);
       (void)hipGraphDestroy(kv.second.first);
@@ -1636,7 +1646,7 @@ int time_stage_of(Engine* e, int32_t stage, int32_t reps, double* ms_per_launch)
           k.ops.advect(d, n, k.ny, sa, k.inertial, k.advect(), k.row_fwd_variant, st);
           break;
         case 2:
-          k.ops.column(COL_CH, d, n, k.nx, sa, B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant,
+          k.column(COL_CH, d, n, k.nx, sa, B_PHIH, B_FH, B_PHIN, B_PHIN, k.col_ch_variant,
                        st);
           break;
         case 3:  // into the real scratch
@@ -1647,10 +1657,10 @@ int time_stage_of(Engine* e, int32_t stage, int32_t reps, double* ms_per_launch)
           break;
         default:  // outputs into the spectral scratch, the state untouched
           if (k.inertial)
-            k.ops.column(COL_FLOW, d, n, k.nx, sa, B_OMH, B_GH, B_PHIH, B_FH,
+            k.column(COL_FLOW, d, n, k.nx, sa, B_OMH, B_GH, B_PHIH, B_FH,
                          k.col_flow_variant, st);
           else
-            k.ops.column(COL_STOKES, d, n, k.nx, sa, B_GH, B_GH, B_PHIN, B_PHIN,
+            k.column(COL_STOKES, d, n, k.nx, sa, B_GH, B_GH, B_PHIN, B_PHIN,
                          k.col_flow_variant, st);
           break;
       }

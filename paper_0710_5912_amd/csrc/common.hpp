@@ -69,6 +69,9 @@ struct Run {
 
 // Column-kernel variants (per-mode update applied between the transforms).
 enum ColMode { COL_CH = 0, COL_FLOW = 1, COL_STOKES = 2, COL_POISSON = 3 };
+// Flag on a column mode: the per-mode operators of the banded scheme switch
+// (a kernel of its own, so the default kernels carry none of its code).
+constexpr int COL_BANDED = 8;
 
 // Observable partial sums (FP64), in this order.
 enum {

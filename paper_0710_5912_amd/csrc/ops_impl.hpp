@@ -261,13 +261,13 @@ struct RowLaunch {
 
 template <typename T, int L>
 struct ColLaunch {
-  template <int MODE, int VAR>
+  template <int MODE, int VAR, bool BANDED = false>
   static void launch(const Run* runs, int nruns, int nx, const StepArgs* sa, int bin0, int bin1,
                      int bout0, int bout1, hipStream_t st) {
     using C = ColCfg<T, L, VAR>;
     const dim3 gr((nx / 2 + 1 + C::CW - 1) / C::CW, 1, nruns), bl(C::THREADS);
-    hipLaunchKernelGGL((k_column<T, L, MODE, VAR>), gr, bl, 0, st, runs, sa, bin0, bin1, bout0,
-                       bout1);
+    hipLaunchKernelGGL((k_column<T, L, MODE, VAR, BANDED>), gr, bl, 0, st, runs, sa, bin0, bin1,
+                       bout0, bout1);
   }
   template <int MODE>
   static void by_variant(int variant, const Run* runs, int nruns, int nx, const StepArgs* sa,
@@ -280,8 +280,27 @@ struct ColLaunch {
       default: launch<MODE, 0>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st); break;
     }
   }
+  // mode: a ColMode, with COL_BANDED for the banded scheme (shape 0 whatever
+  // the variant: a switch for checks of the scheme, not a tuned path)
   static void column(int mode, const Run* runs, int nruns, int nx, const StepArgs* sa,
                      int bin0, int bin1, int bout0, int bout1, int variant, hipStream_t st) {
+    if (mode & COL_BANDED) {
+      switch (mode & ~COL_BANDED) {
+        case COL_CH:
+          launch<COL_CH, 0, true>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st);
+          break;
+        case COL_FLOW:
+          launch<COL_FLOW, 0, true>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st);
+          break;
+        case COL_STOKES:
+          launch<COL_STOKES, 0, true>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st);
+          break;
+        default:
+          launch<COL_POISSON, 0, true>(runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st);
+          break;
+      }
+      return;
+    }
     switch (mode) {
       case COL_CH:
         by_variant<COL_CH>(variant, runs, nruns, nx, sa, bin0, bin1, bout0, bout1, st);

@@ -1472,7 +1472,7 @@ __global__ void k_copy_real(const Run* __restrict__ run, int bin, int bout) {
 //  COL_FLOW    (omega_h, g) -> (omega', psi')   stages 2b and 3
 //  COL_STOKES  g -> psi'                  zero-Reynolds solve
 //  COL_POISSON omega -> psi               set-up: psi from omega
-template <typename T, int L, int MODE, int VAR>
+template <typename T, int L, int MODE, int VAR, bool BANDED = false>
 __global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void k_column(
     const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int bin0, int bin1,
     int bout0, int bout1) {
@@ -1525,7 +1525,7 @@ __global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void
   for (int q = 0; q < C::E; ++q) {
     const int n = t + q * C::P;
     const Modes md = modes(geo, m, n);
-    const double lam = geo.banded ? lambda_banded(geo, m, n, s) : lambda_of(md, s);
+    const double lam = BANDED ? lambda_banded(geo, m, n, s) : lambda_of(md, s);
     const bool zero = (m == 0 && n == 0);
     const double a0x = (double)v0[q].x, a0y = (double)v0[q].y;
     if constexpr (MODE == COL_CH) {
