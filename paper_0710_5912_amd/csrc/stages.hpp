@@ -355,21 +355,31 @@ __global__ __launch_bounds__((RowCfg<L, E, GDIV>::THREADS)) LE_OCCUPANCY void k_
   }
 }
 
+// Row stride of an LDS area that stages NR row spectra for tile-run stores:
+// at least L + 1 (the Nyquist slot), padded so that the NR kTW elements of
+// the tile runs that one bank row's worth of lanes reads (16 lanes in FP64,
+// 32 in FP32) fall on distinct banks.
+template <typename T, int NR>
+constexpr int staged_stride(int L) {
+  constexpr int S = 256 / (int)sizeof(c2<T>);
+  return L + (S / NR > 1 ? S / NR : 1);
+}
+
 // Row transforms with the row spectra staged through LDS.  A block owns RB
 // consecutive rows (RB >= RB0, a power of two): after the row transforms the
 // RB spectra go to LDS and the block stores them tile by tile, consecutive
 // threads writing consecutive elements of a tile (the RB rows' kTW modes),
 // so every store instruction writes whole runs of RB kTW values instead of
 // one row's kTW values per tile; the inverse loads the same runs into LDS
-// and hands each row to its transform group.  Rows in LDS have stride L + 1
-// (the packed DC/Nyquist slot plus the Nyquist mode).
+// and hands each row to its transform group.  Rows in LDS have the stride
+// staged_stride (room for the packed DC/Nyquist slot plus the Nyquist mode).
 template <int L, int E, int RB0>
 struct RowT {
   static constexpr int P = L / E;
   static constexpr int G0 = clampi(128 / P, 1, 16);
   static constexpr int RB = G0 > RB0 ? G0 : RB0;  // rows per block
   static constexpr int THREADS = RB * P;
-  static constexpr bool OK = THREADS <= 1024 && (long)RB * (L + 1) * 16 <= 160L * 1024;
+  static constexpr bool OK = THREADS <= 1024 && (long)RB * (L + 16) * 16 <= 160L * 1024;
 };
 // Blocks of the staged row kernels are taken in launch order (consecutive
 // blocks go to different XCDs and run at the same time), so the blocks in
@@ -382,7 +392,7 @@ template <typename T, int L, int E, int RB0>
 __global__ __launch_bounds__((RowT<L, E, RB0>::THREADS)) LE_OCCUPANCY void k_row_r2c_t(
     const Run* __restrict__ runs, R2cJobs jobs) {
   using C = RowT<L, E, RB0>;
-  constexpr int LS = L + 1;
+  constexpr int LS = staged_stride<T, C::RB>(L);
   __shared__ c2<T> lds[C::RB * LS];
   const BPos bp = block_pos_linear();
   const Run& R = runs[bp.z];
@@ -421,7 +431,7 @@ template <typename T, int L, int E, int RB0>
 __global__ __launch_bounds__((RowT<L, E, RB0>::THREADS)) LE_OCCUPANCY void k_row_c2r_t(
     const Run* __restrict__ runs, int bin0, int bout0, int bin1, int bout1) {
   using C = RowT<L, E, RB0>;
-  constexpr int LS = L + 1;
+  constexpr int LS = staged_stride<T, C::RB>(L);
   __shared__ c2<T> lds[C::RB * LS];
   const BPos bp = block_pos_linear();
   const Run& R = runs[bp.z];
@@ -1004,7 +1014,8 @@ template <typename T, int NX, bool R1, int NR, int EF_>
 __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_adv_batch(
     const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int rows, int inertial) {
   using C = AdvBatch<T, NX, NR, EF_>;
-  constexpr int L = C::L, EF = C::EF, PF = C::PF, TPB = C::TPB, LS = L + 1;
+  constexpr int L = C::L, EF = C::EF, PF = C::PF, TPB = C::TPB;
+  constexpr int LS = staged_stride<T, NR>(L);
   __shared__ c2<T> buf[NR * LS];
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
@@ -1287,7 +1298,8 @@ template <typename T, int NX, int NR, int EF_>
 __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_mug_batch(
     const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int rows) {
   using C = AdvBatch<T, NX, NR, EF_>;
-  constexpr int L = C::L, EF = C::EF, PF = C::PF, TPB = C::TPB, LS = L + 1;
+  constexpr int L = C::L, EF = C::EF, PF = C::PF, TPB = C::TPB;
+  constexpr int LS = staged_stride<T, NR>(L);
   __shared__ c2<T> buf[NR * LS];
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
