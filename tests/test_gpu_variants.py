@@ -26,14 +26,16 @@ KEYS = ("LE_TUNE_ADV", "LE_TUNE_MU", "LE_TUNE_COL_CH", "LE_TUNE_COL_FLOW", "LE_T
 # in one kernel (k-row strips; advect with two / one x pairs per thread);
 # advect and mu_source 128 + k / 192 + k / 256 + k: the batched one-kernel
 # forms (k-row strips in batches of four / two / two rows; at 512 the two-row
-# 16-value form falls back to the strips)
+# 16-value form falls back to the strips); strips shorter than a batch (130,
+# 129, 193) leave the batch's last rows unstored
 COMBOS = [(0, 0, 0, 0, 0), (4, 4, 1, 1, 1), (32, 32, 2, 2, 2), (8, 16, 3, 3, 3),
           (2, 2, 0, 0, 1), (66, 4, 0, 1, 2), (72, 8, 2, 0, 0), (100, 2, 1, 3, 0),
           (98, 66, 0, 0, 3), (4, 68, 1, 1, 0), (100, 72, 3, 2, 1), (8, 8, 4, 4, 4),
           (68, 68, 4, 3, 5), (4, 4, 2, 4, 5), (132, 4, 0, 3, 5), (136, 68, 4, 4, 4),
           (160, 8, 3, 0, 0), (194, 4, 4, 3, 5), (200, 68, 0, 1, 2),
           (132, 132, 0, 0, 0), (196, 196, 3, 3, 5), (136, 144, 1, 2, 4), (4, 194, 4, 4, 1),
-          (68, 200, 2, 1, 3), (258, 260, 0, 3, 5), (264, 258, 1, 1, 2)]
+          (68, 200, 2, 1, 3), (258, 260, 0, 3, 5), (264, 258, 1, 1, 2),
+          (130, 129, 0, 0, 0), (193, 193, 1, 1, 1), (257, 130, 2, 2, 2)]
 
 
 def params(nx, ny, **kw):
