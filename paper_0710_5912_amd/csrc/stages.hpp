@@ -1515,18 +1515,28 @@ __global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void
   // column m of the tiled spectra: element n at col + n kTW
   const size_t col = spec_index(L, 0, m);
   c2<T> v0[C::E], v1[C::E];
+  // PRE: the second field's loads are issued before the first field's
+  // transform, so their latency hides behind it.  Only where the registers
+  // already limit the shape to two waves per SIMD (FP64, 16 values per
+  // thread) and the CH pass (the flow pass would spill): elsewhere the
+  // extra registers cost occupancy (measured slower at 1024^2 and 2048^2).
+  constexpr bool PRE = NIN == 2 && !DUAL && MODE == COL_CH && C::E == 16 && sizeof(T) == 8;
 #pragma unroll
   for (int q = 0; q < C::E; ++q) v0[q] = ldg<T>(in0 + col + (size_t)(t + q * C::P) * kTW);
-  if constexpr (DUAL) {
+  if constexpr (DUAL || PRE) {
 #pragma unroll
     for (int q = 0; q < C::E; ++q) v1[q] = ldg<T>(in1 + col + (size_t)(t + q * C::P) * kTW);
+  }
+  if constexpr (DUAL) {
     fft_group2<T, L, C::E, -1>(v0, v1, lds + c, lds1 + c, C::CW, tw, t);
   } else {
     fft_group<T, L, C::E, -1>(v0, lds + c, C::CW, tw, t);
   }
   if constexpr (NIN == 2 && !DUAL) {
+    if constexpr (!PRE) {
 #pragma unroll
-    for (int q = 0; q < C::E; ++q) v1[q] = ldg<T>(in1 + col + (size_t)(t + q * C::P) * kTW);
+      for (int q = 0; q < C::E; ++q) v1[q] = ldg<T>(in1 + col + (size_t)(t + q * C::P) * kTW);
+    }
     __syncthreads();
     fft_group<T, L, C::E, -1>(v1, lds + c, C::CW, tw, t);
   }
