@@ -215,10 +215,11 @@ int le_set_state(le_ctx* c, const double* phi, const double* omega,
  * le_set_state pass omega and psi through real space, which rounds).
  * le_checkpoint_size: the blob's byte count.  le_checkpoint_save writes into
  * buf (cap >= that size, else LE_EINVAL) a header (format tag, nx, ny,
- * precision, inertia, step, wraps) and the stored fields as they are on the
- * device: phi (real), the row spectra of omega (rho > 0) and psi, in storage
- * precision and the library's layout.  le_checkpoint_load restores such a
- * blob into a context of the same nx, ny, precision and inertia (LE_EINVAL
+ * precision, inertia, the spectral layout's tile width, step, wraps) and the
+ * stored fields as they are on the device: phi (real), the row spectra of
+ * omega (rho > 0) and psi, in storage precision and the library's layout.
+ * le_checkpoint_load restores such a blob into a context of the same nx, ny,
+ * precision and inertia and a library of the same layout (LE_EINVAL
  * otherwise, or for a damaged or short blob); the continued run equals the
  * saved one bit for bit when both contexts use the same kernel variants
  * (le_tuning).  Single contexts only.

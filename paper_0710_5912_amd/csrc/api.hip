@@ -1685,7 +1685,8 @@ int time_stage_of(Engine* e, int32_t stage, int32_t reps, double* ms_per_launch)
 // the library's layout).
 struct CkptHeader {
   uint64_t magic;
-  int32_t version, nx, ny, precision, inertial, pad;
+  int32_t version, nx, ny, precision, inertial;
+  int32_t tile;  // modes per tile of the row-spectral layout (kTW)
   int64_t step, wraps;
   uint64_t bytes;
 };
@@ -1711,6 +1712,7 @@ int le_checkpoint_save(le_ctx* c, void* buf, int64_t cap) {
   std::memset(&h, 0, sizeof(h));
   h.magic = kCkptMagic;
   h.version = 1;
+  h.tile = kTW;
   h.nx = r.p.nx;
   h.ny = r.p.ny;
   h.precision = r.p.precision;
@@ -1737,8 +1739,8 @@ int le_checkpoint_load(le_ctx* c, const void* buf, int64_t bytes) {
   RunHost& r = c->runs[0];
   CkptHeader h;
   std::memcpy(&h, buf, sizeof(h));
-  if (h.magic != kCkptMagic || h.version != 1 || h.nx != r.p.nx || h.ny != r.p.ny ||
-      h.precision != r.p.precision || h.inertial != (r.inertial ? 1 : 0) ||
+  if (h.magic != kCkptMagic || h.version != 1 || h.tile != kTW || h.nx != r.p.nx ||
+      h.ny != r.p.ny || h.precision != r.p.precision || h.inertial != (r.inertial ? 1 : 0) ||
       (int64_t)h.bytes != ckpt_bytes(r) || bytes < ckpt_bytes(r) || h.step < 0 ||
       h.wraps != wrap_count(r.p, h.step))
     return LE_EINVAL;

@@ -142,6 +142,13 @@ def test_checkpoint_resume_is_bitwise(fixed_variants, rho, prec):
         with pytest.raises(le.LeError) as ei:
             b.restore(blob[:-8])
         assert ei.value.code == le.LE_EINVAL
+        # a blob of another spectral layout (the header's tile width, the
+        # int32 after magic, version, nx, ny, precision and inertia)
+        bad = bytearray(blob)
+        bad[28:32] = (int.from_bytes(blob[28:32], "little") + 1).to_bytes(4, "little")
+        with pytest.raises(le.LeError) as ei:
+            b.restore(bytes(bad))
+        assert ei.value.code == le.LE_EINVAL
 
 
 def test_set_state_resume_to_rounding(fixed_variants):
