@@ -184,16 +184,24 @@ __device__ __forceinline__ void twiddle_powers(c2<T>* v, c2<double> w1, c2<T>* v
   }
 }
 
-// LDS slot of element i of a transform's exchange area: i with its low four
-// bits XORed by the next four.  A permutation within each aligned run of 16
-// elements (the area keeps its size), it spreads the strided accesses of the
-// Stockham passes (lanes 16 or more elements apart) over all banks, while
-// accesses to 16 consecutive elements stay on distinct banks.
-__device__ __forceinline__ int lds_slot(int i) { return i ^ ((i >> 4) & 15); }
+// LDS slot of element i of a transform's exchange area, a permutation within
+// aligned runs of elements (the area keeps its size) that spreads the strided
+// accesses of the Stockham passes over the banks.  LDS serves 128 bytes per
+// clock: 8 lanes of 16-byte (FP64) complex values or 16 lanes of 8-byte
+// (FP32) ones.  FP64: the low three bits XORed by bits 3..5 and 4..6, which
+// puts any 8 consecutive lanes of the passes' accesses (first-pass strides of
+// 2 to 16 elements, later passes' groups of 2 to 256) and any 8 consecutive
+// elements on distinct bank groups.  FP32: the low four bits XORed by the
+// next four (lanes 16 or more elements apart).
+template <typename T>
+__device__ __forceinline__ int lds_slot(int i) {
+  if constexpr (sizeof(T) == 8) return i ^ (((i >> 3) ^ (i >> 4)) & 7);
+  return i ^ ((i >> 4) & 15);
+}
 
 // Length-L complex FFT by a group of P = L/E threads; thread t in [0, P).
 // On entry v[q] = x[t + q P]; on exit v[q] = X[t + q P].
-// lds: the group's LDS area, element i at lds[lds_slot(i) * LS].  tw: the FP64 table
+// lds: the group's LDS area, element i at lds[lds_slot<T>(i) * LS].  tw: the FP64 table
 // exp(-2 pi i k / (2L)), k < 2L.  Pass p (stride Ns = R0 E^p) needs w^r,
 // w = exp(-2 pi i k / (Ns E)), k = t mod Ns, r = 1 .. E-1: w is read from
 // the table one pass ahead (its latency hides behind the pass before), the
@@ -221,7 +229,7 @@ __device__ __forceinline__ void fft_group(c2<T>* v, c2<T>* lds, int LS,
     } else {
       const int j = t + q * P;
 #pragma unroll
-      for (int r = 0; r < R0; ++r) lds[lds_slot(j * R0 + r) * LS] = b[r];
+      for (int r = 0; r < R0; ++r) lds[lds_slot<T>(j * R0 + r) * LS] = b[r];
     }
   }
   if constexpr (L > R0) {
@@ -235,7 +243,7 @@ __device__ __forceinline__ void fft_group(c2<T>* v, c2<T>* lds, int LS,
       if (pass + 1 < NP) wn = tw_of(Ns * E);
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < E; ++r) v[r] = lds[lds_slot(t + r * P) * LS];
+      for (int r = 0; r < E; ++r) v[r] = lds[lds_slot<T>(t + r * P) * LS];
       twiddle_powers<T, DIR, E>(v, w);
       dft_reg<T, DIR, E>(v);
       if (pass + 1 == NP) break;
@@ -243,7 +251,7 @@ __device__ __forceinline__ void fft_group(c2<T>* v, c2<T>* lds, int LS,
       const int k = t & (Ns - 1);
       const int idxD = (t / Ns) * Ns * E + k;
 #pragma unroll
-      for (int r = 0; r < E; ++r) lds[lds_slot(idxD + r * Ns) * LS] = v[r];
+      for (int r = 0; r < E; ++r) lds[lds_slot<T>(idxD + r * Ns) * LS] = v[r];
       Ns *= E;
     }
   }
@@ -280,8 +288,8 @@ __device__ __forceinline__ void fft_group2(c2<T>* v0, c2<T>* v1, c2<T>* lds0, c2
       const int j = t + q * P;
 #pragma unroll
       for (int r = 0; r < R0; ++r) {
-        lds0[lds_slot(j * R0 + r) * LS] = b0[r];
-        lds1[lds_slot(j * R0 + r) * LS] = b1[r];
+        lds0[lds_slot<T>(j * R0 + r) * LS] = b0[r];
+        lds1[lds_slot<T>(j * R0 + r) * LS] = b1[r];
       }
     }
   }
@@ -297,8 +305,8 @@ __device__ __forceinline__ void fft_group2(c2<T>* v0, c2<T>* v1, c2<T>* lds0, c2
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < E; ++r) {
-        v0[r] = lds0[lds_slot(t + r * P) * LS];
-        v1[r] = lds1[lds_slot(t + r * P) * LS];
+        v0[r] = lds0[lds_slot<T>(t + r * P) * LS];
+        v1[r] = lds1[lds_slot<T>(t + r * P) * LS];
       }
       twiddle_powers<T, DIR, E, true>(v0, w, v1);
       dft_reg<T, DIR, E>(v0);
@@ -309,8 +317,8 @@ __device__ __forceinline__ void fft_group2(c2<T>* v0, c2<T>* v1, c2<T>* lds0, c2
       const int idxD = (t / Ns) * Ns * E + k;
 #pragma unroll
       for (int r = 0; r < E; ++r) {
-        lds0[lds_slot(idxD + r * Ns) * LS] = v0[r];
-        lds1[lds_slot(idxD + r * Ns) * LS] = v1[r];
+        lds0[lds_slot<T>(idxD + r * Ns) * LS] = v0[r];
+        lds1[lds_slot<T>(idxD + r * Ns) * LS] = v1[r];
       }
       Ns *= E;
     }
