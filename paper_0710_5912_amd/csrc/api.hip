@@ -245,6 +245,25 @@ using Engine = le_ctx;
 
 const Run* desc(const Engine* e, const RunHost& r) { return e->d_desc + r.internal; }
 
+// Drops the cached graphs whose key keep() rejects.  The stream is drained
+// first, so no dropped graph is still executing.
+template <typename Keep>
+void drop_graphs(Engine* e, Keep&& keep) {
+  bool any = false;
+  for (const auto& kv : e->graphs) any = any || !keep(kv.first);
+  if (!any) return;
+  (void)hipStreamSynchronize(e->stream);
+  for (auto it = e->graphs.begin(); it != e->graphs.end();) {
+    if (!keep(it->first)) {
+      (void)hipGraphExecDestroy(it->second.second);
+      (void)hipGraphDestroy(it->second.first);
+      it = e->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
 void release(Engine* e) {
   for (auto& kv : e->graphs) {
     (void)hipGraphExecDestroy(kv.second.second);
@@ -434,6 +453,7 @@ int enqueue_chunk(Engine* e, int64_t key, int64_t count, F&& enqueue_one) {
   if (graph_ok && it == e->graphs.end()) {
     if (e->graphs.size() >= kGraphCacheMax) {
       auto old = e->graphs.begin();
+      (void)hipStreamSynchronize(e->stream);  // the evicted graph may still run
       (void)hipGraphExecDestroy(old->second.second);
       (void)hipGraphDestroy(old->second.first);
       e->graphs.erase(old);
@@ -1563,14 +1583,8 @@ int le_set_scheme(le_ctx* c, int32_t flags) {
     k.upwind3 = up;
     k.banded = band;
   }
-  if (relaunch) {
-    // captured graphs hold the other advection or column kernels
-    for (auto& kv : c->graphs) {
-      (void)hipGraphExecDestroy(kv.second.second);
-      (void)hipGraphDestroy(kv.second.first);
-    }
-    c->graphs.clear();
-  }
+  // captured graphs hold the other advection or column kernels
+  if (relaunch) drop_graphs(c, [](int64_t) { return false; });
   std::vector<Run> h((size_t)c->nruns);
   LE_TRY(hipMemcpy(h.data(), c->d_desc, sizeof(Run) * h.size(), hipMemcpyDeviceToHost));
   for (RunHost& r : c->runs) {
@@ -1849,15 +1863,7 @@ int le_corrector_load(le_ctx* c, const float* params, int32_t nparams, const flo
   c->audits = 0;
   c->audit_dev = 0.0;
   // captured corrected chunks hold the old scales as launch arguments
-  for (auto it = c->graphs.begin(); it != c->graphs.end();) {
-    if (it->first < 0) {
-      (void)hipGraphExecDestroy(it->second.second);
-      (void)hipGraphDestroy(it->second.first);
-      it = c->graphs.erase(it);
-    } else {
-      ++it;
-    }
-  }
+  drop_graphs(c, [](int64_t key) { return key >= 0; });
   LE_TRY(hipStreamSynchronize(c->stream));
   return LE_OK;
 }
@@ -1867,18 +1873,8 @@ int le_step_corrected(le_ctx* c, int64_t ncoarse) { return step_corrected(c, nco
 int le_corrector_projection(le_ctx* c, int32_t mode) {
   if (!c || (mode != 0 && mode != 1)) return LE_EINVAL;
   if (mode == 1 && (c->runs[0].p.nx % 16 || c->runs[0].p.ny % 16)) return LE_EINVAL;
-  if (c->corr_proj != mode) {
-    // captured corrected chunks hold the projection as a launch argument
-    for (auto it = c->graphs.begin(); it != c->graphs.end();) {
-      if (it->first < 0) {
-        (void)hipGraphExecDestroy(it->second.second);
-        (void)hipGraphDestroy(it->second.first);
-        it = c->graphs.erase(it);
-      } else {
-        ++it;
-      }
-    }
-  }
+  // captured corrected chunks hold the projection as a launch argument
+  if (c->corr_proj != mode) drop_graphs(c, [](int64_t key) { return key >= 0; });
   c->corr_proj = mode;
   return LE_OK;
 }
