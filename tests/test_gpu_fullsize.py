@@ -75,6 +75,29 @@ def test_large_workload_4096_two_steps(precision, tol, tol_flow):
     assert rel(g["psi"], st.psi) <= tol_flow
 
 
+def test_large_workload_4096_graph_replayed_steps():
+    """The headline workload in the bench's launch configuration: eight FP64
+    steps as one graph piece (captured, then replayed by a second call), every
+    field against the oracle at 1e-10, with the autotuned kernel variants."""
+    p = configs.LARGE_4096["params"]
+    phi0 = inputs.noise_phi0(4096, 4096, 4, amp=0.5)
+    print("case 4096^2 fp64 two graph-replayed calls of 8 steps, seed 4", flush=True)
+    with le.Context(p, phi0) as c:
+        c.step(8)          # captures the 8-step graph and launches it
+        c.step(8)          # replays it
+        g = c.get_state()
+        print("variants", c.tuning()[0], flush=True)
+    op = mh.Params(**p)
+    st = mh.initial_state(op, phi0, None)
+    for k in range(16):
+        st = mh.step(op, st)
+        print(f"oracle step {k + 1}/16", flush=True)
+    for k in ("phi", "omega", "psi"):
+        r = rel(g[k], getattr(st, k))
+        print(k, r, flush=True)
+        assert r <= 1e-10, k
+
+
 def test_large_workload_4096_mean_phi_and_finiteness():
     """200 steps at 4096^2: mean phi conserved to 1e-13, state finite."""
     p = configs.LARGE_4096["params"]
