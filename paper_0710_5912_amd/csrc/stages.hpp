@@ -365,6 +365,29 @@ constexpr int staged_stride(int L) {
   return L + (S / NR > 1 ? S / NR : 1);
 }
 
+// Visits the elements of the tile runs of nr staged rows, f(r, m) for row r
+// and mode m <= L, thread t taking elements t, t + NT, ...: element e is
+// entry w = e mod (kTW nr) of tile k = e / (kTW nr), i.e. row w / kTW, mode
+// k kTW + w mod kTW.  RUN = kTW nr when known at compile time (the division
+// then folds to shifts), else 0.
+template <int L, int NT, int RUN, typename F>
+__device__ __forceinline__ void for_tile_runs(int nr, F&& f) {
+  const int run = RUN > 0 ? RUN : kTW * nr;
+  const int total = (L / kTW + 1) * run;
+  for (int e = threadIdx.x; e < total; e += NT) {
+    const int k = e / run, w = e % run;
+    const int r = w / kTW, m = k * kTW + w % kTW;
+    if (m <= L) f(r, m);
+  }
+}
+template <int L, int NT, int NR, typename F>
+__device__ __forceinline__ void tile_runs(int nr, F&& f) {
+  if (nr == NR)
+    for_tile_runs<L, NT, kTW * NR>(nr, f);
+  else
+    for_tile_runs<L, NT, 0>(nr, f);
+}
+
 // Row transforms with the row spectra staged through LDS.  A block owns RB
 // consecutive rows (RB >= RB0, a power of two): after the row transforms the
 // RB spectra go to LDS and the block stores them tile by tile, consecutive
@@ -415,16 +438,11 @@ __global__ __launch_bounds__((RowT<L, E, RB0>::THREADS)) LE_OCCUPANCY void k_row
   for (int q = 0; q < E; ++q) lds[g * LS + t + q * C::P] = v[q];
   __syncthreads();
   // tile k holds modes 2k, 2k + 1 (k = L/2: the Nyquist mode and the pad)
-  const int run = kTW * rows;
-  const int total = (L / kTW + 1) * run;
-  for (int e = threadIdx.x; e < total; e += C::THREADS) {
-    const int k = e / run, w = e % run;
-    const int r = w / kTW, m = k * kTW + w % kTW;
-    if (m > L) continue;
+  tile_runs<L, C::THREADS, C::RB>(rows, [&](int r, int m) {
     const c2<T> a = lds[r * LS + (m == L ? 0 : m)];
     const c2<T> val = m == 0 ? c2<T>{a.x, T(0)} : (m == L ? c2<T>{a.y, T(0)} : a);
     stg<T>(X + spec_index(ny, j0 + r, m), val);
-  }
+  });
 }
 
 template <typename T, int L, int E, int RB0>
@@ -442,13 +460,9 @@ __global__ __launch_bounds__((RowT<L, E, RB0>::THREADS)) LE_OCCUPANCY void k_row
   const int g = threadIdx.x / C::P, t = threadIdx.x % C::P;
   const int j0 = bp.x * C::RB;
   const int rows = C::RB < ny ? C::RB : ny;
-  const int run = kTW * rows;
-  const int total = (L / kTW + 1) * run;
-  for (int e = threadIdx.x; e < total; e += C::THREADS) {
-    const int k = e / run, w = e % run;
-    const int r = w / kTW, m = k * kTW + w % kTW;
-    if (m <= L) lds[r * LS + m] = ldg<T>(X + spec_index(ny, j0 + r, m));
-  }
+  tile_runs<L, C::THREADS, C::RB>(rows, [&](int r, int m) {
+    lds[r * LS + m] = ldg<T>(X + spec_index(ny, j0 + r, m));
+  });
   __syncthreads();
   const bool ok = g < rows;
   const int gr = ok ? g : 0;
@@ -1094,16 +1108,11 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_adv_batch(
       __syncthreads();
       auto out = bufp<c2<T>>(R, f == 0 ? B_PHIH : (f == 1 ? B_FH : B_OMH));
       const int nr = min(NR, jb1 - j0);
-      const int run = kTW * nr;
-      const int total = (L / kTW + 1) * run;
-      for (int e = threadIdx.x; e < total; e += TPB) {
-        const int k = e / run, w = e % run;
-        const int r = w / kTW, m = k * kTW + w % kTW;
-        if (m > L) continue;
+      tile_runs<L, TPB, NR>(nr, [&](int r, int m) {
         const c2<T> a = buf[r * LS + (m == L ? 0 : m)];
         const c2<T> val = m == 0 ? c2<T>{a.x, T(0)} : (m == L ? c2<T>{a.y, T(0)} : a);
         stg<T>(out + spec_index(ny, j0 + r, m), val);
-      }
+      });
     }
   }
 }
@@ -1359,16 +1368,11 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_mug_batch(
     for (int q = 0; q < EF; ++q) buf[grp * LS + tt + q * PF] = v[q];
     __syncthreads();
     const int nr = min(NR, jb1 - j0);
-    const int run = kTW * nr;
-    const int total = (L / kTW + 1) * run;
-    for (int e = threadIdx.x; e < total; e += TPB) {
-      const int kk = e / run, w = e % run;
-      const int r = w / kTW, m = kk * kTW + w % kTW;
-      if (m > L) continue;
+    tile_runs<L, TPB, NR>(nr, [&](int r, int m) {
       const c2<T> a = buf[r * LS + (m == L ? 0 : m)];
       const c2<T> val = m == 0 ? c2<T>{a.x, T(0)} : (m == L ? c2<T>{a.y, T(0)} : a);
       stg<T>(out + spec_index(ny, j0 + r, m), val);
-    }
+    });
   }
 }
 
