@@ -1197,9 +1197,8 @@ __global__ __launch_bounds__(strip_threads(NX)) void k_mug_strip(
                        T(-2.0 * s / (4.0 * geo.dx * geo.dy)), T(geo.A), T(geo.B), T(geo.kappa)};
   const Stencil<T> st = make_stencil<T>(geo, s);
   const T neg_inv = T(-1.0 / (geo.rho > 0.0 ? geo.rho : geo.eta));
-  auto row = [&](int j) {
-    j = j % ny;
-    return phi + (size_t)(j < 0 ? j + ny : j) * NX;
+  auto row = [&](int j) {  // j in [-2, ny + 4]: one wrap at most, no division
+    return phi + (size_t)(j < 0 ? j + ny : (j >= ny ? j - ny : j)) * NX;
   };
   PhiRow<T> F0 = to_phirow(load_phi(row(j0 - 2), sl), sl);  // rows j-2 .. j+1 at j = j0
   PhiRow<T> F1 = to_phirow(load_phi(row(j0 - 1), sl), sl);
@@ -1255,9 +1254,8 @@ __global__ __launch_bounds__(NX / 2) void k_mug_strip_fft(const Run* __restrict_
   const Stencil<T> st = make_stencil<T>(geo, s);
   const T neg_inv = T(-1.0 / (geo.rho > 0.0 ? geo.rho : geo.eta));
   const int grp = threadIdx.x / PF, tt = threadIdx.x % PF;
-  auto row = [&](int j) {
-    j = j % ny;
-    return phi + (size_t)(j < 0 ? j + ny : j) * NX;
+  auto row = [&](int j) {  // j in [-2, ny + 4]: one wrap at most, no division
+    return phi + (size_t)(j < 0 ? j + ny : (j >= ny ? j - ny : j)) * NX;
   };
   PhiRow<T> F0 = to_phirow(load_phi(row(j0 - 2), sl), sl);  // rows j-2 .. j+1 at j = j0
   PhiRow<T> F1 = to_phirow(load_phi(row(j0 - 1), sl), sl);
@@ -1325,9 +1323,8 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_mug_batch(
   const Stencil<T> st = make_stencil<T>(geo, s);
   const T neg_inv = T(-1.0 / (geo.rho > 0.0 ? geo.rho : geo.eta));
   const int grp = threadIdx.x / PF, tt = threadIdx.x % PF;
-  auto row = [&](int j) {
-    j = j % ny;
-    return phi + (size_t)(j < 0 ? j + ny : j) * NX;
+  auto row = [&](int j) {  // j in [-2, ny + 4]: one wrap at most, no division
+    return phi + (size_t)(j < 0 ? j + ny : (j >= ny ? j - ny : j)) * NX;
   };
   for (int j0 = jb0; j0 < jb1; j0 += NR) {
     __syncthreads();  // the previous batch's LDS reads are done
