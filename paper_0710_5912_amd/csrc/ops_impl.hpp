@@ -143,11 +143,13 @@ struct RowLaunch {
         hipLaunchKernelGGL((k_mug_batch<T, NX, NR, EF>), gb, dim3(CB::TPB), 0, st, runs, sa,
                            rows);
       else if (ny == NX)
-        hipLaunchKernelGGL((k_adv_batch<T, NX, true, NR, EF>), gb, dim3(CB::TPB), 0, st, runs,
-                           sa, rows, inertial ? 1 : 0);
+        hipLaunchKernelGGL((k_adv_batch<T, NX, true, NR, EF>),
+                           dim3(inertial ? 3 : 2, gb.y, gb.z), dim3(CB::TPB), 0, st, runs, sa,
+                           rows);
       else
-        hipLaunchKernelGGL((k_adv_batch<T, NX, false, NR, EF>), gb, dim3(CB::TPB), 0, st,
-                           runs, sa, rows, inertial ? 1 : 0);
+        hipLaunchKernelGGL((k_adv_batch<T, NX, false, NR, EF>),
+                           dim3(inertial ? 3 : 2, gb.y, gb.z), dim3(CB::TPB), 0, st, runs, sa,
+                           rows);
       return true;
     }
     return false;

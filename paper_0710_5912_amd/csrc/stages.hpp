@@ -1004,18 +1004,23 @@ __global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __res
   }
 }
 
-// Stage 1a for long rows, one field at a time, in batches of NR rows (4 or
-// 2).  The block owns whole rows (NR transform groups of L/EF threads, each
-// thread L/(NR L/EF) x pairs) and walks its strip NR rows at a time.  For
-// each batch and each output field (phi_h, f and, with inertia, omega_h) it
-// walks the NR rows, one x segment of pairs at a time, with a rolling window
-// of input quads (rows j-1, j, j+1), writes the NR output rows to LDS,
-// transforms them (group g row g), stages the NR spectra in LDS and stores
-// them tile by tile, so that each store writes the NR rows' kTW modes of a
-// tile as one run.  The input rows of a batch are read once per field that
-// needs them (the halo rows again by the neighbouring batch: from the L2).
-// LDS: NR rows of L + 1 complex values whatever the field count, so the form
-// fits the 2048-point rows of nx = 4096 in FP64 (NR = 2: two blocks per CU).
+// Stage 1a for long rows in batches of NR rows (4 or 2), one output field
+// per block (phi_h, f and, with inertia, omega_h: the grid's x).  The block
+// owns whole rows (NR transform groups of L/EF threads, each thread
+// L/(NR L/EF) x pairs) and walks its strip NR rows at a time.  For each
+// batch it walks the NR rows, one x segment of pairs at a time, with a
+// rolling window of input quads (rows j-1, j, j+1), writes the NR output
+// rows to LDS, transforms them (group g row g), stages the NR spectra in LDS
+// and stores them tile by tile, so that each store writes the NR rows' kTW
+// modes of a tile as one run.  The fields of a batch are consecutive blocks
+// (one XCD, the same time): the input rows they share, and the halo rows of
+// the neighbouring batch, come from the L2.  One field per block rather
+// than the fields one after another in a block: a wave's loads wait for its
+// earlier stores too (one counter for both), so a block that went on to the
+// next field would wait for the last field's stores at its first load; the
+// next block on the CU starts while they drain.
+// LDS: NR rows of L + 1 complex values, so the form fits the 2048-point rows
+// of nx = 4096 in FP64 (NR = 2: two blocks per CU).
 constexpr bool adv_batch_ok(int nx) { return nx >= 512 && nx <= 4096; }
 
 template <typename T, int NX, int NR, int EF_>
@@ -1026,7 +1031,7 @@ struct AdvBatch {
 
 template <typename T, int NX, bool R1, int NR, int EF_>
 __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_adv_batch(
-    const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int rows, int inertial) {
+    const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int rows) {
   using C = AdvBatch<T, NX, NR, EF_>;
   constexpr int L = C::L, EF = C::EF, PF = C::PF, TPB = C::TPB;
   constexpr int LS = staged_stride<T, NR>(L);
@@ -1035,7 +1040,7 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_adv_batch(
   const Run& R = runs[bp.z];
   const Geo& geo = R.g;
   const int ny = geo.ny;
-    const int jb0 = bp.y * rows;
+  const int jb0 = bp.y * rows;
   const int jb1 = min(jb0 + rows, ny);
   auto phi = bufp<const T>(R, B_PHI);
   auto psi = bufp<const T>(R, B_PS_R);
@@ -1044,76 +1049,74 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_adv_batch(
   const Stencil<T> st = make_stencil<T>(geo, sa[bp.z].s);
   const T dt = T(geo.dt);
   const bool fh = geo.f_half != 0;
-  const int nf = inertial ? 3 : 2;
+  // f = 0: phi_h from (phi, psi); 1: f from phi (phi_h when f_half);
+  // 2: omega_h from (omega, psi)
+  const int f = bp.x;
+  auto fa = (f == 2) ? om : phi;
+  const bool cube_plain = f == 1 && !fh;
+  auto out = bufp<c2<T>>(R, f == 0 ? B_PHIH : (f == 1 ? B_FH : B_OMH));
   const int grp = threadIdx.x / PF, tt = threadIdx.x % PF;
-  auto row = [&](gp<const T> f, int j) {
-    return f + (size_t)(j < 0 ? j + ny : (j >= ny ? j - ny : j)) * NX;
+  auto row = [&](gp<const T> a, int j) {
+    return a + (size_t)(j < 0 ? j + ny : (j >= ny ? j - ny : j)) * NX;
   };
   for (int j0 = jb0; j0 < jb1; j0 += NR) {
-    for (int f = 0; f < nf; ++f) {
-      // f = 0: phi_h from (phi, psi); 1: f from phi (phi_h when f_half);
-      // 2: omega_h from (omega, psi)
-      auto fa = (f == 2) ? om : phi;
-      const bool cube_plain = f == 1 && !fh;
-      __syncthreads();  // the previous round's LDS reads are done
+    __syncthreads();  // the previous batch's LDS reads are done
 #pragma unroll 1
-      for (int g = 0; g < C::SEG; ++g) {
-        const StripLanes<T, NX, TPB> sl(g);
-        if (cube_plain) {
-          for (int r = 0; r < NR; ++r) {
-            const c2<T> pr = ldg<T>(reinterpret_cast<gp<const c2<T>>>(row(phi, j0 + r) + sl.x));
-            buf[r * L + sl.x / 2] = {pr.x * pr.x * pr.x, pr.y * pr.y * pr.y};
-          }
-          continue;
-        }
-        // every input row of the batch requested at once (rows j0-1 .. j0+NR)
-        RawQuad<T> ra[NR + 2], rb[NR + 2];
-#pragma unroll
-        for (int k = 0; k < NR + 2; ++k) {
-          ra[k] = load_raw(row(fa, j0 - 1 + k), sl);
-          rb[k] = load_raw(row(psi, j0 - 1 + k), sl);
-        }
-        Quad<T> Am = to_quad(ra[0], sl), Ac = to_quad(ra[1], sl);
-        Quad<T> Bm = to_quad(rb[0], sl), Bc = to_quad(rb[1], sl);
-#pragma unroll
+    for (int g = 0; g < C::SEG; ++g) {
+      const StripLanes<T, NX, TPB> sl(g);
+      if (cube_plain) {
         for (int r = 0; r < NR; ++r) {
-          const int j = j0 + r;
-          const Quad<T> Ap = to_quad(ra[r + 2], sl);
-          const Quad<T> Bp = to_quad(rb[r + 2], sl);
-          T bx0, bx1, by0, by1, ax0, ax1, ay0, ay1;
-          quad_dx(Bc, st.inv2dx, bx0, bx1);
-          quad_dys<T, NX, R1>(Bp, Bm, row(psi, j + 1), row(psi, j - 1), sl.x, st, by0, by1);
-          quad_dx(Ac, st.inv2dx, ax0, ax1);
-          quad_dys<T, NX, R1>(Ap, Am, row(fa, j + 1), row(fa, j - 1), sl.x, st, ay0, ay1);
-          T h0 = Ac.a0 - dt * (ax0 * by0 - ay0 * bx0);
-          T h1 = Ac.a1 - dt * (ax1 * by1 - ay1 * bx1);
-          if (f == 1) {
-            h0 = h0 * h0 * h0;
-            h1 = h1 * h1 * h1;
-          }
-          buf[r * L + sl.x / 2] = {h0, h1};
-          Am = Ac; Ac = Ap;
-          Bm = Bc; Bc = Bp;
+          const c2<T> pr = ldg<T>(reinterpret_cast<gp<const c2<T>>>(row(phi, j0 + r) + sl.x));
+          buf[r * L + sl.x / 2] = {pr.x * pr.x * pr.x, pr.y * pr.y * pr.y};
         }
+        continue;
       }
-      __syncthreads();
-      c2<T> v[EF];
+      // every input row of the batch requested at once (rows j0-1 .. j0+NR)
+      RawQuad<T> ra[NR + 2], rb[NR + 2];
 #pragma unroll
-      for (int q = 0; q < EF; ++q) v[q] = buf[grp * L + tt + q * PF];
-      __syncthreads();
-      row_r2c<T, L, EF>(v, buf + grp * L, tw, tt);
-      __syncthreads();
+      for (int k = 0; k < NR + 2; ++k) {
+        ra[k] = load_raw(row(fa, j0 - 1 + k), sl);
+        rb[k] = load_raw(row(psi, j0 - 1 + k), sl);
+      }
+      Quad<T> Am = to_quad(ra[0], sl), Ac = to_quad(ra[1], sl);
+      Quad<T> Bm = to_quad(rb[0], sl), Bc = to_quad(rb[1], sl);
 #pragma unroll
-      for (int q = 0; q < EF; ++q) buf[grp * LS + tt + q * PF] = v[q];
-      __syncthreads();
-      auto out = bufp<c2<T>>(R, f == 0 ? B_PHIH : (f == 1 ? B_FH : B_OMH));
-      const int nr = min(NR, jb1 - j0);
-      tile_runs<L, TPB, NR>(nr, [&](int r, int m) {
-        const c2<T> a = buf[r * LS + (m == L ? 0 : m)];
-        const c2<T> val = m == 0 ? c2<T>{a.x, T(0)} : (m == L ? c2<T>{a.y, T(0)} : a);
-        stg<T>(out + spec_index(ny, j0 + r, m), val);
-      });
+      for (int r = 0; r < NR; ++r) {
+        const int j = j0 + r;
+        const Quad<T> Ap = to_quad(ra[r + 2], sl);
+        const Quad<T> Bp = to_quad(rb[r + 2], sl);
+        T bx0, bx1, by0, by1, ax0, ax1, ay0, ay1;
+        quad_dx(Bc, st.inv2dx, bx0, bx1);
+        quad_dys<T, NX, R1>(Bp, Bm, row(psi, j + 1), row(psi, j - 1), sl.x, st, by0, by1);
+        quad_dx(Ac, st.inv2dx, ax0, ax1);
+        quad_dys<T, NX, R1>(Ap, Am, row(fa, j + 1), row(fa, j - 1), sl.x, st, ay0, ay1);
+        T h0 = Ac.a0 - dt * (ax0 * by0 - ay0 * bx0);
+        T h1 = Ac.a1 - dt * (ax1 * by1 - ay1 * bx1);
+        if (f == 1) {
+          h0 = h0 * h0 * h0;
+          h1 = h1 * h1 * h1;
+        }
+        buf[r * L + sl.x / 2] = {h0, h1};
+        Am = Ac; Ac = Ap;
+        Bm = Bc; Bc = Bp;
+      }
     }
+    __syncthreads();
+    c2<T> v[EF];
+#pragma unroll
+    for (int q = 0; q < EF; ++q) v[q] = buf[grp * L + tt + q * PF];
+    __syncthreads();
+    row_r2c<T, L, EF>(v, buf + grp * L, tw, tt);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < EF; ++q) buf[grp * LS + tt + q * PF] = v[q];
+    __syncthreads();
+    const int nr = min(NR, jb1 - j0);
+    tile_runs<L, TPB, NR>(nr, [&](int r, int m) {
+      const c2<T> a = buf[r * LS + (m == L ? 0 : m)];
+      const c2<T> val = m == 0 ? c2<T>{a.x, T(0)} : (m == L ? c2<T>{a.y, T(0)} : a);
+      stg<T>(out + spec_index(ny, j0 + r, m), val);
+    });
   }
 }
 
