@@ -139,17 +139,17 @@ struct RowLaunch {
     constexpr int NX = 2 * L;
     if constexpr (adv_batch_ok(NX) && NR * (NX / 2 / EF) >= 64) {
       using CB = AdvBatch<T, NX, NR, EF>;
+      // FP64 advection: one block per output field (kAdvSplit)
+      const dim3 ga(kAdvSplit<T> ? (inertial ? 3 : 2) : 1, gb.y, gb.z);
       if (mu)
         hipLaunchKernelGGL((k_mug_batch<T, NX, NR, EF>), gb, dim3(CB::TPB), 0, st, runs, sa,
                            rows);
       else if (ny == NX)
-        hipLaunchKernelGGL((k_adv_batch<T, NX, true, NR, EF>),
-                           dim3(inertial ? 3 : 2, gb.y, gb.z), dim3(CB::TPB), 0, st, runs, sa,
-                           rows);
+        hipLaunchKernelGGL((k_adv_batch<T, NX, true, NR, EF>), ga, dim3(CB::TPB), 0, st, runs,
+                           sa, rows, inertial ? 1 : 0);
       else
-        hipLaunchKernelGGL((k_adv_batch<T, NX, false, NR, EF>),
-                           dim3(inertial ? 3 : 2, gb.y, gb.z), dim3(CB::TPB), 0, st, runs, sa,
-                           rows);
+        hipLaunchKernelGGL((k_adv_batch<T, NX, false, NR, EF>), ga, dim3(CB::TPB), 0, st,
+                           runs, sa, rows, inertial ? 1 : 0);
       return true;
     }
     return false;

@@ -1004,21 +1004,24 @@ __global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __res
   }
 }
 
-// Stage 1a for long rows in batches of NR rows (4 or 2), one output field
-// per block (phi_h, f and, with inertia, omega_h: the grid's x).  The block
-// owns whole rows (NR transform groups of L/EF threads, each thread
-// L/(NR L/EF) x pairs) and walks its strip NR rows at a time.  For each
-// batch it walks the NR rows, one x segment of pairs at a time, with a
-// rolling window of input quads (rows j-1, j, j+1), writes the NR output
-// rows to LDS, transforms them (group g row g), stages the NR spectra in LDS
-// and stores them tile by tile, so that each store writes the NR rows' kTW
-// modes of a tile as one run.  The fields of a batch are consecutive blocks
-// (one XCD, the same time): the input rows they share, and the halo rows of
-// the neighbouring batch, come from the L2.  One field per block rather
-// than the fields one after another in a block: a wave's loads wait for its
-// earlier stores too (one counter for both), so a block that went on to the
-// next field would wait for the last field's stores at its first load; the
-// next block on the CU starts while they drain.
+// Stage 1a for long rows in batches of NR rows (4 or 2).  The block owns
+// whole rows (NR transform groups of L/EF threads, each thread L/(NR L/EF)
+// x pairs) and walks its strip NR rows at a time.  For each batch and
+// output field (phi_h, f and, with inertia, omega_h) it walks the NR rows,
+// one x segment of pairs at a time, with a rolling window of input quads
+// (rows j-1, j, j+1), writes the NR output rows to LDS, transforms them
+// (group g row g), stages the NR spectra in LDS and stores them tile by
+// tile, so that each store writes the NR rows' kTW modes of a tile as one
+// run.
+// FP64 (kAdvSplit): one output field per block, the grid's x; the fields of
+// a batch are consecutive blocks (one XCD, the same time), so the input
+// rows they share, and the halo rows of the neighbouring batch, come from
+// the L2.  A wave's loads wait for its earlier stores too (one counter for
+// both): a block that went on to the next field would wait for the last
+// field's stores at its first load, whereas the next block on the CU
+// starts while they drain (one block per CU: LDS).  FP32 (two blocks per
+// CU) computes the fields one after another in one block, which measured
+// faster there.
 // LDS: NR rows of L + 1 complex values, so the form fits the 2048-point rows
 // of nx = 4096 in FP64 (NR = 2: two blocks per CU).
 constexpr bool adv_batch_ok(int nx) { return nx >= 512 && nx <= 4096; }
@@ -1028,10 +1031,12 @@ struct AdvBatch {
   static constexpr int L = NX / 2, EF = EF_, PF = L / EF, TPB = NR * PF, SEG = L / TPB;
   static_assert(TPB * SEG == L && TPB >= 64, "whole wavefronts");
 };
+template <typename T>
+constexpr bool kAdvSplit = sizeof(T) == 8;
 
 template <typename T, int NX, bool R1, int NR, int EF_>
 __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_adv_batch(
-    const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int rows) {
+    const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int rows, int inertial) {
   using C = AdvBatch<T, NX, NR, EF_>;
   constexpr int L = C::L, EF = C::EF, PF = C::PF, TPB = C::TPB;
   constexpr int LS = staged_stride<T, NR>(L);
@@ -1049,74 +1054,77 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_adv_batch(
   const Stencil<T> st = make_stencil<T>(geo, sa[bp.z].s);
   const T dt = T(geo.dt);
   const bool fh = geo.f_half != 0;
-  // f = 0: phi_h from (phi, psi); 1: f from phi (phi_h when f_half);
-  // 2: omega_h from (omega, psi)
-  const int f = bp.x;
-  auto fa = (f == 2) ? om : phi;
-  const bool cube_plain = f == 1 && !fh;
-  auto out = bufp<c2<T>>(R, f == 0 ? B_PHIH : (f == 1 ? B_FH : B_OMH));
+  // fields [f0, f1): 0: phi_h from (phi, psi); 1: f from phi (phi_h when
+  // f_half); 2: omega_h from (omega, psi)
+  const int f0 = kAdvSplit<T> ? bp.x : 0;
+  const int f1 = kAdvSplit<T> ? bp.x + 1 : (inertial ? 3 : 2);
   const int grp = threadIdx.x / PF, tt = threadIdx.x % PF;
   auto row = [&](gp<const T> a, int j) {
     return a + (size_t)(j < 0 ? j + ny : (j >= ny ? j - ny : j)) * NX;
   };
   for (int j0 = jb0; j0 < jb1; j0 += NR) {
-    __syncthreads();  // the previous batch's LDS reads are done
+    for (int f = f0; f < f1; ++f) {
+      auto fa = (f == 2) ? om : phi;
+      const bool cube_plain = f == 1 && !fh;
+      auto out = bufp<c2<T>>(R, f == 0 ? B_PHIH : (f == 1 ? B_FH : B_OMH));
+      __syncthreads();  // the previous round's LDS reads are done
 #pragma unroll 1
-    for (int g = 0; g < C::SEG; ++g) {
-      const StripLanes<T, NX, TPB> sl(g);
-      if (cube_plain) {
+      for (int g = 0; g < C::SEG; ++g) {
+        const StripLanes<T, NX, TPB> sl(g);
+        if (cube_plain) {
+          for (int r = 0; r < NR; ++r) {
+            const c2<T> pr = ldg<T>(reinterpret_cast<gp<const c2<T>>>(row(phi, j0 + r) + sl.x));
+            buf[r * L + sl.x / 2] = {pr.x * pr.x * pr.x, pr.y * pr.y * pr.y};
+          }
+          continue;
+        }
+        // every input row of the batch requested at once (rows j0-1 .. j0+NR)
+        RawQuad<T> ra[NR + 2], rb[NR + 2];
+#pragma unroll
+        for (int k = 0; k < NR + 2; ++k) {
+          ra[k] = load_raw(row(fa, j0 - 1 + k), sl);
+          rb[k] = load_raw(row(psi, j0 - 1 + k), sl);
+        }
+        Quad<T> Am = to_quad(ra[0], sl), Ac = to_quad(ra[1], sl);
+        Quad<T> Bm = to_quad(rb[0], sl), Bc = to_quad(rb[1], sl);
+#pragma unroll
         for (int r = 0; r < NR; ++r) {
-          const c2<T> pr = ldg<T>(reinterpret_cast<gp<const c2<T>>>(row(phi, j0 + r) + sl.x));
-          buf[r * L + sl.x / 2] = {pr.x * pr.x * pr.x, pr.y * pr.y * pr.y};
+          const int j = j0 + r;
+          const Quad<T> Ap = to_quad(ra[r + 2], sl);
+          const Quad<T> Bp = to_quad(rb[r + 2], sl);
+          T bx0, bx1, by0, by1, ax0, ax1, ay0, ay1;
+          quad_dx(Bc, st.inv2dx, bx0, bx1);
+          quad_dys<T, NX, R1>(Bp, Bm, row(psi, j + 1), row(psi, j - 1), sl.x, st, by0, by1);
+          quad_dx(Ac, st.inv2dx, ax0, ax1);
+          quad_dys<T, NX, R1>(Ap, Am, row(fa, j + 1), row(fa, j - 1), sl.x, st, ay0, ay1);
+          T h0 = Ac.a0 - dt * (ax0 * by0 - ay0 * bx0);
+          T h1 = Ac.a1 - dt * (ax1 * by1 - ay1 * bx1);
+          if (f == 1) {
+            h0 = h0 * h0 * h0;
+            h1 = h1 * h1 * h1;
+          }
+          buf[r * L + sl.x / 2] = {h0, h1};
+          Am = Ac; Ac = Ap;
+          Bm = Bc; Bc = Bp;
         }
-        continue;
       }
-      // every input row of the batch requested at once (rows j0-1 .. j0+NR)
-      RawQuad<T> ra[NR + 2], rb[NR + 2];
+      __syncthreads();
+      c2<T> v[EF];
 #pragma unroll
-      for (int k = 0; k < NR + 2; ++k) {
-        ra[k] = load_raw(row(fa, j0 - 1 + k), sl);
-        rb[k] = load_raw(row(psi, j0 - 1 + k), sl);
-      }
-      Quad<T> Am = to_quad(ra[0], sl), Ac = to_quad(ra[1], sl);
-      Quad<T> Bm = to_quad(rb[0], sl), Bc = to_quad(rb[1], sl);
+      for (int q = 0; q < EF; ++q) v[q] = buf[grp * L + tt + q * PF];
+      __syncthreads();
+      row_r2c<T, L, EF>(v, buf + grp * L, tw, tt);
+      __syncthreads();
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int j = j0 + r;
-        const Quad<T> Ap = to_quad(ra[r + 2], sl);
-        const Quad<T> Bp = to_quad(rb[r + 2], sl);
-        T bx0, bx1, by0, by1, ax0, ax1, ay0, ay1;
-        quad_dx(Bc, st.inv2dx, bx0, bx1);
-        quad_dys<T, NX, R1>(Bp, Bm, row(psi, j + 1), row(psi, j - 1), sl.x, st, by0, by1);
-        quad_dx(Ac, st.inv2dx, ax0, ax1);
-        quad_dys<T, NX, R1>(Ap, Am, row(fa, j + 1), row(fa, j - 1), sl.x, st, ay0, ay1);
-        T h0 = Ac.a0 - dt * (ax0 * by0 - ay0 * bx0);
-        T h1 = Ac.a1 - dt * (ax1 * by1 - ay1 * bx1);
-        if (f == 1) {
-          h0 = h0 * h0 * h0;
-          h1 = h1 * h1 * h1;
-        }
-        buf[r * L + sl.x / 2] = {h0, h1};
-        Am = Ac; Ac = Ap;
-        Bm = Bc; Bc = Bp;
-      }
+      for (int q = 0; q < EF; ++q) buf[grp * LS + tt + q * PF] = v[q];
+      __syncthreads();
+      const int nr = min(NR, jb1 - j0);
+      tile_runs<L, TPB, NR>(nr, [&](int r, int m) {
+        const c2<T> a = buf[r * LS + (m == L ? 0 : m)];
+        const c2<T> val = m == 0 ? c2<T>{a.x, T(0)} : (m == L ? c2<T>{a.y, T(0)} : a);
+        stg<T>(out + spec_index(ny, j0 + r, m), val);
+      });
     }
-    __syncthreads();
-    c2<T> v[EF];
-#pragma unroll
-    for (int q = 0; q < EF; ++q) v[q] = buf[grp * L + tt + q * PF];
-    __syncthreads();
-    row_r2c<T, L, EF>(v, buf + grp * L, tw, tt);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < EF; ++q) buf[grp * LS + tt + q * PF] = v[q];
-    __syncthreads();
-    const int nr = min(NR, jb1 - j0);
-    tile_runs<L, TPB, NR>(nr, [&](int r, int m) {
-      const c2<T> a = buf[r * LS + (m == L ? 0 : m)];
-      const c2<T> val = m == 0 ? c2<T>{a.x, T(0)} : (m == L ? c2<T>{a.y, T(0)} : a);
-      stg<T>(out + spec_index(ny, j0 + r, m), val);
-    });
   }
 }
 
