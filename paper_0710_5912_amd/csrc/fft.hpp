@@ -356,6 +356,36 @@ __device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* lds, gp<const c2<double
   }
 }
 
+// row_r2c split for callers that store the spectrum from LDS: row_r2c_z
+// leaves the complex DFT z of the packed row in lds[0 .. L) (stride 1;
+// visible to the block after its next barrier), and r2c_mode forms mode m
+// (0 .. L) of the half spectrum from it with row_r2c's arithmetic, m = 0 and
+// m = L being the real DC and Nyquist values.  This saves the LDS pass that
+// stages row_r2c's result for the stores.
+template <typename T, int L, int E>
+__device__ __forceinline__ void row_r2c_z(c2<T>* v, c2<T>* lds,
+                                          gp<const c2<double>> __restrict__ tw, int t) {
+  constexpr int P = L / E;
+  fft_group<T, L, E, -1>(v, lds, 1, tw, t);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < E; ++q) lds[t + q * P] = v[q];
+}
+template <typename T, int L>
+__device__ __forceinline__ c2<T> r2c_mode(const c2<T>* lds, gp<const c2<double>> __restrict__ tw,
+                                          int m) {
+  if (m == 0 || m == L) {
+    const c2<T> z = lds[0];
+    return m == 0 ? c2<T>{z.x + z.y, T(0)} : c2<T>{z.x - z.y, T(0)};
+  }
+  const c2<T> z = lds[m], zc = lds[L - m];
+  const T h = static_cast<T>(0.5);
+  const c2<T> e = {h * (z.x + zc.x), h * (z.y - zc.y)};
+  const c2<T> o = {h * (z.y + zc.y), -h * (z.x - zc.x)};
+  const c2<double> wd = ldg<double>(tw + m);
+  return cadd(e, cmul(o, c2<T>{static_cast<T>(wd.x), static_cast<T>(wd.y)}));
+}
+
 // Packed half spectrum to the real row, scaled by 1/(2L) so that
 // row_c2r(row_r2c(x)) = x.  On entry v[q] = packed X[m], m = t + q P; on exit
 // v[q] = (x[2m], x[2m+1]).

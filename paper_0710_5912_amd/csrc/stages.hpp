@@ -1113,16 +1113,11 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_adv_batch(
 #pragma unroll
       for (int q = 0; q < EF; ++q) v[q] = buf[grp * L + tt + q * PF];
       __syncthreads();
-      row_r2c<T, L, EF>(v, buf + grp * L, tw, tt);
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < EF; ++q) buf[grp * LS + tt + q * PF] = v[q];
+      row_r2c_z<T, L, EF>(v, buf + grp * LS, tw, tt);
       __syncthreads();
       const int nr = min(NR, jb1 - j0);
       tile_runs<L, TPB, NR>(nr, [&](int r, int m) {
-        const c2<T> a = buf[r * LS + (m == L ? 0 : m)];
-        const c2<T> val = m == 0 ? c2<T>{a.x, T(0)} : (m == L ? c2<T>{a.y, T(0)} : a);
-        stg<T>(out + spec_index(ny, j0 + r, m), val);
+        stg<T>(out + spec_index(ny, j0 + r, m), r2c_mode<T, L>(buf + r * LS, tw, m));
       });
     }
   }
@@ -1370,16 +1365,11 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_mug_batch(
 #pragma unroll
     for (int q = 0; q < EF; ++q) v[q] = buf[grp * L + tt + q * PF];
     __syncthreads();
-    row_r2c<T, L, EF>(v, buf + grp * L, tw, tt);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < EF; ++q) buf[grp * LS + tt + q * PF] = v[q];
+    row_r2c_z<T, L, EF>(v, buf + grp * LS, tw, tt);
     __syncthreads();
     const int nr = min(NR, jb1 - j0);
     tile_runs<L, TPB, NR>(nr, [&](int r, int m) {
-      const c2<T> a = buf[r * LS + (m == L ? 0 : m)];
-      const c2<T> val = m == 0 ? c2<T>{a.x, T(0)} : (m == L ? c2<T>{a.y, T(0)} : a);
-      stg<T>(out + spec_index(ny, j0 + r, m), val);
+      stg<T>(out + spec_index(ny, j0 + r, m), r2c_mode<T, L>(buf + r * LS, tw, m));
     });
   }
 }
