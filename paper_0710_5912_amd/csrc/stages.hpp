@@ -1068,30 +1068,39 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_adv_batch(
       const bool cube_plain = f == 1 && !fh;
       auto out = bufp<c2<T>>(R, f == 0 ? B_PHIH : (f == 1 ? B_FH : B_OMH));
       __syncthreads();  // the previous round's LDS reads are done
+      if (cube_plain) {
 #pragma unroll 1
-      for (int g = 0; g < C::SEG; ++g) {
-        const StripLanes<T, NX, TPB> sl(g);
-        if (cube_plain) {
+        for (int g = 0; g < C::SEG; ++g) {
+          const StripLanes<T, NX, TPB> sl(g);
           for (int r = 0; r < NR; ++r) {
             const c2<T> pr = ldg<T>(reinterpret_cast<gp<const c2<T>>>(row(phi, j0 + r) + sl.x));
             buf[r * L + sl.x / 2] = {pr.x * pr.x * pr.x, pr.y * pr.y * pr.y};
           }
-          continue;
         }
-        // every input row of the batch requested at once (rows j0-1 .. j0+NR)
-        RawQuad<T> ra[NR + 2], rb[NR + 2];
+      }
+      // every input row of a segment requested at once (rows j0-1 .. j0+NR);
+      // PREF: the next segment's before this segment's stencil, their latency
+      // hidden behind it (FP64 square cells at nx = 4096, where the registers
+      // allow it at the occupancy that LDS sets; elsewhere it spilled or
+      // halved the occupancy)
+      constexpr bool PREF = sizeof(T) == 8 && NX >= 4096 && R1;
+      auto load_seg = [&](int g, RawQuad<T>* a, RawQuad<T>* b) {
+        const StripLanes<T, NX, TPB> sl(g);
 #pragma unroll
         for (int k = 0; k < NR + 2; ++k) {
-          ra[k] = load_raw(row(fa, j0 - 1 + k), sl);
-          rb[k] = load_raw(row(psi, j0 - 1 + k), sl);
+          a[k] = load_raw(row(fa, j0 - 1 + k), sl);
+          b[k] = load_raw(row(psi, j0 - 1 + k), sl);
         }
-        Quad<T> Am = to_quad(ra[0], sl), Ac = to_quad(ra[1], sl);
-        Quad<T> Bm = to_quad(rb[0], sl), Bc = to_quad(rb[1], sl);
+      };
+      auto stencil_seg = [&](int g, const RawQuad<T>* a, const RawQuad<T>* b) {
+        const StripLanes<T, NX, TPB> sl(g);
+        Quad<T> Am = to_quad(a[0], sl), Ac = to_quad(a[1], sl);
+        Quad<T> Bm = to_quad(b[0], sl), Bc = to_quad(b[1], sl);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           const int j = j0 + r;
-          const Quad<T> Ap = to_quad(ra[r + 2], sl);
-          const Quad<T> Bp = to_quad(rb[r + 2], sl);
+          const Quad<T> Ap = to_quad(a[r + 2], sl);
+          const Quad<T> Bp = to_quad(b[r + 2], sl);
           T bx0, bx1, by0, by1, ax0, ax1, ay0, ay1;
           quad_dx(Bc, st.inv2dx, bx0, bx1);
           quad_dys<T, NX, R1>(Bp, Bm, row(psi, j + 1), row(psi, j - 1), sl.x, st, by0, by1);
@@ -1106,6 +1115,32 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_adv_batch(
           buf[r * L + sl.x / 2] = {h0, h1};
           Am = Ac; Ac = Ap;
           Bm = Bc; Bc = Bp;
+        }
+      };
+      if (!cube_plain) {
+        if constexpr (PREF) {
+          RawQuad<T> ra[NR + 2], rb[NR + 2];
+          load_seg(0, ra, rb);
+#pragma unroll
+          for (int g = 0; g < C::SEG; ++g) {
+            RawQuad<T> na[NR + 2], nb[NR + 2];
+            if (g + 1 < C::SEG) load_seg(g + 1, na, nb);
+            stencil_seg(g, ra, rb);
+            if (g + 1 < C::SEG) {
+#pragma unroll
+              for (int k = 0; k < NR + 2; ++k) {
+                ra[k] = na[k];
+                rb[k] = nb[k];
+              }
+            }
+          }
+        } else {
+#pragma unroll 1
+          for (int g = 0; g < C::SEG; ++g) {
+            RawQuad<T> ra[NR + 2], rb[NR + 2];
+            load_seg(g, ra, rb);
+            stencil_seg(g, ra, rb);
+          }
         }
       }
       __syncthreads();
