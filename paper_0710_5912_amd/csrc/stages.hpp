@@ -389,8 +389,9 @@ __device__ __forceinline__ void tile_runs(int nr, F&& f) {
 }
 
 // Row transforms with the row spectra staged through LDS.  A block owns RB
-// consecutive rows (RB >= RB0, a power of two): after the row transforms the
-// RB spectra go to LDS and the block stores them tile by tile, consecutive
+// consecutive rows (RB >= RB0, a power of two): the forward transforms leave
+// the RB rows' complex transforms in LDS (row_r2c_z), and the block stores
+// the half spectra tile by tile (r2c_mode), consecutive
 // threads writing consecutive elements of a tile (the RB rows' kTW modes),
 // so every store instruction writes whole runs of RB kTW values instead of
 // one row's kTW values per tile; the inverse loads the same runs into LDS
@@ -432,16 +433,11 @@ __global__ __launch_bounds__((RowT<L, E, RB0>::THREADS)) LE_OCCUPANCY void k_row
   c2<T> v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) v[q] = ldg<T>(xr + t + q * C::P);
-  row_r2c<T, L, E>(v, lds + g * L, tw, t);
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < E; ++q) lds[g * LS + t + q * C::P] = v[q];
+  row_r2c_z<T, L, E>(v, lds + g * LS, tw, t);
   __syncthreads();
   // tile k holds modes 2k, 2k + 1 (k = L/2: the Nyquist mode and the pad)
   tile_runs<L, C::THREADS, C::RB>(rows, [&](int r, int m) {
-    const c2<T> a = lds[r * LS + (m == L ? 0 : m)];
-    const c2<T> val = m == 0 ? c2<T>{a.x, T(0)} : (m == L ? c2<T>{a.y, T(0)} : a);
-    stg<T>(X + spec_index(ny, j0 + r, m), val);
+    stg<T>(X + spec_index(ny, j0 + r, m), r2c_mode<T, L>(lds + r * LS, tw, m));
   });
 }
 
