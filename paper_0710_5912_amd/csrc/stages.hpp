@@ -1006,9 +1006,9 @@ __global__ __launch_bounds__(NX / 2 / SEG) void k_adv_strip_fft(const Run* __res
 // output field (phi_h, f and, with inertia, omega_h) it walks the NR rows,
 // one x segment of pairs at a time, with a rolling window of input quads
 // (rows j-1, j, j+1), writes the NR output rows to LDS, transforms them
-// (group g row g), stages the NR spectra in LDS and stores them tile by
-// tile, so that each store writes the NR rows' kTW modes of a tile as one
-// run.
+// (group g row g; the complex transforms stay in LDS) and stores the half
+// spectra tile by tile, formed as they are stored (r2c_mode), so that each
+// store writes the NR rows' kTW modes of a tile as one run.
 // FP64 (kAdvSplit): one output field per block, the grid's x; the fields of
 // a batch are consecutive blocks (one XCD, the same time), so the input
 // rows they share, and the halo rows of the neighbouring batch, come from
@@ -1335,8 +1335,8 @@ __global__ __launch_bounds__(NX / 2) void k_mug_strip_fft(const Run* __restrict_
 // a segment a thread requests its x pair of the phi rows j0-2 .. j0+NR+1 at
 // once, forms mu on rows j0-1 .. j0+NR in registers (the k_mug_strip
 // neighbourhoods) and g on the NR rows into LDS; the NR rows are then
-// transformed (group g row g), staged in LDS and stored tile by tile as
-// k_adv_batch stores them (B_GH).  The phi halo rows are read again by the
+// transformed (group g row g) and stored tile by tile as k_adv_batch stores
+// them (B_GH).  The phi halo rows are read again by the
 // neighbouring batch (from the L2); nothing goes through the real scratch.
 template <typename T, int NX, int NR, int EF_>
 __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_mug_batch(
