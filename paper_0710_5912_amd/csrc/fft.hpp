@@ -325,6 +325,29 @@ __device__ __forceinline__ void fft_group2(c2<T>* v0, c2<T>* v1, c2<T>* lds0, c2
   }
 }
 
+// exp(-i pi q / E) for q < E, E a power of two up to 16 (cos and sin of
+// multiples of pi/16, correctly rounded).  The table entry m = t + q L/E of
+// exp(-2 pi i m / (2L)) is tw[t] times this, so a transform thread that
+// needs the E entries t + q L/E reads one and forms the others in FP64.
+template <int E>
+__device__ __forceinline__ c2<double> root_step(int q) {
+  static_assert(E >= 1 && E <= 16 && (E & (E - 1)) == 0, "E: power of two up to 16");
+  constexpr double c[9] = {1.0,
+                           0.98078528040323044913,
+                           0.92387953251128675613,
+                           0.83146961230254523708,
+                           0.70710678118654752440,
+                           0.55557023301960222474,
+                           0.38268343236508977173,
+                           0.19509032201612826785,
+                           0.0};
+  const int k = q * (16 / E);  // angle k pi / 16, k < 16
+  // cos(k pi/16) = c[k] (k <= 8) or -c[16 - k]; sin(k pi/16) = c[8 - k] or c[k - 8]
+  const double cs = k <= 8 ? c[k] : -c[16 - k];
+  const double sn = k <= 8 ? c[8 - k] : c[k - 8];
+  return {cs, -sn};
+}
+
 // Real row x[0 .. 2L) to its packed half spectrum.
 // On entry v[q] = (x[2m], x[2m+1]) for m = t + q P.  On exit v[q] = X[m]
 // for m >= 1 and v[q] = (X[0], X[L]) for m = 0 (DC and Nyquist are real).
@@ -339,6 +362,7 @@ __device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* lds, gp<const c2<double
 #pragma unroll
   for (int q = 0; q < E; ++q) lds[t + q * P] = v[q];
   __syncthreads();
+  const c2<double> w0 = ldg<double>(tw + t);  // tw[t + q P] = w0 root_step<E>(q)
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int m = t + q * P;
@@ -350,7 +374,7 @@ __device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* lds, gp<const c2<double
       const T h = static_cast<T>(0.5);
       const c2<T> e = {h * (z.x + zc.x), h * (z.y - zc.y)};
       const c2<T> o = {h * (z.y + zc.y), -h * (z.x - zc.x)};
-      const c2<double> wd = ldg<double>(tw + m);
+      const c2<double> wd = q == 0 ? w0 : cmul(w0, root_step<E>(q));
       v[q] = cadd(e, cmul(o, c2<T>{static_cast<T>(wd.x), static_cast<T>(wd.y)}));
     }
   }
@@ -396,6 +420,7 @@ __device__ __forceinline__ void row_c2r(c2<T>* v, c2<T>* lds, gp<const c2<double
 #pragma unroll
   for (int q = 0; q < E; ++q) lds[t + q * P] = v[q];
   __syncthreads();
+  const c2<double> w0 = ldg<double>(tw + t);  // tw[t + q P] = w0 root_step<E>(q)
 #pragma unroll
   for (int q = 0; q < E; ++q) {
     const int m = t + q * P;
@@ -406,7 +431,7 @@ __device__ __forceinline__ void row_c2r(c2<T>* v, c2<T>* lds, gp<const c2<double
       const c2<T> Xc = lds[L - m];
       const c2<T> a = {X.x + Xc.x, X.y - Xc.y};          // X + conj(Xc)
       const c2<T> d = {X.x - Xc.x, X.y + Xc.y};          // X - conj(Xc)
-      const c2<double> wd = ldg<double>(tw + m);
+      const c2<double> wd = q == 0 ? w0 : cmul(w0, root_step<E>(q));
       const c2<T> b = cmulc(d, c2<T>{static_cast<T>(wd.x), static_cast<T>(wd.y)});                   // times exp(+2 pi i m / 2L)
       v[q] = {a.x - b.y, a.y + b.x};                      // a + i b
     }

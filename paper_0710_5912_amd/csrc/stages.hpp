@@ -1336,8 +1336,8 @@ __global__ __launch_bounds__(NX / 2) void k_mug_strip_fft(const Run* __restrict_
 // once, forms mu on rows j0-1 .. j0+NR in registers (the k_mug_strip
 // neighbourhoods) and g on the NR rows into LDS; the NR rows are then
 // transformed (group g row g) and stored tile by tile as k_adv_batch stores
-// them (B_GH).  The phi halo rows are read again by the
-// neighbouring batch (from the L2); nothing goes through the real scratch.
+// them (B_GH).  The phi halo rows are read again by the neighbouring batch
+// (from the L2); nothing goes through the real scratch.
 template <typename T, int NX, int NR, int EF_>
 __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_mug_batch(
     const Run* __restrict__ runs, const StepArgs* __restrict__ sa, int rows) {
