@@ -380,12 +380,35 @@ __device__ __forceinline__ void row_r2c(c2<T>* v, c2<T>* lds, gp<const c2<double
   }
 }
 
+// The table entries tw[m], m <= L, as products of two small LDS tables (the
+// low entries tw[0 .. LO) and every LO-th entry), for loops that store to
+// global memory: a table read from global memory there would wait for the
+// loop's earlier stores (a wave's loads and stores share one counter), an
+// LDS read does not.  tw_tab_fill (every thread of the block) before a
+// barrier, then tw_tab.
+template <int L>
+struct TwTab {
+  static constexpr int LO = L < 64 ? L : 64, NH = L / LO + 1, N = LO + NH;
+};
+template <int L, int NT>
+__device__ __forceinline__ void tw_tab_fill(c2<double>* tab, gp<const c2<double>> __restrict__ tw) {
+  using W = TwTab<L>;
+  for (int i = threadIdx.x; i < W::N; i += NT)
+    tab[i] = ldg<double>(tw + (i < W::LO ? i : (i - W::LO) * W::LO));
+}
+template <int L>
+__device__ __forceinline__ c2<double> tw_tab(const c2<double>* tab, int m) {
+  using W = TwTab<L>;
+  return cmul(tab[m % W::LO], tab[W::LO + m / W::LO]);
+}
+
 // row_r2c split for callers that store the spectrum from LDS: row_r2c_z
 // leaves the complex DFT z of the packed row in lds[0 .. L) (stride 1;
 // visible to the block after its next barrier), and r2c_mode forms mode m
 // (0 .. L) of the half spectrum from it with row_r2c's arithmetic, m = 0 and
-// m = L being the real DC and Nyquist values.  This saves the LDS pass that
-// stages row_r2c's result for the stores.
+// m = L being the real DC and Nyquist values, the twiddle from the LDS
+// tables of tw_tab.  This saves the LDS pass that stages row_r2c's result
+// for the stores.
 template <typename T, int L, int E>
 __device__ __forceinline__ void row_r2c_z(c2<T>* v, c2<T>* lds,
                                           gp<const c2<double>> __restrict__ tw, int t) {
@@ -396,8 +419,7 @@ __device__ __forceinline__ void row_r2c_z(c2<T>* v, c2<T>* lds,
   for (int q = 0; q < E; ++q) lds[t + q * P] = v[q];
 }
 template <typename T, int L>
-__device__ __forceinline__ c2<T> r2c_mode(const c2<T>* lds, gp<const c2<double>> __restrict__ tw,
-                                          int m) {
+__device__ __forceinline__ c2<T> r2c_mode(const c2<T>* lds, const c2<double>* wtab, int m) {
   if (m == 0 || m == L) {
     const c2<T> z = lds[0];
     return m == 0 ? c2<T>{z.x + z.y, T(0)} : c2<T>{z.x - z.y, T(0)};
@@ -406,7 +428,7 @@ __device__ __forceinline__ c2<T> r2c_mode(const c2<T>* lds, gp<const c2<double>>
   const T h = static_cast<T>(0.5);
   const c2<T> e = {h * (z.x + zc.x), h * (z.y - zc.y)};
   const c2<T> o = {h * (z.y + zc.y), -h * (z.x - zc.x)};
-  const c2<double> wd = ldg<double>(tw + m);
+  const c2<double> wd = tw_tab<L>(wtab, m);
   return cadd(e, cmul(o, c2<T>{static_cast<T>(wd.x), static_cast<T>(wd.y)}));
 }
 

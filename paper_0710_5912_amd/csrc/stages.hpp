@@ -418,6 +418,7 @@ __global__ __launch_bounds__((RowT<L, E, RB0>::THREADS)) LE_OCCUPANCY void k_row
   using C = RowT<L, E, RB0>;
   constexpr int LS = staged_stride<T, C::RB>(L);
   __shared__ c2<T> lds[C::RB * LS];
+  __shared__ c2<double> wtab[TwTab<L>::N];
   const BPos bp = block_pos_linear();
   const Run& R = runs[bp.z];
   const R2cJob job = jobs.j[bp.y];
@@ -433,11 +434,12 @@ __global__ __launch_bounds__((RowT<L, E, RB0>::THREADS)) LE_OCCUPANCY void k_row
   c2<T> v[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) v[q] = ldg<T>(xr + t + q * C::P);
+  tw_tab_fill<L, C::THREADS>(wtab, tw);
   row_r2c_z<T, L, E>(v, lds + g * LS, tw, t);
   __syncthreads();
   // tile k holds modes 2k, 2k + 1 (k = L/2: the Nyquist mode and the pad)
   tile_runs<L, C::THREADS, C::RB>(rows, [&](int r, int m) {
-    stg<T>(X + spec_index(ny, j0 + r, m), r2c_mode<T, L>(lds + r * LS, tw, m));
+    stg<T>(X + spec_index(ny, j0 + r, m), r2c_mode<T, L>(lds + r * LS, wtab, m));
   });
 }
 
@@ -1037,6 +1039,7 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_adv_batch(
   constexpr int L = C::L, EF = C::EF, PF = C::PF, TPB = C::TPB;
   constexpr int LS = staged_stride<T, NR>(L);
   __shared__ c2<T> buf[NR * LS];
+  __shared__ c2<double> wtab[TwTab<L>::N];
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
   const Geo& geo = R.g;
@@ -1047,6 +1050,7 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_adv_batch(
   auto psi = bufp<const T>(R, B_PS_R);
   auto om = bufp<const T>(R, B_OM_R);
   auto tw = to_global<const c2<double>>(R.twx);
+  tw_tab_fill<L, TPB>(wtab, tw);  // read after the loop's first barrier
   const Stencil<T> st = make_stencil<T>(geo, sa[bp.z].s);
   const T dt = T(geo.dt);
   const bool fh = geo.f_half != 0;
@@ -1148,7 +1152,7 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_adv_batch(
       __syncthreads();
       const int nr = min(NR, jb1 - j0);
       tile_runs<L, TPB, NR>(nr, [&](int r, int m) {
-        stg<T>(out + spec_index(ny, j0 + r, m), r2c_mode<T, L>(buf + r * LS, tw, m));
+        stg<T>(out + spec_index(ny, j0 + r, m), r2c_mode<T, L>(buf + r * LS, wtab, m));
       });
     }
   }
@@ -1345,6 +1349,7 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_mug_batch(
   constexpr int L = C::L, EF = C::EF, PF = C::PF, TPB = C::TPB;
   constexpr int LS = staged_stride<T, NR>(L);
   __shared__ c2<T> buf[NR * LS];
+  __shared__ c2<double> wtab[TwTab<L>::N];
   const BPos bp = block_pos();
   const Run& R = runs[bp.z];
   const Geo& geo = R.g;
@@ -1354,6 +1359,7 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_mug_batch(
   auto phi = bufp<const T>(R, B_PHI);
   auto out = bufp<c2<T>>(R, B_GH);
   auto tw = to_global<const c2<double>>(R.twx);
+  tw_tab_fill<L, TPB>(wtab, tw);  // read after the loop's first barrier
   const double s = sa[bp.z].s;
   const MuCoef<T> k = {T((1.0 + s * s) / (geo.dx * geo.dx)), T(1.0 / (geo.dy * geo.dy)),
                        T(-2.0 * s / (4.0 * geo.dx * geo.dy)), T(geo.A), T(geo.B), T(geo.kappa)};
@@ -1400,7 +1406,7 @@ __global__ __launch_bounds__((AdvBatch<T, NX, NR, EF_>::TPB)) void k_mug_batch(
     __syncthreads();
     const int nr = min(NR, jb1 - j0);
     tile_runs<L, TPB, NR>(nr, [&](int r, int m) {
-      stg<T>(out + spec_index(ny, j0 + r, m), r2c_mode<T, L>(buf + r * LS, tw, m));
+      stg<T>(out + spec_index(ny, j0 + r, m), r2c_mode<T, L>(buf + r * LS, wtab, m));
     });
   }
 }
