@@ -209,9 +209,18 @@ __device__ __forceinline__ int lds_slot(int i) {
 // block must call this with the same L (the passes contain
 // __syncthreads()).  On return other threads may still read lds: barrier
 // before reusing it.
-template <typename T, int L, int E, int DIR>
+// TWL: w from ltw, an LDS copy of the table's even entries ltw[i] =
+// tw[2 i], i < L/E (fft_ltw_fill), instead of global memory, for transforms
+// that follow stores of the same thread (a global read would wait for
+// them: a wave's loads and stores share one counter).
+template <int L, int E, int NT>
+__device__ __forceinline__ void fft_ltw_fill(c2<double>* ltw, gp<const c2<double>> __restrict__ tw) {
+  for (int i = threadIdx.x; i < L / E; i += NT) ltw[i] = ldg<double>(tw + 2 * i);
+}
+template <typename T, int L, int E, int DIR, bool TWL = false>
 __device__ __forceinline__ void fft_group(c2<T>* v, c2<T>* lds, int LS,
-                                          gp<const c2<double>> __restrict__ tw, int t) {
+                                          gp<const c2<double>> __restrict__ tw, int t,
+                                          const c2<double>* ltw = nullptr) {
   constexpr int P = L / E;
   constexpr int R0 = first_radix(L, E);
   constexpr int Q = E / R0;
@@ -234,7 +243,14 @@ __device__ __forceinline__ void fft_group(c2<T>* v, c2<T>* lds, int LS,
   }
   if constexpr (L > R0) {
     constexpr int NP = fft_passes(L, E);
-    auto tw_of = [&](int Ns) { return ldg<double>(tw + (2 * L / E) / Ns * (t & (Ns - 1))); };
+    // entry (2L/E)/Ns (t mod Ns): even, below 2L/E, as Ns <= L/E
+    auto tw_of = [&](int Ns) {
+      const int k = (2 * L / E) / Ns * (t & (Ns - 1));
+      if constexpr (TWL)
+        return ltw[k >> 1];
+      else
+        return ldg<double>(tw + k);
+    };
     c2<double> wn = tw_of(R0);
     int Ns = R0;
 #pragma unroll

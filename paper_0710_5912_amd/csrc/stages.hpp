@@ -1546,6 +1546,10 @@ __global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void
                         2L * C::CW * L * (long)sizeof(c2<T>) <= 160L * 1024;
   __shared__ c2<T> lds[(DUAL ? 2 : 1) * C::CW * L];
   c2<T>* const lds1 = lds + (DUAL ? C::CW * L : 0);
+  // the flow pass's second inverse transform follows the first output's
+  // stores: its twiddles come from an LDS copy (fft_group TWL)
+  constexpr bool LTW = MODE == COL_FLOW && !DUAL && L > C::E;
+  __shared__ c2<double> ltw[LTW ? L / C::E : 1];
   const int S = geo.nx / 2 + 1;
   const int c = threadIdx.x % C::CW, t = threadIdx.x / C::CW;
   const int m0 = bp.x * C::CW + c;
@@ -1553,6 +1557,7 @@ __global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void
   const int m = ok ? m0 : 0;
   // column m of the tiled spectra: element n at col + n kTW
   const size_t col = spec_index(L, 0, m);
+  if constexpr (LTW) fft_ltw_fill<L, C::E, C::THREADS>(ltw, tw);  // read after later barriers
   c2<T> v0[C::E], v1[C::E];
   // PRE: the second field's loads are issued before the first field's
   // transform, so their latency hides behind it.  Only where the registers
@@ -1641,7 +1646,7 @@ __global__ __launch_bounds__((ColCfg<T, L, VAR>::THREADS)) LE_OCCUPANCY_COL void
   }
   if constexpr (NOUT == 2) {
     __syncthreads();
-    fft_group<T, L, C::E, +1>(v1, lds + c, C::CW, tw, t);
+    fft_group<T, L, C::E, +1, LTW>(v1, lds + c, C::CW, tw, t, ltw);
     if (ok) {
 #pragma unroll
       for (int q = 0; q < C::E; ++q) stg<T>(out1 + col + (size_t)(t + q * C::P) * kTW, v1[q]);
